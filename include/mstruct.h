@@ -1,0 +1,178 @@
+/*
+ * mstruct: MI355X (gfx950) library for the pointwise phase update of the
+ * Ti-6Al-4V microstructure model of Proell et al., "A highly efficient
+ * computational approach for part-scale microstructure predictions in
+ * Ti-6Al-4V additive manufacturing" (arXiv 2402.17580).
+ *
+ * Conventions for every entry point
+ *  - Return value: MSTRUCT_OK (0) or a negative mstruct_status.  Nothing
+ *    throws across this boundary and nothing calls exit().
+ *  - Argument checks happen on the host before anything is enqueued; a
+ *    rejected call enqueues no work and leaves every buffer untouched.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream)
+ *    and runs asynchronously; device-side faults surface as MSTRUCT_EDEVICE
+ *    at the next call that synchronises.  A context must not be used by two
+ *    host threads at the same time, and its calls must be ordered (one
+ *    stream, or ordering enforced by the caller).
+ *  - Per-point arrays are device pointers owned by the caller (float32,
+ *    structure of arrays, n entries).  The library never frees them and keeps
+ *    no pointer to them after a call returns.  The context owns only small
+ *    buffers of its own (scan tables, counters, network weights).
+ *  - Units: temperature K, time s, length m, power W.
+ */
+#ifndef MSTRUCT_H
+#define MSTRUCT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MSTRUCT_OK = 0,
+    MSTRUCT_EINVAL = -1,       /* invalid argument (null, size, non-finite, range) */
+    MSTRUCT_EDEVICE = -2,      /* HIP runtime error (see mstruct_last_error) */
+    MSTRUCT_ENOMEM = -3,       /* context could not allocate its own buffers */
+    MSTRUCT_EUNSUPPORTED = -4, /* option not available (e.g. window > 4) */
+    MSTRUCT_ESTATE = -5        /* context not ready (e.g. surrogate without weights) */
+} mstruct_status;
+
+typedef struct mstruct_ctx mstruct_ctx;
+
+/* Phase fractions of n points, device float32 arrays (structure of arrays). */
+typedef struct {
+    float *beta;    /* X_beta */
+    float *alpha_s; /* X_alpha_s (stable alpha) */
+    float *alpha_m; /* X_alpha_m (martensite) */
+    int64_t n;
+} mstruct_phases;
+
+/* Laser scan as a host table of straight tracks (row-major n_tracks x 9,
+ * float64, sorted by t_on): x0, y0, z0, ux, uy, t_on, dur, q, v  -- start
+ * point on the layer surface [m], in-plane unit direction, switch-on time
+ * [s], on-duration [s], absorbed power [W], speed [m/s].  The temperature at
+ * a point is T0 plus the superposed contributions of the last `window` tracks
+ * switched on by time t (each a moving point source on the adiabatic surface
+ * of a semi-infinite body, switched on at t_on and off after dur), clamped at
+ * T_clamp.  window is 1..4. */
+typedef struct {
+    const double *tracks;
+    int64_t n_tracks;
+    double conductivity; /* k [W/(m K)] */
+    double diffusivity;  /* alpha [m^2/s] */
+    double T0;           /* far-field / initial temperature [K] */
+    double T_clamp;      /* upper clamp [K] */
+    int window;
+} mstruct_scan;
+
+/* Material points on a regular box grid: point (i, j, k) sits at
+ * (ox + i h, oy + j h, oz - k h) with box linear index i + nx (j + ny k).
+ * `index` (device int32, n sorted box linear indices) selects a masked subset;
+ * NULL means all nx*ny*nz box points in linear order (then n must equal
+ * nx*ny*nz).  Points with z > z_top + 1e-3 h are inactive: the fused call
+ * leaves them untouched (material not yet deposited). */
+typedef struct {
+    int64_t nx, ny, nz;
+    double h, ox, oy, oz;
+    const int32_t *index;
+    int64_t n;
+    double z_top;
+} mstruct_points;
+
+enum { MSTRUCT_MODE_PLAIN = 0, MSTRUCT_MODE_SURROGATE = 1 };
+
+/* Create a context on HIP device `device` (the caller's current device is
+ * restored).  *out receives the context; free it with mstruct_destroy. */
+int mstruct_init(int device, mstruct_ctx **out);
+int mstruct_destroy(mstruct_ctx *ctx);
+const char *mstruct_status_string(int status);
+/* Last error message recorded on ctx (never NULL). */
+const char *mstruct_last_error(const mstruct_ctx *ctx);
+
+/* One explicit time step for all n points, in place: Sec. 3.1 of the paper,
+ * eq. explicit_integration (forward Euler on the diffusive rates, eqs.
+ * beta_to_alpha_s, alpha_m_to_alpha_s, alpha_s_to_beta, at T_prev) followed
+ * by eq. explicit_correction (instantaneous martensite formation and
+ * dissolution, alpha_s regularisation, continuity constraints, at T_next),
+ * with the closed-form start of diffusion from zero-rate states (Sec. 3.1,
+ * Appendix A).  This is the local update of Algorithm 1 / Algorithm 2.
+ * T_prev, T_next: device float32 [n] temperatures at t_n and t_n + dt.  The
+ * input beta is not read (X_beta follows from the sum rule, eq.
+ * time_integration_beta_postprocess); alpha_s, alpha_m are read, all three
+ * are written.  dt > 0 and finite.  Arrays need no particular alignment
+ * (16-byte alignment of all five enables vector access). */
+int mstruct_step(mstruct_ctx *ctx, const float *T_prev, const float *T_next, double dt,
+                 const mstruct_phases *ph, void *stream);
+
+/* Temperature of the active points at time t (the scan model above), written
+ * to T_out[n] (device float32; inactive points get T0). */
+int mstruct_temperature(mstruct_ctx *ctx, const mstruct_scan *scan, const mstruct_points *pts,
+                        double t, float *T_out, void *stream);
+
+/* n_steps explicit steps t0 + s dt -> t0 + (s+1) dt for the active points
+ * with the temperature evaluated from the scan inside the kernel, K steps per
+ * launch with the phase state held in registers (Sec. 4.1 names this
+ * "subcycling on loaded data").  Simulated time and source positions are
+ * computed on the host in float64.  mode PLAIN runs the explicit step of
+ * mstruct_step at every step (with compensated accumulation of the Euler
+ * increments inside a launch).  mode SURROGATE replaces each block of K steps
+ * of a point by one evaluation of the trained network followed by the
+ * correction g at the block's end temperature, except where the error
+ * indicator flags the point (temperature window touching the martensite
+ * start, beta-transus or melting bands, or a start-up state), which get the
+ * K plain steps; requires weights loaded with mstruct_mlp_set_params.
+ * K in 1..64.  pts->n must equal ph->n. */
+int mstruct_fused_scan_steps(mstruct_ctx *ctx, const mstruct_scan *scan, const mstruct_points *pts,
+                             double t0, double dt, int64_t n_steps, int K, int mode,
+                             const mstruct_phases *ph, void *stream);
+
+/* dst[i] = src[idx[i]] for i < m (device arrays). */
+int mstruct_gather(mstruct_ctx *ctx, const float *src, const int64_t *idx, int64_t m, float *dst,
+                   void *stream);
+
+/* Count points violating the model's invariants (fractions outside [0, 1],
+ * alpha_s + alpha_m > 0.9 + tol, phase sum differing from X_sol(T) by more
+ * than tol when T is given, NaN).  T may be NULL.  Synchronises the stream;
+ * *violations receives the count. */
+int mstruct_check_invariants(mstruct_ctx *ctx, const mstruct_phases *ph, const float *T, float tol,
+                             int64_t *violations, void *stream);
+
+/* ---- learned surrogate: MLP 6 -> 64 -> 64 -> 3, ReLU, BF16 MFMA with
+ * float32 accumulation (not part of the paper). ----
+ * Inputs per point: (T_n, T_{n+K}, ln dt, beta, alpha_s, alpha_m), each
+ * normalised as (x - mean) / scale; outputs: (d alpha_s, d alpha_m) and a
+ * third (d beta) channel, each multiplied by out_scale.  Parameter vector
+ * layout (float32, MSTRUCT_MLP_NPARAM entries): W1[64][6], b1[64],
+ * W2[64][64], b2[64], W3[3][64], b3[3] (row = output unit). */
+#define MSTRUCT_MLP_NPARAM 4803
+
+/* Upload float32 parameters (host array) and normalisation (host arrays
+ * in_mean[6], in_scale[6], out_scale[3]); the context keeps float32 master
+ * copies and BF16 working copies. */
+int mstruct_mlp_set_params(mstruct_ctx *ctx, const float *params, const float *in_mean,
+                           const float *in_scale, const float *out_scale);
+/* Copy the float32 master parameters to a host array. */
+int mstruct_mlp_get_params(mstruct_ctx *ctx, float *params);
+
+/* Forward pass on B samples: X device float32 [B][6] (normalised inputs),
+ * Y device float32 [B][3] (raw network outputs, before out_scale). */
+int mstruct_mlp_forward(mstruct_ctx *ctx, const float *X, int64_t B, float *Y, void *stream);
+
+/* Mean-squared-error loss 0.5/B sum ||f(X) - Y||^2 and its gradient with
+ * respect to the parameters: grad device float32 [MSTRUCT_MLP_NPARAM]
+ * (deterministic: fixed-order reduction), loss device float32 [1]. */
+int mstruct_mlp_grad(mstruct_ctx *ctx, const float *X, const float *Y, int64_t B, float *grad,
+                     float *loss, void *stream);
+
+/* One Adam step (learning rate lr, betas 0.9/0.999, eps 1e-8) on the
+ * context's parameters using the gradient of the given batch; loss (device
+ * float32 [1], may be NULL) receives the batch loss. */
+int mstruct_mlp_train_step(mstruct_ctx *ctx, const float *X, const float *Y, int64_t B, float lr,
+                           float *loss, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSTRUCT_H */

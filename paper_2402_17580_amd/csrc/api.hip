@@ -1,0 +1,423 @@
+// C-ABI of the mstruct library: argument checks, the context, float64
+// bookkeeping of simulated time and source positions, and kernel launches.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/mstruct.h"
+#include "kernels.h"
+#include "mlp.h"
+
+using namespace mstruct;
+
+namespace {
+
+constexpr int kSlots = 4;  // tables in flight per context
+
+struct TableSlot {
+    SrcRec* host = nullptr;  // pinned staging
+    SrcRec* dev = nullptr;
+    size_t cap = 0;  // records
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+
+}  // namespace
+
+struct mstruct_ctx {
+    int device = 0;
+    std::string err;
+    TableSlot slots[kSlots];
+    int next_slot = 0;
+    unsigned long long* counter = nullptr;
+    MlpState mlp;
+};
+
+namespace {
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+int fail(mstruct_ctx* ctx, int code, const char* fmt, const char* detail = "") {
+    if (ctx) {
+        char buf[512];
+        snprintf(buf, sizeof buf, fmt, detail);
+        ctx->err = buf;
+    }
+    return code;
+}
+
+int hip_fail(mstruct_ctx* ctx, hipError_t e, const char* where) {
+    if (ctx) ctx->err = std::string(where) + ": " + hipGetErrorString(e);
+    return MSTRUCT_EDEVICE;
+}
+
+#define HIP_CHECK(ctx, expr)                                   \
+    do {                                                       \
+        hipError_t e_ = (expr);                                \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+    } while (0)
+
+bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
+
+int check_phases(mstruct_ctx* ctx, const mstruct_phases* ph) {
+    if (!ph) return fail(ctx, MSTRUCT_EINVAL, "phases is NULL");
+    if (ph->n < 0) return fail(ctx, MSTRUCT_EINVAL, "phases n < 0");
+    if (ph->n > 0 && (!ph->beta || !ph->alpha_s || !ph->alpha_m))
+        return fail(ctx, MSTRUCT_EINVAL, "phase array is NULL");
+    if (ph->n >= (int64_t)1 << 31) return fail(ctx, MSTRUCT_EINVAL, "more than 2^31 - 1 points");
+    return MSTRUCT_OK;
+}
+
+int check_scan(mstruct_ctx* ctx, const mstruct_scan* sc) {
+    if (!sc) return fail(ctx, MSTRUCT_EINVAL, "scan is NULL");
+    if (sc->n_tracks < 0 || (sc->n_tracks > 0 && !sc->tracks)) return fail(ctx, MSTRUCT_EINVAL, "bad track table");
+    if (sc->window < 1 || sc->window > 4) return fail(ctx, MSTRUCT_EUNSUPPORTED, "window must be 1..4");
+    if (!finite_pos(sc->conductivity) || !finite_pos(sc->diffusivity) || !isfinite(sc->T0) ||
+        !isfinite(sc->T_clamp) || sc->T_clamp < sc->T0)
+        return fail(ctx, MSTRUCT_EINVAL, "bad scan material constants");
+    for (int64_t j = 0; j < sc->n_tracks; ++j) {
+        const double* r = sc->tracks + 9 * j;
+        for (int c = 0; c < 9; ++c)
+            if (!isfinite(r[c])) return fail(ctx, MSTRUCT_EINVAL, "non-finite entry in track table");
+        if (!(r[6] >= 0.0) || !(r[7] >= 0.0) || !(r[8] >= 0.0))
+            return fail(ctx, MSTRUCT_EINVAL, "track with negative duration, power or speed");
+        if (fabs(hypot(r[3], r[4]) - 1.0) > 1e-6) return fail(ctx, MSTRUCT_EINVAL, "track direction not unit");
+        if (j > 0 && r[5] < r[5 - 9]) return fail(ctx, MSTRUCT_EINVAL, "tracks not sorted by t_on");
+    }
+    return MSTRUCT_OK;
+}
+
+// smallest plane k with oz - k h <= z_top + 1e-3 h (nz if none)
+int64_t first_active_plane(const mstruct_points* p) {
+    for (int64_t k = 0; k < p->nz; ++k)
+        if (p->oz - (double)k * p->h <= p->z_top + 1e-3 * p->h) return k;
+    return p->nz;
+}
+
+int make_geom(mstruct_ctx* ctx, const mstruct_points* p, int64_t n, PointGeom& pg) {
+    if (!p) return fail(ctx, MSTRUCT_EINVAL, "points is NULL");
+    if (p->nx <= 0 || p->ny <= 0 || p->nz <= 0 || p->nx * p->ny * p->nz >= ((int64_t)1 << 31))
+        return fail(ctx, MSTRUCT_EINVAL, "bad box dimensions");
+    if (!finite_pos(p->h) || !isfinite(p->ox) || !isfinite(p->oy) || !isfinite(p->oz) || isnan(p->z_top))
+        return fail(ctx, MSTRUCT_EINVAL, "bad grid geometry");
+    if (p->n != n) return fail(ctx, MSTRUCT_EINVAL, "points n differs from phases n");
+    const int64_t nbox = p->nx * p->ny * p->nz;
+    if (!p->index && n != nbox) return fail(ctx, MSTRUCT_EINVAL, "without an index list n must be nx*ny*nz");
+    if (p->index && n > nbox) return fail(ctx, MSTRUCT_EINVAL, "index list longer than the box");
+    const int64_t k0 = first_active_plane(p);
+    pg.index = p->index;
+    pg.nx = (int32_t)p->nx;
+    pg.nxy = (int32_t)(p->nx * p->ny);
+    pg.k0 = (int32_t)k0;
+    pg.r2min = (float)((1e-9 / p->h) * (1e-9 / p->h));
+    if (p->index) {
+        pg.first = 0;
+        pg.count = n;
+    } else {
+        pg.first = k0 * p->nx * p->ny;
+        pg.count = n - pg.first;
+    }
+    return MSTRUCT_OK;
+}
+
+// index of the last track with t_on <= t, or -1
+int64_t last_on(const mstruct_scan* sc, double t) {
+    int64_t lo = 0, hi = sc->n_tracks;
+    while (lo < hi) {
+        const int64_t mid = (lo + hi) / 2;
+        if (sc->tracks[9 * mid + 5] <= t) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo - 1;
+}
+
+void split(double g, int32_t& i, float& f) {
+    const double fl = floor(g);
+    i = (int32_t)fl;
+    f = (float)(g - fl);
+}
+
+// window slot w at time t: float64 position and timing -> float32 record
+void fill_record(SrcRec& r, const mstruct_scan* sc, const mstruct_points* p, int64_t j, double t) {
+    memset(&r, 0, sizeof r);
+    if (j < 0) return;
+    const double* tr = sc->tracks + 9 * j;
+    const double tau = t - tr[5];
+    if (!(tau > 0.0) || !(tr[7] > 0.0)) return;
+    const double ux = tr[3], uy = tr[4], q = tr[7], v = tr[8], dur = tr[6];
+    const double h = p->h, a = sc->diffusivity, k = sc->conductivity;
+    const double LOG2E = 1.4426950408889634;
+    split((tr[0] + v * tau * ux - p->ox) / h, r.ix, r.fx);
+    split((tr[1] + v * tau * uy - p->oy) / h, r.iy, r.fy);
+    split((tr[2] - p->oz) / h, r.iz, r.fz);
+    r.ux = (float)ux;
+    r.uy = (float)uy;
+    r.amp = (float)(q / (4.0 * M_PI * k * h));
+    r.c1 = (float)(v * h / (2.0 * a) * LOG2E);
+    r.vt = (float)(v * tau / h);
+    r.is = (float)(h / (2.0 * sqrt(a * tau)));
+    r.e2 = (float)(h * h / (4.0 * a * tau) * LOG2E);
+    if (tau > dur) {
+        const double t1 = tau - dur;
+        r.vt1 = (float)(v * t1 / h);
+        r.is1 = (float)(h / (2.0 * sqrt(a * t1)));
+        r.e21 = (float)(h * h / (4.0 * a * t1) * LOG2E);
+    }
+}
+
+// build (n_times x W) records for t = t0 + s dt, s = 0..n_times-1
+void build_table(SrcRec* out, const mstruct_scan* sc, const mstruct_points* p, double t0, double dt,
+                 int64_t n_times) {
+    const int W = sc->window;
+    for (int64_t s = 0; s < n_times; ++s) {
+        const double t = t0 + (double)s * dt;
+        const int64_t c = last_on(sc, t);
+        for (int w = 0; w < W; ++w) fill_record(out[s * W + w], sc, p, c - w, t);
+    }
+}
+
+// acquire a table slot with room for `records` entries; waits until its
+// previous use on the GPU is complete
+int acquire_slot(mstruct_ctx* ctx, size_t records, TableSlot*& out) {
+    TableSlot& s = ctx->slots[ctx->next_slot];
+    ctx->next_slot = (ctx->next_slot + 1) % kSlots;
+    if (!s.done) HIP_CHECK(ctx, hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
+    if (s.pending) {
+        HIP_CHECK(ctx, hipEventSynchronize(s.done));
+        s.pending = false;
+    }
+    if (s.cap < records) {
+        if (s.host) HIP_CHECK(ctx, hipHostFree(s.host));
+        if (s.dev) HIP_CHECK(ctx, hipFree(s.dev));
+        s.host = nullptr;
+        s.dev = nullptr;
+        s.cap = 0;
+        size_t cap = records < 1024 ? 1024 : records + records / 4;
+        if (hipHostMalloc((void**)&s.host, cap * sizeof(SrcRec), hipHostMallocDefault) != hipSuccess)
+            return fail(ctx, MSTRUCT_ENOMEM, "pinned table allocation failed");
+        if (hipMalloc((void**)&s.dev, cap * sizeof(SrcRec)) != hipSuccess)
+            return fail(ctx, MSTRUCT_ENOMEM, "device table allocation failed");
+        s.cap = cap;
+    }
+    out = &s;
+    return MSTRUCT_OK;
+}
+
+int release_slot(mstruct_ctx* ctx, TableSlot* s, hipStream_t st) {
+    HIP_CHECK(ctx, hipEventRecord(s->done, st));
+    s->pending = true;
+    return MSTRUCT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* mstruct_status_string(int status) {
+    switch (status) {
+        case MSTRUCT_OK: return "ok";
+        case MSTRUCT_EINVAL: return "invalid argument";
+        case MSTRUCT_EDEVICE: return "HIP device error";
+        case MSTRUCT_ENOMEM: return "out of memory";
+        case MSTRUCT_EUNSUPPORTED: return "unsupported option";
+        case MSTRUCT_ESTATE: return "context not ready";
+        default: return "unknown status";
+    }
+}
+
+const char* mstruct_last_error(const mstruct_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int mstruct_init(int device, mstruct_ctx** out) {
+    if (!out) return MSTRUCT_EINVAL;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return MSTRUCT_EINVAL;
+    mstruct_ctx* ctx = new (std::nothrow) mstruct_ctx();
+    if (!ctx) return MSTRUCT_ENOMEM;
+    ctx->device = device;
+    DeviceGuard g(device);
+    if (hipMalloc((void**)&ctx->counter, sizeof(unsigned long long)) != hipSuccess) {
+        delete ctx;
+        return MSTRUCT_ENOMEM;
+    }
+    *out = ctx;
+    return MSTRUCT_OK;
+}
+
+int mstruct_destroy(mstruct_ctx* ctx) {
+    if (!ctx) return MSTRUCT_EINVAL;
+    DeviceGuard g(ctx->device);
+    for (auto& s : ctx->slots) {
+        if (s.pending) (void)hipEventSynchronize(s.done);
+        if (s.done) (void)hipEventDestroy(s.done);
+        if (s.host) (void)hipHostFree(s.host);
+        if (s.dev) (void)hipFree(s.dev);
+    }
+    if (ctx->counter) (void)hipFree(ctx->counter);
+    mlp_free(ctx->mlp);
+    delete ctx;
+    return MSTRUCT_OK;
+}
+
+int mstruct_step(mstruct_ctx* ctx, const float* T_prev, const float* T_next, double dt, const mstruct_phases* ph,
+                 void* stream) {
+    if (!ctx) return MSTRUCT_EINVAL;
+    int rc = check_phases(ctx, ph);
+    if (rc) return rc;
+    if (!finite_pos(dt)) return fail(ctx, MSTRUCT_EINVAL, "dt must be positive and finite");
+    if (ph->n > 0 && (!T_prev || !T_next)) return fail(ctx, MSTRUCT_EINVAL, "temperature array is NULL");
+    DeviceGuard g(ctx->device);
+    hipError_t e = launch_step(T_prev, T_next, ph->beta, ph->alpha_s, ph->alpha_m, ph->n, (float)dt,
+                               (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "step launch");
+    return MSTRUCT_OK;
+}
+
+int mstruct_temperature(mstruct_ctx* ctx, const mstruct_scan* scan, const mstruct_points* pts, double t,
+                        float* T_out, void* stream) {
+    if (!ctx) return MSTRUCT_EINVAL;
+    int rc = check_scan(ctx, scan);
+    if (rc) return rc;
+    if (!pts) return fail(ctx, MSTRUCT_EINVAL, "points is NULL");
+    if (!isfinite(t)) return fail(ctx, MSTRUCT_EINVAL, "t must be finite");
+    PointGeom pg;
+    if ((rc = make_geom(ctx, pts, pts->n, pg))) return rc;
+    if (pts->n > 0 && !T_out) return fail(ctx, MSTRUCT_EINVAL, "T_out is NULL");
+    if (pts->n == 0) return MSTRUCT_OK;
+    // the temperature call covers every point (inactive ones get T0)
+    pg.first = 0;
+    pg.count = pts->n;
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    TableSlot* s;
+    if ((rc = acquire_slot(ctx, scan->window, s))) return rc;
+    build_table(s->host, scan, pts, t, 0.0, 1);
+    HIP_CHECK(ctx, hipMemcpyAsync(s->dev, s->host, scan->window * sizeof(SrcRec), hipMemcpyHostToDevice, st));
+    hipError_t e = launch_temperature(pg, scan->window, s->dev, ScanArgs{(float)scan->T0, (float)scan->T_clamp},
+                                      T_out, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "temperature launch");
+    return release_slot(ctx, s, st);
+}
+
+int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const mstruct_points* pts, double t0,
+                             double dt, int64_t n_steps, int K, int mode, const mstruct_phases* ph, void* stream) {
+    if (!ctx) return MSTRUCT_EINVAL;
+    int rc = check_phases(ctx, ph);
+    if (rc) return rc;
+    if ((rc = check_scan(ctx, scan))) return rc;
+    if (!finite_pos(dt) || !isfinite(t0)) return fail(ctx, MSTRUCT_EINVAL, "bad t0 or dt");
+    if (n_steps < 0) return fail(ctx, MSTRUCT_EINVAL, "n_steps < 0");
+    if (K < 1 || K > 64) return fail(ctx, MSTRUCT_EINVAL, "K must be in 1..64");
+    if (mode != MSTRUCT_MODE_PLAIN && mode != MSTRUCT_MODE_SURROGATE) return fail(ctx, MSTRUCT_EINVAL, "bad mode");
+    PointGeom pg;
+    if ((rc = make_geom(ctx, pts, ph->n, pg))) return rc;
+    if (mode == MSTRUCT_MODE_SURROGATE && !ctx->mlp.ready)
+        return fail(ctx, MSTRUCT_ESTATE, "surrogate mode needs network parameters (mstruct_mlp_set_params)");
+    if (n_steps == 0 || pg.count == 0) return MSTRUCT_OK;
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    const int W = scan->window;
+    const size_t recs = (size_t)(n_steps + 1) * W;
+    TableSlot* s;
+    if ((rc = acquire_slot(ctx, recs, s))) return rc;
+    build_table(s->host, scan, pts, t0, dt, n_steps + 1);
+    HIP_CHECK(ctx, hipMemcpyAsync(s->dev, s->host, recs * sizeof(SrcRec), hipMemcpyHostToDevice, st));
+    const ScanArgs sa{(float)scan->T0, (float)scan->T_clamp};
+    for (int64_t s0 = 0; s0 < n_steps; s0 += K) {
+        const int Kb = (int)((n_steps - s0) < K ? (n_steps - s0) : K);
+        hipError_t e;
+        if (mode == MSTRUCT_MODE_PLAIN)
+            e = launch_fused_plain(pg, W, s->dev + s0 * W, Kb, (float)dt, sa, ph->beta, ph->alpha_s, ph->alpha_m, st);
+        else
+            e = launch_surrogate(ctx->mlp, pg, W, s->dev + s0 * W, Kb, (float)dt, sa, ph->beta, ph->alpha_s,
+                                 ph->alpha_m, st);
+        if (e != hipSuccess) {
+            (void)release_slot(ctx, s, st);
+            return hip_fail(ctx, e, "fused launch");
+        }
+    }
+    return release_slot(ctx, s, st);
+}
+
+int mstruct_gather(mstruct_ctx* ctx, const float* src, const int64_t* idx, int64_t m, float* dst, void* stream) {
+    if (!ctx) return MSTRUCT_EINVAL;
+    if (m < 0) return fail(ctx, MSTRUCT_EINVAL, "m < 0");
+    if (m > 0 && (!src || !idx || !dst)) return fail(ctx, MSTRUCT_EINVAL, "NULL array");
+    DeviceGuard g(ctx->device);
+    hipError_t e = launch_gather(src, idx, m, dst, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "gather launch");
+    return MSTRUCT_OK;
+}
+
+int mstruct_check_invariants(mstruct_ctx* ctx, const mstruct_phases* ph, const float* T, float tol,
+                             int64_t* violations, void* stream) {
+    if (!ctx) return MSTRUCT_EINVAL;
+    int rc = check_phases(ctx, ph);
+    if (rc) return rc;
+    if (!violations) return fail(ctx, MSTRUCT_EINVAL, "violations is NULL");
+    if (!(tol >= 0.0f)) return fail(ctx, MSTRUCT_EINVAL, "tol must be >= 0");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    const unsigned long long zero = 0;
+    HIP_CHECK(ctx, hipMemcpyAsync(ctx->counter, &zero, sizeof zero, hipMemcpyHostToDevice, st));
+    hipError_t e = launch_invariants(ph->beta, ph->alpha_s, ph->alpha_m, T, ph->n, tol, ctx->counter, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "invariants launch");
+    unsigned long long h = 0;
+    HIP_CHECK(ctx, hipMemcpyAsync(&h, ctx->counter, sizeof h, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(ctx, hipStreamSynchronize(st));
+    *violations = (int64_t)h;
+    return MSTRUCT_OK;
+}
+
+}  // extern "C"
+
+// ---- learned surrogate entry points (implemented in the MLP translation unit) ----
+extern "C" {
+
+int mstruct_mlp_set_params(mstruct_ctx* ctx, const float* params, const float* in_mean, const float* in_scale,
+                           const float* out_scale) {
+    if (!ctx) return MSTRUCT_EINVAL;
+    if (!params || !in_mean || !in_scale || !out_scale) return fail(ctx, MSTRUCT_EINVAL, "NULL argument");
+    return fail(ctx, MSTRUCT_EUNSUPPORTED, "not built yet");
+}
+
+int mstruct_mlp_get_params(mstruct_ctx* ctx, float* params) {
+    if (!ctx) return MSTRUCT_EINVAL;
+    if (!params) return fail(ctx, MSTRUCT_EINVAL, "NULL argument");
+    return fail(ctx, MSTRUCT_EUNSUPPORTED, "not built yet");
+}
+
+int mstruct_mlp_forward(mstruct_ctx* ctx, const float* X, int64_t B, float* Y, void* stream) {
+    if (!ctx) return MSTRUCT_EINVAL;
+    (void)X; (void)B; (void)Y; (void)stream;
+    return fail(ctx, MSTRUCT_EUNSUPPORTED, "not built yet");
+}
+
+int mstruct_mlp_grad(mstruct_ctx* ctx, const float* X, const float* Y, int64_t B, float* grad, float* loss,
+                     void* stream) {
+    if (!ctx) return MSTRUCT_EINVAL;
+    (void)X; (void)Y; (void)B; (void)grad; (void)loss; (void)stream;
+    return fail(ctx, MSTRUCT_EUNSUPPORTED, "not built yet");
+}
+
+int mstruct_mlp_train_step(mstruct_ctx* ctx, const float* X, const float* Y, int64_t B, float lr, float* loss,
+                           void* stream) {
+    if (!ctx) return MSTRUCT_EINVAL;
+    (void)X; (void)Y; (void)B; (void)lr; (void)loss; (void)stream;
+    return fail(ctx, MSTRUCT_EUNSUPPORTED, "not built yet");
+}
+
+}  // extern "C"

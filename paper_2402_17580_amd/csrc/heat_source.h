@@ -1,0 +1,138 @@
+// Device evaluation of the scan temperature: superposed moving point sources
+// on the adiabatic surface of a semi-infinite body (linear conduction), each
+// switched on at t_on and off after dur, clamped at T_clamp.  This replaces
+// the paper's FEM heat solve (Sec. 2.1) as the driver of the phase update.
+//
+// For a source of absorbed power q, speed v, on for tau, the rise at a point a
+// distance R from the current source position and xi ahead of it along the
+// motion is
+//   F = q/(4 pi k R) [ e^{-v(xi+R)/(2 alpha)} erfc((R - v tau)/s)
+//                    + e^{-|x - P0|^2/(4 alpha tau)} erfcx((R + v tau)/s) ],
+// s = 2 sqrt(alpha tau), P0 the start point (time integral of instantaneous
+// point sources; the second term is written with erfcx so that nothing
+// overflows).  A switched-off track subtracts the same expression for a
+// virtual source started at its end point dur later (same current position).
+//
+// Coordinates are in grid units relative to the grid origin.  The host splits
+// each source position into an integer and a fractional part so that the
+// offset point - source keeps full float32 relative precision at any
+// distance.  erfc/erfcx use the Chebyshev-fitted form of Numerical Recipes
+// (Press et al., 2nd ed., Sec. 6.2, "erfcc": relative error below 1.2e-7):
+//   erfc(z) = t exp(-z^2 + P(t)), t = 1/(1 + z/2), z >= 0.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "phase_model.h"
+
+namespace mstruct {
+
+// one window slot of the scan at one time point (64 bytes)
+struct SrcRec {
+    int32_t ix, iy, iz;  // integer part of the current source position [grid units]
+    float fx, fy, fz;    // fractional part
+    float ux, uy;        // unit direction of motion
+    float amp;           // q / (4 pi k h) [K grid]; 0 marks an unused slot
+    float c1;            // v h / (2 alpha) log2(e)
+    float vt;            // v tau / h
+    float is;            // h / (2 sqrt(alpha tau))
+    float e2;            // h^2 / (4 alpha tau) log2(e)
+    float vt1, is1, e21; // same for tau - dur of a switched-off track; is1 = 0 while on
+};
+static_assert(sizeof(SrcRec) == 64, "SrcRec layout");
+
+// P(t) of the erfcc form, converted to base 2: returns log2(e) P(t)
+__device__ __forceinline__ float erfc_poly_log2(float t) {
+    float p = fmaf(t, 0.17087277f, -0.82215223f);
+    p = fmaf(t, p, 1.48851587f);
+    p = fmaf(t, p, -1.13520398f);
+    p = fmaf(t, p, 0.27886807f);
+    p = fmaf(t, p, -0.18628806f);
+    p = fmaf(t, p, 0.09678418f);
+    p = fmaf(t, p, 0.37409196f);
+    p = fmaf(t, p, 1.00002368f);
+    p = fmaf(t, p, -1.26551223f);
+    return p * kLog2e;
+}
+
+// exp2(lg) * erfc(|y|) for any y, i.e. the small part of erfc; the caller adds
+// 2 e^{...} for negative y.  lg is an extra base-2 exponent folded in.
+__device__ __forceinline__ float scaled_erfc_abs(float y, float lg) {
+    const float z = fabsf(y);
+    const float t = frcp(fmaf(0.5f, z, 1.0f));
+    return t * fexp2(fmaf(-z * z, kLog2e, erfc_poly_log2(t)) + lg);
+}
+
+// exp2(lg) * erfcx(y) for y >= 0
+__device__ __forceinline__ float scaled_erfcx(float y, float lg) {
+    const float t = frcp(fmaf(0.5f, y, 1.0f));
+    return t * fexp2(erfc_poly_log2(t) + lg);
+}
+
+// below this base-2 exponent a term is dropped (2^-40 of the amplitude)
+constexpr float kDropLog2 = -40.0f;
+
+// Contribution of one slot at grid point (gi, gj, gk) (z grid coordinate -gk).
+// Returns +inf when the point is within sqrt(r2min) of the source (clamp applies).
+__device__ __forceinline__ float source_rise(const SrcRec& s, int gi, int gj, int gk, float r2min) {
+    const float dx = (float)(gi - s.ix) - s.fx;
+    const float dy = (float)(gj - s.iy) - s.fy;
+    const float dz = (float)(-gk - s.iz) - s.fz;
+    const float R2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    if (R2 < r2min) return __builtin_inff();
+    const float rR = __builtin_amdgcn_rsqf(R2);
+    const float R = R2 * rR;
+    const float xi = fmaf(dx, s.ux, dy * s.uy);
+    const float cr = fmaf(dx, s.uy, -dy * s.ux);  // in-plane offset across the track
+    const float rho2 = fmaf(cr, cr, dz * dz);
+    // xi + R without cancellation behind the source: rho^2 / (R - xi)
+    const float xr = xi >= 0.0f ? xi + R : rho2 * frcp(R - xi);
+    const float lg1 = -s.c1 * xr;  // log2 of e^{-v(xi+R)/(2 alpha)} (<= 0)
+
+    // leading term e1 erfc(y1) of the source switched on at P0, minus
+    // e1 erfc(y1b) of the virtual source after switch-off; erfc(y) is split
+    // as base + sign * E(|y|) with base 2 for y < 0, so that equal bases
+    // cancel exactly
+    float acc = 0.0f;
+    if (lg1 > kDropLog2) {
+        const float y1 = (R - s.vt) * s.is;
+        const bool n1 = y1 < 0.0f;
+        const float E1 = (n1 || y1 < 6.0f) ? scaled_erfc_abs(y1, lg1) : 0.0f;
+        float base = n1 ? 2.0f : 0.0f;
+        acc = n1 ? -E1 : E1;
+        if (s.is1 > 0.0f) {
+            const float y1b = (R - s.vt1) * s.is1;
+            const bool nb = y1b < 0.0f;
+            const float Eb = (nb || y1b < 6.0f) ? scaled_erfc_abs(y1b, lg1) : 0.0f;
+            acc -= nb ? -Eb : Eb;
+            base -= nb ? 2.0f : 0.0f;
+        }
+        if (base != 0.0f) acc = fmaf(base, fexp2(lg1), acc);
+    }
+    // start-point terms
+    {
+        const float d = xi + s.vt;
+        const float lg2 = -s.e2 * fmaf(d, d, rho2);
+        if (lg2 > kDropLog2) acc += scaled_erfcx((R + s.vt) * s.is, lg2);
+    }
+    if (s.is1 > 0.0f) {
+        const float d = xi + s.vt1;
+        const float lg2 = -s.e21 * fmaf(d, d, rho2);
+        if (lg2 > kDropLog2) acc -= scaled_erfcx((R + s.vt1) * s.is1, lg2);
+    }
+    return s.amp * rR * acc;
+}
+
+template <int W>
+__device__ __forceinline__ float scan_temperature(const SrcRec* __restrict__ recs, int gi, int gj, int gk,
+                                                  float T0, float Tclamp, float r2min) {
+    float T = T0;
+#pragma unroll
+    for (int w = 0; w < W; ++w) {
+        const SrcRec s = recs[w];
+        if (s.amp > 0.0f) T += source_rise(s, gi, gj, gk, r2min);
+    }
+    return fminf(T, Tclamp);
+}
+
+}  // namespace mstruct

@@ -1,0 +1,35 @@
+// Kernel launch interface shared by the C-ABI layer and the kernel sources.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "heat_source.h"
+
+namespace mstruct {
+
+// the active points of one call
+struct PointGeom {
+    const int32_t* index;  // box linear indices, or nullptr for the whole box
+    int64_t first;         // first local point number processed
+    int64_t count;         // number of local points processed
+    int32_t nx, nxy;       // box dimensions
+    int32_t k0;            // points on planes k < k0 are inactive
+    float r2min;           // squared clamp radius [grid units^2]
+};
+
+// scan constants of one call
+struct ScanArgs {
+    float T0, Tclamp;
+};
+
+hipError_t launch_step(const float* Tp, const float* Tn, float* beta, float* as, float* am, int64_t n,
+                       float dt, hipStream_t st);
+hipError_t launch_temperature(const PointGeom& pg, int W, const SrcRec* rec, ScanArgs sa, float* T,
+                              hipStream_t st);
+hipError_t launch_fused_plain(const PointGeom& pg, int W, const SrcRec* tab, int K, float dt, ScanArgs sa,
+                              float* beta, float* as, float* am, hipStream_t st);
+hipError_t launch_gather(const float* src, const int64_t* idx, int64_t m, float* dst, hipStream_t st);
+hipError_t launch_invariants(const float* beta, const float* as, const float* am, const float* T, int64_t n,
+                             float tol, unsigned long long* counter, hipStream_t st);
+
+}  // namespace mstruct

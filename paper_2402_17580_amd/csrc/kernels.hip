@@ -1,0 +1,207 @@
+// Phase-update kernels for gfx950: the plain explicit step over temperature
+// arrays (HBM-bound streaming), the temperature field of a scan, and the fused
+// kernel that keeps each point's state in registers for K steps while
+// evaluating the temperature analytically (VALU-bound).
+#include "kernels.h"
+
+namespace mstruct {
+
+constexpr int kBlock = 256;
+typedef float vf4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void decode_point(const PointGeom& pg, int64_t local, int& gi, int& gj, int& gk) {
+    const int lin = pg.index ? pg.index[local] : (int)local;
+    gk = lin / pg.nxy;
+    const int rem = lin - gk * pg.nxy;
+    gj = rem / pg.nx;
+    gi = rem - gj * pg.nx;
+}
+
+// ---------------------------------------------------------------------------
+// plain step: Algorithm 1's loop over points with the local explicit step of
+// Algorithm 2; reads alpha_s, alpha_m, T^n, T^{n+1} and writes the three
+// fractions (28 bytes per point).  VEC: four consecutive points per thread
+// with 16-byte accesses (all five arrays 16-byte aligned).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void step_point(float Tp, float Tn, float& b, float& a, float& m, float dt) {
+    float alo = 0.0f, mlo = 0.0f;
+    b = explicit_step<false>(a, m, alo, mlo, Tp, alpha_eq(Tp), Tn, alpha_eq(Tn), dt);
+}
+
+template <bool VEC>
+__global__ __launch_bounds__(kBlock) void step_kernel(const float* __restrict__ Tp, const float* __restrict__ Tn,
+                                                     float* __restrict__ beta, float* __restrict__ as,
+                                                     float* __restrict__ am, int64_t n, float dt) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (VEC) {
+        const int64_t i = 4 * g;
+        if (i + 3 < n) {
+            const vf4 tp = __builtin_nontemporal_load(reinterpret_cast<const vf4*>(Tp) + g);
+            const vf4 tn = __builtin_nontemporal_load(reinterpret_cast<const vf4*>(Tn) + g);
+            vf4 a = __builtin_nontemporal_load(reinterpret_cast<const vf4*>(as) + g);
+            vf4 m = __builtin_nontemporal_load(reinterpret_cast<const vf4*>(am) + g);
+            vf4 b;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                float ac = a[c], mc = m[c], bc;
+                step_point(tp[c], tn[c], bc, ac, mc, dt);
+                a[c] = ac;
+                m[c] = mc;
+                b[c] = bc;
+            }
+            __builtin_nontemporal_store(a, reinterpret_cast<vf4*>(as) + g);
+            __builtin_nontemporal_store(m, reinterpret_cast<vf4*>(am) + g);
+            __builtin_nontemporal_store(b, reinterpret_cast<vf4*>(beta) + g);
+        } else {
+            for (int64_t j = i; j < n; ++j) {
+                float a = as[j], m = am[j], b;
+                step_point(Tp[j], Tn[j], b, a, m, dt);
+                as[j] = a;
+                am[j] = m;
+                beta[j] = b;
+            }
+        }
+    } else {
+        if (g < n) {
+            float a = as[g], m = am[g], b;
+            step_point(Tp[g], Tn[g], b, a, m, dt);
+            as[g] = a;
+            am[g] = m;
+            beta[g] = b;
+        }
+    }
+}
+
+hipError_t launch_step(const float* Tp, const float* Tn, float* beta, float* as, float* am, int64_t n,
+                       float dt, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    const uintptr_t align = (uintptr_t)Tp | (uintptr_t)Tn | (uintptr_t)beta | (uintptr_t)as | (uintptr_t)am;
+    if ((align & 15) == 0) {
+        const int64_t threads = (n + 3) / 4;
+        const int64_t blocks = (threads + kBlock - 1) / kBlock;
+        hipLaunchKernelGGL(step_kernel<true>, dim3((unsigned)blocks), dim3(kBlock), 0, st, Tp, Tn, beta, as, am,
+                           n, dt);
+    } else {
+        const int64_t blocks = (n + kBlock - 1) / kBlock;
+        hipLaunchKernelGGL(step_kernel<false>, dim3((unsigned)blocks), dim3(kBlock), 0, st, Tp, Tn, beta, as, am,
+                           n, dt);
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// temperature field at one time point
+// ---------------------------------------------------------------------------
+template <int W>
+__global__ __launch_bounds__(kBlock) void temperature_kernel(PointGeom pg, const SrcRec* __restrict__ rec,
+                                                            ScanArgs sa, float* __restrict__ T) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= pg.count) return;
+    const int64_t local = pg.first + g;
+    int gi, gj, gk;
+    decode_point(pg, local, gi, gj, gk);
+    T[local] = (gk < pg.k0) ? sa.T0 : scan_temperature<W>(rec, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min);
+}
+
+// ---------------------------------------------------------------------------
+// fused K steps with the analytic temperature: one point per lane, its state
+// held in registers (with compensated Euler accumulation); tab holds the
+// K + 1 time points x W window slots of this launch.
+// ---------------------------------------------------------------------------
+template <int W>
+__global__ __launch_bounds__(kBlock) void fused_plain_kernel(PointGeom pg, const SrcRec* __restrict__ tab, int K,
+                                                            float dt, ScanArgs sa, float* __restrict__ beta,
+                                                            float* __restrict__ as, float* __restrict__ am) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= pg.count) return;
+    const int64_t local = pg.first + g;
+    int gi, gj, gk;
+    decode_point(pg, local, gi, gj, gk);
+    if (gk < pg.k0) return;
+    float a = as[local], m = am[local], alo = 0.0f, mlo = 0.0f;
+    float Tn = scan_temperature<W>(tab, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min);
+    float xeq_n = alpha_eq(Tn);
+    for (int s = 0; s < K; ++s) {
+        const float Tn1 = scan_temperature<W>(tab + (s + 1) * W, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min);
+        const float xeq_n1 = alpha_eq(Tn1);
+        explicit_step<true>(a, m, alo, mlo, Tn, xeq_n, Tn1, xeq_n1, dt);
+        Tn = Tn1;
+        xeq_n = xeq_n1;
+    }
+    a += alo;
+    m += mlo;
+    as[local] = a;
+    am[local] = m;
+    beta[local] = solid_fraction(Tn) - a - m;
+}
+
+hipError_t launch_temperature(const PointGeom& pg, int W, const SrcRec* rec, ScanArgs sa, float* T,
+                              hipStream_t st) {
+    if (pg.count <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((pg.count + kBlock - 1) / kBlock)), block(kBlock);
+    switch (W) {
+        case 1: hipLaunchKernelGGL(temperature_kernel<1>, grid, block, 0, st, pg, rec, sa, T); break;
+        case 2: hipLaunchKernelGGL(temperature_kernel<2>, grid, block, 0, st, pg, rec, sa, T); break;
+        case 3: hipLaunchKernelGGL(temperature_kernel<3>, grid, block, 0, st, pg, rec, sa, T); break;
+        case 4: hipLaunchKernelGGL(temperature_kernel<4>, grid, block, 0, st, pg, rec, sa, T); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fused_plain(const PointGeom& pg, int W, const SrcRec* tab, int K, float dt, ScanArgs sa,
+                              float* beta, float* as, float* am, hipStream_t st) {
+    if (pg.count <= 0) return hipSuccess;
+    const dim3 grid((unsigned)((pg.count + kBlock - 1) / kBlock)), block(kBlock);
+    switch (W) {
+        case 1: hipLaunchKernelGGL(fused_plain_kernel<1>, grid, block, 0, st, pg, tab, K, dt, sa, beta, as, am); break;
+        case 2: hipLaunchKernelGGL(fused_plain_kernel<2>, grid, block, 0, st, pg, tab, K, dt, sa, beta, as, am); break;
+        case 3: hipLaunchKernelGGL(fused_plain_kernel<3>, grid, block, 0, st, pg, tab, K, dt, sa, beta, as, am); break;
+        case 4: hipLaunchKernelGGL(fused_plain_kernel<4>, grid, block, 0, st, pg, tab, K, dt, sa, beta, as, am); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// sample gather and invariant check
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void gather_kernel(const float* __restrict__ src, const int64_t* __restrict__ idx,
+                                                       int64_t m, float* __restrict__ dst) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g < m) dst[g] = src[idx[g]];
+}
+
+hipError_t launch_gather(const float* src, const int64_t* idx, int64_t m, float* dst, hipStream_t st) {
+    if (m <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gather_kernel, dim3((unsigned)((m + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, src, idx, m,
+                       dst);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void invariants_kernel(const float* __restrict__ beta, const float* __restrict__ as,
+                                                           const float* __restrict__ am, const float* __restrict__ T,
+                                                           int64_t n, float tol,
+                                                           unsigned long long* __restrict__ counter) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    bool bad = false;
+    if (g < n) {
+        const float b = beta[g], a = as[g], m = am[g];
+        bad = !(a >= -tol && a <= 1.0f + tol && m >= -tol && m <= 1.0f + tol && b >= -tol && b <= 1.0f + tol);
+        bad = bad || !(a + m <= kXmax + tol);
+        if (T) bad = bad || !(fabsf(a + m + b - solid_fraction(T[g])) <= tol);
+    }
+    // one atomic per wave
+    const unsigned long long mask = __ballot(bad);
+    if ((threadIdx.x & 63) == 0 && mask) atomicAdd(counter, (unsigned long long)__popcll(mask));
+}
+
+hipError_t launch_invariants(const float* beta, const float* as, const float* am, const float* T, int64_t n,
+                             float tol, unsigned long long* counter, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(invariants_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, beta, as,
+                       am, T, n, tol, counter);
+    return hipGetLastError();
+}
+
+}  // namespace mstruct

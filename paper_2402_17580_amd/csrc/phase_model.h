@@ -1,0 +1,211 @@
+// Device (gfx950) implementation of the Ti-6Al-4V phase model of Proell et
+// al., arXiv 2402.17580, Sec. 2.2 and Sec. 3.1, in float32.
+//
+// Transcendentals go to the hardware units: v_exp_f32 / v_log_f32 are base-2,
+// so powers a^p (eq. power_exp_log) are exp2(p * log2 a); a = 0 gives
+// log2 = -inf and exp2(-inf) = 0, which is the value of the rate factors at
+// a zero fraction.  1 - exp(-x) in the Koistinen-Marburger laws uses a
+// Taylor polynomial for small x so that the equilibria stay accurate near
+// their start temperatures.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mstruct {
+
+// Table 1 / Table 2 / Table 3 of the paper and T_as,reg = 100 K (Sec. 2.2)
+constexpr float kTsol = 1878.0f;
+constexpr float kTliq = 1928.0f;
+constexpr float kTinf = 293.0f;
+constexpr float kTasStart = 1273.0f;
+constexpr float kTasEnd = 935.0f;
+constexpr float kTamStart = 848.0f;
+constexpr float kKalphaEq = 0.0068f;
+constexpr float kKamEq = 0.00415f;
+constexpr float kCas = 2.51f;
+constexpr float kCbeta = 11.0f;
+constexpr float kK1 = 0.294f;
+constexpr float kK2 = 850.0f;
+constexpr float kK3 = 0.0337f;
+constexpr float kF = 3.8f;
+constexpr float kTreg = 100.0f;
+constexpr float kXmax = 0.9f;            // maximum alpha fraction
+constexpr float kStartupLimit = 1e-15f;  // Appendix A exit test on X~beta * dt
+
+// exponents (c -/+ 1)/c of the generalised logistic rates
+constexpr float kPa = (kCas - 1.0f) / kCas;
+constexpr float kQa = (kCas + 1.0f) / kCas;
+constexpr float kPb = (kCbeta - 1.0f) / kCbeta;
+constexpr float kQb = (kCbeta + 1.0f) / kCbeta;
+constexpr float kLog2e = 1.4426950408889634f;
+
+__device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float flog2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// 1 - exp(-x) for x >= 0, accurate to a few ulp of the result
+__device__ __forceinline__ float one_minus_exp_neg(float x) {
+    if (x < 0.25f) {
+        // x (1 - x/2 + x^2/6 - x^3/24 + x^4/120 - x^5/720 + x^6/5040)
+        float p = fmaf(x, 1.0f / 5040.0f, -1.0f / 720.0f);
+        p = fmaf(x, p, 1.0f / 120.0f);
+        p = fmaf(x, p, -1.0f / 24.0f);
+        p = fmaf(x, p, 1.0f / 6.0f);
+        p = fmaf(x, p, -0.5f);
+        p = fmaf(x, p, 1.0f);
+        return x * p;
+    }
+    return 1.0f - fexp2(-x * kLog2e);
+}
+
+// liquid fraction g(T), eq. liquid_fraction; X_sol = 1 - g
+__device__ __forceinline__ float solid_fraction(float T) {
+    if (T < kTsol) return 1.0f;
+    if (T > kTliq) return 0.0f;
+    return 1.0f - (T - kTsol) * (1.0f / (kTliq - kTsol));
+}
+
+// X_alpha^eq(T), eq. equilibrium_phase_as
+__device__ __forceinline__ float alpha_eq(float T) {
+    if (T < kTasEnd) return kXmax;
+    if (T > kTasStart) return 0.0f;
+    return one_minus_exp_neg(kKalphaEq * (kTasStart - T));
+}
+
+// X_alpha_m,0^eq(T), eq. equilibrium_phase_am0 (zero above the martensite start)
+__device__ __forceinline__ float am0_eq(float T) {
+    if (T < kTinf) return kXmax;
+    if (T > kTamStart) return 0.0f;
+    return one_minus_exp_neg(kKamEq * (kTamStart - T));
+}
+
+// k_alpha_s(T) = k1 / (1 + exp(-k3 (T - k2)))
+__device__ __forceinline__ float k_alpha_s(float T) {
+    return kK1 * frcp(1.0f + fexp2(-kK3 * kLog2e * (T - kK2)));
+}
+
+// Appendix A closed form: fraction X = D xi after dt for
+// xi' = kt xi^((c-1)/c) (1-xi)^((c+1)/c) at constant kt.
+__device__ __forceinline__ float logistic_step(float X, float D, float kt, float c, float inv_c,
+                                               float dt) {
+    if (!(D > 0.0f)) return X;
+    float xi = fmaxf(X, 0.0f) * frcp(D);
+    if (!(xi < 1.0f)) return X;
+    float u = fexp2(inv_c * flog2(xi * frcp(1.0f - xi)));  // (xi/(1-xi))^(1/c); 0 at xi = 0
+    float w = c * frcp(fmaf(kt, dt, c * u));
+    float wc = fexp2(c * flog2(w));  // overflow -> inf -> result 0
+    return D * frcp(1.0f + wc);
+}
+
+// Diffusive increments over one explicit step (eq. explicit_integration) at
+// T^n: beta -> alpha_s, alpha_m -> alpha_s, alpha_s -> beta, with the
+// closed-form start from zero-rate states.  X~beta = 0.9 - X_alpha.
+__device__ __forceinline__ void diffusive_increment(float a, float m, float Tn, float xeq, float dt,
+                                                    float& da, float& dm) {
+    float xa = a + m;
+    da = 0.0f;
+    dm = 0.0f;
+    const bool grow = xa < xeq, dissolve = xa > xeq, marten = m > 0.0f;
+    if (!(grow | dissolve | marten)) return;
+    const float kas = k_alpha_s(Tn);
+    const float la = flog2(a);  // -inf at a = 0
+    if (grow) {
+        if (a > 0.0f) {
+            da = dt * kas * fexp2(fmaf(kPa, la, kQa * flog2(xeq - xa)));
+        } else {
+            const float D = xeq - m;
+            if (D > 0.0f) da = logistic_step(0.0f, D, kas * D, kCas, 1.0f / kCas, dt);
+        }
+    }
+    if (marten) {
+        const float r2 = kas * fexp2(fmaf(kPa, la, kQa * flog2(m)));
+        da = fmaf(dt, r2, da);
+        dm = -dt * r2;
+    }
+    if (dissolve) {
+        const float kb = kF * kas;
+        const float bt = fmaxf(kXmax - xa, 0.0f);
+        if (bt * dt <= kStartupLimit) {
+            const float D = kXmax - xeq;
+            const float nb = logistic_step(bt, D, D * kb, kCbeta, 1.0f / kCbeta, dt);
+            da -= (nb - bt);
+        } else {
+            da -= dt * kb * fexp2(fmaf(kPb, flog2(bt), kQb * flog2(xa - xeq)));
+        }
+    }
+}
+
+// Correction g(T^{n+1}, m~), eq. explicit_correction: clip at zero, cap the
+// alpha total at 0.9 keeping the ratio, alpha_s regularisation above the
+// alpha_s start temperature, instantaneous martensite dissolution (eq.
+// inst_martensite_dissolution) and formation (eq. inst_martensite_formation,
+// never lowering alpha_m), the 0.9 cap again, the solid-fraction cap; returns
+// X_beta from the sum rule (eq. beta_post_processing).  xeq = X_alpha^eq(T).
+__device__ __forceinline__ float correct(float T, float xeq, float& a_io, float& m_io) {
+    float a = fmaxf(a_io, 0.0f), m = fmaxf(m_io, 0.0f);
+    float s = a + m;
+    if (s > kXmax) {
+        const float f = kXmax * frcp(s);
+        a *= f;
+        m *= f;
+    }
+    if (T > kTasStart) {
+        const float f = fminf(fmaxf((kTasStart + kTreg - T) * (1.0f / kTreg), 0.0f), 1.0f);
+        a = fminf(a, kXmax * f);
+    }
+    if (a + m > xeq) m = fmaxf(xeq - a, 0.0f);
+    if (T < kTamStart) m = fmaxf(m, am0_eq(T) * (kXmax - a) * (1.0f / kXmax));
+    s = a + m;
+    if (s > kXmax) {
+        const float f = kXmax * frcp(s);
+        a *= f;
+        m *= f;
+    }
+    const float xsol = solid_fraction(T);
+    s = a + m;
+    if (s > xsol) {
+        const float f = (s > 0.0f) ? xsol * frcp(s) : 0.0f;
+        a *= f;
+        m *= f;
+    }
+    a_io = a;
+    m_io = m;
+    return xsol - a - m;
+}
+
+// error-free sum: s + e == a + b exactly (Knuth's two-sum)
+__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+// One explicit step on a register state.  With COMPENSATED the Euler
+// increments are accumulated in (hi, lo) pairs so that increments below half
+// an ulp of the fraction are not lost; any correction that changes a
+// fraction resets its lo part.  Returns X_beta^{n+1}.
+template <bool COMPENSATED>
+__device__ __forceinline__ float explicit_step(float& a, float& m, float& a_lo, float& m_lo, float Tn,
+                                               float xeq_n, float Tn1, float xeq_n1, float dt) {
+    float da, dm;
+    diffusive_increment(a, m, Tn, xeq_n, dt, da, dm);
+    float at, mt;
+    if (COMPENSATED) {
+        two_sum(a, a_lo + da, at, a_lo);
+        two_sum(m, m_lo + dm, mt, m_lo);
+    } else {
+        at = a + da;
+        mt = m + dm;
+    }
+    const float a_before = at, m_before = mt;
+    const float beta = correct(Tn1, xeq_n1, at, mt);
+    if (COMPENSATED) {
+        if (at != a_before) a_lo = 0.0f;
+        if (mt != m_before) m_lo = 0.0f;
+    }
+    a = at;
+    m = mt;
+    return beta;
+}
+
+}  // namespace mstruct

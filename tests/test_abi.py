@@ -1,0 +1,75 @@
+"""The C-ABI library loads and exports every entry point that
+include/mstruct.h declares; host-side argument checks reject bad calls
+without touching a GPU.  CPU only (no compute calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mstruct.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mstruct_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    import paper_2402_17580_amd as ms
+    if not os.path.exists(ms.LIB_PATH):
+        pytest.fail("libmstruct.so is not built; run __graft_entry__.build()")
+    return ms.lib()
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("mstruct_init", "mstruct_step", "mstruct_fused_scan_steps", "mstruct_temperature",
+                 "mstruct_mlp_train_step", "mstruct_mlp_forward", "mstruct_mlp_grad"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(L):
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_binding_covers_every_symbol():
+    import paper_2402_17580_amd as ms
+    assert sorted(ms.EXPORTS) == _declared()
+
+
+def test_status_strings(L):
+    for code in (0, -1, -2, -3, -4, -5):
+        assert L.mstruct_status_string(code)
+    assert L.mstruct_status_string(12345) == b"unknown status"
+    assert L.mstruct_last_error(None) == b"null context"
+
+
+def test_null_context_rejected_without_device(L):
+    p = ctypes.c_void_p()
+    assert L.mstruct_init(0, None) == -1
+    assert L.mstruct_destroy(None) == -1
+    assert L.mstruct_step(None, None, None, 1e-6, None, None) == -1
+    assert L.mstruct_temperature(None, None, None, 0.0, None, None) == -1
+    assert L.mstruct_fused_scan_steps(None, None, None, 0.0, 1e-6, 1, 1, 0, None, None) == -1
+    assert L.mstruct_gather(None, None, None, 0, None, None) == -1
+    assert L.mstruct_check_invariants(None, None, None, 0.0, None, None) == -1
+    assert L.mstruct_mlp_set_params(None, None, None, None, None) == -1
+    assert L.mstruct_mlp_get_params(None, None) == -1
+    assert L.mstruct_mlp_forward(None, None, 0, None, None) == -1
+    assert L.mstruct_mlp_grad(None, None, None, 0, None, None, None) == -1
+    assert L.mstruct_mlp_train_step(None, None, None, 0, 0.0, None, None) == -1
+
+
+def test_product_path_does_not_use_the_oracle():
+    pkg = os.path.join(ROOT, "paper_2402_17580_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".h", ".cpp")):
+                txt = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(import|from)\s+oracle", txt, re.M), f
+                assert "mstruct_oracle" not in txt and "liborc" not in txt, f
