@@ -1,0 +1,231 @@
+"""Benchmark: microstructure point-updates/s on the 256x256x128 multi-layer
+block (8.4M points, 10 layers of 30 um, 20,000 steps of 2 us), float32 on one
+MI355X.
+
+One benchmark step = one whole run of the workload from the initial state
+through every layer (all 20,000 time steps; 150,077,440,000 active
+point-updates) with the temperature evaluated from the scan inside the fused
+kernel (K = 16 steps per launch).  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import workload  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+FP32_VECTOR_PEAK_TFLOPS = 157.3
+# VALU ceiling in lane-ops: the FP32 vector peak counts 2 FLOPs per FMA lane-op,
+# i.e. 256 CUs x 128 lane-ops/clock x 2.4 GHz = 78.6 T lane-ops/s
+VALU_PEAK_TLANEOPS = FP32_VECTOR_PEAK_TFLOPS / 2
+K_FUSED = 16
+STEP_BYTES = 28  # plain step: reads alpha_s, alpha_m, T^n, T^{n+1}; writes beta, alpha_s, alpha_m (float32)
+
+
+def fused_bytes_per_update(K):
+    return 20.0 / K  # per launch: read alpha_s, alpha_m; write beta, alpha_s, alpha_m (float32)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--K", type=int, default=K_FUSED)
+    ap.add_argument("--sample", type=float, default=1e-3, help="oracle sample fraction (cpu_baseline, errors)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-stepwise", action="store_true")
+    ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration under rocprofv3)")
+    ap.add_argument("--threads", type=int, default=0)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; the multi-GPU path is a design note only",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import torch
+
+    import paper_2402_17580_amd as ms
+
+    dev = torch.device("cuda:0")
+    wl = workload.multilayer_block()
+    n = wl.grid.n
+    updates = wl.point_updates()
+    launches = sum(math.ceil((L.step_end - L.step_begin) / args.K) for L in wl.layers)
+    ctx = ms.Context(0)
+    init = [torch.from_numpy(x).to(dev) for x in workload.initial_state(n, np.float32)]
+    b, a, m = [x.clone() for x in init]
+
+    def reset():
+        for dst, src in zip((b, a, m), init):
+            dst.copy_(src)
+
+    def one_step():
+        reset()
+        ms.run_layers(ctx, wl, b, a, m, K=args.K)
+
+    for _ in range(args.warmup):
+        one_step()
+    torch.cuda.synchronize()
+    t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_start.record()
+    wall0 = time.perf_counter()
+    for _ in range(args.steps):
+        one_step()
+    t_end.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_total = t_start.elapsed_time(t_end)
+    ms_per_step = ms_total / args.steps
+    value = updates * args.steps / (ms_total * 1e-3)
+    # average duration of one fused launch over the timed region (the fused
+    # kernel is the only kernel in it besides three state resets per step)
+    avg_launch_s = ms_total * 1e-3 / (args.steps * launches)
+    upd_per_launch = updates / launches
+    bytes_per_launch = fused_bytes_per_update(args.K) * upd_per_launch
+
+    result = {
+        "metric": "microstructure point-updates/s @8.4M pts (256x256x128 block, 10 layers, 20k steps): FP32 plain",
+        "value": value,
+        "unit": "point-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded scan, analytic moving-source temperature)",
+        "config": {"workload": "multilayer_block", "grid": [256, 256, 128], "points": n, "layers": 10,
+                   "time_steps": wl.n_steps, "dt_s": wl.dt, "active_point_updates": updates,
+                   "K": args.K, "window": wl.scan.window, "path": "fused (mstruct_fused_scan_steps, PLAIN)"},
+        "wall_s_timed": wall,
+    }
+    rate = upd_per_launch / avg_launch_s  # point-updates/s inside one launch
+    ops = FUSED_PROFILE["valu_lane_ops_per_update"]
+    result["roofline"] = {
+        "kernel": f"fused_plain_kernel<{wl.scan.window}>",
+        "bound": "alu",
+        "achieved": rate * ops / 1e12,
+        "peak": VALU_PEAK_TLANEOPS,
+        "unit": "Tlane-op/s",
+        "frac": rate * ops / 1e12 / VALU_PEAK_TLANEOPS,
+        "traffic": FUSED_PROFILE["traffic_bytes_per_launch"] if args.K == K_FUSED else None,
+        "traffic_unit": "bytes/launch",
+        "algorithmic_bytes_per_launch": bytes_per_launch,
+        "lane_ops_per_update": ops,
+        "fp32_tflops": rate * FUSED_PROFILE["fp32_flops_per_update"] / 1e12,
+        "fp32_tflops_peak": FP32_VECTOR_PEAK_TFLOPS,
+        "hbm_GBs": bytes_per_launch / avg_launch_s / 1e9,
+        "avg_launch_us": avg_launch_s * 1e6,
+        "launches_timed": args.steps * launches,
+    }
+    final_state = [x.clone() for x in (b, a, m)]
+
+    if not args.no_stepwise:
+        result["plain_step"] = bench_stepwise(torch, ms, ctx, wl, dev)
+
+    if args.copy_probe:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        src.fill_(1.0)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        result["copy_probe_bytes"] = {"read": src.numel() * 4, "write": src.numel() * 4}
+
+    if not args.no_cpu_baseline:
+        result.update(cpu_baseline_and_errors(torch, wl, final_state, args))
+
+    print(json.dumps(result))
+    ctx.close()
+
+
+# Per-kernel figures of the fused kernel on this workload, from rocprofv3
+# counter runs of this script (profiles/fused_plain_kernel_multilayer_block.txt):
+# executed VALU instructions x 64 lanes and FP32 FLOPs per point-update, and
+# HBM bytes per launch (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0: the factors a
+# plain 1 GiB device copy reads on the same counters).
+FUSED_PROFILE = {
+    "valu_lane_ops_per_update": 209.52,
+    "fp32_flops_per_update": 169.9,
+    "traffic_bytes_per_launch": (29387.65 * 2.0 + 87936.0) * 1024,
+}
+
+def bench_stepwise(torch, ms, ctx, wl, dev):
+    """The unfused path: temperature-field kernel + plain step kernel per time
+    step (T arrays ping-pong in HBM), timed on the first 200 steps of the top
+    layer; the step kernel alone is timed over T arrays already in HBM."""
+    n = wl.grid.n
+    L = wl.layers[-1]
+    b, a, m = [torch.from_numpy(x).to(dev) for x in workload.initial_state(n, np.float32)]
+    Ta, Tb = torch.empty(n, device=dev), torch.empty(n, device=dev)
+    sub = workload.Layer(L.step_begin, L.step_begin + 200, L.z_top)
+    ms.run_layers_stepwise(ctx, wl, b, a, m, Ta, Tb, layers=[workload.Layer(L.step_begin, L.step_begin + 20, L.z_top)])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ms.run_layers_stepwise(ctx, wl, b, a, m, Ta, Tb, layers=[sub])
+    e1.record()
+    torch.cuda.synchronize()
+    ms_stepwise = e0.elapsed_time(e1)
+    off = wl.grid.first_active_k(L.z_top) * wl.grid.nx * wl.grid.ny
+    n_act = n - off
+    rate_stepwise = n_act * 200 / (ms_stepwise * 1e-3)
+    # the step kernel alone, 200 launches on resident T arrays
+    reps = 200
+    e0.record()
+    for _ in range(reps):
+        ctx.step(Ta[off:], Tb[off:], wl.dt, b[off:], a[off:], m[off:])
+    e1.record()
+    torch.cuda.synchronize()
+    avg = e0.elapsed_time(e1) * 1e-3 / reps
+    achieved = STEP_BYTES * n_act / avg / 1e9
+    return {"value": rate_stepwise, "unit": "point-updates/s",
+            "path": "mstruct_temperature + mstruct_step per time step (200 steps of the top layer)",
+            "roofline": {"kernel": "step_kernel<true>", "bound": "hbm", "achieved": achieved,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                         "bytes_per_update": STEP_BYTES, "avg_launch_us": avg * 1e6,
+                         "point_updates_per_s": n_act / avg}}
+
+
+def cpu_baseline_and_errors(torch, wl, final_state, args):
+    import oracle
+    threads = args.threads or min(16, os.cpu_count() or 1)
+    idx = workload.sample_indices(wl.grid.n, args.sample, wl.seed)
+    xyz = wl.grid.coords(idx)
+    upd = sum(int(np.count_nonzero(xyz[:, 2] <= L.z_top + 1e-3 * wl.grid.h)) * (L.step_end - L.step_begin)
+              for L in wl.layers)
+    t0 = time.perf_counter()
+    st = oracle.run_workload(wl, idx, threads=threads)
+    el = time.perf_counter() - t0
+    errs = {}
+    for name, g, o in zip(("beta", "alpha_s", "alpha_m"), final_state, (st.beta, st.alpha_s, st.alpha_m)):
+        d = np.abs(g.double().cpu().numpy()[idx] - o)
+        errs[name] = {"max": float(d.max()), "rms": float(np.sqrt(np.mean(d * d)))}
+    return {
+        "cpu_baseline": {"value": upd / el, "unit": "point-updates/s", "cores": threads, "kind": "oracle",
+                         "sample": f"{idx.size} seeded points (p={args.sample}) x all 20,000 steps "
+                                   f"({upd} point-updates, FP64, {el:.1f} s)"},
+        "errors_vs_oracle": errs,
+    }
+
+
+if __name__ == "__main__":
+    main()
