@@ -138,38 +138,49 @@ int mstruct_gather(mstruct_ctx *ctx, const float *src, const int64_t *idx, int64
 int mstruct_check_invariants(mstruct_ctx *ctx, const mstruct_phases *ph, const float *T, float tol,
                              int64_t *violations, void *stream);
 
-/* ---- learned surrogate: MLP 6 -> 64 -> 64 -> 3, ReLU, BF16 MFMA with
- * float32 accumulation (not part of the paper). ----
- * Inputs per point: (T_n, T_{n+K}, ln dt, beta, alpha_s, alpha_m), each
- * normalised as (x - mean) / scale; outputs: (d alpha_s, d alpha_m) and a
- * third (d beta) channel, each multiplied by out_scale.  Parameter vector
- * layout (float32, MSTRUCT_MLP_NPARAM entries): W1[64][6], b1[64],
- * W2[64][64], b2[64], W3[3][64], b3[3] (row = output unit). */
+/* The correction g of eq. explicit_correction alone, at temperatures T[n]
+ * (device float32), in place: instantaneous martensite formation and
+ * dissolution, alpha_s regularisation, continuity constraints; beta written
+ * from the sum rule.  Used to separate instantaneous from diffusive changes. */
+int mstruct_correct(mstruct_ctx *ctx, const float *T, const mstruct_phases *ph, void *stream);
+
+/* ---- learned surrogate (not part of the paper): MLP 6 -> 64 -> 64 -> 3,
+ * ReLU, BF16 MFMA products with float32 accumulation ----
+ * Raw inputs per sample: (T_n, T_{n+K}, ln dt, beta, alpha_s, alpha_m), each
+ * normalised in the library as (x - in_mean) / in_scale.  Network outputs
+ * times out_scale are the changes of (alpha_s, alpha_m, beta) over K explicit
+ * steps beyond what the correction g at T_{n+K} alone gives.  Parameter
+ * vector (float32, MSTRUCT_MLP_NPARAM entries, row = output unit):
+ * W1[64][6], b1[64], W2[64][64], b2[64], W3[3][64], b3[3]. */
 #define MSTRUCT_MLP_NPARAM 4803
 
-/* Upload float32 parameters (host array) and normalisation (host arrays
- * in_mean[6], in_scale[6], out_scale[3]); the context keeps float32 master
- * copies and BF16 working copies. */
-int mstruct_mlp_set_params(mstruct_ctx *ctx, const float *params, const float *in_mean,
-                           const float *in_scale, const float *out_scale);
-/* Copy the float32 master parameters to a host array. */
+/* Upload parameters (host float32) and normalisation (host in_mean[6],
+ * in_scale[6] > 0, out_scale[3] > 0); indicator (host float32[4] or NULL for
+ * the defaults 823, 1398, 1853, 50): the surrogate is used for a K-block only
+ * when both block-end temperatures lie below indicator[0] K or both inside
+ * [indicator[1], indicator[2]] K, and they differ by at most indicator[3] K.
+ * Resets the optimiser state.  Synchronises the device. */
+int mstruct_mlp_set_params(mstruct_ctx *ctx, const float *params, const float *in_mean, const float *in_scale,
+                           const float *out_scale, const float *indicator);
+/* Copy the float32 parameters to a host array (synchronises). */
 int mstruct_mlp_get_params(mstruct_ctx *ctx, float *params);
 
-/* Forward pass on B samples: X device float32 [B][6] (normalised inputs),
- * Y device float32 [B][3] (raw network outputs, before out_scale). */
+/* Network on B samples: X device float32 [B][6] raw inputs; Y device float32
+ * [B][3] = outputs times out_scale. */
 int mstruct_mlp_forward(mstruct_ctx *ctx, const float *X, int64_t B, float *Y, void *stream);
 
-/* Mean-squared-error loss 0.5/B sum ||f(X) - Y||^2 and its gradient with
- * respect to the parameters: grad device float32 [MSTRUCT_MLP_NPARAM]
- * (deterministic: fixed-order reduction), loss device float32 [1]. */
-int mstruct_mlp_grad(mstruct_ctx *ctx, const float *X, const float *Y, int64_t B, float *grad,
-                     float *loss, void *stream);
+/* Loss 0.5/B sum_i ||f(norm(X_i)) - Y_i / out_scale||^2 and its gradient with
+ * respect to the parameters (layout above): grad device float32
+ * [MSTRUCT_MLP_NPARAM], loss device float32 [1].  Deterministic (per-wave
+ * partial sums reduced in a fixed order).  B >= 1. */
+int mstruct_mlp_grad(mstruct_ctx *ctx, const float *X, const float *Y, int64_t B, float *grad, float *loss,
+                     void *stream);
 
-/* One Adam step (learning rate lr, betas 0.9/0.999, eps 1e-8) on the
- * context's parameters using the gradient of the given batch; loss (device
- * float32 [1], may be NULL) receives the batch loss. */
-int mstruct_mlp_train_step(mstruct_ctx *ctx, const float *X, const float *Y, int64_t B, float lr,
-                           float *loss, void *stream);
+/* One Adam step (betas 0.9, 0.999, eps 1e-8, learning rate lr) on the
+ * context's parameters with the gradient of the batch; loss (device float32
+ * [1], may be NULL) receives the batch loss before the step. */
+int mstruct_mlp_train_step(mstruct_ctx *ctx, const float *X, const float *Y, int64_t B, float lr, float *loss,
+                           void *stream);
 
 #ifdef __cplusplus
 }

@@ -50,8 +50,8 @@ class PointsC(ctypes.Structure):
 
 EXPORTS = ("mstruct_init", "mstruct_destroy", "mstruct_status_string", "mstruct_last_error", "mstruct_step",
            "mstruct_temperature", "mstruct_fused_scan_steps", "mstruct_gather", "mstruct_check_invariants",
-           "mstruct_mlp_set_params", "mstruct_mlp_get_params", "mstruct_mlp_forward", "mstruct_mlp_grad",
-           "mstruct_mlp_train_step")
+           "mstruct_correct", "mstruct_mlp_set_params", "mstruct_mlp_get_params", "mstruct_mlp_forward",
+           "mstruct_mlp_grad", "mstruct_mlp_train_step")
 
 _lib = None
 
@@ -70,7 +70,8 @@ def lib() -> ctypes.CDLL:
             "mstruct_temperature": [p, p, p, d, p, p],
             "mstruct_fused_scan_steps": [p, p, p, d, d, i64, i, i, p, p],
             "mstruct_gather": [p, p, p, i64, p, p], "mstruct_check_invariants": [p, p, p, ctypes.c_float, p, p],
-            "mstruct_mlp_set_params": [p, p, p, p, p], "mstruct_mlp_get_params": [p, p],
+            "mstruct_correct": [p, p, p, p],
+            "mstruct_mlp_set_params": [p, p, p, p, p, p], "mstruct_mlp_get_params": [p, p],
             "mstruct_mlp_forward": [p, p, i64, p, p], "mstruct_mlp_grad": [p, p, p, i64, p, p, p],
             "mstruct_mlp_train_step": [p, p, p, i64, ctypes.c_float, p, p],
         }
@@ -189,11 +190,19 @@ class Context:
         return out.value
 
     # -- learned surrogate ---------------------------------------------------
-    def mlp_set_params(self, params, in_mean, in_scale, out_scale):
+    def correct(self, T, beta, alpha_s, alpha_m, stream=None):
+        import torch
+        ph = self._phases(beta, alpha_s, alpha_m)
+        self._check(lib().mstruct_correct(self._h, _dev_ptr(T, torch.float32, ph.n, "T"), ctypes.byref(ph),
+                                          _stream(stream)), "mstruct_correct")
+
+    def mlp_set_params(self, params, in_mean, in_scale, out_scale, indicator=None):
         f = lambda a, n: np.ascontiguousarray(a, dtype=np.float32).reshape(n)
         p, im, isc, osc = f(params, MLP_NPARAM), f(in_mean, 6), f(in_scale, 6), f(out_scale, 3)
+        ind = None if indicator is None else f(indicator, 4)
         self._check(lib().mstruct_mlp_set_params(self._h, p.ctypes.data, im.ctypes.data, isc.ctypes.data,
-                                                 osc.ctypes.data), "mstruct_mlp_set_params")
+                                                 osc.ctypes.data, None if ind is None else ind.ctypes.data),
+                    "mstruct_mlp_set_params")
 
     def mlp_get_params(self):
         out = np.zeros(MLP_NPARAM, np.float32)

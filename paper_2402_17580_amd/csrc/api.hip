@@ -384,40 +384,111 @@ int mstruct_check_invariants(mstruct_ctx* ctx, const mstruct_phases* ph, const f
 
 }  // extern "C"
 
-// ---- learned surrogate entry points (implemented in the MLP translation unit) ----
+// ---- learned surrogate and correction entry points ----
 extern "C" {
 
+int mstruct_correct(mstruct_ctx* ctx, const float* T, const mstruct_phases* ph, void* stream) {
+    if (!ctx) return MSTRUCT_EINVAL;
+    int rc = check_phases(ctx, ph);
+    if (rc) return rc;
+    if (ph->n > 0 && !T) return fail(ctx, MSTRUCT_EINVAL, "T is NULL");
+    DeviceGuard g(ctx->device);
+    hipError_t e = launch_correct(T, ph->beta, ph->alpha_s, ph->alpha_m, ph->n, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "correct launch");
+    return MSTRUCT_OK;
+}
+
 int mstruct_mlp_set_params(mstruct_ctx* ctx, const float* params, const float* in_mean, const float* in_scale,
-                           const float* out_scale) {
+                           const float* out_scale, const float* indicator) {
     if (!ctx) return MSTRUCT_EINVAL;
     if (!params || !in_mean || !in_scale || !out_scale) return fail(ctx, MSTRUCT_EINVAL, "NULL argument");
-    return fail(ctx, MSTRUCT_EUNSUPPORTED, "not built yet");
+    for (int i = 0; i < kMlpParams; ++i)
+        if (!isfinite(params[i])) return fail(ctx, MSTRUCT_EINVAL, "non-finite parameter");
+    MlpNorm nrm{};
+    for (int k = 0; k < kMlpIn; ++k) {
+        if (!isfinite(in_mean[k]) || !(in_scale[k] > 0.0f) || !isfinite(in_scale[k]))
+            return fail(ctx, MSTRUCT_EINVAL, "bad input normalisation");
+        nrm.in_mean[k] = in_mean[k];
+        nrm.in_inv_scale[k] = 1.0f / in_scale[k];
+    }
+    for (int k = 0; k < kMlpOut; ++k) {
+        if (!(out_scale[k] > 0.0f) || !isfinite(out_scale[k])) return fail(ctx, MSTRUCT_EINVAL, "bad output scale");
+        nrm.out_scale[k] = out_scale[k];
+    }
+    // error indicator: default bands around the martensite start (848 K),
+    // the beta transus / regularisation range (935..1373 K) and melting
+    const float def[4] = {823.0f, 1398.0f, 1853.0f, 50.0f};
+    const float* ind = indicator ? indicator : def;
+    for (int k = 0; k < 4; ++k)
+        if (!isfinite(ind[k])) return fail(ctx, MSTRUCT_EINVAL, "non-finite indicator threshold");
+    if (!(ind[3] >= 0.0f)) return fail(ctx, MSTRUCT_EINVAL, "dT_max must be >= 0");
+    nrm.T_cold = ind[0];
+    nrm.T_hot_lo = ind[1];
+    nrm.T_hot_hi = ind[2];
+    nrm.dT_max = ind[3];
+    DeviceGuard g(ctx->device);
+    MlpState& s = ctx->mlp;
+    HIP_CHECK(ctx, mlp_alloc(s));
+    HIP_CHECK(ctx, hipDeviceSynchronize());
+    HIP_CHECK(ctx, hipMemcpy(s.master, params, kMlpParams * sizeof(float), hipMemcpyHostToDevice));
+    HIP_CHECK(ctx, hipMemset(s.adam_m, 0, kMlpParams * sizeof(float)));
+    HIP_CHECK(ctx, hipMemset(s.adam_v, 0, kMlpParams * sizeof(float)));
+    s.adam_t = 0;
+    s.norm = nrm;
+    HIP_CHECK(ctx, mlp_pack(s, nullptr));
+    HIP_CHECK(ctx, hipDeviceSynchronize());
+    s.ready = true;
+    return MSTRUCT_OK;
 }
 
 int mstruct_mlp_get_params(mstruct_ctx* ctx, float* params) {
     if (!ctx) return MSTRUCT_EINVAL;
     if (!params) return fail(ctx, MSTRUCT_EINVAL, "NULL argument");
-    return fail(ctx, MSTRUCT_EUNSUPPORTED, "not built yet");
+    if (!ctx->mlp.ready) return fail(ctx, MSTRUCT_ESTATE, "no network parameters set");
+    DeviceGuard g(ctx->device);
+    HIP_CHECK(ctx, hipDeviceSynchronize());
+    HIP_CHECK(ctx, hipMemcpy(params, ctx->mlp.master, kMlpParams * sizeof(float), hipMemcpyDeviceToHost));
+    return MSTRUCT_OK;
 }
 
 int mstruct_mlp_forward(mstruct_ctx* ctx, const float* X, int64_t B, float* Y, void* stream) {
     if (!ctx) return MSTRUCT_EINVAL;
-    (void)X; (void)B; (void)Y; (void)stream;
-    return fail(ctx, MSTRUCT_EUNSUPPORTED, "not built yet");
+    if (B < 0) return fail(ctx, MSTRUCT_EINVAL, "B < 0");
+    if (B > 0 && (!X || !Y)) return fail(ctx, MSTRUCT_EINVAL, "NULL array");
+    if (!ctx->mlp.ready) return fail(ctx, MSTRUCT_ESTATE, "no network parameters set");
+    DeviceGuard g(ctx->device);
+    hipError_t e = mlp_forward(ctx->mlp, X, B, Y, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "mlp forward launch");
+    return MSTRUCT_OK;
 }
 
 int mstruct_mlp_grad(mstruct_ctx* ctx, const float* X, const float* Y, int64_t B, float* grad, float* loss,
                      void* stream) {
     if (!ctx) return MSTRUCT_EINVAL;
-    (void)X; (void)Y; (void)B; (void)grad; (void)loss; (void)stream;
-    return fail(ctx, MSTRUCT_EUNSUPPORTED, "not built yet");
+    if (B < 1) return fail(ctx, MSTRUCT_EINVAL, "B must be >= 1");
+    if (!X || !Y || !grad || !loss) return fail(ctx, MSTRUCT_EINVAL, "NULL array");
+    if (!ctx->mlp.ready) return fail(ctx, MSTRUCT_ESTATE, "no network parameters set");
+    DeviceGuard g(ctx->device);
+    hipError_t e = mlp_grad(ctx->mlp, X, Y, B, grad, loss, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "mlp gradient launch");
+    return MSTRUCT_OK;
 }
 
 int mstruct_mlp_train_step(mstruct_ctx* ctx, const float* X, const float* Y, int64_t B, float lr, float* loss,
                            void* stream) {
     if (!ctx) return MSTRUCT_EINVAL;
-    (void)X; (void)Y; (void)B; (void)lr; (void)loss; (void)stream;
-    return fail(ctx, MSTRUCT_EUNSUPPORTED, "not built yet");
+    if (B < 1) return fail(ctx, MSTRUCT_EINVAL, "B must be >= 1");
+    if (!X || !Y) return fail(ctx, MSTRUCT_EINVAL, "NULL array");
+    if (!(lr > 0.0f) || !isfinite(lr)) return fail(ctx, MSTRUCT_EINVAL, "lr must be positive");
+    if (!ctx->mlp.ready) return fail(ctx, MSTRUCT_ESTATE, "no network parameters set");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    MlpState& s = ctx->mlp;
+    hipError_t e = mlp_grad(s, X, Y, B, s.grad, s.loss, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "mlp gradient launch");
+    if ((e = mlp_adam(s, lr, st)) != hipSuccess) return hip_fail(ctx, e, "adam launch");
+    if (loss) HIP_CHECK(ctx, hipMemcpyAsync(loss, s.loss, sizeof(float), hipMemcpyDeviceToDevice, st));
+    return MSTRUCT_OK;
 }
 
 }  // extern "C"

@@ -1,12 +1,558 @@
+// Surrogate MLP kernels for gfx950: inference fused into the K-step update,
+// and training (forward + backward + deterministic gradient reduction + Adam).
+//
+// All products use v_mfma_f32_32x32x8_bf16 (A 32x8, B 8x32, C 32x32).  With
+// h = lane / 32 and j = lane % 32, lane l supplies A[j][4h..4h+3] and
+// B[4h..4h+3][j] and holds C[(r%4) + 4h + 8(r/4)][j] in accumulator r.  A layer
+// is computed transposed, features x points: its accumulator rows 8kb..8kb+7
+// of column j sit in registers 4kb..4kb+3 of lanes j and j+32 in exactly the
+// order the next layer's B operand for k-block kb needs, so activations pass
+// from layer to layer in registers (after ReLU and conversion to bf16).
 #include "mlp.h"
 
 namespace mstruct {
 
-void mlp_free(MlpState& s) { s.ready = false; }
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef float f16v __attribute__((ext_vector_type(16)));
+typedef float f2v __attribute__((ext_vector_type(2)));
+typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
+typedef uint32_t u2v __attribute__((ext_vector_type(2)));
 
-hipError_t launch_surrogate(const MlpState&, const PointGeom&, int, const SrcRec*, int, float, ScanArgs, float*,
-                            float*, float*, hipStream_t) {
-    return hipErrorNotSupported;
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+    const bf2v v = __builtin_convertvector((f2v){a, b}, bf2v);  // round to nearest even
+    return __builtin_bit_cast(uint32_t, v);
+}
+__device__ __forceinline__ s4 make_s4(uint32_t lo, uint32_t hi) { return __builtin_bit_cast(s4, (u2v){lo, hi}); }
+__device__ __forceinline__ f16v mfma(s4 a, s4 b, f16v c) {
+    return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ float bf16_bits_to_float(uint16_t v) { return __uint_as_float((uint32_t)v << 16); }
+
+struct FwdFrag {
+    s4 w1[2];
+    s4 w2[2][8];
+    s4 w3[8];
+    f16v b2[2];
+    f16v b3;
+};
+
+__device__ __forceinline__ s4 frag_s4(const uint32_t* __restrict__ frag, int word, int lane) {
+    return make_s4(frag[word * 64 + lane], frag[(word + 1) * 64 + lane]);
+}
+
+__device__ __forceinline__ void load_fwd_frag(FwdFrag& F, const uint32_t* __restrict__ frag, int lane) {
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+        F.w1[mt] = frag_s4(frag, kFragW1 + 2 * mt, lane);
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) F.w2[mt][kb] = frag_s4(frag, kFragW2 + 2 * (mt * 8 + kb), lane);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) F.b2[mt][r] = __uint_as_float(frag[(kFragB2 + mt * 16 + r) * 64 + lane]);
+    }
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) F.w3[kb] = frag_s4(frag, kFragW3 + 2 * kb, lane);
+#pragma unroll
+    for (int r = 0; r < 16; ++r) F.b3[r] = __uint_as_float(frag[(kFragB3 + r) * 64 + lane]);
+}
+
+// ReLU of accumulator registers r0..r0+3 packed as a bf16 B operand
+__device__ __forceinline__ s4 relu_pack(const f16v& d, int r0) {
+    return make_s4(pack_bf16x2(fmaxf(d[r0], 0.0f), fmaxf(d[r0 + 1], 0.0f)),
+                   pack_bf16x2(fmaxf(d[r0 + 2], 0.0f), fmaxf(d[r0 + 3], 0.0f)));
+}
+
+// forward of one tile of 32 points: xb = input B operand (inputs 4h..4h+3 of
+// point j); returns layer-3 accumulators (outputs in rows 0..2 = registers
+// 0..2 of lanes with h = 0); h1, h2 receive the bf16 activations
+__device__ __forceinline__ f16v forward_tile(const FwdFrag& F, s4 xb, s4 h1[8], s4 h2[8]) {
+    const f16v zero = {};
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+        const f16v d = mfma(F.w1[mt], xb, zero);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) h1[mt * 4 + q] = relu_pack(d, 4 * q);
+    }
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+        f16v acc = F.b2[mt];
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) acc = mfma(F.w2[mt][kb], h1[kb], acc);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) h2[mt * 4 + q] = relu_pack(acc, 4 * q);
+    }
+    f16v o = F.b3;
+#pragma unroll
+    for (int kb = 0; kb < 8; ++kb) o = mfma(F.w3[kb], h2[kb], o);
+    return o;
+}
+
+// network on the 64 points of a wave, one per lane: x = normalised inputs of
+// the lane's point (x[6] = 1 carries the first-layer bias); y = raw outputs.
+// Must be reached by all 64 lanes.
+__device__ __forceinline__ void mlp_wave(const FwdFrag& F, const float x[8], float y[3], int lane) {
+    const bool hi = lane >= 32;
+    const uint32_t w0 = pack_bf16x2(x[0], x[1]), w1 = pack_bf16x2(x[2], x[3]);
+    const uint32_t w2 = pack_bf16x2(x[4], x[5]), w3 = pack_bf16x2(x[6], x[7]);
+    // tile 0 = points 0..31, tile 1 = points 32..63; the partner lane l ^ 32
+    // holds the other half of the inputs of the same tile column
+    const uint32_t r0 = __shfl_xor(hi ? w0 : w2, 32), r1 = __shfl_xor(hi ? w1 : w3, 32);
+    const s4 b0 = hi ? make_s4(r0, r1) : make_s4(w0, w1);
+    const s4 b1 = hi ? make_s4(w2, w3) : make_s4(r0, r1);
+    s4 h1[8], h2[8];
+    const f16v o0 = forward_tile(F, b0, h1, h2);
+    const f16v o1 = forward_tile(F, b1, h1, h2);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float e = __shfl_xor(o1[c], 32);
+        y[c] = hi ? e : o0[c];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// fragment packing from the float32 master parameters (one wave)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float w1ext(const float* P, int r, int k) {
+    return k < 6 ? P[kOffW1 + r * 6 + k] : (k == 6 ? P[kOffB1 + r] : 0.0f);
+}
+
+__global__ __launch_bounds__(64) void pack_kernel(const float* __restrict__ P, uint32_t* __restrict__ frag) {
+    const int lane = threadIdx.x, h = lane >> 5, j = lane & 31;
+    auto put = [&](int word, float a, float b) { frag[word * 64 + lane] = pack_bf16x2(a, b); };
+    for (int mt = 0; mt < 2; ++mt) {
+        const int row = mt * 32 + j;
+        put(kFragW1 + 2 * mt, w1ext(P, row, 4 * h), w1ext(P, row, 4 * h + 1));
+        put(kFragW1 + 2 * mt + 1, w1ext(P, row, 4 * h + 2), w1ext(P, row, 4 * h + 3));
+        for (int kb = 0; kb < 8; ++kb) {
+            const int col = kb * 8 + 4 * h;
+            const float* w = P + kOffW2 + row * 64 + col;
+            put(kFragW2 + 2 * (mt * 8 + kb), w[0], w[1]);
+            put(kFragW2 + 2 * (mt * 8 + kb) + 1, w[2], w[3]);
+            // transposed W2: A[i = row][k = col + c] = W2[col + c][row]
+            const float* t = P + kOffW2 + col * 64 + row;
+            put(kFragW2T + 2 * (mt * 8 + kb), t[0], t[64]);
+            put(kFragW2T + 2 * (mt * 8 + kb) + 1, t[128], t[192]);
+        }
+        // transposed W3: A[i = hidden row][k = output 4h + c]
+        float v[4];
+        for (int c = 0; c < 4; ++c) v[c] = (4 * h + c < 3) ? P[kOffW3 + (4 * h + c) * 64 + row] : 0.0f;
+        put(kFragW3T + 2 * mt, v[0], v[1]);
+        put(kFragW3T + 2 * mt + 1, v[2], v[3]);
+        for (int r = 0; r < 16; ++r) {
+            const int i = mt * 32 + (r & 3) + 4 * h + 8 * (r >> 2);
+            frag[(kFragB2 + mt * 16 + r) * 64 + lane] = __float_as_uint(P[kOffB2 + i]);
+        }
+    }
+    for (int kb = 0; kb < 8; ++kb) {
+        const int col = kb * 8 + 4 * h;
+        float v[4];
+        for (int c = 0; c < 4; ++c) v[c] = (j < 3) ? P[kOffW3 + j * 64 + col + c] : 0.0f;
+        put(kFragW3 + 2 * kb, v[0], v[1]);
+        put(kFragW3 + 2 * kb + 1, v[2], v[3]);
+    }
+    for (int r = 0; r < 16; ++r) {
+        const int i = (r & 3) + 4 * h + 8 * (r >> 2);
+        frag[(kFragB3 + r) * 64 + lane] = __float_as_uint(i < 3 ? P[kOffB3 + i] : 0.0f);
+    }
+}
+
+hipError_t mlp_pack(const MlpState& s, hipStream_t st) {
+    hipLaunchKernelGGL(pack_kernel, dim3(1), dim3(64), 0, st, s.master, s.frag);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// batched inference on raw inputs X[B][6] -> deltas Y[B][3] (outputs x out_scale)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void normalise(const MlpNorm& n, const float raw[6], float x[8]) {
+#pragma unroll
+    for (int k = 0; k < 6; ++k) x[k] = (raw[k] - n.in_mean[k]) * n.in_inv_scale[k];
+    x[6] = 1.0f;
+    x[7] = 0.0f;
+}
+
+__global__ __launch_bounds__(256) void forward_kernel(const float* __restrict__ X, int64_t B,
+                                                     float* __restrict__ Y, const uint32_t* __restrict__ frag,
+                                                     MlpNorm nrm) {
+    const int lane = threadIdx.x & 63;
+    FwdFrag F;
+    load_fwd_frag(F, frag, lane);
+    const int64_t n_chunks = (B + 63) >> 6;
+    const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t chunk = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; chunk < n_chunks;
+         chunk += n_waves) {
+        const int64_t p = chunk * 64 + lane;
+        const bool valid = p < B;
+        float raw[6], x[8], y[3];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) raw[k] = valid ? X[p * 6 + k] : nrm.in_mean[k];
+        normalise(nrm, raw, x);
+        mlp_wave(F, x, y, lane);
+        if (valid) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) Y[p * 3 + c] = y[c] * nrm.out_scale[c];
+        }
+    }
+}
+
+hipError_t mlp_forward(const MlpState& s, const float* X, int64_t B, float* Y, hipStream_t st) {
+    if (B <= 0) return hipSuccess;
+    const int64_t chunks = (B + 63) / 64;
+    const int64_t blocks = chunks < 1024 ? (chunks + 3) / 4 : 256;
+    hipLaunchKernelGGL(forward_kernel, dim3((unsigned)blocks), dim3(256), 0, st, X, B, Y, s.frag, s.norm);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// training: one wave per block; per 64-sample chunk a forward and backward
+// pass in registers, then the weight gradients as products over the chunk's
+// samples from LDS copies (features x samples, bf16) of X, H1, H2, dY, dH2,
+// dH1.  Each wave writes its partial gradient; a second kernel sums the
+// partials in wave order (deterministic).  Loss: 0.5/B sum ||f(x) - y/s||^2.
+// ---------------------------------------------------------------------------
+constexpr int kMaxTrainWaves = 1024;
+
+struct TrainLds {
+    uint16_t X[8][64];
+    uint16_t H1[64][64];
+    uint16_t H2[64][64];
+    uint16_t dH2[64][64];
+    uint16_t dH1[64][64];
+    uint16_t dY[8][64];
+};
+
+__device__ __forceinline__ s4 lds_s4(const uint16_t* row, int col) {
+    return *reinterpret_cast<const s4*>(row + col);
+}
+
+__device__ __forceinline__ void store_cols(uint16_t (*M)[64], int row0, int col, s4 v) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) M[row0 + c][col] = (uint16_t)v[c];
+}
+
+__global__ __launch_bounds__(64) void train_kernel(const float* __restrict__ X, const float* __restrict__ Y, int64_t B,
+                                                  const uint32_t* __restrict__ frag, MlpNorm nrm,
+                                                  float* __restrict__ partial) {
+    __shared__ TrainLds L;
+    const int lane = threadIdx.x, h = lane >> 5, j = lane & 31;
+    const int wave = blockIdx.x, n_waves = gridDim.x;
+    FwdFrag F;
+    load_fwd_frag(F, frag, lane);
+    s4 w3t[2], w2t[2][8];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+        w3t[mt] = frag_s4(frag, kFragW3T + 2 * mt, lane);
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) w2t[mt][kb] = frag_s4(frag, kFragW2T + 2 * (mt * 8 + kb), lane);
+    }
+    const f16v zero = {};
+    f16v gW1[2] = {zero, zero}, gW2[2][2] = {{zero, zero}, {zero, zero}}, gW3[2] = {zero, zero};
+    float gb2 = 0.0f, gb3 = 0.0f, lsum = 0.0f;
+    const float invB = 1.0f / (float)B;
+    const int64_t n_chunks = (B + 63) >> 6;
+
+    for (int64_t chunk = wave; chunk < n_chunks; chunk += n_waves) {
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            const int col = 32 * t + j;
+            const int64_t p = chunk * 64 + col;
+            const bool valid = p < B;
+            float xin[4];
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const int k = 4 * h + c;
+                float v = 0.0f;
+                if (valid) v = k < 6 ? (X[p * 6 + k] - nrm.in_mean[k]) * nrm.in_inv_scale[k] : (k == 6 ? 1.0f : 0.0f);
+                xin[c] = v;
+            }
+            const s4 xb = make_s4(pack_bf16x2(xin[0], xin[1]), pack_bf16x2(xin[2], xin[3]));
+            store_cols(L.X, 4 * h, col, xb);
+            s4 h1[8], h2[8];
+            const f16v o = forward_tile(F, xb, h1, h2);
+#pragma unroll
+            for (int kb = 0; kb < 8; ++kb) {
+                store_cols(L.H1, kb * 8 + 4 * h, col, h1[kb]);
+                store_cols(L.H2, kb * 8 + 4 * h, col, h2[kb]);
+            }
+            // residual and output gradient on the lanes that hold the outputs
+            float dy[3] = {0.0f, 0.0f, 0.0f};
+            if (h == 0 && valid) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float r = o[c] - Y[p * 3 + c] / nrm.out_scale[c];
+                    lsum = fmaf(0.5f * r, r, lsum);
+                    dy[c] = r * invB;
+                }
+            }
+            const s4 dyb = make_s4(pack_bf16x2(dy[0], dy[1]), pack_bf16x2(dy[2], 0.0f));
+            store_cols(L.dY, 4 * h, col, dyb);
+            // dH2^T = W3^T dY^T, masked by H2 > 0
+            s4 dh2[8];
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+                const f16v d = mfma(w3t[mt], dyb, zero);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const s4 m = h2[mt * 4 + q];
+                    float v[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) v[c] = (m[c] > 0) ? d[4 * q + c] : 0.0f;
+                    dh2[mt * 4 + q] = make_s4(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3]));
+                    store_cols(L.dH2, mt * 32 + 8 * q + 4 * h, col, dh2[mt * 4 + q]);
+                }
+            }
+            // dH1^T = W2^T dH2^T, masked by H1 > 0
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+                f16v acc = zero;
+#pragma unroll
+                for (int kb = 0; kb < 8; ++kb) acc = mfma(w2t[mt][kb], dh2[kb], acc);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const s4 m = h1[mt * 4 + q];
+                    float v[4];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) v[c] = (m[c] > 0) ? acc[4 * q + c] : 0.0f;
+                    store_cols(L.dH1, mt * 32 + 8 * q + 4 * h,
+                               col, make_s4(pack_bf16x2(v[0], v[1]), pack_bf16x2(v[2], v[3])));
+                }
+            }
+        }
+        __syncthreads();
+        // weight gradients: sums over the 64 samples of the chunk
+#pragma unroll
+        for (int kb = 0; kb < 8; ++kb) {
+            const int c0 = kb * 8 + 4 * h;
+            const s4 xB = j < 8 ? lds_s4(L.X[j & 7], c0) : s4{0, 0, 0, 0};
+            const s4 dyA = j < 3 ? lds_s4(L.dY[j & 7], c0) : s4{0, 0, 0, 0};
+#pragma unroll
+            for (int mt = 0; mt < 2; ++mt) {
+                const s4 a2 = lds_s4(L.dH2[mt * 32 + j], c0);
+                const s4 a1 = lds_s4(L.dH1[mt * 32 + j], c0);
+                gW1[mt] = mfma(a1, xB, gW1[mt]);
+#pragma unroll
+                for (int nt = 0; nt < 2; ++nt) gW2[mt][nt] = mfma(a2, lds_s4(L.H1[nt * 32 + j], c0), gW2[mt][nt]);
+            }
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) gW3[nt] = mfma(dyA, lds_s4(L.H2[nt * 32 + j], c0), gW3[nt]);
+        }
+        // bias gradients: row sums (lane l owns hidden row l and output row l < 3)
+        {
+            float s2 = 0.0f, s3 = 0.0f;
+            for (int c = 0; c < 64; ++c) {
+                s2 += bf16_bits_to_float(L.dH2[lane][c]);
+                if (lane < 3) s3 += bf16_bits_to_float(L.dY[lane][c]);
+            }
+            gb2 += s2;
+            gb3 += s3;
+        }
+        __syncthreads();
+    }
+    // partial gradient of this wave
+    float* P = partial + (int64_t)wave * (kMlpParams + 1);
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int i = mt * 32 + (r & 3) + 4 * h + 8 * (r >> 2);
+            if (j < 6) P[kOffW1 + i * 6 + j] = gW1[mt][r];
+            else if (j == 6) P[kOffB1 + i] = gW1[mt][r];
+#pragma unroll
+            for (int nt = 0; nt < 2; ++nt) P[kOffW2 + i * 64 + nt * 32 + j] = gW2[mt][nt][r];
+        }
+    }
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            const int o = (r & 3) + 4 * h + 8 * (r >> 2);
+            if (o < 3) P[kOffW3 + o * 64 + nt * 32 + j] = gW3[nt][r];
+        }
+    }
+    P[kOffB2 + lane] = gb2;
+    if (lane < 3) P[kOffB3 + lane] = gb3;
+    // loss: wave sum in a fixed order
+    for (int off = 32; off > 0; off >>= 1) lsum += __shfl_down(lsum, off);
+    if (lane == 0) P[kMlpParams] = lsum;
+}
+
+__global__ __launch_bounds__(256) void reduce_kernel(const float* __restrict__ partial, int n_waves,
+                                                    float* __restrict__ grad, float* __restrict__ loss,
+                                                    float invB) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p > kMlpParams) return;
+    float s = 0.0f;
+    for (int w = 0; w < n_waves; ++w) s += partial[(int64_t)w * (kMlpParams + 1) + p];
+    if (p < kMlpParams) grad[p] = s;
+    else loss[0] = s * invB;
+}
+
+hipError_t mlp_grad(MlpState& s, const float* X, const float* Y, int64_t B, float* grad, float* loss,
+                    hipStream_t st) {
+    const int64_t chunks = (B + 63) / 64;
+    const int waves = (int)(chunks < kMaxTrainWaves ? chunks : kMaxTrainWaves);
+    hipLaunchKernelGGL(train_kernel, dim3(waves), dim3(64), 0, st, X, Y, B, s.frag, s.norm, s.partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_kernel, dim3((kMlpParams + 1 + 255) / 256), dim3(256), 0, st, s.partial, waves, grad,
+                       loss, 1.0f / (float)B);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                                                  const float* __restrict__ g, float lr, float bc1, float bc2) {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p >= kMlpParams) return;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float gi = g[p];
+    const float mi = b1 * m[p] + (1.0f - b1) * gi;
+    const float vi = b2 * v[p] + (1.0f - b2) * gi * gi;
+    m[p] = mi;
+    v[p] = vi;
+    w[p] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+}
+
+hipError_t mlp_adam(MlpState& s, float lr, hipStream_t st) {
+    s.adam_t += 1;
+    const float bc1 = 1.0f - powf(0.9f, (float)s.adam_t), bc2 = 1.0f - powf(0.999f, (float)s.adam_t);
+    hipLaunchKernelGGL(adam_kernel, dim3((kMlpParams + 255) / 256), dim3(256), 0, st, s.master, s.adam_m, s.adam_v,
+                       s.grad, lr, bc1, bc2);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return mlp_pack(s, st);
+}
+
+// ---------------------------------------------------------------------------
+// surrogate K-block update: persistent waves; per 64 points the temperatures
+// at the block ends, the error indicator, one network evaluation for all
+// lanes, then either base + delta (network) or the K plain steps (flagged)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool needs_plain(float T0, float TK, const MlpNorm& n) {
+    const float lo = fminf(T0, TK), hi = fmaxf(T0, TK);
+    const bool cold = hi < n.T_cold;
+    const bool hot = lo >= n.T_hot_lo && hi <= n.T_hot_hi;
+    return !(cold || hot) || fabsf(TK - T0) > n.dT_max;
+}
+
+template <int W>
+__global__ __launch_bounds__(256) void surrogate_kernel(PointGeom pg, const SrcRec* __restrict__ tab, int K, float dt,
+                                                       float ln_dt, ScanArgs sa, float* __restrict__ beta,
+                                                       float* __restrict__ as, float* __restrict__ am,
+                                                       const uint32_t* __restrict__ frag, MlpNorm nrm) {
+    const int lane = threadIdx.x & 63;
+    FwdFrag F;
+    load_fwd_frag(F, frag, lane);
+    const int64_t n_chunks = (pg.count + 63) >> 6;
+    const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t chunk = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; chunk < n_chunks;
+         chunk += n_waves) {
+        const int64_t g = chunk * 64 + lane;
+        bool valid = g < pg.count;
+        const int64_t local = pg.first + (valid ? g : 0);
+        int gi = 0, gj = 0, gk = 0;
+        float a = 0.0f, m = 0.0f, T0 = sa.T0, TK = sa.T0;
+        if (valid) {
+            const int lin = pg.index ? pg.index[local] : (int)local;
+            gk = lin / pg.nxy;
+            const int rem = lin - gk * pg.nxy;
+            gj = rem / pg.nx;
+            gi = rem - gj * pg.nx;
+            valid = gk >= pg.k0;
+        }
+        if (valid) {
+            a = as[local];
+            m = am[local];
+            T0 = scan_temperature<W>(tab, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min);
+            TK = scan_temperature<W>(tab + K * W, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min);
+        }
+        const bool flag = needs_plain(T0, TK, nrm);
+        const float raw[6] = {T0, TK, ln_dt, solid_fraction(T0) - a - m, a, m};
+        float x[8], y[3];
+        normalise(nrm, raw, x);
+        mlp_wave(F, x, y, lane);
+        if (valid) {
+            float an = a, mn = m, bn;
+            if (!flag) {
+                const float xeqK = alpha_eq(TK);
+                correct(TK, xeqK, an, mn);  // instantaneous changes at the block end
+                an = fmaf(y[0], nrm.out_scale[0], an);
+                mn = fmaf(y[1], nrm.out_scale[1], mn);
+                bn = correct(TK, xeqK, an, mn);
+            } else {
+                float alo = 0.0f, mlo = 0.0f, Tn = T0, xeq_n = alpha_eq(T0);
+                for (int s = 0; s < K; ++s) {
+                    const float Tn1 = scan_temperature<W>(tab + (s + 1) * W, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min);
+                    const float xeq_n1 = alpha_eq(Tn1);
+                    explicit_step<true>(an, mn, alo, mlo, Tn, xeq_n, Tn1, xeq_n1, dt);
+                    Tn = Tn1;
+                    xeq_n = xeq_n1;
+                }
+                an += alo;
+                mn += mlo;
+                bn = solid_fraction(Tn) - an - mn;
+            }
+            as[local] = an;
+            am[local] = mn;
+            beta[local] = bn;
+        }
+    }
+}
+
+hipError_t launch_surrogate(const MlpState& s, const PointGeom& pg, int W, const SrcRec* tab, int K, float dt,
+                            ScanArgs sa, float* beta, float* as, float* am, hipStream_t st) {
+    if (pg.count <= 0) return hipSuccess;
+    const int64_t chunks = (pg.count + 63) / 64;
+    const int64_t blocks = chunks < 8192 ? (chunks + 3) / 4 : 2048;
+    const float ln_dt = logf(dt);
+    const dim3 grid((unsigned)blocks), block(256);
+    switch (W) {
+        case 1: hipLaunchKernelGGL(surrogate_kernel<1>, grid, block, 0, st, pg, tab, K, dt, ln_dt, sa, beta, as, am, s.frag, s.norm); break;
+        case 2: hipLaunchKernelGGL(surrogate_kernel<2>, grid, block, 0, st, pg, tab, K, dt, ln_dt, sa, beta, as, am, s.frag, s.norm); break;
+        case 3: hipLaunchKernelGGL(surrogate_kernel<3>, grid, block, 0, st, pg, tab, K, dt, ln_dt, sa, beta, as, am, s.frag, s.norm); break;
+        case 4: hipLaunchKernelGGL(surrogate_kernel<4>, grid, block, 0, st, pg, tab, K, dt, ln_dt, sa, beta, as, am, s.frag, s.norm); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// the correction g at a given temperature, in place (training targets)
+__global__ __launch_bounds__(256) void correct_kernel(const float* __restrict__ T, float* __restrict__ beta,
+                                                     float* __restrict__ as, float* __restrict__ am, int64_t n) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    float a = as[i], m = am[i];
+    const float Ti = T[i];
+    beta[i] = correct(Ti, alpha_eq(Ti), a, m);
+    as[i] = a;
+    am[i] = m;
+}
+
+hipError_t launch_correct(const float* T, float* beta, float* as, float* am, int64_t n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(correct_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, T, beta, as, am, n);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+hipError_t mlp_alloc(MlpState& s) {
+    if (s.master) return hipSuccess;
+    hipError_t e;
+    if ((e = hipMalloc((void**)&s.master, kMlpParams * sizeof(float))) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&s.adam_m, kMlpParams * sizeof(float))) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&s.adam_v, kMlpParams * sizeof(float))) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&s.grad, kMlpParams * sizeof(float))) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&s.loss, sizeof(float))) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&s.frag, kFragWords * 64 * sizeof(uint32_t))) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&s.partial, (size_t)kMaxTrainWaves * (kMlpParams + 1) * sizeof(float))) != hipSuccess)
+        return e;
+    s.partial_waves = kMaxTrainWaves;
+    return hipSuccess;
+}
+
+void mlp_free(MlpState& s) {
+    for (void* p : {(void*)s.master, (void*)s.adam_m, (void*)s.adam_v, (void*)s.grad, (void*)s.loss, (void*)s.frag,
+                    (void*)s.partial})
+        if (p) (void)hipFree(p);
+    s = MlpState{};
 }
 
 }  // namespace mstruct

@@ -58,7 +58,8 @@ def test_null_context_rejected_without_device(L):
     assert L.mstruct_fused_scan_steps(None, None, None, 0.0, 1e-6, 1, 1, 0, None, None) == -1
     assert L.mstruct_gather(None, None, None, 0, None, None) == -1
     assert L.mstruct_check_invariants(None, None, None, 0.0, None, None) == -1
-    assert L.mstruct_mlp_set_params(None, None, None, None, None) == -1
+    assert L.mstruct_correct(None, None, None, None) == -1
+    assert L.mstruct_mlp_set_params(None, None, None, None, None, None) == -1
     assert L.mstruct_mlp_get_params(None, None) == -1
     assert L.mstruct_mlp_forward(None, None, 0, None, None) == -1
     assert L.mstruct_mlp_grad(None, None, None, 0, None, None, None) == -1

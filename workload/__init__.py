@@ -33,8 +33,8 @@ import numpy as np
 TRACK_COLS = ("x0", "y0", "z0", "ux", "uy", "t_on", "dur", "q", "v")
 N_TRACK_COLS = len(TRACK_COLS)
 
-# Initial phase state used by every workload (BJ config 1: alpha_s = 0.9,
-# beta = 0.1, alpha_m = 0).
+# Initial phase state used by every workload: alpha_s = 0.9, beta = 0.1,
+# alpha_m = 0.
 INIT_ALPHA_S = 0.9
 INIT_ALPHA_M = 0.0
 INIT_BETA = 0.1
@@ -348,3 +348,12 @@ def truncated(wl: Workload, n_layers: int = None, steps_per_layer: int = None) -
         layers = [Layer(L.step_begin, min(L.step_end, L.step_begin + steps_per_layer), L.z_top)
                   for L in layers]
     return dataclasses.replace(wl, layers=layers)
+
+
+def mlp_init_params(seed=0) -> np.ndarray:
+    """Seeded He-style random parameters of the 6-64-64-3 network (float32),
+    layout W1[64][6], b1[64], W2[64][64], b2[64], W3[3][64], b3[3]."""
+    rng = np.random.default_rng(seed)
+    parts = [rng.normal(0, math.sqrt(2 / 7), 64 * 6), np.zeros(64), rng.normal(0, math.sqrt(2 / 64), 64 * 64),
+             np.zeros(64), rng.normal(0, math.sqrt(1 / 64), 3 * 64), np.zeros(3)]
+    return np.concatenate(parts).astype(np.float32)
