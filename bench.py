@@ -5,7 +5,9 @@ MI355X.
 One benchmark step = one whole run of the workload from the initial state
 through every layer (all 20,000 time steps; 150,077,440,000 active
 point-updates) with the temperature evaluated from the scan inside the fused
-kernel (K = 16 steps per launch).  Prints one JSON line.
+kernel (K = 16 steps per launch).  `value` is the plain float32 path; the
+`surrogate` entry is the same workload with the learned surrogate (K = 8).
+Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -29,6 +31,7 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 # i.e. 256 CUs x 128 lane-ops/clock x 2.4 GHz = 78.6 T lane-ops/s
 VALU_PEAK_TLANEOPS = FP32_VECTOR_PEAK_TFLOPS / 2
 K_FUSED = 16
+K_SURROGATE = 8
 STEP_BYTES = 28  # plain step: reads alpha_s, alpha_m, T^n, T^{n+1}; writes beta, alpha_s, alpha_m (float32)
 
 
@@ -75,22 +78,24 @@ def main():
         for dst, src in zip((b, a, m), init):
             dst.copy_(src)
 
-    def one_step():
-        reset()
-        ms.run_layers(ctx, wl, b, a, m, K=args.K)
+    def timed(mode, K):
+        def one_step():
+            reset()
+            ms.run_layers(ctx, wl, b, a, m, K=K, mode=mode)
 
-    for _ in range(args.warmup):
-        one_step()
-    torch.cuda.synchronize()
-    t_start, t_end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    t_start.record()
-    wall0 = time.perf_counter()
-    for _ in range(args.steps):
-        one_step()
-    t_end.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms_total = t_start.elapsed_time(t_end)
+        for _ in range(args.warmup):
+            one_step()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        w0 = time.perf_counter()
+        for _ in range(args.steps):
+            one_step()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1), time.perf_counter() - w0
+
+    ms_total, wall = timed(ms.MODE_PLAIN, args.K)
     ms_per_step = ms_total / args.steps
     value = updates * args.steps / (ms_total * 1e-3)
     # average duration of one fused launch over the timed region (the fused
@@ -138,6 +143,28 @@ def main():
     }
     final_state = [x.clone() for x in (b, a, m)]
 
+    sur_state = None
+    if not args.no_surrogate:
+        from paper_2402_17580_amd import surrogate as S
+        t_tr = 0.0
+        if os.path.exists(S.DEFAULT_WEIGHTS):
+            sur = S.Surrogate.load(S.DEFAULT_WEIGHTS)
+        else:
+            t0 = time.perf_counter()
+            X, Y = S.generate_transitions(ctx, wl, K=K_SURROGATE)
+            sur, _ = S.fit(ctx, X, Y, K_SURROGATE)
+            t_tr = time.perf_counter() - t0
+        sur.load_into(ctx)
+        ms_sur, _ = timed(ms.MODE_SURROGATE, sur.K)
+        sur_state = [x.clone() for x in (b, a, m)]
+        result["surrogate"] = {
+            "value": updates * args.steps / (ms_sur * 1e-3), "unit": "point-updates/s",
+            "ms_per_step": ms_sur / args.steps, "speedup_vs_plain": ms_total / ms_sur, "K": sur.K,
+            "path": "mstruct_fused_scan_steps, SURROGATE: one explicit step of K dt + BF16-MFMA network "
+                    "correction where the indicator allows, K plain steps elsewhere",
+            "indicator": list(sur.indicator), "trained_in_bench_s": t_tr,
+        }
+
     if not args.no_stepwise:
         result["plain_step"] = bench_stepwise(torch, ms, ctx, wl, dev)
 
@@ -151,7 +178,11 @@ def main():
         result["copy_probe_bytes"] = {"read": src.numel() * 4, "write": src.numel() * 4}
 
     if not args.no_cpu_baseline:
-        result.update(cpu_baseline_and_errors(torch, wl, final_state, args))
+        base, st, idx = cpu_baseline(wl, args)
+        result["cpu_baseline"] = base
+        result["errors_vs_oracle"] = errors(final_state, st, idx)
+        if sur_state is not None:
+            result["surrogate"]["errors_vs_oracle"] = errors(sur_state, st, idx)
 
     print(json.dumps(result))
     ctx.close()
@@ -205,7 +236,9 @@ def bench_stepwise(torch, ms, ctx, wl, dev):
                          "point_updates_per_s": n_act / avg}}
 
 
-def cpu_baseline_and_errors(torch, wl, final_state, args):
+def cpu_baseline(wl, args):
+    """The FP64 oracle on a seeded sample of the workload's points (all
+    20,000 steps), timed on the host cores."""
     import oracle
     threads = args.threads or min(16, os.cpu_count() or 1)
     idx = workload.sample_indices(wl.grid.n, args.sample, wl.seed)
@@ -215,16 +248,18 @@ def cpu_baseline_and_errors(torch, wl, final_state, args):
     t0 = time.perf_counter()
     st = oracle.run_workload(wl, idx, threads=threads)
     el = time.perf_counter() - t0
-    errs = {}
-    for name, g, o in zip(("beta", "alpha_s", "alpha_m"), final_state, (st.beta, st.alpha_s, st.alpha_m)):
+    base = {"value": upd / el, "unit": "point-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{idx.size} seeded points (p={args.sample}) x all 20,000 steps "
+                      f"({upd} point-updates, FP64, {el:.1f} s)"}
+    return base, st, idx
+
+
+def errors(state, st, idx):
+    out = {}
+    for name, g, o in zip(("beta", "alpha_s", "alpha_m"), state, (st.beta, st.alpha_s, st.alpha_m)):
         d = np.abs(g.double().cpu().numpy()[idx] - o)
-        errs[name] = {"max": float(d.max()), "rms": float(np.sqrt(np.mean(d * d)))}
-    return {
-        "cpu_baseline": {"value": upd / el, "unit": "point-updates/s", "cores": threads, "kind": "oracle",
-                         "sample": f"{idx.size} seeded points (p={args.sample}) x all 20,000 steps "
-                                   f"({upd} point-updates, FP64, {el:.1f} s)"},
-        "errors_vs_oracle": errs,
-    }
+        out[name] = {"max": float(d.max()), "rms": float(np.sqrt(np.mean(d * d)))}
+    return out
 
 
 if __name__ == "__main__":

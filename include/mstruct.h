@@ -53,7 +53,8 @@ typedef struct {
  * point on the layer surface [m], in-plane unit direction, switch-on time
  * [s], on-duration [s], absorbed power [W], speed [m/s].  The temperature at
  * a point is T0 plus the superposed contributions of the last `window` tracks
- * switched on by time t (each a moving point source on the adiabatic surface
+ * switched on by time t, i.e. with t_on <= t + 1e-12 s (each a moving point
+ * source on the adiabatic surface
  * of a semi-infinite body, switched on at t_on and off after dur), clamped at
  * T_clamp.  window is 1..4. */
 typedef struct {
@@ -117,8 +118,9 @@ int mstruct_temperature(mstruct_ctx *ctx, const mstruct_scan *scan, const mstruc
  * computed on the host in float64.  mode PLAIN runs the explicit step of
  * mstruct_step at every step (with compensated accumulation of the Euler
  * increments inside a launch).  mode SURROGATE replaces each block of K steps
- * of a point by one evaluation of the trained network followed by the
- * correction g at the block's end temperature, except where the error
+ * of a point by one explicit step of K dt (rates at the block-start
+ * temperature, correction at the block-end temperature) plus the correction
+ * to it predicted by the trained network, except where the error
  * indicator flags the point (temperature window touching the martensite
  * start, beta-transus or melting bands, or a start-up state), which get the
  * K plain steps; requires weights loaded with mstruct_mlp_set_params.
@@ -148,8 +150,8 @@ int mstruct_correct(mstruct_ctx *ctx, const float *T, const mstruct_phases *ph, 
  * ReLU, BF16 MFMA products with float32 accumulation ----
  * Raw inputs per sample: (T_n, T_{n+K}, ln dt, beta, alpha_s, alpha_m), each
  * normalised in the library as (x - in_mean) / in_scale.  Network outputs
- * times out_scale are the changes of (alpha_s, alpha_m, beta) over K explicit
- * steps beyond what the correction g at T_{n+K} alone gives.  Parameter
+ * times out_scale are the differences of (alpha_s, alpha_m, beta) between K
+ * explicit steps of dt and one explicit step of K dt over the same block.  Parameter
  * vector (float32, MSTRUCT_MLP_NPARAM entries, row = output unit):
  * W1[64][6], b1[64], W2[64][64], b2[64], W3[3][64], b3[3]. */
 #define MSTRUCT_MLP_NPARAM 4803

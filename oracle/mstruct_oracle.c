@@ -33,7 +33,8 @@
  *       D' = X_alpha^eq - X_am, k~ = k_as D', c = c_as, from X_as = 0.
  *   R8  when D <= 0 (or the start-up ratio is >= 1) no start-up change.
  *   R9  temperature: switched moving point source on a semi-infinite body
- *       (not part of the paper, which uses an FEM heat solve).
+ *       (not part of the paper, which uses an FEM heat solve); the window of
+ *       superposed tracks is the last `window` tracks with t_on <= t + 1e-12 s.
  */
 #include <math.h>
 #include <stdint.h>
@@ -313,13 +314,17 @@ double orc_source_F(const double *tr, double tau, double k, double alpha,
     return source_F(tr[0], tr[1], tr[2], tr[3], tr[4], tr[7], tr[8], tau, k, alpha, x, y, z);
 }
 
-/* index of the last track with t_on <= t, or -1 (tracks sorted by t_on) */
+/* index of the last track switched on by time t, or -1 (tracks sorted by
+ * t_on).  A track counts as switched on when t_on <= t + 1e-12 s, so that the
+ * same window results whether a time is formed as t0 + n dt or as (s + n) dt
+ * (the two can differ by an ulp exactly where a track starts). */
+#define T_ON_TOL 1e-12
 static int64_t last_on(const double *tracks, int64_t n_tracks, double t)
 {
-    int64_t lo = 0, hi = n_tracks; /* first index with t_on > t */
+    int64_t lo = 0, hi = n_tracks; /* first index with t_on > t + tol */
     while (lo < hi) {
         int64_t mid = (lo + hi) / 2;
-        if (tracks[mid * 9 + 5] <= t) lo = mid + 1;
+        if (tracks[mid * 9 + 5] <= t + T_ON_TOL) lo = mid + 1;
         else hi = mid;
     }
     return lo - 1;

@@ -133,12 +133,15 @@ int make_geom(mstruct_ctx* ctx, const mstruct_points* p, int64_t n, PointGeom& p
     return MSTRUCT_OK;
 }
 
-// index of the last track with t_on <= t, or -1
+// index of the last track switched on by time t, or -1; a track is on when
+// t_on <= t + 1e-12 s, so that t0 + n dt and (s + n) dt (which may differ by
+// an ulp where a track starts) give the same window
 int64_t last_on(const mstruct_scan* sc, double t) {
+    const double tol = 1e-12;
     int64_t lo = 0, hi = sc->n_tracks;
     while (lo < hi) {
         const int64_t mid = (lo + hi) / 2;
-        if (sc->tracks[9 * mid + 5] <= t) lo = mid + 1;
+        if (sc->tracks[9 * mid + 5] <= t + tol) lo = mid + 1;
         else hi = mid;
     }
     return lo - 1;
@@ -336,6 +339,13 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
     build_table(s->host, scan, pts, t0, dt, n_steps + 1);
     HIP_CHECK(ctx, hipMemcpyAsync(s->dev, s->host, recs * sizeof(SrcRec), hipMemcpyHostToDevice, st));
     const ScanArgs sa{(float)scan->T0, (float)scan->T_clamp};
+    if (mode == MSTRUCT_MODE_SURROGATE) {
+        hipError_t e = surrogate_prepare(ctx->mlp, pg.count, st);
+        if (e != hipSuccess) {
+            (void)release_slot(ctx, s, st);
+            return hip_fail(ctx, e, "surrogate queue");
+        }
+    }
     for (int64_t s0 = 0; s0 < n_steps; s0 += K) {
         const int Kb = (int)((n_steps - s0) < K ? (n_steps - s0) : K);
         hipError_t e;
@@ -343,7 +353,7 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
             e = launch_fused_plain(pg, W, s->dev + s0 * W, Kb, (float)dt, sa, ph->beta, ph->alpha_s, ph->alpha_m, st);
         else
             e = launch_surrogate(ctx->mlp, pg, W, s->dev + s0 * W, Kb, (float)dt, sa, ph->beta, ph->alpha_s,
-                                 ph->alpha_m, st);
+                                 ph->alpha_m, s0 / K, st);
         if (e != hipSuccess) {
             (void)release_slot(ctx, s, st);
             return hip_fail(ctx, e, "fused launch");

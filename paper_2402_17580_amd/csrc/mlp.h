@@ -23,7 +23,12 @@ constexpr int kFragW3T = 52;   // [mt 2][2 words]     (backward)
 constexpr int kFragW2T = 56;   // [mt 2][kb 8][2 words] (backward)
 constexpr int kFragB2 = 88;    // [mt 2][16] float accumulator init
 constexpr int kFragB3 = 120;   // [16] float accumulator init
-constexpr int kFragWords = 136;
+// inference operands for v_mfma_f32_32x32x16_bf16 (K index permuted, see mlp.hip)
+constexpr int kFragI2 = 136;   // [mt 2][kb 4][4 words]
+constexpr int kFragI3 = 168;   // [kb 4][4 words]
+constexpr int kFragWords = 184;
+constexpr int kFragUniform = kFragWords * 64;  // then b3[3] as plain floats
+constexpr int kFragTotal = kFragUniform + 16;
 
 // normalisation and error-indicator constants (host-set)
 struct MlpNorm {
@@ -44,11 +49,18 @@ struct MlpState {
     float* adam_v = nullptr;
     float* grad = nullptr;     // reduced gradient
     float* loss = nullptr;     // reduced loss
-    uint32_t* frag = nullptr;  // bf16 fragments (+ float bias words)
+    uint32_t* frag = nullptr;  // bf16 fragments (+ float bias words), kFragTotal words
     float* partial = nullptr;  // per-wave partial gradients [waves][kMlpParams + 1]
     int partial_waves = 0;
     int adam_t = 0;
+    // surrogate work queue: one entry (kQueueWords floats) per wave that needs
+    // the network, and two alternating entry counters
+    float* queue = nullptr;
+    int64_t queue_entries = 0;
+    unsigned* counters = nullptr;
 };
+
+constexpr int kQueueWords = 7 * 64;  // index, T0, TK, alpha_s, alpha_m, pre_alpha_s, pre_alpha_m
 
 hipError_t mlp_alloc(MlpState& s);
 void mlp_free(MlpState& s);
@@ -57,8 +69,9 @@ hipError_t mlp_forward(const MlpState& s, const float* X, int64_t B, float* Y, h
 hipError_t mlp_grad(MlpState& s, const float* X, const float* Y, int64_t B, float* grad, float* loss,
                     hipStream_t st);
 hipError_t mlp_adam(MlpState& s, float lr, hipStream_t st);
+hipError_t surrogate_prepare(MlpState& s, int64_t points, hipStream_t st);
 hipError_t launch_surrogate(const MlpState& s, const PointGeom& pg, int W, const SrcRec* tab, int K, float dt,
-                            ScanArgs sa, float* beta, float* as, float* am, hipStream_t st);
+                            ScanArgs sa, float* beta, float* as, float* am, int64_t block, hipStream_t st);
 hipError_t launch_correct(const float* T, float* beta, float* as, float* am, int64_t n, hipStream_t st);
 
 }  // namespace mstruct

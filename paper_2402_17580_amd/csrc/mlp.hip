@@ -8,6 +8,12 @@
 // of column j sit in registers 4kb..4kb+3 of lanes j and j+32 in exactly the
 // order the next layer's B operand for k-block kb needs, so activations pass
 // from layer to layer in registers (after ReLU and conversion to bf16).
+//
+// Inference uses v_mfma_f32_32x32x16_bf16 for the two 64-wide layers (lane l
+// supplies B[8h..8h+7][j]).  A C tile's registers 8q..8q+7 of lane half h hold
+// features 16q + 4h + {0..3} and 16q + 8 + 4h + {0..3}; the product sums over
+// k, so the same permutation of k is applied to the weights and those eight
+// registers become the B operand as they are.
 #include "mlp.h"
 
 namespace mstruct {
@@ -17,6 +23,9 @@ typedef float f16v __attribute__((ext_vector_type(16)));
 typedef float f2v __attribute__((ext_vector_type(2)));
 typedef __bf16 bf2v __attribute__((ext_vector_type(2)));
 typedef uint32_t u2v __attribute__((ext_vector_type(2)));
+typedef uint32_t u4v __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8v __attribute__((ext_vector_type(8)));
+typedef short s2v __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
     const bf2v v = __builtin_convertvector((f2v){a, b}, bf2v);  // round to nearest even
@@ -27,6 +36,19 @@ __device__ __forceinline__ f16v mfma(s4 a, s4 b, f16v c) {
     return __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, c, 0, 0, 0);
 }
 __device__ __forceinline__ float bf16_bits_to_float(uint16_t v) { return __uint_as_float((uint32_t)v << 16); }
+__device__ __forceinline__ f16v mfma16(bf8v a, bf8v b, f16v c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, c, 0, 0, 0);
+}
+// ReLU of two packed bf16 values: as 16-bit integers every negative value
+// (and -0) is below 0, so an integer max with 0 zeroes exactly those
+__device__ __forceinline__ uint32_t relu_bf16x2(uint32_t w) {
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s2v, w), (s2v){0, 0}));
+}
+// feature carried by item i of lane half h in the 16-wide k-block kb of a
+// chained operand (the order in which an accumulator tile holds its rows)
+__host__ __device__ __forceinline__ int chained_feature(int kb, int h, int i) {
+    return 16 * kb + 4 * h + (i & 3) + ((i >> 2) << 3);
+}
 
 struct FwdFrag {
     s4 w1[2];
@@ -109,6 +131,88 @@ __device__ __forceinline__ void mlp_wave(const FwdFrag& F, const float x[8], flo
 }
 
 // ---------------------------------------------------------------------------
+// inference path (x16 products, activations chained in registers)
+// ---------------------------------------------------------------------------
+// Inference operands of one lane, staged in LDS once per block (all waves of
+// the block read their lane's copy just before each product):
+//   [0, 32)  W2 x16 A operands [mt][kb][4]     [32, 48) W3 x16 [kb][4]
+//   [48, 80) b2 accumulator init [mt][16]       [80, 84) W1 x8 [mt][2]
+constexpr int kLdsI2 = 0, kLdsI3 = 32, kLdsB2 = 48, kLdsW1 = 80, kLdsStride = 84;
+
+struct InferLds {
+    uint32_t w[64 * kLdsStride];
+    float b3[4];
+};
+
+__device__ __forceinline__ void stage_infer_frag(InferLds& L, const uint32_t* __restrict__ frag) {
+    for (int e = threadIdx.x; e < 64 * kLdsStride; e += blockDim.x) {
+        const int lane = e / kLdsStride, o = e - lane * kLdsStride;
+        int word;
+        if (o < kLdsI3) word = kFragI2 + o;
+        else if (o < kLdsB2) word = kFragI3 + (o - kLdsI3);
+        else if (o < kLdsW1) word = kFragB2 + (o - kLdsB2);
+        else word = kFragW1 + (o - kLdsW1);
+        L.w[e] = frag[word * 64 + lane];
+    }
+    if (threadIdx.x < 3) L.b3[threadIdx.x] = __uint_as_float(frag[kFragUniform + threadIdx.x]);
+    __syncthreads();
+}
+
+__device__ __forceinline__ bf8v lds_bf8(const InferLds& L, int lane, int o) {
+    return *reinterpret_cast<const bf8v*>(&L.w[lane * kLdsStride + o]);
+}
+__device__ __forceinline__ f16v lds_f16(const InferLds& L, int lane, int o) {
+    return *reinterpret_cast<const f16v*>(&L.w[lane * kLdsStride + o]);
+}
+__device__ __forceinline__ s4 lds_w1(const InferLds& L, int lane, int mt) {
+    return *reinterpret_cast<const s4*>(&L.w[lane * kLdsStride + kLdsW1 + 2 * mt]);
+}
+
+// ReLU + bf16 of accumulator registers r0..r0+7 as an x16 B operand
+__device__ __forceinline__ bf8v act8(const f16v& d, int r0) {
+    const u4v w = {relu_bf16x2(pack_bf16x2(d[r0], d[r0 + 1])), relu_bf16x2(pack_bf16x2(d[r0 + 2], d[r0 + 3])),
+                   relu_bf16x2(pack_bf16x2(d[r0 + 4], d[r0 + 5])), relu_bf16x2(pack_bf16x2(d[r0 + 6], d[r0 + 7]))};
+    return __builtin_bit_cast(bf8v, w);
+}
+
+// outputs of one 32-point tile (rows 0..2 of lanes with h = 0, without b3)
+__device__ __forceinline__ f16v infer_tile(const InferLds& L, int lane, s4 xb) {
+    const f16v zero = {};
+    const f16v d0 = mfma(lds_w1(L, lane, 0), xb, zero), d1 = mfma(lds_w1(L, lane, 1), xb, zero);
+    const bf8v h1[4] = {act8(d0, 0), act8(d0, 8), act8(d1, 0), act8(d1, 8)};
+    f16v e0 = lds_f16(L, lane, kLdsB2), e1 = lds_f16(L, lane, kLdsB2 + 16);
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) {
+        e0 = mfma16(lds_bf8(L, lane, kLdsI2 + kb * 4), h1[kb], e0);
+        e1 = mfma16(lds_bf8(L, lane, kLdsI2 + (4 + kb) * 4), h1[kb], e1);
+    }
+    const bf8v h2[4] = {act8(e0, 0), act8(e0, 8), act8(e1, 0), act8(e1, 8)};
+    f16v o = zero;
+#pragma unroll
+    for (int kb = 0; kb < 4; ++kb) o = mfma16(lds_bf8(L, lane, kLdsI3 + kb * 4), h2[kb], o);
+    return o;
+}
+
+// network on the 64 points of a wave (one per lane); must be reached by all
+// 64 lanes
+__device__ __forceinline__ void mlp_infer(const InferLds& L, const float x[8], float y[3], int lane) {
+    // compiler-only barrier: keeps the operand loads from LDS here instead of
+    // letting them be hoisted out of the point loop into (many) registers
+    __asm__ volatile("" ::: "memory");
+    const bool hi = lane >= 32;
+    const uint32_t w0 = pack_bf16x2(x[0], x[1]), w1 = pack_bf16x2(x[2], x[3]);
+    const uint32_t w2 = pack_bf16x2(x[4], x[5]), w3 = pack_bf16x2(x[6], x[7]);
+    const uint32_t r0 = __shfl_xor(hi ? w0 : w2, 32), r1 = __shfl_xor(hi ? w1 : w3, 32);
+    const f16v o0 = infer_tile(L, lane, hi ? make_s4(r0, r1) : make_s4(w0, w1));
+    const f16v o1 = infer_tile(L, lane, hi ? make_s4(w2, w3) : make_s4(r0, r1));
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        const float e = __shfl_xor(o1[c], 32);
+        y[c] = (hi ? e : o0[c]) + L.b3[c];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // fragment packing from the float32 master parameters (one wave)
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ float w1ext(const float* P, int r, int k) {
@@ -153,6 +257,18 @@ __global__ __launch_bounds__(64) void pack_kernel(const float* __restrict__ P, u
         const int i = (r & 3) + 4 * h + 8 * (r >> 2);
         frag[(kFragB3 + r) * 64 + lane] = __float_as_uint(i < 3 ? P[kOffB3 + i] : 0.0f);
     }
+    // inference operands with the chained k order
+    for (int kb = 0; kb < 4; ++kb) {
+        for (int pr = 0; pr < 4; ++pr) {
+            const int f0 = chained_feature(kb, h, 2 * pr), f1 = chained_feature(kb, h, 2 * pr + 1);
+            for (int mt = 0; mt < 2; ++mt) {
+                const int row = mt * 32 + j;
+                put(kFragI2 + (mt * 4 + kb) * 4 + pr, P[kOffW2 + row * 64 + f0], P[kOffW2 + row * 64 + f1]);
+            }
+            put(kFragI3 + kb * 4 + pr, j < 3 ? P[kOffW3 + j * 64 + f0] : 0.0f, j < 3 ? P[kOffW3 + j * 64 + f1] : 0.0f);
+        }
+    }
+    if (lane < 3) frag[kFragUniform + lane] = __float_as_uint(P[kOffB3 + lane]);
 }
 
 hipError_t mlp_pack(const MlpState& s, hipStream_t st) {
@@ -170,12 +286,12 @@ __device__ __forceinline__ void normalise(const MlpNorm& n, const float raw[6], 
     x[7] = 0.0f;
 }
 
-__global__ __launch_bounds__(256) void forward_kernel(const float* __restrict__ X, int64_t B,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void forward_kernel(const float* __restrict__ X, int64_t B,
                                                      float* __restrict__ Y, const uint32_t* __restrict__ frag,
                                                      MlpNorm nrm) {
+    __shared__ InferLds L;
+    stage_infer_frag(L, frag);
     const int lane = threadIdx.x & 63;
-    FwdFrag F;
-    load_fwd_frag(F, frag, lane);
     const int64_t n_chunks = (B + 63) >> 6;
     const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x >> 6);
     for (int64_t chunk = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; chunk < n_chunks;
@@ -186,7 +302,7 @@ __global__ __launch_bounds__(256) void forward_kernel(const float* __restrict__ 
 #pragma unroll
         for (int k = 0; k < 6; ++k) raw[k] = valid ? X[p * 6 + k] : nrm.in_mean[k];
         normalise(nrm, raw, x);
-        mlp_wave(F, x, y, lane);
+        mlp_infer(L, x, y, lane);
         if (valid) {
 #pragma unroll
             for (int c = 0; c < 3; ++c) Y[p * 3 + c] = y[c] * nrm.out_scale[c];
@@ -422,9 +538,13 @@ hipError_t mlp_adam(MlpState& s, float lr, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// surrogate K-block update: persistent waves; per 64 points the temperatures
-// at the block ends, the error indicator, one network evaluation for all
-// lanes, then either base + delta (network) or the K plain steps (flagged)
+// surrogate K-block update in two passes.
+// Pass A (one point per lane, no matrix code, high occupancy): temperatures at
+// the block ends, the error indicator, the K plain steps for flagged points,
+// and for the others one explicit step of K dt, stored; a wave with any
+// non-zero diffusive increment appends its inputs to the queue.
+// Pass B (persistent, weights staged in LDS): the network on queued waves,
+// whose output corrects the increment before the block-end correction.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool needs_plain(float T0, float TK, const MlpNorm& n) {
     const float lo = fminf(T0, TK), hi = fmaxf(T0, TK);
@@ -434,83 +554,143 @@ __device__ __forceinline__ bool needs_plain(float T0, float TK, const MlpNorm& n
 }
 
 template <int W>
-__global__ __launch_bounds__(256) void surrogate_kernel(PointGeom pg, const SrcRec* __restrict__ tab, int K, float dt,
-                                                       float ln_dt, ScanArgs sa, float* __restrict__ beta,
-                                                       float* __restrict__ as, float* __restrict__ am,
-                                                       const uint32_t* __restrict__ frag, MlpNorm nrm) {
+__global__ __launch_bounds__(256) void surrogate_a_kernel(PointGeom pg, const SrcRec* __restrict__ tab, int K,
+                                                         float dt, ScanArgs sa, float* __restrict__ beta,
+                                                         float* __restrict__ as, float* __restrict__ am,
+                                                         MlpNorm nrm, float* __restrict__ queue,
+                                                         unsigned* __restrict__ counter) {
     const int lane = threadIdx.x & 63;
-    FwdFrag F;
-    load_fwd_frag(F, frag, lane);
-    const int64_t n_chunks = (pg.count + 63) >> 6;
-    const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x >> 6);
-    for (int64_t chunk = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; chunk < n_chunks;
-         chunk += n_waves) {
-        const int64_t g = chunk * 64 + lane;
-        bool valid = g < pg.count;
-        const int64_t local = pg.first + (valid ? g : 0);
-        int gi = 0, gj = 0, gk = 0;
-        float a = 0.0f, m = 0.0f, T0 = sa.T0, TK = sa.T0;
-        if (valid) {
-            const int lin = pg.index ? pg.index[local] : (int)local;
-            gk = lin / pg.nxy;
-            const int rem = lin - gk * pg.nxy;
-            gj = rem / pg.nx;
-            gi = rem - gj * pg.nx;
-            valid = gk >= pg.k0;
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    bool valid = g < pg.count;
+    const int64_t local = pg.first + (valid ? g : 0);
+    int gi = 0, gj = 0, gk = 0;
+    if (valid) {
+        const int lin = pg.index ? pg.index[local] : (int)local;
+        gk = lin / pg.nxy;
+        const int rem = lin - gk * pg.nxy;
+        gj = rem / pg.nx;
+        gi = rem - gj * pg.nx;
+        valid = gk >= pg.k0;
+    }
+    float a = 0.0f, m = 0.0f, T0 = sa.T0, TK = sa.T0, pa = 0.0f, pm = 0.0f;
+    bool need = false;
+    if (valid) {
+        a = as[local];
+        m = am[local];
+        T0 = scan_temperature<W>(tab, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min);
+        TK = scan_temperature<W>(tab + K * W, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min);
+        float an = a, mn = m, bn;
+        const float xeq0 = alpha_eq(T0);
+        if (needs_plain(T0, TK, nrm)) {
+            float alo = 0.0f, mlo = 0.0f, Tn = T0, xeq_n = xeq0;
+            for (int s = 0; s < K; ++s) {
+                const float Tn1 = scan_temperature<W>(tab + (s + 1) * W, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min);
+                const float xeq_n1 = alpha_eq(Tn1);
+                explicit_step<true>(an, mn, alo, mlo, Tn, xeq_n, Tn1, xeq_n1, dt);
+                Tn = Tn1;
+                xeq_n = xeq_n1;
+            }
+            an += alo;
+            mn += mlo;
+            bn = solid_fraction(Tn) - an - mn;
+        } else {
+            float da, dm;
+            diffusive_increment(a, m, T0, xeq0, dt * (float)K, da, dm);
+            pa = a + da;
+            pm = m + dm;
+            need = (da != 0.0f) || (dm != 0.0f);
+            an = pa;
+            mn = pm;
+            bn = correct(TK, alpha_eq(TK), an, mn);
         }
-        if (valid) {
-            a = as[local];
-            m = am[local];
-            T0 = scan_temperature<W>(tab, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min);
-            TK = scan_temperature<W>(tab + K * W, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min);
-        }
-        const bool flag = needs_plain(T0, TK, nrm);
+        as[local] = an;
+        am[local] = mn;
+        beta[local] = bn;
+    }
+    if (__ballot(need) != 0) {
+        unsigned slot = 0;
+        if (lane == 0) slot = atomicAdd(counter, 1u);
+        slot = __shfl(slot, 0);
+        float* e = queue + (int64_t)slot * kQueueWords;
+        e[lane] = __int_as_float(need ? (int)local : -1);
+        e[64 + lane] = T0;
+        e[128 + lane] = TK;
+        e[192 + lane] = a;
+        e[256 + lane] = m;
+        e[320 + lane] = pa;
+        e[384 + lane] = pm;
+    }
+}
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void surrogate_b_kernel(
+    const float* __restrict__ queue, const unsigned* __restrict__ counter, unsigned* __restrict__ counter_next,
+    float ln_dt, float* __restrict__ beta, float* __restrict__ as, float* __restrict__ am,
+    const uint32_t* __restrict__ frag, MlpNorm nrm) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *counter_next = 0u;  // for the next block's pass A
+    __shared__ InferLds L;
+    stage_infer_frag(L, frag);
+    const int lane = threadIdx.x & 63;
+    const unsigned count = *counter;
+    const unsigned n_waves = gridDim.x * (blockDim.x >> 6);
+    for (unsigned q = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; q < count; q += n_waves) {
+        const float* e = queue + (int64_t)q * kQueueWords;
+        const int idx = __float_as_int(e[lane]);
+        const float T0 = e[64 + lane], TK = e[128 + lane], a = e[192 + lane], m = e[256 + lane];
+        const float pa = e[320 + lane], pm = e[384 + lane];
         const float raw[6] = {T0, TK, ln_dt, solid_fraction(T0) - a - m, a, m};
         float x[8], y[3];
         normalise(nrm, raw, x);
-        mlp_wave(F, x, y, lane);
-        if (valid) {
-            float an = a, mn = m, bn;
-            if (!flag) {
-                const float xeqK = alpha_eq(TK);
-                correct(TK, xeqK, an, mn);  // instantaneous changes at the block end
-                an = fmaf(y[0], nrm.out_scale[0], an);
-                mn = fmaf(y[1], nrm.out_scale[1], mn);
-                bn = correct(TK, xeqK, an, mn);
-            } else {
-                float alo = 0.0f, mlo = 0.0f, Tn = T0, xeq_n = alpha_eq(T0);
-                for (int s = 0; s < K; ++s) {
-                    const float Tn1 = scan_temperature<W>(tab + (s + 1) * W, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min);
-                    const float xeq_n1 = alpha_eq(Tn1);
-                    explicit_step<true>(an, mn, alo, mlo, Tn, xeq_n, Tn1, xeq_n1, dt);
-                    Tn = Tn1;
-                    xeq_n = xeq_n1;
-                }
-                an += alo;
-                mn += mlo;
-                bn = solid_fraction(Tn) - an - mn;
-            }
-            as[local] = an;
-            am[local] = mn;
-            beta[local] = bn;
+        mlp_infer(L, x, y, lane);
+        if (idx >= 0) {
+            float an = fmaf(y[0], nrm.out_scale[0], pa), mn = fmaf(y[1], nrm.out_scale[1], pm);
+            const float bn = correct(TK, alpha_eq(TK), an, mn);
+            as[idx] = an;
+            am[idx] = mn;
+            beta[idx] = bn;
         }
     }
 }
 
+__global__ void reset_counters_kernel(unsigned* c) {
+    if (threadIdx.x < 2) c[threadIdx.x] = 0u;
+}
+
+hipError_t surrogate_prepare(MlpState& s, int64_t points, hipStream_t st) {
+    const int64_t need = (points + 63) / 64 + 1;
+    if (need > s.queue_entries) {
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return e;
+        if (s.queue) (void)hipFree(s.queue);
+        s.queue = nullptr;
+        s.queue_entries = 0;
+        if ((e = hipMalloc((void**)&s.queue, (size_t)need * kQueueWords * sizeof(float))) != hipSuccess) return e;
+        s.queue_entries = need;
+    }
+    if (!s.counters) {
+        hipError_t e = hipMalloc((void**)&s.counters, 2 * sizeof(unsigned));
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, st, s.counters);
+    return hipGetLastError();
+}
+
 hipError_t launch_surrogate(const MlpState& s, const PointGeom& pg, int W, const SrcRec* tab, int K, float dt,
-                            ScanArgs sa, float* beta, float* as, float* am, hipStream_t st) {
+                            ScanArgs sa, float* beta, float* as, float* am, int64_t block, hipStream_t st) {
     if (pg.count <= 0) return hipSuccess;
-    const int64_t chunks = (pg.count + 63) / 64;
-    const int64_t blocks = chunks < 8192 ? (chunks + 3) / 4 : 2048;
-    const float ln_dt = logf(dt);
-    const dim3 grid((unsigned)blocks), block(256);
+    unsigned* cur = s.counters + (block & 1);
+    unsigned* nxt = s.counters + ((block + 1) & 1);
+    const dim3 grid((unsigned)((pg.count + 255) / 256)), blk(256);
     switch (W) {
-        case 1: hipLaunchKernelGGL(surrogate_kernel<1>, grid, block, 0, st, pg, tab, K, dt, ln_dt, sa, beta, as, am, s.frag, s.norm); break;
-        case 2: hipLaunchKernelGGL(surrogate_kernel<2>, grid, block, 0, st, pg, tab, K, dt, ln_dt, sa, beta, as, am, s.frag, s.norm); break;
-        case 3: hipLaunchKernelGGL(surrogate_kernel<3>, grid, block, 0, st, pg, tab, K, dt, ln_dt, sa, beta, as, am, s.frag, s.norm); break;
-        case 4: hipLaunchKernelGGL(surrogate_kernel<4>, grid, block, 0, st, pg, tab, K, dt, ln_dt, sa, beta, as, am, s.frag, s.norm); break;
+        case 1: hipLaunchKernelGGL(surrogate_a_kernel<1>, grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur); break;
+        case 2: hipLaunchKernelGGL(surrogate_a_kernel<2>, grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur); break;
+        case 3: hipLaunchKernelGGL(surrogate_a_kernel<3>, grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur); break;
+        case 4: hipLaunchKernelGGL(surrogate_a_kernel<4>, grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur); break;
         default: return hipErrorInvalidValue;
     }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(surrogate_b_kernel, dim3(512), dim3(256), 0, st, s.queue, cur, nxt, logf(dt), beta, as, am,
+                       s.frag, s.norm);
     return hipGetLastError();
 }
 
@@ -541,7 +721,7 @@ hipError_t mlp_alloc(MlpState& s) {
     if ((e = hipMalloc((void**)&s.adam_v, kMlpParams * sizeof(float))) != hipSuccess) return e;
     if ((e = hipMalloc((void**)&s.grad, kMlpParams * sizeof(float))) != hipSuccess) return e;
     if ((e = hipMalloc((void**)&s.loss, sizeof(float))) != hipSuccess) return e;
-    if ((e = hipMalloc((void**)&s.frag, kFragWords * 64 * sizeof(uint32_t))) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&s.frag, kFragTotal * sizeof(uint32_t))) != hipSuccess) return e;
     if ((e = hipMalloc((void**)&s.partial, (size_t)kMaxTrainWaves * (kMlpParams + 1) * sizeof(float))) != hipSuccess)
         return e;
     s.partial_waves = kMaxTrainWaves;
@@ -550,7 +730,7 @@ hipError_t mlp_alloc(MlpState& s) {
 
 void mlp_free(MlpState& s) {
     for (void* p : {(void*)s.master, (void*)s.adam_m, (void*)s.adam_v, (void*)s.grad, (void*)s.loss, (void*)s.frag,
-                    (void*)s.partial})
+                    (void*)s.partial, (void*)s.queue, (void*)s.counters})
         if (p) (void)hipFree(p);
     s = MlpState{};
 }

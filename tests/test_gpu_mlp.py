@@ -119,8 +119,8 @@ def test_training_reduces_loss(torch, ctx):
 
 
 def test_surrogate_mode_with_zero_network(torch, ctx, orc):
-    """Surrogate mode with an all-zero network: unflagged blocks take only the
-    correction at the block-end temperature, flagged ones the plain steps.
+    """Surrogate mode with an all-zero network: unflagged blocks take one
+    explicit step of K dt, flagged ones the K plain steps.
     The result stays within the surrogate tolerance of the oracle and keeps
     the invariants."""
     import paper_2402_17580_amd as ms
