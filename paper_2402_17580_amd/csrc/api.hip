@@ -156,6 +156,7 @@ void split(double g, int32_t& i, float& f) {
 // window slot w at time t: float64 position and timing -> float32 record
 void fill_record(SrcRec& r, const mstruct_scan* sc, const mstruct_points* p, int64_t j, double t) {
     memset(&r, 0, sizeof r);
+    r.lamp = -INFINITY;  // unused slot
     if (j < 0) return;
     const double* tr = sc->tracks + 9 * j;
     const double tau = t - tr[5];
@@ -168,7 +169,7 @@ void fill_record(SrcRec& r, const mstruct_scan* sc, const mstruct_points* p, int
     split((tr[2] - p->oz) / h, r.iz, r.fz);
     r.ux = (float)ux;
     r.uy = (float)uy;
-    r.amp = (float)(q / (4.0 * M_PI * k * h));
+    r.lamp = (float)log2(q / (4.0 * M_PI * k * h));
     r.c1 = (float)(v * h / (2.0 * a) * LOG2E);
     r.vt = (float)(v * tau / h);
     r.is = (float)(h / (2.0 * sqrt(a * tau)));

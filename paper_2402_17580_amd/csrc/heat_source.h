@@ -32,7 +32,7 @@ struct SrcRec {
     int32_t ix, iy, iz;  // integer part of the current source position [grid units]
     float fx, fy, fz;    // fractional part
     float ux, uy;        // unit direction of motion
-    float amp;           // q / (4 pi k h) [K grid]; 0 marks an unused slot
+    float lamp;          // log2(q / (4 pi k h)) [K grid]; -inf marks an unused slot
     float c1;            // v h / (2 alpha) log2(e)
     float vt;            // v tau / h
     float is;            // h / (2 sqrt(alpha tau))
@@ -69,8 +69,11 @@ __device__ __forceinline__ float scaled_erfcx(float y, float lg) {
     return t * fexp2(erfc_poly_log2(t) + lg);
 }
 
-// below this base-2 exponent a term is dropped (2^-40 of the amplitude)
-constexpr float kDropLog2 = -40.0f;
+// A term whose magnitude is provably below 1e-4 K is dropped: every term is
+// rR * (factor <= 2) * 2^(lg + lamp) with rR = 1/R <= 2^(-(e-1)/2) when
+// R^2 = f 2^e, f in [0.5, 1).  Up to four dropped terms per slot change T by
+// less than 4e-4 K.
+constexpr float kLog2DropK = -13.2877f;  // log2(1e-4)
 
 // Contribution of one slot at grid point (gi, gj, gk) (z grid coordinate -gk).
 // Returns +inf when the point is within sqrt(r2min) of the source (clamp applies).
@@ -85,16 +88,18 @@ __device__ __forceinline__ float source_rise(const SrcRec& s, int gi, int gj, in
     const float xi = fmaf(dx, s.ux, dy * s.uy);
     const float cr = fmaf(dx, s.uy, -dy * s.ux);  // in-plane offset across the track
     const float rho2 = fmaf(cr, cr, dz * dz);
+    // threshold on lg + lamp below which a term is negligible
+    const float cut = kLog2DropK - 1.0f + 0.5f * (float)(__builtin_amdgcn_frexp_expf(R2) - 1);
     // xi + R without cancellation behind the source: rho^2 / (R - xi)
     const float xr = xi >= 0.0f ? xi + R : rho2 * frcp(R - xi);
-    const float lg1 = -s.c1 * xr;  // log2 of e^{-v(xi+R)/(2 alpha)} (<= 0)
+    const float lg1 = fmaf(-s.c1, xr, s.lamp);  // log2 of amp e^{-v(xi+R)/(2 alpha)}
 
     // leading term e1 erfc(y1) of the source switched on at P0, minus
     // e1 erfc(y1b) of the virtual source after switch-off; erfc(y) is split
     // as base + sign * E(|y|) with base 2 for y < 0, so that equal bases
     // cancel exactly
     float acc = 0.0f;
-    if (lg1 > kDropLog2) {
+    if (lg1 > cut) {
         const float y1 = (R - s.vt) * s.is;
         const bool n1 = y1 < 0.0f;
         const float E1 = (n1 || y1 < 6.0f) ? scaled_erfc_abs(y1, lg1) : 0.0f;
@@ -109,18 +114,18 @@ __device__ __forceinline__ float source_rise(const SrcRec& s, int gi, int gj, in
         }
         if (base != 0.0f) acc = fmaf(base, fexp2(lg1), acc);
     }
-    // start-point terms
+    // start-point terms (erfcx <= 1)
     {
         const float d = xi + s.vt;
-        const float lg2 = -s.e2 * fmaf(d, d, rho2);
-        if (lg2 > kDropLog2) acc += scaled_erfcx((R + s.vt) * s.is, lg2);
+        const float lg2 = fmaf(-s.e2, fmaf(d, d, rho2), s.lamp);
+        if (lg2 > cut) acc += scaled_erfcx((R + s.vt) * s.is, lg2);
     }
     if (s.is1 > 0.0f) {
         const float d = xi + s.vt1;
-        const float lg2 = -s.e21 * fmaf(d, d, rho2);
-        if (lg2 > kDropLog2) acc -= scaled_erfcx((R + s.vt1) * s.is1, lg2);
+        const float lg2 = fmaf(-s.e21, fmaf(d, d, rho2), s.lamp);
+        if (lg2 > cut) acc -= scaled_erfcx((R + s.vt1) * s.is1, lg2);
     }
-    return s.amp * rR * acc;
+    return rR * acc;
 }
 
 template <int W>
@@ -130,7 +135,7 @@ __device__ __forceinline__ float scan_temperature(const SrcRec* __restrict__ rec
 #pragma unroll
     for (int w = 0; w < W; ++w) {
         const SrcRec s = recs[w];
-        if (s.amp > 0.0f) T += source_rise(s, gi, gj, gk, r2min);
+        if (s.lamp > -1e30f) T += source_rise(s, gi, gj, gk, r2min);
     }
     return fminf(T, Tclamp);
 }

@@ -108,8 +108,9 @@ def test_temperature_matches_oracle(torch, ctx, orc):
             act = xyz[:, 2] <= z_top + 1e-3 * wl.grid.h
             want = np.where(act, want, wl.scan.T0)
             err = np.abs(got - want)
-            # float32 source geometry and erfc (rel. 1.2e-7): well below 1e-5 relative
-            assert np.all(err <= 2e-6 * want + 2e-4), (wl.name, t, float(err.max()))
+            # float32 arithmetic and erfc (rel. 1.2e-7) plus terms dropped by the
+            # kernel when provably below 1e-4 K each (at most 4 per window slot)
+            assert np.all(err <= 2e-6 * want + 6e-4 * wl.scan.window + 2e-4), (wl.name, t, float(err.max()))
 
 
 @pytest.mark.parametrize("K", [1, 7, 16])
