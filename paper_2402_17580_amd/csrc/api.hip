@@ -341,7 +341,7 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
     HIP_CHECK(ctx, hipMemcpyAsync(s->dev, s->host, recs * sizeof(SrcRec), hipMemcpyHostToDevice, st));
     const ScanArgs sa{(float)scan->T0, (float)scan->T_clamp};
     if (mode == MSTRUCT_MODE_SURROGATE) {
-        hipError_t e = surrogate_prepare(ctx->mlp, pg.count, st);
+        hipError_t e = surrogate_prepare(ctx->mlp, pg.first + pg.count, st);
         if (e != hipSuccess) {
             (void)release_slot(ctx, s, st);
             return hip_fail(ctx, e, "surrogate queue");
@@ -354,7 +354,7 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
             e = launch_fused_plain(pg, W, s->dev + s0 * W, Kb, (float)dt, sa, ph->beta, ph->alpha_s, ph->alpha_m, st);
         else
             e = launch_surrogate(ctx->mlp, pg, W, s->dev + s0 * W, Kb, (float)dt, sa, ph->beta, ph->alpha_s,
-                                 ph->alpha_m, s0 / K, st);
+                                 ph->alpha_m, s0 / K, s0 == 0, st);
         if (e != hipSuccess) {
             (void)release_slot(ctx, s, st);
             return hip_fail(ctx, e, "fused launch");

@@ -7,6 +7,9 @@
 namespace mstruct {
 
 constexpr int kBlock = 256;
+#ifndef FUSED_PPT
+#define FUSED_PPT 1
+#endif
 typedef float vf4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void decode_point(const PointGeom& pg, int64_t local, int& gi, int& gj, int& gk) {
@@ -108,31 +111,51 @@ __global__ __launch_bounds__(kBlock) void temperature_kernel(PointGeom pg, const
 // held in registers (with compensated Euler accumulation); tab holds the
 // K + 1 time points x W window slots of this launch.
 // ---------------------------------------------------------------------------
-template <int W>
+template <int W, int PPT>
 __global__ __launch_bounds__(kBlock) void fused_plain_kernel(PointGeom pg, const SrcRec* __restrict__ tab, int K,
                                                             float dt, ScanArgs sa, float* __restrict__ beta,
                                                             float* __restrict__ as, float* __restrict__ am) {
-    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (g >= pg.count) return;
-    const int64_t local = pg.first + g;
-    int gi, gj, gk;
-    decode_point(pg, local, gi, gj, gk);
-    if (gk < pg.k0) return;
-    float a = as[local], m = am[local], alo = 0.0f, mlo = 0.0f;
-    float Tn = scan_temperature<W>(tab, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min);
-    float xeq_n = alpha_eq(Tn);
-    for (int s = 0; s < K; ++s) {
-        const float Tn1 = scan_temperature<W>(tab + (s + 1) * W, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min);
-        const float xeq_n1 = alpha_eq(Tn1);
-        explicit_step<true>(a, m, alo, mlo, Tn, xeq_n, Tn1, xeq_n1, dt);
-        Tn = Tn1;
-        xeq_n = xeq_n1;
+    // PPT points per lane, kBlock apart (coalesced), advanced together for ILP
+    const int64_t g0 = (int64_t)blockIdx.x * kBlock * PPT + threadIdx.x;
+    int64_t local[PPT];
+    int gi[PPT], gj[PPT], gk[PPT];
+    bool act[PPT];
+    float a[PPT], m[PPT], alo[PPT], mlo[PPT], Tn[PPT], xeq_n[PPT];
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+        const int64_t g = g0 + u * kBlock;
+        act[u] = g < pg.count;
+        local[u] = pg.first + (act[u] ? g : 0);
+        decode_point(pg, local[u], gi[u], gj[u], gk[u]);
+        act[u] = act[u] && gk[u] >= pg.k0;
+        a[u] = act[u] ? as[local[u]] : 0.0f;
+        m[u] = act[u] ? am[local[u]] : 0.0f;
+        alo[u] = 0.0f;
+        mlo[u] = 0.0f;
     }
-    a += alo;
-    m += mlo;
-    as[local] = a;
-    am[local] = m;
-    beta[local] = solid_fraction(Tn) - a - m;
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+        Tn[u] = scan_temperature<W>(tab, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min);
+        xeq_n[u] = alpha_eq(Tn[u]);
+    }
+    for (int s = 0; s < K; ++s) {
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+            const float Tn1 = scan_temperature<W>(tab + (s + 1) * W, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min);
+            const float xeq_n1 = alpha_eq(Tn1);
+            explicit_step<true>(a[u], m[u], alo[u], mlo[u], Tn[u], xeq_n[u], Tn1, xeq_n1, dt);
+            Tn[u] = Tn1;
+            xeq_n[u] = xeq_n1;
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+        if (!act[u]) continue;
+        const float af = a[u] + alo[u], mf = m[u] + mlo[u];
+        as[local[u]] = af;
+        am[local[u]] = mf;
+        beta[local[u]] = solid_fraction(Tn[u]) - af - mf;
+    }
 }
 
 hipError_t launch_temperature(const PointGeom& pg, int W, const SrcRec* rec, ScanArgs sa, float* T,
@@ -149,15 +172,17 @@ hipError_t launch_temperature(const PointGeom& pg, int W, const SrcRec* rec, Sca
     return hipGetLastError();
 }
 
+constexpr int kFusedPPT = FUSED_PPT;
+
 hipError_t launch_fused_plain(const PointGeom& pg, int W, const SrcRec* tab, int K, float dt, ScanArgs sa,
                               float* beta, float* as, float* am, hipStream_t st) {
     if (pg.count <= 0) return hipSuccess;
-    const dim3 grid((unsigned)((pg.count + kBlock - 1) / kBlock)), block(kBlock);
+    const dim3 grid((unsigned)((pg.count + kBlock * kFusedPPT - 1) / (kBlock * kFusedPPT))), block(kBlock);
     switch (W) {
-        case 1: hipLaunchKernelGGL(fused_plain_kernel<1>, grid, block, 0, st, pg, tab, K, dt, sa, beta, as, am); break;
-        case 2: hipLaunchKernelGGL(fused_plain_kernel<2>, grid, block, 0, st, pg, tab, K, dt, sa, beta, as, am); break;
-        case 3: hipLaunchKernelGGL(fused_plain_kernel<3>, grid, block, 0, st, pg, tab, K, dt, sa, beta, as, am); break;
-        case 4: hipLaunchKernelGGL(fused_plain_kernel<4>, grid, block, 0, st, pg, tab, K, dt, sa, beta, as, am); break;
+        case 1: hipLaunchKernelGGL((fused_plain_kernel<1, kFusedPPT>), grid, block, 0, st, pg, tab, K, dt, sa, beta, as, am); break;
+        case 2: hipLaunchKernelGGL((fused_plain_kernel<2, kFusedPPT>), grid, block, 0, st, pg, tab, K, dt, sa, beta, as, am); break;
+        case 3: hipLaunchKernelGGL((fused_plain_kernel<3, kFusedPPT>), grid, block, 0, st, pg, tab, K, dt, sa, beta, as, am); break;
+        case 4: hipLaunchKernelGGL((fused_plain_kernel<4, kFusedPPT>), grid, block, 0, st, pg, tab, K, dt, sa, beta, as, am); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

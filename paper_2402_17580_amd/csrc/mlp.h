@@ -58,6 +58,10 @@ struct MlpState {
     float* queue = nullptr;
     int64_t queue_entries = 0;
     unsigned* counters = nullptr;
+    // block-end temperatures of the previous surrogate block of a call (the
+    // next block's start temperatures), indexed by local point number
+    float* tcache = nullptr;
+    int64_t tcache_n = 0;
 };
 
 constexpr int kQueueWords = 7 * 64;  // index, T0, TK, alpha_s, alpha_m, pre_alpha_s, pre_alpha_m
@@ -71,7 +75,8 @@ hipError_t mlp_grad(MlpState& s, const float* X, const float* Y, int64_t B, floa
 hipError_t mlp_adam(MlpState& s, float lr, hipStream_t st);
 hipError_t surrogate_prepare(MlpState& s, int64_t points, hipStream_t st);
 hipError_t launch_surrogate(const MlpState& s, const PointGeom& pg, int W, const SrcRec* tab, int K, float dt,
-                            ScanArgs sa, float* beta, float* as, float* am, int64_t block, hipStream_t st);
+                            ScanArgs sa, float* beta, float* as, float* am, int64_t block, bool first_block,
+                            hipStream_t st);
 hipError_t launch_correct(const float* T, float* beta, float* as, float* am, int64_t n, hipStream_t st);
 
 }  // namespace mstruct

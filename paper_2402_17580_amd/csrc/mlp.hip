@@ -16,6 +16,10 @@
 // registers become the B operand as they are.
 #include "mlp.h"
 
+#ifndef SURROGATE_PPT
+#define SURROGATE_PPT 2
+#endif
+
 namespace mstruct {
 
 typedef short s4 __attribute__((ext_vector_type(4)));
@@ -553,72 +557,94 @@ __device__ __forceinline__ bool needs_plain(float T0, float TK, const MlpNorm& n
     return !(cold || hot) || fabsf(TK - T0) > n.dT_max;
 }
 
-template <int W>
+template <int W, int PPT>
 __global__ __launch_bounds__(256) void surrogate_a_kernel(PointGeom pg, const SrcRec* __restrict__ tab, int K,
                                                          float dt, ScanArgs sa, float* __restrict__ beta,
                                                          float* __restrict__ as, float* __restrict__ am,
                                                          MlpNorm nrm, float* __restrict__ queue,
-                                                         unsigned* __restrict__ counter) {
+                                                         unsigned* __restrict__ counter,
+                                                         const float* __restrict__ tin, float* __restrict__ tout) {
+    // PPT points per lane, 256 apart (coalesced); their loads are issued
+    // together and their temperatures computed side by side.  tin (may be
+    // null) holds the block-start temperatures; tout receives the block-end ones
     const int lane = threadIdx.x & 63;
-    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    bool valid = g < pg.count;
-    const int64_t local = pg.first + (valid ? g : 0);
-    int gi = 0, gj = 0, gk = 0;
-    if (valid) {
-        const int lin = pg.index ? pg.index[local] : (int)local;
-        gk = lin / pg.nxy;
-        const int rem = lin - gk * pg.nxy;
-        gj = rem / pg.nx;
-        gi = rem - gj * pg.nx;
-        valid = gk >= pg.k0;
-    }
-    float a = 0.0f, m = 0.0f, T0 = sa.T0, TK = sa.T0, pa = 0.0f, pm = 0.0f;
-    bool need = false;
-    if (valid) {
-        a = as[local];
-        m = am[local];
-        T0 = scan_temperature<W>(tab, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min);
-        TK = scan_temperature<W>(tab + K * W, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min);
-        float an = a, mn = m, bn;
-        const float xeq0 = alpha_eq(T0);
-        if (needs_plain(T0, TK, nrm)) {
-            float alo = 0.0f, mlo = 0.0f, Tn = T0, xeq_n = xeq0;
-            for (int s = 0; s < K; ++s) {
-                const float Tn1 = scan_temperature<W>(tab + (s + 1) * W, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min);
-                const float xeq_n1 = alpha_eq(Tn1);
-                explicit_step<true>(an, mn, alo, mlo, Tn, xeq_n, Tn1, xeq_n1, dt);
-                Tn = Tn1;
-                xeq_n = xeq_n1;
-            }
-            an += alo;
-            mn += mlo;
-            bn = solid_fraction(Tn) - an - mn;
-        } else {
-            float da, dm;
-            diffusive_increment(a, m, T0, xeq0, dt * (float)K, da, dm);
-            pa = a + da;
-            pm = m + dm;
-            need = (da != 0.0f) || (dm != 0.0f);
-            an = pa;
-            mn = pm;
-            bn = correct(TK, alpha_eq(TK), an, mn);
+    const int64_t g0 = (int64_t)blockIdx.x * 256 * PPT + threadIdx.x;
+    int64_t local[PPT];
+    int gi[PPT], gj[PPT], gk[PPT];
+    bool valid[PPT];
+    float a[PPT], m[PPT];
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+        const int64_t g = g0 + u * 256;
+        valid[u] = g < pg.count;
+        local[u] = pg.first + (valid[u] ? g : 0);
+        gi[u] = gj[u] = gk[u] = 0;
+        if (valid[u]) {
+            const int lin = pg.index ? pg.index[local[u]] : (int)local[u];
+            gk[u] = lin / pg.nxy;
+            const int rem = lin - gk[u] * pg.nxy;
+            gj[u] = rem / pg.nx;
+            gi[u] = rem - gj[u] * pg.nx;
+            valid[u] = gk[u] >= pg.k0;
         }
-        as[local] = an;
-        am[local] = mn;
-        beta[local] = bn;
+        a[u] = valid[u] ? as[local[u]] : 0.0f;
+        m[u] = valid[u] ? am[local[u]] : 0.0f;
     }
-    if (__ballot(need) != 0) {
-        unsigned slot = 0;
-        if (lane == 0) slot = atomicAdd(counter, 1u);
-        slot = __shfl(slot, 0);
-        float* e = queue + (int64_t)slot * kQueueWords;
-        e[lane] = __int_as_float(need ? (int)local : -1);
-        e[64 + lane] = T0;
-        e[128 + lane] = TK;
-        e[192 + lane] = a;
-        e[256 + lane] = m;
-        e[320 + lane] = pa;
-        e[384 + lane] = pm;
+    float T0[PPT], TK[PPT];
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+        T0[u] = !valid[u] ? sa.T0
+                          : (tin ? tin[local[u]] : scan_temperature<W>(tab, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min));
+        TK[u] = valid[u] ? scan_temperature<W>(tab + K * W, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min) : sa.T0;
+        if (valid[u]) tout[local[u]] = TK[u];
+    }
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+        float pa = 0.0f, pm = 0.0f;
+        bool need = false;
+        if (valid[u]) {
+            float an = a[u], mn = m[u], bn;
+            const float xeq0 = alpha_eq(T0[u]);
+            if (needs_plain(T0[u], TK[u], nrm)) {
+                float alo = 0.0f, mlo = 0.0f, Tn = T0[u], xeq_n = xeq0;
+                for (int s = 0; s < K; ++s) {
+                    const float Tn1 =
+                        scan_temperature<W>(tab + (s + 1) * W, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min);
+                    const float xeq_n1 = alpha_eq(Tn1);
+                    explicit_step<true>(an, mn, alo, mlo, Tn, xeq_n, Tn1, xeq_n1, dt);
+                    Tn = Tn1;
+                    xeq_n = xeq_n1;
+                }
+                an += alo;
+                mn += mlo;
+                bn = solid_fraction(Tn) - an - mn;
+            } else {
+                float da, dm;
+                diffusive_increment(a[u], m[u], T0[u], xeq0, dt * (float)K, da, dm);
+                pa = a[u] + da;
+                pm = m[u] + dm;
+                need = (da != 0.0f) || (dm != 0.0f);
+                an = pa;
+                mn = pm;
+                bn = correct(TK[u], alpha_eq(TK[u]), an, mn);
+            }
+            as[local[u]] = an;
+            am[local[u]] = mn;
+            beta[local[u]] = bn;
+        }
+        if (__ballot(need) != 0) {
+            unsigned slot = 0;
+            if (lane == 0) slot = atomicAdd(counter, 1u);
+            slot = __shfl(slot, 0);
+            float* e = queue + (int64_t)slot * kQueueWords;
+            e[lane] = __int_as_float(need ? (int)local[u] : -1);
+            e[64 + lane] = T0[u];
+            e[128 + lane] = TK[u];
+            e[192 + lane] = a[u];
+            e[256 + lane] = m[u];
+            e[320 + lane] = pa;
+            e[384 + lane] = pm;
+        }
     }
 }
 
@@ -656,7 +682,17 @@ __global__ void reset_counters_kernel(unsigned* c) {
 }
 
 hipError_t surrogate_prepare(MlpState& s, int64_t points, hipStream_t st) {
-    const int64_t need = (points + 63) / 64 + 1;
+    if (points > s.tcache_n) {
+        hipError_t e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return e;
+        if (s.tcache) (void)hipFree(s.tcache);
+        s.tcache = nullptr;
+        s.tcache_n = 0;
+        if ((e = hipMalloc((void**)&s.tcache, (size_t)points * sizeof(float))) != hipSuccess) return e;
+        s.tcache_n = points;
+    }
+    // at most one queue entry per wave and point group of pass A
+    const int64_t need = (points + 63) / 64 + SURROGATE_PPT + 1;
     if (need > s.queue_entries) {
         hipError_t e = hipStreamSynchronize(st);
         if (e != hipSuccess) return e;
@@ -675,21 +711,24 @@ hipError_t surrogate_prepare(MlpState& s, int64_t points, hipStream_t st) {
 }
 
 hipError_t launch_surrogate(const MlpState& s, const PointGeom& pg, int W, const SrcRec* tab, int K, float dt,
-                            ScanArgs sa, float* beta, float* as, float* am, int64_t block, hipStream_t st) {
+                            ScanArgs sa, float* beta, float* as, float* am, int64_t block, bool first_block,
+                            hipStream_t st) {
+    const float* tin = first_block ? nullptr : s.tcache;
     if (pg.count <= 0) return hipSuccess;
     unsigned* cur = s.counters + (block & 1);
     unsigned* nxt = s.counters + ((block + 1) & 1);
-    const dim3 grid((unsigned)((pg.count + 255) / 256)), blk(256);
+    constexpr int P = SURROGATE_PPT;
+    const dim3 grid((unsigned)((pg.count + 256 * P - 1) / (256 * P))), blk(256);
     switch (W) {
-        case 1: hipLaunchKernelGGL(surrogate_a_kernel<1>, grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur); break;
-        case 2: hipLaunchKernelGGL(surrogate_a_kernel<2>, grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur); break;
-        case 3: hipLaunchKernelGGL(surrogate_a_kernel<3>, grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur); break;
-        case 4: hipLaunchKernelGGL(surrogate_a_kernel<4>, grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur); break;
+        case 1: hipLaunchKernelGGL((surrogate_a_kernel<1, P>), grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, s.tcache); break;
+        case 2: hipLaunchKernelGGL((surrogate_a_kernel<2, P>), grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, s.tcache); break;
+        case 3: hipLaunchKernelGGL((surrogate_a_kernel<3, P>), grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, s.tcache); break;
+        case 4: hipLaunchKernelGGL((surrogate_a_kernel<4, P>), grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, s.tcache); break;
         default: return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(surrogate_b_kernel, dim3(512), dim3(256), 0, st, s.queue, cur, nxt, logf(dt), beta, as, am,
+    hipLaunchKernelGGL(surrogate_b_kernel, dim3(256), dim3(256), 0, st, s.queue, cur, nxt, logf(dt), beta, as, am,
                        s.frag, s.norm);
     return hipGetLastError();
 }
@@ -730,7 +769,7 @@ hipError_t mlp_alloc(MlpState& s) {
 
 void mlp_free(MlpState& s) {
     for (void* p : {(void*)s.master, (void*)s.adam_m, (void*)s.adam_v, (void*)s.grad, (void*)s.loss, (void*)s.frag,
-                    (void*)s.partial, (void*)s.queue, (void*)s.counters})
+                    (void*)s.partial, (void*)s.queue, (void*)s.counters, (void*)s.tcache})
         if (p) (void)hipFree(p);
     s = MlpState{};
 }
