@@ -35,8 +35,11 @@ K_SURROGATE = 8
 STEP_BYTES = 28  # plain step: reads alpha_s, alpha_m, T^n, T^{n+1}; writes beta, alpha_s, alpha_m (float32)
 
 
-def fused_bytes_per_update(K):
-    return 20.0 / K  # per launch: read alpha_s, alpha_m; write beta, alpha_s, alpha_m (float32)
+def fused_bytes_per_point(launches, calls):
+    """Algorithmic HBM bytes per active point and fused launch: every launch
+    reads and writes alpha_s, alpha_m (16 B); the last launch of each call also
+    writes beta (4 B)."""
+    return 16.0 + 4.0 * calls / launches
 
 
 def parse():
@@ -102,7 +105,7 @@ def main():
     # kernel is the only kernel in it besides three state resets per step)
     avg_launch_s = ms_total * 1e-3 / (args.steps * launches)
     upd_per_launch = updates / launches
-    bytes_per_launch = fused_bytes_per_update(args.K) * upd_per_launch
+    bytes_per_launch = fused_bytes_per_point(launches, len(wl.layers)) * upd_per_launch / args.K
 
     result = {
         "metric": "microstructure point-updates/s @8.4M pts (256x256x128 block, 10 layers, 20k steps): FP32 plain",
@@ -143,27 +146,29 @@ def main():
     }
     final_state = [x.clone() for x in (b, a, m)]
 
-    sur_state = None
+    sur_states = {}
     if not args.no_surrogate:
         from paper_2402_17580_amd import surrogate as S
-        t_tr = 0.0
-        if os.path.exists(S.DEFAULT_WEIGHTS):
-            sur = S.Surrogate.load(S.DEFAULT_WEIGHTS)
-        else:
-            t0 = time.perf_counter()
-            X, Y = S.generate_transitions(ctx, wl, K=K_SURROGATE)
-            sur, _ = S.fit(ctx, X, Y, K_SURROGATE)
-            t_tr = time.perf_counter() - t0
-        sur.load_into(ctx)
-        ms_sur, _ = timed(ms.MODE_SURROGATE, sur.K)
-        sur_state = [x.clone() for x in (b, a, m)]
-        result["surrogate"] = {
-            "value": updates * args.steps / (ms_sur * 1e-3), "unit": "point-updates/s",
-            "ms_per_step": ms_sur / args.steps, "speedup_vs_plain": ms_total / ms_sur, "K": sur.K,
-            "path": "mstruct_fused_scan_steps, SURROGATE: one explicit step of K dt + BF16-MFMA network "
-                    "correction where the indicator allows, K plain steps elsewhere",
-            "indicator": list(sur.indicator), "trained_in_bench_s": t_tr,
-        }
+        for key, path in (("surrogate", S.DEFAULT_WEIGHTS), ("surrogate_k16", S.WEIGHTS_K16)):
+            t_tr = 0.0
+            if os.path.exists(path):
+                sur = S.Surrogate.load(path)
+            else:
+                K_s = K_SURROGATE if key == "surrogate" else 16
+                t0 = time.perf_counter()
+                X, Y = S.generate_transitions(ctx, wl, K=K_s)
+                sur, _ = S.fit(ctx, X, Y, K_s)
+                t_tr = time.perf_counter() - t0
+            sur.load_into(ctx)
+            ms_sur, _ = timed(ms.MODE_SURROGATE, sur.K)
+            sur_states[key] = [x.clone() for x in (b, a, m)]
+            result[key] = {
+                "value": updates * args.steps / (ms_sur * 1e-3), "unit": "point-updates/s",
+                "ms_per_step": ms_sur / args.steps, "speedup_vs_plain": ms_total / ms_sur, "K": sur.K,
+                "path": "mstruct_fused_scan_steps, SURROGATE: one explicit step of K dt + BF16-MFMA network "
+                        "correction where the indicator allows, K plain steps elsewhere",
+                "indicator": list(sur.indicator), "trained_in_bench_s": t_tr,
+            }
 
     if not args.no_stepwise:
         result["plain_step"] = bench_stepwise(torch, ms, ctx, wl, dev)
@@ -181,8 +186,8 @@ def main():
         base, st, idx = cpu_baseline(wl, args)
         result["cpu_baseline"] = base
         result["errors_vs_oracle"] = errors(final_state, st, idx)
-        if sur_state is not None:
-            result["surrogate"]["errors_vs_oracle"] = errors(sur_state, st, idx)
+        for key, state in sur_states.items():
+            result[key]["errors_vs_oracle"] = errors(state, st, idx)
 
     print(json.dumps(result))
     ctx.close()

@@ -124,7 +124,8 @@ int mstruct_temperature(mstruct_ctx *ctx, const mstruct_scan *scan, const mstruc
  * indicator flags the point (temperature window touching the martensite
  * start, beta-transus or melting bands, or a start-up state), which get the
  * K plain steps; requires weights loaded with mstruct_mlp_set_params.
- * K in 1..64.  pts->n must equal ph->n. */
+ * K in 1..64.  pts->n must equal ph->n.  Inside a call beta is not read and
+ * is written once, by the last launch (it follows from the sum rule). */
 int mstruct_fused_scan_steps(mstruct_ctx *ctx, const mstruct_scan *scan, const mstruct_points *pts,
                              double t0, double dt, int64_t n_steps, int K, int mode,
                              const mstruct_phases *ph, void *stream);

@@ -349,12 +349,15 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
     }
     for (int64_t s0 = 0; s0 < n_steps; s0 += K) {
         const int Kb = (int)((n_steps - s0) < K ? (n_steps - s0) : K);
+        const bool last = s0 + Kb >= n_steps;
+        // beta is written by the last launch only (no kernel reads it)
+        float* beta = last ? ph->beta : nullptr;
         hipError_t e;
         if (mode == MSTRUCT_MODE_PLAIN)
-            e = launch_fused_plain(pg, W, s->dev + s0 * W, Kb, (float)dt, sa, ph->beta, ph->alpha_s, ph->alpha_m, st);
+            e = launch_fused_plain(pg, W, s->dev + s0 * W, Kb, (float)dt, sa, beta, ph->alpha_s, ph->alpha_m, st);
         else
             e = launch_surrogate(ctx->mlp, pg, W, s->dev + s0 * W, Kb, (float)dt, sa, ph->beta, ph->alpha_s,
-                                 ph->alpha_m, s0 / K, s0 == 0, st);
+                                 ph->alpha_m, s0 / K, s0 == 0, last, st);
         if (e != hipSuccess) {
             (void)release_slot(ctx, s, st);
             return hip_fail(ctx, e, "fused launch");

@@ -115,6 +115,8 @@ template <int W, int PPT>
 __global__ __launch_bounds__(kBlock) void fused_plain_kernel(PointGeom pg, const SrcRec* __restrict__ tab, int K,
                                                             float dt, ScanArgs sa, float* __restrict__ beta,
                                                             float* __restrict__ as, float* __restrict__ am) {
+    // beta == nullptr: not written (inside a call only the last launch writes
+    // it; no kernel reads beta, it follows from the sum rule)
     // PPT points per lane, kBlock apart (coalesced), advanced together for ILP
     const int64_t g0 = (int64_t)blockIdx.x * kBlock * PPT + threadIdx.x;
     int64_t local[PPT];
@@ -154,7 +156,7 @@ __global__ __launch_bounds__(kBlock) void fused_plain_kernel(PointGeom pg, const
         const float af = a[u] + alo[u], mf = m[u] + mlo[u];
         as[local[u]] = af;
         am[local[u]] = mf;
-        beta[local[u]] = solid_fraction(Tn[u]) - af - mf;
+        if (beta) beta[local[u]] = solid_fraction(Tn[u]) - af - mf;
     }
 }
 

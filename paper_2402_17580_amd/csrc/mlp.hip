@@ -572,31 +572,41 @@ __global__ __launch_bounds__(256) void surrogate_a_kernel(PointGeom pg, const Sr
     int64_t local[PPT];
     int gi[PPT], gj[PPT], gk[PPT];
     bool valid[PPT];
-    float a[PPT], m[PPT];
+    float a[PPT], m[PPT], T0[PPT], TK[PPT];
+    // indices, then every load issued before any arithmetic that needs it
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
         const int64_t g = g0 + u * 256;
         valid[u] = g < pg.count;
         local[u] = pg.first + (valid[u] ? g : 0);
-        gi[u] = gj[u] = gk[u] = 0;
-        if (valid[u]) {
-            const int lin = pg.index ? pg.index[local[u]] : (int)local[u];
-            gk[u] = lin / pg.nxy;
-            const int rem = lin - gk[u] * pg.nxy;
-            gj[u] = rem / pg.nx;
-            gi[u] = rem - gj[u] * pg.nx;
-            valid[u] = gk[u] >= pg.k0;
-        }
-        a[u] = valid[u] ? as[local[u]] : 0.0f;
-        m[u] = valid[u] ? am[local[u]] : 0.0f;
+        const int lin = pg.index ? pg.index[local[u]] : (int)local[u];
+        gk[u] = lin / pg.nxy;
+        const int rem = lin - gk[u] * pg.nxy;
+        gj[u] = rem / pg.nx;
+        gi[u] = rem - gj[u] * pg.nx;
+        valid[u] = valid[u] && gk[u] >= pg.k0;
     }
-    float T0[PPT], TK[PPT];
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
-        T0[u] = !valid[u] ? sa.T0
-                          : (tin ? tin[local[u]] : scan_temperature<W>(tab, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min));
-        TK[u] = valid[u] ? scan_temperature<W>(tab + K * W, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min) : sa.T0;
-        if (valid[u]) tout[local[u]] = TK[u];
+        a[u] = as[local[u]];
+        m[u] = am[local[u]];
+        T0[u] = tin ? tin[local[u]] : 0.0f;
+    }
+    // block-end temperature: independent of the loads above
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) TK[u] = scan_temperature<W>(tab + K * W, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min);
+    if (!tin) {
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) T0[u] = scan_temperature<W>(tab, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min);
+    }
+#pragma unroll
+    for (int u = 0; u < PPT; ++u) {
+        if (valid[u]) {
+            if (tout) tout[local[u]] = TK[u];
+        } else {
+            a[u] = m[u] = 0.0f;
+            T0[u] = TK[u] = sa.T0;
+        }
     }
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
@@ -630,7 +640,7 @@ __global__ __launch_bounds__(256) void surrogate_a_kernel(PointGeom pg, const Sr
             }
             as[local[u]] = an;
             am[local[u]] = mn;
-            beta[local[u]] = bn;
+            if (beta) beta[local[u]] = bn;
         }
         if (__ballot(need) != 0) {
             unsigned slot = 0;
@@ -672,7 +682,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void s
             const float bn = correct(TK, alpha_eq(TK), an, mn);
             as[idx] = an;
             am[idx] = mn;
-            beta[idx] = bn;
+            if (beta) beta[idx] = bn;
         }
     }
 }
@@ -712,18 +722,20 @@ hipError_t surrogate_prepare(MlpState& s, int64_t points, hipStream_t st) {
 
 hipError_t launch_surrogate(const MlpState& s, const PointGeom& pg, int W, const SrcRec* tab, int K, float dt,
                             ScanArgs sa, float* beta, float* as, float* am, int64_t block, bool first_block,
-                            hipStream_t st) {
+                            bool last_block, hipStream_t st) {
     const float* tin = first_block ? nullptr : s.tcache;
+    float* tout = last_block ? nullptr : s.tcache;
+    if (!last_block) beta = nullptr;
     if (pg.count <= 0) return hipSuccess;
     unsigned* cur = s.counters + (block & 1);
     unsigned* nxt = s.counters + ((block + 1) & 1);
     constexpr int P = SURROGATE_PPT;
     const dim3 grid((unsigned)((pg.count + 256 * P - 1) / (256 * P))), blk(256);
     switch (W) {
-        case 1: hipLaunchKernelGGL((surrogate_a_kernel<1, P>), grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, s.tcache); break;
-        case 2: hipLaunchKernelGGL((surrogate_a_kernel<2, P>), grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, s.tcache); break;
-        case 3: hipLaunchKernelGGL((surrogate_a_kernel<3, P>), grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, s.tcache); break;
-        case 4: hipLaunchKernelGGL((surrogate_a_kernel<4, P>), grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, s.tcache); break;
+        case 1: hipLaunchKernelGGL((surrogate_a_kernel<1, P>), grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, tout); break;
+        case 2: hipLaunchKernelGGL((surrogate_a_kernel<2, P>), grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, tout); break;
+        case 3: hipLaunchKernelGGL((surrogate_a_kernel<3, P>), grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, tout); break;
+        case 4: hipLaunchKernelGGL((surrogate_a_kernel<4, P>), grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, tout); break;
         default: return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();

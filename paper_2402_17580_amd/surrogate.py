@@ -25,7 +25,8 @@ import paper_2402_17580_amd as ms
 T_COLD, T_HOT_LO, T_HOT_HI, DT_MAX = 823.0, 1398.0, 1853.0, 50.0
 INDICATOR = (T_COLD, T_HOT_LO, T_HOT_HI, DT_MAX)
 HERE = os.path.dirname(os.path.abspath(__file__))
-DEFAULT_WEIGHTS = os.path.join(HERE, "surrogate_multilayer_block.npz")
+DEFAULT_WEIGHTS = os.path.join(HERE, "surrogate_multilayer_block.npz")  # K = 8
+WEIGHTS_K16 = os.path.join(HERE, "surrogate_multilayer_block_k16.npz")
 
 
 @dataclasses.dataclass
