@@ -139,6 +139,42 @@ def _transitions(ctx, wl, L, idx, b, a, m, T0, TK, t_s, dtp, K):
     return X, Y
 
 
+def ramp_transitions(ctx, n, K=8, T_range=(600.0, 820.0), dT=40.0, dts=(1e-3, 4e-3, 16e-3), seed=0):
+    """Transitions of a cool-down regime: over a block of K steps the
+    temperature is linear in time from T0 to TK, both inside the network's
+    cold band; states are seeded random solid states.  The target is the
+    difference between K plain steps (``mstruct_step`` per sub-step) and one
+    explicit step of K dt.  Returns X [n, 6], Y [n, 3] (float32, GPU)."""
+    import torch
+    dev = torch.device("cuda")
+    rng = np.random.default_rng(seed)
+    T0 = rng.uniform(T_range[0], T_range[1], n)
+    TK = np.clip(T0 + rng.uniform(-dT, dT, n), T_range[0], T_range[1])
+    dt = np.asarray(dts, np.float64)[rng.integers(0, len(dts), n)]
+    am = rng.uniform(0.0, 0.9, n)
+    am[rng.random(n) < 0.25] = 0.0
+    a_s = rng.uniform(0.0, 1.0, n) * (0.9 - am)
+    beta = 1.0 - a_s - am
+    X = torch.empty(n, 6, device=dev)
+    Y = torch.empty(n, 3, device=dev)
+    f32 = lambda v: torch.from_numpy(np.ascontiguousarray(v, np.float32)).to(dev)
+    for d in dts:
+        sel = np.nonzero(dt == d)[0]
+        if sel.size == 0:
+            continue
+        t0, tk = T0[sel], TK[sel]
+        start = [f32(v[sel]) for v in (beta, a_s, am)]
+        small = [x.clone() for x in start]
+        for s in range(K):
+            ctx.step(f32(t0 + (tk - t0) * s / K), f32(t0 + (tk - t0) * (s + 1) / K), float(d), *small)
+        big = [x.clone() for x in start]
+        ctx.step(f32(t0), f32(tk), float(d) * K, *big)
+        it = torch.from_numpy(sel).to(dev)
+        X[it] = torch.stack([f32(t0), f32(tk), torch.full_like(start[0], math.log(d)), *start], 1)
+        Y[it] = torch.stack([small[1] - big[1], small[2] - big[2], small[0] - big[0]], 1)
+    return X, Y
+
+
 def corrections_only_delta(ctx, X, K):
     """Change of (alpha_s, alpha_m, beta) that the correction g at the block
     start and end temperatures alone gives, relative to one explicit step of

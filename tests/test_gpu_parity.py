@@ -217,3 +217,27 @@ def test_fused_argument_errors(torch, ctx):
     before = g[1].clone()
     ctx.fused_scan_steps(wl.scan, wl.grid, 0.0, 1e-6, 0, 16, *g)
     assert torch.equal(before, g[1])
+
+
+def test_cantilever_islands_full_size_sampled(torch, ctx, orc):
+    """The masked workload at full size: a seeded cantilever-like body of
+    32.4M points (int32 index list into a 1024x512x128 box), 5x5 mm island
+    scan with seeded rotation, 10 layers x 5,000 steps of 2 us, K = 16.  A
+    seeded 0.1 % sample of the index list against the oracle."""
+    import paper_2402_17580_amd as ms
+    wl = workload.cantilever_islands()
+    n = wl.grid.n
+    g = _state(torch, n)
+    it = torch.from_numpy(wl.grid.index).cuda()
+    print("cantilever_islands", n, "points", flush=True)
+    ms.run_layers(ctx, wl, *g, K=16, index=it)
+    torch.cuda.synchronize()
+    idx = workload.sample_indices(n, 1e-3, wl.seed)
+    st = orc.run_workload(wl, idx)
+    err = _errors(torch, g, st, idx)
+    print("cantilever islands sample", idx.size, err)
+    for k, (mx, rms) in err.items():
+        assert mx <= RUN_TOL, (k, err)
+    # the scan transformed part of the sample (martensite formed under the tracks)
+    assert float(st.alpha_m.max()) > 0.1
+    assert ctx.check_invariants(*g, tol=2e-6) == 0
