@@ -71,8 +71,10 @@ __device__ __forceinline__ float scaled_erfcx(float y, float lg) {
 
 // A term whose magnitude is provably below 1e-4 K is dropped: every term is
 // rR * (factor <= 2) * 2^(lg + lamp) with rR = 1/R <= 2^(-(e-1)/2) when
-// R^2 = f 2^e, f in [0.5, 1).  Up to four dropped terms per slot change T by
-// less than 4e-4 K.
+// R^2 = f 2^e, f in [0.5, 1).  The small part E(|y|) of an erfc is bounded by
+// e^{-y^2} (erfc(z) <= e^{-z^2} for z >= 0) and dropped on the same test.  Up
+// to four dropped terms per slot (E1, Eb, the two start-point terms, or the
+// whole leading term) change T by less than 4e-4 K.
 constexpr float kLog2DropK = -13.2877f;  // log2(1e-4)
 
 // Contribution of one slot at grid point (gi, gj, gk) (z grid coordinate -gk).
@@ -102,14 +104,18 @@ __device__ __forceinline__ float source_rise(const SrcRec& s, int gi, int gj, in
     if (lg1 > cut) {
         const float y1 = (R - s.vt) * s.is;
         const bool n1 = y1 < 0.0f;
-        const float E1 = (n1 || y1 < 6.0f) ? scaled_erfc_abs(y1, lg1) : 0.0f;
         float base = n1 ? 2.0f : 0.0f;
-        acc = n1 ? -E1 : E1;
+        if (fmaf(-y1 * y1, kLog2e, lg1) > cut) {
+            const float E1 = scaled_erfc_abs(y1, lg1);
+            acc = n1 ? -E1 : E1;
+        }
         if (s.is1 > 0.0f) {
             const float y1b = (R - s.vt1) * s.is1;
             const bool nb = y1b < 0.0f;
-            const float Eb = (nb || y1b < 6.0f) ? scaled_erfc_abs(y1b, lg1) : 0.0f;
-            acc -= nb ? -Eb : Eb;
+            if (fmaf(-y1b * y1b, kLog2e, lg1) > cut) {
+                const float Eb = scaled_erfc_abs(y1b, lg1);
+                acc -= nb ? -Eb : Eb;
+            }
             base -= nb ? 2.0f : 0.0f;
         }
         if (base != 0.0f) acc = fmaf(base, fexp2(lg1), acc);

@@ -62,6 +62,7 @@ struct MlpState {
     // next block's start temperatures), indexed by local point number
     float* tcache = nullptr;
     int64_t tcache_n = 0;
+    int cu_count = 0;  // compute units of the context's device (pass A grid)
 };
 
 constexpr int kQueueWords = 7 * 64;  // index, T0, TK, alpha_s, alpha_m, pre_alpha_s, pre_alpha_m

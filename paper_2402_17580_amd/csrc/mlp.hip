@@ -17,7 +17,11 @@
 #include "mlp.h"
 
 #ifndef SURROGATE_PPT
-#define SURROGATE_PPT 2
+#define SURROGATE_PPT 1
+#endif
+// pass A grid: blocks per compute unit (the grid strides over the chunks)
+#ifndef SURROGATE_BLOCKS_PER_CU
+#define SURROGATE_BLOCKS_PER_CU 32
 #endif
 
 namespace mstruct {
@@ -148,15 +152,29 @@ struct InferLds {
     float b3[4];
 };
 
+// Weight fragments into LDS (lane-major rows of kLdsStride words).  Element
+// e = o * 64 + lane reads word(o) of that lane, so that each group of 64
+// consecutive threads reads 256 contiguous bytes; all loads are issued before
+// the first LDS store.  Requires blockDim.x == 256.
 __device__ __forceinline__ void stage_infer_frag(InferLds& L, const uint32_t* __restrict__ frag) {
-    for (int e = threadIdx.x; e < 64 * kLdsStride; e += blockDim.x) {
-        const int lane = e / kLdsStride, o = e - lane * kLdsStride;
+    constexpr int kIter = 64 * kLdsStride / 256;
+    static_assert(64 * kLdsStride % 256 == 0, "whole iterations");
+    uint32_t v[kIter];
+#pragma unroll
+    for (int i = 0; i < kIter; ++i) {
+        const int e = i * 256 + threadIdx.x;
+        const int o = e >> 6, lane = e & 63;
         int word;
         if (o < kLdsI3) word = kFragI2 + o;
         else if (o < kLdsB2) word = kFragI3 + (o - kLdsI3);
         else if (o < kLdsW1) word = kFragB2 + (o - kLdsB2);
         else word = kFragW1 + (o - kLdsW1);
-        L.w[e] = frag[word * 64 + lane];
+        v[i] = frag[word * 64 + lane];
+    }
+#pragma unroll
+    for (int i = 0; i < kIter; ++i) {
+        const int e = i * 256 + threadIdx.x;
+        L.w[(e & 63) * kLdsStride + (e >> 6)] = v[i];
     }
     if (threadIdx.x < 3) L.b3[threadIdx.x] = __uint_as_float(frag[kFragUniform + threadIdx.x]);
     __syncthreads();
@@ -557,103 +575,110 @@ __device__ __forceinline__ bool needs_plain(float T0, float TK, const MlpNorm& n
     return !(cold || hot) || fabsf(TK - T0) > n.dT_max;
 }
 
+// tin and tout may be the same buffer (a point's block-start temperature is
+// read before its block-end temperature is written), so they are not restrict.
 template <int W, int PPT>
 __global__ __launch_bounds__(256) void surrogate_a_kernel(PointGeom pg, const SrcRec* __restrict__ tab, int K,
                                                          float dt, ScanArgs sa, float* __restrict__ beta,
                                                          float* __restrict__ as, float* __restrict__ am,
                                                          MlpNorm nrm, float* __restrict__ queue,
-                                                         unsigned* __restrict__ counter,
-                                                         const float* __restrict__ tin, float* __restrict__ tout) {
-    // PPT points per lane, 256 apart (coalesced); their loads are issued
-    // together and their temperatures computed side by side.  tin (may be
-    // null) holds the block-start temperatures; tout receives the block-end ones
+                                                         unsigned* __restrict__ counter, const float* tin,
+                                                         float* tout, int64_t n_chunks) {
+    // A chunk is 256 * PPT consecutive points; the grid strides over the
+    // chunks (a few blocks per CU).  Each lane takes PPT points 256 apart
+    // (coalesced); their loads are issued together and their temperatures
+    // computed side by side.
     const int lane = threadIdx.x & 63;
-    const int64_t g0 = (int64_t)blockIdx.x * 256 * PPT + threadIdx.x;
-    int64_t local[PPT];
-    int gi[PPT], gj[PPT], gk[PPT];
-    bool valid[PPT];
-    float a[PPT], m[PPT], T0[PPT], TK[PPT];
-    // indices, then every load issued before any arithmetic that needs it
+    for (int64_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
+        const int64_t g0 = chunk * 256 * PPT + threadIdx.x;
+        int64_t local[PPT];
+        int gi[PPT], gj[PPT], gk[PPT];
+        bool valid[PPT];
+        float a[PPT], m[PPT], T0[PPT], TK[PPT];
+        // indices, then every load issued before any arithmetic that needs it
 #pragma unroll
-    for (int u = 0; u < PPT; ++u) {
-        const int64_t g = g0 + u * 256;
-        valid[u] = g < pg.count;
-        local[u] = pg.first + (valid[u] ? g : 0);
-        const int lin = pg.index ? pg.index[local[u]] : (int)local[u];
-        gk[u] = lin / pg.nxy;
-        const int rem = lin - gk[u] * pg.nxy;
-        gj[u] = rem / pg.nx;
-        gi[u] = rem - gj[u] * pg.nx;
-        valid[u] = valid[u] && gk[u] >= pg.k0;
-    }
-#pragma unroll
-    for (int u = 0; u < PPT; ++u) {
-        a[u] = as[local[u]];
-        m[u] = am[local[u]];
-        T0[u] = tin ? tin[local[u]] : 0.0f;
-    }
-    // block-end temperature: independent of the loads above
-#pragma unroll
-    for (int u = 0; u < PPT; ++u) TK[u] = scan_temperature<W>(tab + K * W, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min);
-    if (!tin) {
-#pragma unroll
-        for (int u = 0; u < PPT; ++u) T0[u] = scan_temperature<W>(tab, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min);
-    }
-#pragma unroll
-    for (int u = 0; u < PPT; ++u) {
-        if (valid[u]) {
-            if (tout) tout[local[u]] = TK[u];
-        } else {
-            a[u] = m[u] = 0.0f;
-            T0[u] = TK[u] = sa.T0;
+        for (int u = 0; u < PPT; ++u) {
+            const int64_t g = g0 + u * 256;
+            valid[u] = g < pg.count;
+            local[u] = pg.first + (valid[u] ? g : 0);
+            const int lin = pg.index ? pg.index[local[u]] : (int)local[u];
+            gk[u] = lin / pg.nxy;
+            const int rem = lin - gk[u] * pg.nxy;
+            gj[u] = rem / pg.nx;
+            gi[u] = rem - gj[u] * pg.nx;
+            valid[u] = valid[u] && gk[u] >= pg.k0;
         }
-    }
 #pragma unroll
-    for (int u = 0; u < PPT; ++u) {
-        float pa = 0.0f, pm = 0.0f;
-        bool need = false;
-        if (valid[u]) {
-            float an = a[u], mn = m[u], bn;
-            const float xeq0 = alpha_eq(T0[u]);
-            if (needs_plain(T0[u], TK[u], nrm)) {
-                float alo = 0.0f, mlo = 0.0f, Tn = T0[u], xeq_n = xeq0;
-                for (int s = 0; s < K; ++s) {
-                    const float Tn1 =
-                        scan_temperature<W>(tab + (s + 1) * W, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min);
-                    const float xeq_n1 = alpha_eq(Tn1);
-                    explicit_step<true>(an, mn, alo, mlo, Tn, xeq_n, Tn1, xeq_n1, dt);
-                    Tn = Tn1;
-                    xeq_n = xeq_n1;
-                }
-                an += alo;
-                mn += mlo;
-                bn = solid_fraction(Tn) - an - mn;
+        for (int u = 0; u < PPT; ++u) {
+            a[u] = as[local[u]];
+            m[u] = am[local[u]];
+            T0[u] = tin ? tin[local[u]] : 0.0f;
+        }
+        // block-end temperature: independent of the loads above
+#pragma unroll
+        for (int u = 0; u < PPT; ++u)
+            TK[u] = scan_temperature<W>(tab + K * W, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min);
+        if (!tin) {
+#pragma unroll
+            for (int u = 0; u < PPT; ++u)
+                T0[u] = scan_temperature<W>(tab, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min);
+        }
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+            if (valid[u]) {
+                if (tout) tout[local[u]] = TK[u];
             } else {
-                float da, dm;
-                diffusive_increment(a[u], m[u], T0[u], xeq0, dt * (float)K, da, dm);
-                pa = a[u] + da;
-                pm = m[u] + dm;
-                need = (da != 0.0f) || (dm != 0.0f);
-                an = pa;
-                mn = pm;
-                bn = correct(TK[u], alpha_eq(TK[u]), an, mn);
+                a[u] = m[u] = 0.0f;
+                T0[u] = TK[u] = sa.T0;
             }
-            as[local[u]] = an;
-            am[local[u]] = mn;
-            if (beta) beta[local[u]] = bn;
         }
-        if (__ballot(need) != 0) {
-            unsigned slot = 0;
-            if (lane == 0) slot = atomicAdd(counter, 1u);
-            slot = __shfl(slot, 0);
-            float* e = queue + (int64_t)slot * kQueueWords;
-            e[lane] = __int_as_float(need ? (int)local[u] : -1);
-            e[64 + lane] = T0[u];
-            e[128 + lane] = TK[u];
-            e[192 + lane] = a[u];
-            e[256 + lane] = m[u];
-            e[320 + lane] = pa;
-            e[384 + lane] = pm;
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+            float pa = 0.0f, pm = 0.0f;
+            bool need = false;
+            if (valid[u]) {
+                float an = a[u], mn = m[u], bn;
+                const float xeq0 = alpha_eq(T0[u]);
+                if (needs_plain(T0[u], TK[u], nrm)) {
+                    float alo = 0.0f, mlo = 0.0f, Tn = T0[u], xeq_n = xeq0;
+                    for (int s = 0; s < K; ++s) {
+                        const float Tn1 = scan_temperature<W>(tab + (s + 1) * W, gi[u], gj[u], gk[u], sa.T0,
+                                                              sa.Tclamp, pg.r2min);
+                        const float xeq_n1 = alpha_eq(Tn1);
+                        explicit_step<true>(an, mn, alo, mlo, Tn, xeq_n, Tn1, xeq_n1, dt);
+                        Tn = Tn1;
+                        xeq_n = xeq_n1;
+                    }
+                    an += alo;
+                    mn += mlo;
+                    bn = solid_fraction(Tn) - an - mn;
+                } else {
+                    float da, dm;
+                    diffusive_increment(a[u], m[u], T0[u], xeq0, dt * (float)K, da, dm);
+                    pa = a[u] + da;
+                    pm = m[u] + dm;
+                    need = (da != 0.0f) || (dm != 0.0f);
+                    an = pa;
+                    mn = pm;
+                    bn = correct(TK[u], alpha_eq(TK[u]), an, mn);
+                }
+                as[local[u]] = an;
+                am[local[u]] = mn;
+                if (beta) beta[local[u]] = bn;
+            }
+            if (__ballot(need) != 0) {
+                unsigned slot = 0;
+                if (lane == 0) slot = atomicAdd(counter, 1u);
+                slot = __shfl(slot, 0);
+                float* e = queue + (int64_t)slot * kQueueWords;
+                e[lane] = __int_as_float(need ? (int)local[u] : -1);
+                e[64 + lane] = T0[u];
+                e[128 + lane] = TK[u];
+                e[192 + lane] = a[u];
+                e[256 + lane] = m[u];
+                e[320 + lane] = pa;
+                e[384 + lane] = pm;
+            }
         }
     }
 }
@@ -663,11 +688,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void s
     float ln_dt, float* __restrict__ beta, float* __restrict__ as, float* __restrict__ am,
     const uint32_t* __restrict__ frag, MlpNorm nrm) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *counter_next = 0u;  // for the next block's pass A
+    const unsigned count = *counter;
+    const unsigned n_waves = gridDim.x * (blockDim.x >> 6);
+    if (blockIdx.x * (blockDim.x >> 6) >= count) return;  // no queued wave for this block (uniform)
     __shared__ InferLds L;
     stage_infer_frag(L, frag);
     const int lane = threadIdx.x & 63;
-    const unsigned count = *counter;
-    const unsigned n_waves = gridDim.x * (blockDim.x >> 6);
     for (unsigned q = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; q < count; q += n_waves) {
         const float* e = queue + (int64_t)q * kQueueWords;
         const int idx = __float_as_int(e[lane]);
@@ -716,6 +742,12 @@ hipError_t surrogate_prepare(MlpState& s, int64_t points, hipStream_t st) {
         hipError_t e = hipMalloc((void**)&s.counters, 2 * sizeof(unsigned));
         if (e != hipSuccess) return e;
     }
+    if (s.cu_count <= 0) {
+        int dev = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&s.cu_count, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, st, s.counters);
     return hipGetLastError();
 }
@@ -730,12 +762,14 @@ hipError_t launch_surrogate(const MlpState& s, const PointGeom& pg, int W, const
     unsigned* cur = s.counters + (block & 1);
     unsigned* nxt = s.counters + ((block + 1) & 1);
     constexpr int P = SURROGATE_PPT;
-    const dim3 grid((unsigned)((pg.count + 256 * P - 1) / (256 * P))), blk(256);
+    const int64_t n_chunks = (pg.count + 256 * P - 1) / (256 * P);
+    const int64_t cap = (int64_t)s.cu_count * SURROGATE_BLOCKS_PER_CU;
+    const dim3 grid((unsigned)(cap > 0 && cap < n_chunks ? cap : n_chunks)), blk(256);
     switch (W) {
-        case 1: hipLaunchKernelGGL((surrogate_a_kernel<1, P>), grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, tout); break;
-        case 2: hipLaunchKernelGGL((surrogate_a_kernel<2, P>), grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, tout); break;
-        case 3: hipLaunchKernelGGL((surrogate_a_kernel<3, P>), grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, tout); break;
-        case 4: hipLaunchKernelGGL((surrogate_a_kernel<4, P>), grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, tout); break;
+        case 1: hipLaunchKernelGGL((surrogate_a_kernel<1, P>), grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, tout, n_chunks); break;
+        case 2: hipLaunchKernelGGL((surrogate_a_kernel<2, P>), grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, tout, n_chunks); break;
+        case 3: hipLaunchKernelGGL((surrogate_a_kernel<3, P>), grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, tout, n_chunks); break;
+        case 4: hipLaunchKernelGGL((surrogate_a_kernel<4, P>), grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, tout, n_chunks); break;
         default: return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();
