@@ -65,6 +65,12 @@ def lib():
         L.orc_constants.restype = ctypes.c_int
         L.orc_constants.argtypes = [p, ctypes.c_int]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_step_cn.restype = ctypes.c_int
+        L.orc_step_cn.argtypes = [p, p, p, p, d, d, d, ctypes.c_int, d, d]
+        L.orc_substeps.restype = i64
+        L.orc_substeps.argtypes = [d, d]
+        L.orc_step_implicit_n.restype = i64
+        L.orc_step_implicit_n.argtypes = [i64, p, p, p, p, p, p, d, d, ctypes.c_int, d, d, p]
         _lib = L
     return _lib
 
@@ -133,6 +139,26 @@ def step(state: State, Tn, Tn1, dt):
     Tn, Tn1 = _f64(np.broadcast_to(Tn, state.beta.shape)), _f64(np.broadcast_to(Tn1, state.beta.shape))
     lib().orc_step_n(state.beta.size, *[_ptr(a) for a in state.arrays()], _ptr(Tn), _ptr(Tn1), float(dt))
     return state
+
+
+CN_EPS_ABS, CN_EPS_REL, CN_MAX_ITER, DT_SUB = 1e-10, 1e-3, 50, 0.01
+
+
+def step_implicit(state: State, Tn, Tn1, dt, dt_sub=DT_SUB, max_iter=CN_MAX_ITER, eps_abs=CN_EPS_ABS,
+                  eps_rel=CN_EPS_REL):
+    """Crank-Nicolson step with fixed-point iteration and subcycling, in
+    place.  Returns (number of substeps that hit max_iter, iterations per
+    point)."""
+    Tn, Tn1 = _f64(np.broadcast_to(Tn, state.beta.shape)), _f64(np.broadcast_to(Tn1, state.beta.shape))
+    iters = np.zeros(state.beta.size, dtype=np.int64)
+    bad = lib().orc_step_implicit_n(state.beta.size, *[_ptr(a) for a in state.arrays()], _ptr(Tn), _ptr(Tn1),
+                                    float(dt), float(dt_sub), int(max_iter), float(eps_abs), float(eps_rel),
+                                    iters.ctypes.data_as(ctypes.c_void_p))
+    return int(bad), iters
+
+
+def substeps(dt, dt_sub=DT_SUB):
+    return int(lib().orc_substeps(float(dt), float(dt_sub)))
 
 
 def history_run(state: State, T_hist, dt):

@@ -35,6 +35,17 @@
  *   R9  temperature: switched moving point source on a semi-infinite body
  *       (not part of the paper, which uses an FEM heat solve); the window of
  *       superposed tracks is the last `window` tracks with t_on <= t + 1e-12 s.
+ *   R12 implicit scheme: the fixed-point iteration starts from
+ *       g(T^{n+1}, m^n), as the implicit algorithm does (the iteration's
+ *       equation writes m^n; both reach the same fixed point).
+ *   R13 the WRMS norm runs over the two components (alpha_s, alpha_m) without
+ *       a square root (the test "< 1" is unaffected), with weights from the
+ *       absolute value of the newest iterate; at most max_iter iterations.
+ *   R14 a state in a start-up regime at T^n takes the explicit step with its
+ *       closed form, since the paper initiates diffusion with the closed form
+ *       in both schemes.
+ *   R15 subcycling: a step longer than dt_sub is split into the fewest equal
+ *       substeps not longer than dt_sub, with T linear in time.
  */
 #include <math.h>
 #include <stdint.h>
@@ -258,6 +269,110 @@ void orc_step_n(int64_t n, double *as, double *am, double *b, double *bt,
                 const double *Tn, const double *Tn1, double dt)
 {
     for (int64_t i = 0; i < n; ++i) orc_step(&as[i], &am[i], &b[i], &bt[i], Tn[i], Tn1[i], dt);
+}
+
+/* ---------------- implicit scheme (Sec. 3.1, eqs. implicit_integration,
+ * implicit_correction, implicit_fp_iteration and the WRMS stop; the
+ * implicit algorithm of Sec. 3.2; readings R12-R15) ---------------- */
+
+/* diffusive part of the rate vector m' = [alpha_s', alpha_m'] (eq.
+ * diff_inst_split) at (T, state), X~beta taken as 0.9 - X_alpha */
+static void diff_rates(double as, double am, double T, double *fa, double *fm)
+{
+    double r1, r2, r3;
+    orc_rates(as, am, X_ALPHA_MAX - (as + am), T, &r1, &r2, &r3);
+    *fa = r1 + r2 - r3;
+    *fm = -r2;
+}
+
+/* the zero-rate start of either transformation at T^n (R6, R7, R14) */
+static int startup_regime(double as, double am, double bt, double T, double dt)
+{
+    double xa = as + am, xeq = orc_alpha_eq(T);
+    if (xa < xeq && !(as > 0.0)) return 1;
+    if (xa > xeq && (bt > 0.0 ? bt : 0.0) * dt <= STARTUP_LIMIT) return 1;
+    return 0;
+}
+
+/* One Crank-Nicolson step of the diffusive term followed by g at T^{n+1},
+ * the nonlinear equation solved by fixed-point iteration.  Returns the number
+ * of iterations taken (0 for a start-up step), negated when the WRMS norm of
+ * the residual did not fall below 1 within max_iter iterations. */
+int orc_step_cn(double *as_, double *am_, double *b_, double *bt_, double Tn, double Tn1, double dt,
+                int max_iter, double eps_abs, double eps_rel)
+{
+    const double as = *as_, am = *am_;
+    if (startup_regime(as, am, *bt_, Tn, dt)) {
+        orc_step(as_, am_, b_, bt_, Tn, Tn1, dt);
+        return 0;
+    }
+    double fa_n, fm_n;
+    diff_rates(as, am, Tn, &fa_n, &fm_n);
+    /* initial iterate: the correction at T^{n+1} applied to m^n (R12) */
+    double a = as, m = am;
+    double b = orc_correct(Tn1, &a, &m);
+    double fa, fm;
+    diff_rates(a, m, Tn1, &fa, &fm);
+    int it = 0, converged = 0;
+    while (it < max_iter) {
+        double a1 = as + 0.5 * dt * (fa + fa_n);
+        double m1 = am + 0.5 * dt * (fm + fm_n);
+        b = orc_correct(Tn1, &a1, &m1);
+        double fa1, fm1;
+        diff_rates(a1, m1, Tn1, &fa1, &fm1);
+        /* residual of the implicit equation at the new iterate */
+        double ra = 0.5 * dt * (fa1 - fa), rm = 0.5 * dt * (fm1 - fm);
+        double wa = 1.0 / (eps_abs + fabs(a1) * eps_rel), wm = 1.0 / (eps_abs + fabs(m1) * eps_rel);
+        double e = 0.5 * ((ra * wa) * (ra * wa) + (rm * wm) * (rm * wm));
+        a = a1;
+        m = m1;
+        fa = fa1;
+        fm = fm1;
+        ++it;
+        if (e < 1.0) {
+            converged = 1;
+            break;
+        }
+    }
+    *as_ = a;
+    *am_ = m;
+    *b_ = b;
+    *bt_ = X_ALPHA_MAX - (a + m);
+    return converged ? it : -it;
+}
+
+/* number of equal substeps of a step of length dt (R15) */
+int64_t orc_substeps(double dt, double dt_sub)
+{
+    if (!(dt > dt_sub)) return 1;
+    return (int64_t)ceil(dt / dt_sub * (1.0 - 1e-12));
+}
+
+/* implicit step with subcycling for n points; returns the number of
+ * substeps (over all points) whose iteration hit max_iter; iters (may be
+ * NULL) receives each point's total iteration count */
+int64_t orc_step_implicit_n(int64_t n, double *as, double *am, double *b, double *bt, const double *Tn,
+                            const double *Tn1, double dt, double dt_sub, int max_iter, double eps_abs,
+                            double eps_rel, int64_t *iters)
+{
+    int64_t bad = 0;
+    const int64_t ns = orc_substeps(dt, dt_sub);
+    const double h = dt / (double)ns;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t total = 0;
+        for (int64_t s = 0; s < ns; ++s) {
+            double T0 = Tn[i] + (Tn1[i] - Tn[i]) * (double)s / (double)ns;
+            double T1 = Tn[i] + (Tn1[i] - Tn[i]) * (double)(s + 1) / (double)ns;
+            int it = orc_step_cn(&as[i], &am[i], &b[i], &bt[i], T0, T1, h, max_iter, eps_abs, eps_rel);
+            if (it < 0) {
+                ++bad;
+                it = -it;
+            }
+            total += it;
+        }
+        if (iters) iters[i] = total;
+    }
+    return bad;
 }
 
 /* ---------------- temperature model (reading R9) ----------------
