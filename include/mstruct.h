@@ -106,6 +106,25 @@ const char *mstruct_last_error(const mstruct_ctx *ctx);
 int mstruct_step(mstruct_ctx *ctx, const float *T_prev, const float *T_next, double dt,
                  const mstruct_phases *ph, void *stream);
 
+/* One step of the implicit scheme (Sec. 3.1, eqs. implicit_integration,
+ * implicit_correction, implicit_fp_iteration; the implicit algorithm of
+ * Sec. 3.2) for n points, in place: Crank-Nicolson on the diffusive rates
+ * with the correction g at T^{n+1}, the nonlinear equation solved by
+ * fixed-point iteration from g(T^{n+1}, m^n) until the WRMS norm of the
+ * residual over (alpha_s, alpha_m), with eps_abs = 1e-10 and eps_rel = 1e-3,
+ * falls below 1, or max_iter iterations (1..1000; the paper's scheme is
+ * used with 50).  A state in a start-up regime (zero rate of a starting
+ * transformation at T^n) takes the explicit step with its Appendix A closed
+ * form.  Steps longer than dt_sub (the paper uses 0.01 s) are split into the
+ * fewest equal substeps not longer than dt_sub, with T linear in time
+ * (dt / dt_sub at most 1e6).  T_prev, T_next, phases: device float32 arrays
+ * of ph->n points, no alignment needed.  unconverged (device, may be NULL)
+ * is incremented by the number of substeps whose iteration hit max_iter; the
+ * caller zeroes it.  Asynchronous on the stream. */
+int mstruct_step_implicit(mstruct_ctx *ctx, const float *T_prev, const float *T_next, double dt,
+                          double dt_sub, int max_iter, const mstruct_phases *ph,
+                          unsigned long long *unconverged, void *stream);
+
 /* Temperature of the active points at time t (the scan model above), written
  * to T_out[n] (device float32; inactive points get T0). */
 int mstruct_temperature(mstruct_ctx *ctx, const mstruct_scan *scan, const mstruct_points *pts,

@@ -49,7 +49,7 @@ class PointsC(ctypes.Structure):
 
 
 EXPORTS = ("mstruct_init", "mstruct_destroy", "mstruct_status_string", "mstruct_last_error", "mstruct_step",
-           "mstruct_temperature", "mstruct_fused_scan_steps", "mstruct_gather", "mstruct_check_invariants",
+           "mstruct_step_implicit", "mstruct_temperature", "mstruct_fused_scan_steps", "mstruct_gather", "mstruct_check_invariants",
            "mstruct_correct", "mstruct_mlp_set_params", "mstruct_mlp_get_params", "mstruct_mlp_forward",
            "mstruct_mlp_grad", "mstruct_mlp_train_step")
 
@@ -67,6 +67,7 @@ def lib() -> ctypes.CDLL:
         sig = {
             "mstruct_init": [i, p], "mstruct_destroy": [p], "mstruct_status_string": [i],
             "mstruct_last_error": [p], "mstruct_step": [p, p, p, d, p, p],
+            "mstruct_step_implicit": [p, p, p, d, d, i, p, p, p],
             "mstruct_temperature": [p, p, p, d, p, p],
             "mstruct_fused_scan_steps": [p, p, p, d, d, i64, i, i, p, p],
             "mstruct_gather": [p, p, p, i64, p, p], "mstruct_check_invariants": [p, p, p, ctypes.c_float, p, p],
@@ -154,6 +155,19 @@ class Context:
         self._check(lib().mstruct_step(self._h, _dev_ptr(T_prev, torch.float32, ph.n, "T_prev"),
                                        _dev_ptr(T_next, torch.float32, ph.n, "T_next"), float(dt),
                                        ctypes.byref(ph), _stream(stream)), "mstruct_step")
+
+    def step_implicit(self, T_prev, T_next, dt, beta, alpha_s, alpha_m, dt_sub=0.01, max_iter=50,
+                      unconverged=None, stream=None):
+        """Implicit (Crank-Nicolson, fixed-point) step; unconverged: optional
+        CUDA int64 tensor of one element, incremented by the number of
+        substeps that hit max_iter."""
+        import torch
+        ph = self._phases(beta, alpha_s, alpha_m)
+        up = _dev_ptr(unconverged, torch.int64, 1, "unconverged") if unconverged is not None else None
+        self._check(lib().mstruct_step_implicit(self._h, _dev_ptr(T_prev, torch.float32, ph.n, "T_prev"),
+                                                _dev_ptr(T_next, torch.float32, ph.n, "T_next"), float(dt),
+                                                float(dt_sub), int(max_iter), ctypes.byref(ph), up,
+                                                _stream(stream)), "mstruct_step_implicit")
 
     def temperature(self, scan, grid, t, T_out, z_top=math.inf, index=None, stream=None):
         import torch

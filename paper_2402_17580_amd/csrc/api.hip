@@ -290,6 +290,26 @@ int mstruct_step(mstruct_ctx* ctx, const float* T_prev, const float* T_next, dou
     return MSTRUCT_OK;
 }
 
+int mstruct_step_implicit(mstruct_ctx* ctx, const float* T_prev, const float* T_next, double dt, double dt_sub,
+                          int max_iter, const mstruct_phases* ph, unsigned long long* unconverged, void* stream) {
+    if (!ctx) return MSTRUCT_EINVAL;
+    int rc = check_phases(ctx, ph);
+    if (rc) return rc;
+    if (!finite_pos(dt)) return fail(ctx, MSTRUCT_EINVAL, "dt must be positive and finite");
+    if (!finite_pos(dt_sub)) return fail(ctx, MSTRUCT_EINVAL, "dt_sub must be positive and finite");
+    if (max_iter < 1 || max_iter > 1000) return fail(ctx, MSTRUCT_EINVAL, "max_iter must be in 1..1000");
+    if (ph->n > 0 && (!T_prev || !T_next)) return fail(ctx, MSTRUCT_EINVAL, "temperature array is NULL");
+    // fewest equal substeps not longer than dt_sub (the same rule as the reference)
+    const double ratio = dt / dt_sub;
+    if (ratio > 1e6) return fail(ctx, MSTRUCT_EINVAL, "dt / dt_sub exceeds 1e6 substeps");
+    const int n_sub = dt > dt_sub ? (int)ceil(ratio * (1.0 - 1e-12)) : 1;
+    DeviceGuard g(ctx->device);
+    hipError_t e = launch_implicit_step(T_prev, T_next, ph->beta, ph->alpha_s, ph->alpha_m, ph->n,
+                                        (float)(dt / n_sub), n_sub, max_iter, unconverged, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "implicit step launch");
+    return MSTRUCT_OK;
+}
+
 int mstruct_temperature(mstruct_ctx* ctx, const mstruct_scan* scan, const mstruct_points* pts, double t,
                         float* T_out, void* stream) {
     if (!ctx) return MSTRUCT_EINVAL;

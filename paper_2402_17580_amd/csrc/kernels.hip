@@ -93,6 +93,51 @@ hipError_t launch_step(const float* Tp, const float* Tn, float* beta, float* as,
 }
 
 // ---------------------------------------------------------------------------
+// implicit step: n_sub equal substeps of length h with T linear in time, the
+// Crank-Nicolson fixed-point step on each (28 bytes per point like the
+// explicit step; the iteration makes it compute-heavier).  Substeps whose
+// iteration hit max_iter are counted, one atomic per wave.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void implicit_step_kernel(const float* __restrict__ Tp,
+                                                              const float* __restrict__ Tn,
+                                                              float* __restrict__ beta, float* __restrict__ as,
+                                                              float* __restrict__ am, int64_t n, float h,
+                                                              int n_sub, int max_iter,
+                                                              unsigned long long* __restrict__ unconverged) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int bad = 0;
+    if (g < n) {
+        float a = as[g], m = am[g], b = 0.0f;
+        const float T0 = Tp[g], dT = Tn[g] - T0;
+        const float inv = 1.0f / (float)n_sub;
+        float Ta = T0;
+        for (int s = 0; s < n_sub; ++s) {
+            const float Tb = (s + 1 == n_sub) ? Tn[g] : fmaf(dT, (float)(s + 1) * inv, T0);
+            if (implicit_step(a, m, b, Ta, Tb, h, max_iter) < 0) ++bad;
+            Ta = Tb;
+        }
+        as[g] = a;
+        am[g] = m;
+        beta[g] = b;
+    }
+    if (unconverged) {
+        // sum of the per-lane counts over the wave (counts are small)
+        int total = bad;
+        for (int o = 32; o > 0; o >>= 1) total += __shfl_xor(total, o);
+        if ((threadIdx.x & 63) == 0 && total) atomicAdd(unconverged, (unsigned long long)total);
+    }
+}
+
+hipError_t launch_implicit_step(const float* Tp, const float* Tn, float* beta, float* as, float* am, int64_t n,
+                                float h, int n_sub, int max_iter, unsigned long long* unconverged,
+                                hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(implicit_step_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, Tp,
+                       Tn, beta, as, am, n, h, n_sub, max_iter, unconverged);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // temperature field at one time point
 // ---------------------------------------------------------------------------
 template <int W>

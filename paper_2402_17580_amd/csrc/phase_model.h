@@ -31,6 +31,8 @@ constexpr float kF = 3.8f;
 constexpr float kTreg = 100.0f;
 constexpr float kXmax = 0.9f;            // maximum alpha fraction
 constexpr float kStartupLimit = 1e-15f;  // Appendix A exit test on X~beta * dt
+constexpr float kCnEpsAbs = 1e-10f;      // WRMS weights of the implicit scheme (Sec. 3.1)
+constexpr float kCnEpsRel = 1e-3f;
 
 // exponents (c -/+ 1)/c of the generalised logistic rates
 constexpr float kPa = (kCas - 1.0f) / kCas;
@@ -206,6 +208,76 @@ __device__ __forceinline__ float explicit_step(float& a, float& m, float& a_lo, 
     a = at;
     m = mt;
     return beta;
+}
+
+// Diffusive rate vector [alpha_s', alpha_m'] (eqs. beta_to_alpha_s,
+// alpha_m_to_alpha_s, alpha_s_to_beta, split as in eq. diff_inst_split) at a
+// temperature with X_alpha^eq = xeq and k_alpha_s = kas; X~beta = 0.9 - X_alpha.
+__device__ __forceinline__ void diffusive_rates(float a, float m, float xeq, float kas, float& fa, float& fm) {
+    const float xa = a + m;
+    const float la = flog2(a);  // -inf at a = 0: the rates that carry a^p vanish
+    fa = 0.0f;
+    fm = 0.0f;
+    if (xa < xeq) fa = kas * fexp2(fmaf(kPa, la, kQa * flog2(xeq - xa)));
+    if (m > 0.0f) {
+        const float r2 = kas * fexp2(fmaf(kPa, la, kQa * flog2(m)));
+        fa += r2;
+        fm = -r2;
+    }
+    if (xa > xeq) {
+        const float bt = fmaxf(kXmax - xa, 0.0f);
+        fa -= kF * kas * fexp2(fmaf(kPb, flog2(bt), kQb * flog2(xa - xeq)));
+    }
+}
+
+// One step of the implicit scheme (eqs. implicit_integration,
+// implicit_correction): Crank-Nicolson on the diffusive term with g at
+// T^{n+1}, solved by the fixed-point iteration of eq. implicit_fp_iteration
+// from g(T^{n+1}, m^n).  The iteration stops when the WRMS norm of the
+// residual over (alpha_s, alpha_m), weights 1 / (eps_abs + |m_j| eps_rel) of
+// the newest iterate, falls below 1, or after max_iter iterations.  A state
+// in a start-up regime at T^n (zero rate of a starting transformation) takes
+// the explicit step with its Appendix A closed form instead.  Returns the
+// iteration count (0 for a start-up step), negated if the stop test failed.
+__device__ __forceinline__ int implicit_step(float& a, float& m, float& beta, float Tn, float Tn1, float dt,
+                                             int max_iter) {
+    const float xeq_n = alpha_eq(Tn), xeq_1 = alpha_eq(Tn1);
+    const float xa = a + m;
+    if ((xa < xeq_n && !(a > 0.0f)) || (xa > xeq_n && fmaxf(kXmax - xa, 0.0f) * dt <= kStartupLimit)) {
+        float alo = 0.0f, mlo = 0.0f;
+        beta = explicit_step<false>(a, m, alo, mlo, Tn, xeq_n, Tn1, xeq_1, dt);
+        return 0;
+    }
+    const float k_1 = k_alpha_s(Tn1);
+    float fa_n, fm_n;
+    diffusive_rates(a, m, xeq_n, k_alpha_s(Tn), fa_n, fm_n);
+    float ai = a, mi = m;
+    beta = correct(Tn1, xeq_1, ai, mi);
+    float fa, fm;
+    diffusive_rates(ai, mi, xeq_1, k_1, fa, fm);
+    const float h = 0.5f * dt;
+    int it = 0;
+    bool converged = false;
+    while (it < max_iter) {
+        float a1 = fmaf(h, fa + fa_n, a), m1 = fmaf(h, fm + fm_n, m);
+        beta = correct(Tn1, xeq_1, a1, m1);
+        float fa1, fm1;
+        diffusive_rates(a1, m1, xeq_1, k_1, fa1, fm1);
+        const float wa = h * (fa1 - fa) * frcp(fmaf(fabsf(a1), kCnEpsRel, kCnEpsAbs));
+        const float wm = h * (fm1 - fm) * frcp(fmaf(fabsf(m1), kCnEpsRel, kCnEpsAbs));
+        ai = a1;
+        mi = m1;
+        fa = fa1;
+        fm = fm1;
+        ++it;
+        if (0.5f * fmaf(wa, wa, wm * wm) < 1.0f) {
+            converged = true;
+            break;
+        }
+    }
+    a = ai;
+    m = mi;
+    return converged ? it : -it;
 }
 
 }  // namespace mstruct
