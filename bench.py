@@ -172,6 +172,7 @@ def main():
 
     if not args.no_stepwise:
         result["plain_step"] = bench_stepwise(torch, ms, ctx, wl, dev)
+        result["implicit_step"] = bench_implicit(torch, ms, ctx, wl, final_state)
 
     if args.copy_probe:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
@@ -239,6 +240,49 @@ def bench_stepwise(torch, ms, ctx, wl, dev):
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                          "bytes_per_update": STEP_BYTES, "avg_launch_us": avg * 1e6,
                          "point_updates_per_s": n_act / avg}}
+
+
+# Per-point VALU lane-ops of the implicit step kernel on the two regimes timed
+# below, from rocprofv3 counter runs of this script (SQ_INSTS_VALU x 64 / points)
+IMPLICIT_PROFILE = {"scan": 315.2, "cooldown": 2561.2}
+
+
+def bench_implicit(torch, ms, ctx, wl, state):
+    """The implicit step (mstruct_step_implicit) on all 8.4M points, starting
+    from the state the plain run leaves: (a) a scan step of 2 us with the
+    temperature arrays of the top layer, (b) a cool-down step of 0.1 s
+    (ten substeps of 0.01 s) with T relaxing towards 300 K.  Each launch moves
+    28 bytes per point, like the explicit step."""
+    n = wl.grid.n
+    L = wl.layers[-1]
+    b, a, m = [x.clone() for x in state]
+    Ta, Tb = torch.empty(n, device="cuda"), torch.empty(n, device="cuda")
+    t = wl.t0(L) + 1000 * wl.dt
+    ctx.temperature(wl.scan, wl.grid, t, Ta, z_top=L.z_top)
+    ctx.temperature(wl.scan, wl.grid, t + wl.dt, Tb, z_top=L.z_top)
+    Tc = 300.0 + (Ta - 300.0) * math.exp(-0.05)
+    unc = torch.zeros(1, dtype=torch.int64, device="cuda")
+    out = {"path": "mstruct_step_implicit on all points of the block (state after the plain run)"}
+    for key, T1, dt, reps in (("scan", Tb, wl.dt, 100), ("cooldown", Tc, 0.1, 20)):
+        ctx.step_implicit(Ta, T1, dt, b, a, m, unconverged=unc)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            ctx.step_implicit(Ta, T1, dt, b, a, m, unconverged=unc)
+        e1.record()
+        torch.cuda.synchronize()
+        avg = e0.elapsed_time(e1) * 1e-3 / reps
+        gbs = STEP_BYTES * n / avg / 1e9
+        entry = {"dt_s": dt, "substeps": max(1, math.ceil(dt / 0.01 * (1 - 1e-12))), "avg_launch_us": avg * 1e6,
+                 "point_updates_per_s": n / avg, "hbm_GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS}
+        ops = IMPLICIT_PROFILE[key]
+        if ops is not None:
+            entry["lane_ops_per_point"] = ops
+            entry["valu_frac"] = n * ops / avg / 1e12 / VALU_PEAK_TLANEOPS
+        out[key] = entry
+    out["unconverged_substeps"] = int(unc.item())
+    return out
 
 
 def cpu_baseline(wl, args):
