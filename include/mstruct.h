@@ -81,7 +81,7 @@ typedef struct {
     double z_top;
 } mstruct_points;
 
-enum { MSTRUCT_MODE_PLAIN = 0, MSTRUCT_MODE_SURROGATE = 1 };
+enum { MSTRUCT_MODE_PLAIN = 0, MSTRUCT_MODE_SURROGATE = 1, MSTRUCT_MODE_IMPLICIT = 2 };
 
 /* Create a context on HIP device `device` (the caller's current device is
  * restored).  *out receives the context; free it with mstruct_destroy. */
@@ -143,11 +143,21 @@ int mstruct_temperature(mstruct_ctx *ctx, const mstruct_scan *scan, const mstruc
  * indicator flags the point (temperature window touching the martensite
  * start, beta-transus or melting bands, or a start-up state), which get the
  * K plain steps; requires weights loaded with mstruct_mlp_set_params.
+ * mode IMPLICIT runs the implicit step of mstruct_step_implicit at every
+ * step (substep limit 0.01 s, T linear in time between the analytic values
+ * at the step ends, at most 50 iterations; no compensated accumulation);
+ * substeps that hit the cap are counted in the context (see
+ * mstruct_implicit_unconverged).
  * K in 1..64.  pts->n must equal ph->n.  Inside a call beta is not read and
  * is written once, by the last launch (it follows from the sum rule). */
 int mstruct_fused_scan_steps(mstruct_ctx *ctx, const mstruct_scan *scan, const mstruct_points *pts,
                              double t0, double dt, int64_t n_steps, int K, int mode,
                              const mstruct_phases *ph, void *stream);
+
+/* Number of substeps of fused IMPLICIT runs on this context whose fixed-point
+ * iteration hit the cap, since the context was created or last reset
+ * (reset != 0 zeroes it after reading).  Synchronises the stream. */
+int mstruct_implicit_unconverged(mstruct_ctx *ctx, int64_t *count, int reset, void *stream);
 
 /* dst[i] = src[idx[i]] for i < m (device arrays). */
 int mstruct_gather(mstruct_ctx *ctx, const float *src, const int64_t *idx, int64_t m, float *dst,

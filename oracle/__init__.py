@@ -70,6 +70,9 @@ def lib():
         L.orc_substeps.restype = i64
         L.orc_substeps.argtypes = [d, d]
         L.orc_step_implicit_n.restype = i64
+        L.orc_scan_run_implicit.restype = i64
+        L.orc_scan_run_implicit.argtypes = [p, i64, p, p, i64, d, d, d, d, i64, d, ctypes.c_int, p, p, p, p,
+                                            ctypes.c_int]
         L.orc_step_implicit_n.argtypes = [i64, p, p, p, p, p, p, d, d, ctypes.c_int, d, d, p]
         _lib = L
     return _lib
@@ -194,13 +197,29 @@ def scan_run(scan, xyz, state: State, z_top, h, t0, dt, n_steps, threads=0):
     return state
 
 
-def run_workload(wl, local_points, state: State = None, threads=0, layers=None):
-    """Run every layer of a workload at the given local point numbers."""
+def scan_run_implicit(scan, xyz, state: State, z_top, h, t0, dt, n_steps, dt_sub=DT_SUB, max_iter=CN_MAX_ITER,
+                      threads=0):
+    """scan_run with the implicit scheme; returns the number of substeps that
+    hit max_iter."""
+    xyz = _f64(xyz)
+    tr, sp = _f64(scan.tracks), _scan_params(scan)
+    return int(lib().orc_scan_run_implicit(_ptr(tr), tr.shape[0], _ptr(sp), _ptr(xyz), xyz.shape[0], float(z_top),
+                                           float(h), float(t0), float(dt), int(n_steps), float(dt_sub),
+                                           int(max_iter), *[_ptr(a) for a in state.arrays()], int(threads)))
+
+
+def run_workload(wl, local_points, state: State = None, threads=0, layers=None, implicit=False):
+    """Run every layer of a workload at the given local point numbers (with
+    the explicit scheme, or the implicit one)."""
     xyz = wl.grid.coords(np.asarray(local_points))
     if state is None:
         state = State.initial(xyz.shape[0])
     for L in (wl.layers if layers is None else layers):
-        scan_run(wl.scan, xyz, state, L.z_top, wl.grid.h, wl.t0(L), wl.dt, L.step_end - L.step_begin, threads)
+        if implicit:
+            scan_run_implicit(wl.scan, xyz, state, L.z_top, wl.grid.h, wl.t0(L), wl.dt, L.step_end - L.step_begin,
+                              threads=threads)
+        else:
+            scan_run(wl.scan, xyz, state, L.z_top, wl.grid.h, wl.t0(L), wl.dt, L.step_end - L.step_begin, threads)
     return state
 
 

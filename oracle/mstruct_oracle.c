@@ -503,6 +503,40 @@ void orc_scan_run(const double *tracks, int64_t n_tracks, const double *sp,
     }
 }
 
+/* the same run with the implicit scheme at every step (Crank-Nicolson,
+ * fixed point, the paper's tolerances; steps longer than dt_sub are split
+ * with T linear between the analytic end values, R15).  Returns the number
+ * of substeps whose iteration hit max_iter. */
+int64_t orc_scan_run_implicit(const double *tracks, int64_t n_tracks, const double *sp,
+                              const double *xyz, int64_t n, double z_top, double h,
+                              double t0, double dt, int64_t n_steps, double dt_sub, int max_iter,
+                              double *as, double *am, double *b, double *bt, int n_threads)
+{
+    int64_t bad = 0;
+    const int64_t ns = orc_substeps(dt, dt_sub);
+    const double hs = dt / (double)ns;
+#ifdef _OPENMP
+    if (n_threads <= 0) n_threads = omp_get_max_threads();
+#pragma omp parallel for schedule(dynamic, 16) num_threads(n_threads) reduction(+ : bad)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        double x = xyz[3 * i], y = xyz[3 * i + 1], z = xyz[3 * i + 2];
+        if (!(z <= z_top + 1e-3 * h)) continue;
+        double Tn = orc_temperature(tracks, n_tracks, sp, x, y, z, t0);
+        for (int64_t s = 0; s < n_steps; ++s) {
+            double t1 = t0 + (double)(s + 1) * dt;
+            double Tn1 = orc_temperature(tracks, n_tracks, sp, x, y, z, t1);
+            for (int64_t k = 0; k < ns; ++k) {
+                double Ta = Tn + (Tn1 - Tn) * (double)k / (double)ns;
+                double Tb = Tn + (Tn1 - Tn) * (double)(k + 1) / (double)ns;
+                if (orc_step_cn(&as[i], &am[i], &b[i], &bt[i], Ta, Tb, hs, max_iter, 1e-10, 1e-3) < 0) ++bad;
+            }
+            Tn = Tn1;
+        }
+    }
+    return bad;
+}
+
 /* same, with the temperature history given per point (n x (n_steps+1)) */
 void orc_history_run(int64_t n, int64_t n_steps, const double *T_hist, double dt,
                      double *as, double *am, double *b, double *bt)

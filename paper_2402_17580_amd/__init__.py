@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libmstruct.so")
 
 MODE_PLAIN = 0
 MODE_SURROGATE = 1
+MODE_IMPLICIT = 2
 MLP_NPARAM = 4803
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "HIP device error", -3: "out of memory",
@@ -49,7 +50,7 @@ class PointsC(ctypes.Structure):
 
 
 EXPORTS = ("mstruct_init", "mstruct_destroy", "mstruct_status_string", "mstruct_last_error", "mstruct_step",
-           "mstruct_step_implicit", "mstruct_temperature", "mstruct_fused_scan_steps", "mstruct_gather", "mstruct_check_invariants",
+           "mstruct_step_implicit", "mstruct_implicit_unconverged", "mstruct_temperature", "mstruct_fused_scan_steps", "mstruct_gather", "mstruct_check_invariants",
            "mstruct_correct", "mstruct_mlp_set_params", "mstruct_mlp_get_params", "mstruct_mlp_forward",
            "mstruct_mlp_grad", "mstruct_mlp_train_step")
 
@@ -68,6 +69,7 @@ def lib() -> ctypes.CDLL:
             "mstruct_init": [i, p], "mstruct_destroy": [p], "mstruct_status_string": [i],
             "mstruct_last_error": [p], "mstruct_step": [p, p, p, d, p, p],
             "mstruct_step_implicit": [p, p, p, d, d, i, p, p, p],
+            "mstruct_implicit_unconverged": [p, p, i, p],
             "mstruct_temperature": [p, p, p, d, p, p],
             "mstruct_fused_scan_steps": [p, p, p, d, d, i64, i, i, p, p],
             "mstruct_gather": [p, p, p, i64, p, p], "mstruct_check_invariants": [p, p, p, ctypes.c_float, p, p],
@@ -168,6 +170,13 @@ class Context:
                                                 _dev_ptr(T_next, torch.float32, ph.n, "T_next"), float(dt),
                                                 float(dt_sub), int(max_iter), ctypes.byref(ph), up,
                                                 _stream(stream)), "mstruct_step_implicit")
+
+    def implicit_unconverged(self, reset=False, stream=None) -> int:
+        """Substeps of fused IMPLICIT runs that hit the iteration cap."""
+        c = ctypes.c_int64()
+        self._check(lib().mstruct_implicit_unconverged(self._h, ctypes.byref(c), int(bool(reset)), _stream(stream)),
+                    "mstruct_implicit_unconverged")
+        return c.value
 
     def temperature(self, scan, grid, t, T_out, z_top=math.inf, index=None, stream=None):
         import torch

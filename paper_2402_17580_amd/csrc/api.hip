@@ -33,6 +33,7 @@ struct mstruct_ctx {
     TableSlot slots[kSlots];
     int next_slot = 0;
     unsigned long long* counter = nullptr;
+    unsigned long long* implicit_bad = nullptr;  // substeps of fused implicit runs that hit the cap
     MlpState mlp;
 };
 
@@ -147,6 +148,13 @@ int64_t last_on(const mstruct_scan* sc, double t) {
     return lo - 1;
 }
 
+// fewest equal substeps of a step dt that are not longer than dt_sub
+int substeps(double dt, double dt_sub) { return dt > dt_sub ? (int)ceil(dt / dt_sub * (1.0 - 1e-12)) : 1; }
+
+// substep limit and iteration cap of the implicit scheme in the fused path (Sec. 3.1)
+constexpr double kImplicitDtSub = 0.01;
+constexpr int kImplicitMaxIter = 50;
+
 void split(double g, int32_t& i, float& f) {
     const double fl = floor(g);
     i = (int32_t)fl;
@@ -253,9 +261,18 @@ int mstruct_init(int device, mstruct_ctx** out) {
     if (!ctx) return MSTRUCT_ENOMEM;
     ctx->device = device;
     DeviceGuard g(device);
-    if (hipMalloc((void**)&ctx->counter, sizeof(unsigned long long)) != hipSuccess) {
+    if (hipMalloc((void**)&ctx->counter, sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc((void**)&ctx->implicit_bad, sizeof(unsigned long long)) != hipSuccess) {
+        if (ctx->counter) (void)hipFree(ctx->counter);
         delete ctx;
         return MSTRUCT_ENOMEM;
+    }
+    const unsigned long long zero = 0;
+    if (hipMemcpy(ctx->implicit_bad, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(ctx->counter);
+        (void)hipFree(ctx->implicit_bad);
+        delete ctx;
+        return MSTRUCT_EDEVICE;
     }
     *out = ctx;
     return MSTRUCT_OK;
@@ -271,6 +288,7 @@ int mstruct_destroy(mstruct_ctx* ctx) {
         if (s.dev) (void)hipFree(s.dev);
     }
     if (ctx->counter) (void)hipFree(ctx->counter);
+    if (ctx->implicit_bad) (void)hipFree(ctx->implicit_bad);
     mlp_free(ctx->mlp);
     delete ctx;
     return MSTRUCT_OK;
@@ -299,10 +317,8 @@ int mstruct_step_implicit(mstruct_ctx* ctx, const float* T_prev, const float* T_
     if (!finite_pos(dt_sub)) return fail(ctx, MSTRUCT_EINVAL, "dt_sub must be positive and finite");
     if (max_iter < 1 || max_iter > 1000) return fail(ctx, MSTRUCT_EINVAL, "max_iter must be in 1..1000");
     if (ph->n > 0 && (!T_prev || !T_next)) return fail(ctx, MSTRUCT_EINVAL, "temperature array is NULL");
-    // fewest equal substeps not longer than dt_sub (the same rule as the reference)
-    const double ratio = dt / dt_sub;
-    if (ratio > 1e6) return fail(ctx, MSTRUCT_EINVAL, "dt / dt_sub exceeds 1e6 substeps");
-    const int n_sub = dt > dt_sub ? (int)ceil(ratio * (1.0 - 1e-12)) : 1;
+    if (dt / dt_sub > 1e6) return fail(ctx, MSTRUCT_EINVAL, "dt / dt_sub exceeds 1e6 substeps");
+    const int n_sub = substeps(dt, dt_sub);
     DeviceGuard g(ctx->device);
     hipError_t e = launch_implicit_step(T_prev, T_next, ph->beta, ph->alpha_s, ph->alpha_m, ph->n,
                                         (float)(dt / n_sub), n_sub, max_iter, unconverged, (hipStream_t)stream);
@@ -345,7 +361,10 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
     if (!finite_pos(dt) || !isfinite(t0)) return fail(ctx, MSTRUCT_EINVAL, "bad t0 or dt");
     if (n_steps < 0) return fail(ctx, MSTRUCT_EINVAL, "n_steps < 0");
     if (K < 1 || K > 64) return fail(ctx, MSTRUCT_EINVAL, "K must be in 1..64");
-    if (mode != MSTRUCT_MODE_PLAIN && mode != MSTRUCT_MODE_SURROGATE) return fail(ctx, MSTRUCT_EINVAL, "bad mode");
+    if (mode != MSTRUCT_MODE_PLAIN && mode != MSTRUCT_MODE_SURROGATE && mode != MSTRUCT_MODE_IMPLICIT)
+        return fail(ctx, MSTRUCT_EINVAL, "bad mode");
+    if (mode == MSTRUCT_MODE_IMPLICIT && dt / kImplicitDtSub > 1e6)
+        return fail(ctx, MSTRUCT_EINVAL, "dt / 0.01 s exceeds 1e6 substeps");
     PointGeom pg;
     if ((rc = make_geom(ctx, pts, ph->n, pg))) return rc;
     if (mode == MSTRUCT_MODE_SURROGATE && !ctx->mlp.ready)
@@ -373,9 +392,13 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
         // beta is written by the last launch only (no kernel reads it)
         float* beta = last ? ph->beta : nullptr;
         hipError_t e;
-        if (mode == MSTRUCT_MODE_PLAIN)
+        if (mode == MSTRUCT_MODE_PLAIN) {
             e = launch_fused_plain(pg, W, s->dev + s0 * W, Kb, (float)dt, sa, beta, ph->alpha_s, ph->alpha_m, st);
-        else
+        } else if (mode == MSTRUCT_MODE_IMPLICIT) {
+            const int n_sub = substeps(dt, kImplicitDtSub);
+            e = launch_fused_implicit(pg, W, s->dev + s0 * W, Kb, (float)(dt / n_sub), n_sub, kImplicitMaxIter, sa,
+                                      beta, ph->alpha_s, ph->alpha_m, ctx->implicit_bad, st);
+        } else
             e = launch_surrogate(ctx->mlp, pg, W, s->dev + s0 * W, Kb, (float)dt, sa, ph->beta, ph->alpha_s,
                                  ph->alpha_m, s0 / K, s0 == 0, last, st);
         if (e != hipSuccess) {
@@ -384,6 +407,22 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
         }
     }
     return release_slot(ctx, s, st);
+}
+
+int mstruct_implicit_unconverged(mstruct_ctx* ctx, int64_t* count, int reset, void* stream) {
+    if (!ctx) return MSTRUCT_EINVAL;
+    if (!count) return fail(ctx, MSTRUCT_EINVAL, "count is NULL");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    unsigned long long h = 0;
+    HIP_CHECK(ctx, hipMemcpyAsync(&h, ctx->implicit_bad, sizeof h, hipMemcpyDeviceToHost, st));
+    if (reset) {
+        const unsigned long long zero = 0;
+        HIP_CHECK(ctx, hipMemcpyAsync(ctx->implicit_bad, &zero, sizeof zero, hipMemcpyHostToDevice, st));
+    }
+    HIP_CHECK(ctx, hipStreamSynchronize(st));
+    *count = (int64_t)h;
+    return MSTRUCT_OK;
 }
 
 int mstruct_gather(mstruct_ctx* ctx, const float* src, const int64_t* idx, int64_t m, float* dst, void* stream) {

@@ -24,6 +24,9 @@ struct ScanArgs {
 
 hipError_t launch_step(const float* Tp, const float* Tn, float* beta, float* as, float* am, int64_t n,
                        float dt, hipStream_t st);
+hipError_t launch_fused_implicit(const PointGeom& pg, int W, const SrcRec* tab, int K, float h, int n_sub,
+                                 int max_iter, ScanArgs sa, float* beta, float* as, float* am,
+                                 unsigned long long* unconverged, hipStream_t st);
 hipError_t launch_implicit_step(const float* Tp, const float* Tn, float* beta, float* as, float* am, int64_t n,
                                 float h, int n_sub, int max_iter, unsigned long long* unconverged,
                                 hipStream_t st);

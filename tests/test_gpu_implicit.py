@@ -131,3 +131,55 @@ def test_implicit_argument_errors(torch, ctx):
         assert e.value.code == -1
     empty = [torch.empty(0, device="cuda") for _ in range(3)]
     ctx.step_implicit(empty[0], empty[0], 1e-3, *empty)
+
+
+def _errors(torch, g, st):
+    out = {}
+    for name, x, y in zip(("beta", "alpha_s", "alpha_m"), g, (st.beta, st.alpha_s, st.alpha_m)):
+        out[name] = float(np.abs(x.double().cpu().numpy() - y).max())
+    return out
+
+
+@pytest.mark.parametrize("K", [1, 16])
+def test_fused_implicit_single_track(torch, ctx, orc, K):
+    """The single track (2000 steps of 1 us) with the implicit scheme in the
+    fused kernel against the oracle's implicit scan run, all points."""
+    import paper_2402_17580_amd as ms
+    import workload
+    wl = workload.single_track()
+    n = wl.grid.n
+    g = [torch.from_numpy(x).cuda() for x in workload.initial_state(n, np.float32)]
+    ctx.implicit_unconverged(reset=True)
+    ms.run_layers(ctx, wl, *g, K=K, mode=ms.MODE_IMPLICIT)
+    assert ctx.implicit_unconverged() == 0
+    st = orc.run_workload(wl, np.arange(n), implicit=True)
+    err = _errors(torch, g, st)
+    assert max(err.values()) <= 1e-4, err
+    assert float(g[2].max()) > 0.3
+
+
+def test_fused_implicit_preheated_cooldown(torch, ctx, orc):
+    """A track on a body preheated to 1000 K, then 1 s in steps of 20 ms
+    (two substeps each): diffusive transformations everywhere, the implicit
+    scheme with subcycling in the fused kernel against the oracle."""
+    import dataclasses
+
+    import paper_2402_17580_amd as ms
+    import workload
+    wl0 = workload.single_track(nx=32, ny=32, nz=8)
+    scan = dataclasses.replace(wl0.scan, T0=1000.0)
+    n = wl0.grid.n
+    g = [torch.from_numpy(x).cuda() for x in workload.initial_state(n, np.float32)]
+    xyz = wl0.grid.coords(np.arange(n))
+    st = orc.State.initial(n)
+    ctx.implicit_unconverged(reset=True)
+    # the scan itself (600 steps of 1 us), then the cool-down calls
+    for t0, dt, steps, K in ((0.0, 1e-6, 600, 16), (6e-4, 0.02, 50, 8)):
+        ctx.fused_scan_steps(scan, wl0.grid, t0, dt, steps, K, *g, mode=ms.MODE_IMPLICIT)
+        bad = orc.scan_run_implicit(scan, xyz, st, 0.0, wl0.grid.h, t0, dt, steps)
+        assert bad == 0
+    assert ctx.implicit_unconverged() == 0
+    err = _errors(torch, g, st)
+    assert max(err.values()) <= 1e-4, err
+    # the long steps transformed alpha_s towards the 1000 K equilibrium
+    assert abs(float(st.alpha_s.mean()) - 0.9) > 0.01

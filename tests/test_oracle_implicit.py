@@ -179,3 +179,19 @@ def test_invariants_random(orc):
         assert np.all(st.alpha_s + st.alpha_m <= 0.9 + 1e-15)
         assert np.allclose(st.alpha_s + st.alpha_m + st.beta, xsol, atol=1e-14)
         T = T1
+
+
+def test_scan_run_implicit_is_stepping_with_the_scan_temperature(orc):
+    import workload
+    wl = workload.single_track()
+    idx = np.arange(0, wl.grid.n, 331)
+    xyz = wl.grid.coords(idx)
+    st1 = orc.State.initial(idx.size)
+    orc.scan_run_implicit(wl.scan, xyz, st1, 0.0, wl.grid.h, 0.0, 4e-6, 150)
+    st2 = orc.State.initial(idx.size)
+    T = orc.temperature(wl.scan, xyz, 0.0)
+    for s in range(150):
+        T1 = orc.temperature(wl.scan, xyz, (s + 1) * 4e-6)
+        orc.step_implicit(st2, T, T1, 4e-6)
+        T = T1
+    assert np.array_equal(st1.alpha_s, st2.alpha_s) and np.array_equal(st1.alpha_m, st2.alpha_m)
