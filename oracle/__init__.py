@@ -225,3 +225,20 @@ def run_workload(wl, local_points, state: State = None, threads=0, layers=None, 
 
 def num_threads():
     return lib().orc_num_threads()
+
+
+def run_phases(pw, local_points, state: State = None, threads=0):
+    """Run the phases of a phased workload at the given local point numbers
+    (scan_run for explicit phases, scan_run_implicit for implicit ones).
+    Returns (state, substeps that hit the iteration cap)."""
+    xyz = pw.grid.coords(np.asarray(local_points))
+    if state is None:
+        state = State.initial(xyz.shape[0])
+    bad = 0
+    for ph in pw.phases:
+        if ph.scheme == "implicit":
+            bad += scan_run_implicit(pw.scan, xyz, state, ph.z_top, pw.grid.h, ph.t0, ph.dt, ph.n_steps,
+                                     threads=threads)
+        else:
+            scan_run(pw.scan, xyz, state, ph.z_top, pw.grid.h, ph.t0, ph.dt, ph.n_steps, threads)
+    return state, bad

@@ -265,6 +265,15 @@ def run_layers(ctx: Context, wl, beta, alpha_s, alpha_m, K=16, mode=MODE_PLAIN, 
                              alpha_m, z_top=L.z_top, mode=mode, index=index, stream=stream)
 
 
+def run_phases(ctx: Context, pw, beta, alpha_s, alpha_m, K=16, stream=None):
+    """Run the phases of a phased workload (scan phases with the explicit
+    scheme, cool-down phases with the implicit one), one fused call each."""
+    for ph in pw.phases:
+        mode = MODE_IMPLICIT if ph.scheme == "implicit" else MODE_PLAIN
+        ctx.fused_scan_steps(pw.scan, pw.grid, ph.t0, ph.dt, ph.n_steps, K, beta, alpha_s, alpha_m, z_top=ph.z_top,
+                             mode=mode, stream=stream)
+
+
 def run_layers_stepwise(ctx: Context, wl, beta, alpha_s, alpha_m, T_a, T_b, layers=None, stream=None):
     """Run the layers with the temperature-field kernel and the plain step
     kernel (T arrays ping-pong); box grids only, active suffix per layer."""

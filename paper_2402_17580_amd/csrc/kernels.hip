@@ -107,13 +107,13 @@ __global__ __launch_bounds__(kBlock) void implicit_step_kernel(const float* __re
     const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     int bad = 0;
     if (g < n) {
-        float a = as[g], m = am[g], b = 0.0f;
+        float a = as[g], m = am[g], b = 0.0f, alo = 0.0f, mlo = 0.0f;
         const float T0 = Tp[g], dT = Tn[g] - T0;
         const float inv = 1.0f / (float)n_sub;
         float Ta = T0;
         for (int s = 0; s < n_sub; ++s) {
             const float Tb = (s + 1 == n_sub) ? Tn[g] : fmaf(dT, (float)(s + 1) * inv, T0);
-            if (implicit_step(a, m, b, Ta, Tb, h, max_iter) < 0) ++bad;
+            if (implicit_step<false>(a, m, alo, mlo, b, Ta, Tb, h, max_iter) < 0) ++bad;
             Ta = Tb;
         }
         as[g] = a;
@@ -209,8 +209,8 @@ __global__ __launch_bounds__(kBlock) void fused_plain_kernel(PointGeom pg, const
 // fused K steps with the implicit scheme: as the plain fused kernel, with the
 // Crank-Nicolson fixed-point step at every step (n_sub equal substeps of
 // length h when the step exceeds the substep limit, T linear between the
-// analytic step-end values).  No compensated accumulation: the implicit
-// scheme is meant for the longer steps of cooling phases.
+// analytic step-end values), with compensated accumulation of the increments
+// inside a launch as in the plain fused kernel.
 // ---------------------------------------------------------------------------
 template <int W>
 __global__ __launch_bounds__(kBlock) void fused_implicit_kernel(PointGeom pg, const SrcRec* __restrict__ tab, int K,
@@ -224,7 +224,7 @@ __global__ __launch_bounds__(kBlock) void fused_implicit_kernel(PointGeom pg, co
     int gi, gj, gk;
     decode_point(pg, local, gi, gj, gk);
     act = act && gk >= pg.k0;
-    float a = act ? as[local] : 0.0f, m = act ? am[local] : 0.0f, b = 0.0f;
+    float a = act ? as[local] : 0.0f, m = act ? am[local] : 0.0f, b = 0.0f, alo = 0.0f, mlo = 0.0f;
     int bad = 0;
     float Tn = scan_temperature<W>(tab, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min);
     const float inv = 1.0f / (float)n_sub;
@@ -233,15 +233,17 @@ __global__ __launch_bounds__(kBlock) void fused_implicit_kernel(PointGeom pg, co
         float Ta = Tn;
         for (int k = 0; k < n_sub; ++k) {
             const float Tb = (k + 1 == n_sub) ? Tn1 : fmaf(Tn1 - Tn, (float)(k + 1) * inv, Tn);
-            if (implicit_step(a, m, b, Ta, Tb, h, max_iter) < 0) ++bad;
+            if (implicit_step<true>(a, m, alo, mlo, b, Ta, Tb, h, max_iter) < 0) ++bad;
             Ta = Tb;
         }
         Tn = Tn1;
     }
     if (act) {
+        a += alo;
+        m += mlo;
         as[local] = a;
         am[local] = m;
-        if (beta) beta[local] = b;
+        if (beta) beta[local] = solid_fraction(Tn) - a - m;
     }
     if (!act) bad = 0;
     int total = bad;

@@ -237,21 +237,23 @@ __device__ __forceinline__ void diffusive_rates(float a, float m, float xeq, flo
 // residual over (alpha_s, alpha_m), weights 1 / (eps_abs + |m_j| eps_rel) of
 // the newest iterate, falls below 1, or after max_iter iterations.  A state
 // in a start-up regime at T^n (zero rate of a starting transformation) takes
-// the explicit step with its Appendix A closed form instead.  Returns the
-// iteration count (0 for a start-up step), negated if the stop test failed.
-__device__ __forceinline__ int implicit_step(float& a, float& m, float& beta, float Tn, float Tn1, float dt,
-                                             int max_iter) {
+// the explicit step with its Appendix A closed form instead.  With
+// COMPENSATED the increment m^{n+1} - m^n is added to (hi, lo) pairs as in
+// explicit_step.  Returns the iteration count (0 for a start-up step),
+// negated if the stop test failed.
+template <bool COMPENSATED>
+__device__ __forceinline__ int implicit_step(float& a, float& m, float& a_lo, float& m_lo, float& beta, float Tn,
+                                             float Tn1, float dt, int max_iter) {
     const float xeq_n = alpha_eq(Tn), xeq_1 = alpha_eq(Tn1);
     const float xa = a + m;
     if ((xa < xeq_n && !(a > 0.0f)) || (xa > xeq_n && fmaxf(kXmax - xa, 0.0f) * dt <= kStartupLimit)) {
-        float alo = 0.0f, mlo = 0.0f;
-        beta = explicit_step<false>(a, m, alo, mlo, Tn, xeq_n, Tn1, xeq_1, dt);
+        beta = explicit_step<COMPENSATED>(a, m, a_lo, m_lo, Tn, xeq_n, Tn1, xeq_1, dt);
         return 0;
     }
     const float k_1 = k_alpha_s(Tn1);
     float fa_n, fm_n;
     diffusive_rates(a, m, xeq_n, k_alpha_s(Tn), fa_n, fm_n);
-    float ai = a, mi = m;
+    float ai = a, mi = m, ali = 0.0f, mli = 0.0f;
     beta = correct(Tn1, xeq_1, ai, mi);
     float fa, fm;
     diffusive_rates(ai, mi, xeq_1, k_1, fa, fm);
@@ -259,14 +261,29 @@ __device__ __forceinline__ int implicit_step(float& a, float& m, float& beta, fl
     int it = 0;
     bool converged = false;
     while (it < max_iter) {
-        float a1 = fmaf(h, fa + fa_n, a), m1 = fmaf(h, fm + fm_n, m);
+        const float da = h * (fa + fa_n), dm = h * (fm + fm_n);
+        float a1, m1, al1 = 0.0f, ml1 = 0.0f;
+        if (COMPENSATED) {
+            two_sum(a, a_lo + da, a1, al1);
+            two_sum(m, m_lo + dm, m1, ml1);
+        } else {
+            a1 = a + da;
+            m1 = m + dm;
+        }
+        const float a_before = a1, m_before = m1;
         beta = correct(Tn1, xeq_1, a1, m1);
+        if (COMPENSATED) {
+            if (a1 != a_before) al1 = 0.0f;
+            if (m1 != m_before) ml1 = 0.0f;
+        }
         float fa1, fm1;
         diffusive_rates(a1, m1, xeq_1, k_1, fa1, fm1);
         const float wa = h * (fa1 - fa) * frcp(fmaf(fabsf(a1), kCnEpsRel, kCnEpsAbs));
         const float wm = h * (fm1 - fm) * frcp(fmaf(fabsf(m1), kCnEpsRel, kCnEpsAbs));
         ai = a1;
         mi = m1;
+        ali = al1;
+        mli = ml1;
         fa = fa1;
         fm = fm1;
         ++it;
@@ -277,6 +294,10 @@ __device__ __forceinline__ int implicit_step(float& a, float& m, float& beta, fl
     }
     a = ai;
     m = mi;
+    if (COMPENSATED) {
+        a_lo = ali;
+        m_lo = mli;
+    }
     return converged ? it : -it;
 }
 

@@ -275,6 +275,79 @@ def multilayer_block(nx=256, ny=256, nz=128, n_layers=10, layer_thick=30e-6,
     return Workload("multilayer_block", grid, scan, layers, dt, seed)
 
 
+@dataclasses.dataclass
+class Phase:
+    """n_steps steps of dt from simulated time t0 with one scheme
+    ("explicit" or "implicit"); points above z_top are inactive."""
+    t0: float
+    dt: float
+    n_steps: int
+    z_top: float
+    scheme: str
+
+
+@dataclasses.dataclass
+class PhasedWorkload:
+    name: str
+    grid: Grid
+    scan: Scan
+    phases: List[Phase]
+    seed: int
+
+    def point_updates(self) -> int:
+        g = self.grid
+        return sum((g.nz - g.first_active_k(p.z_top)) * g.nx * g.ny * p.n_steps for p in self.phases)
+
+
+def cooldown_schedule(t_start, duration, dt_first, n_first=2000, double_every=10, dt_max=0.1):
+    """Time steps of a cool-down phase as in the paper's cube example
+    (Sec. 4.2): n_first steps of dt_first, then the step doubled after every
+    `double_every` steps up to dt_max, until t_start + duration (the last step
+    shortened to end there).  Returns [(t0, dt, n_steps)] segments."""
+    segs = []
+    t, t_end = t_start, t_start + duration
+    dt, n = dt_first, n_first
+    while t_end - t > 1e-12:
+        fit = int(math.floor((t_end - t) / dt * (1.0 + 1e-12)))
+        k = min(n, fit)
+        if k > 0:
+            segs.append((t, dt, k))
+            t = t + k * dt
+        if k < n:
+            if t_end - t > 1e-12:
+                segs.append((t, t_end - t, 1))
+            break
+        dt, n = min(2.0 * dt, dt_max), double_every
+    return segs
+
+
+def multilayer_cooldown(nx=256, ny=256, nz=128, n_layers=10, layer_thick=30e-6, steps_per_layer=2000,
+                        dt=2e-6, hatch=100e-6, cooldown=1.0, seed=1002, window=2) -> PhasedWorkload:
+    """The multi-layer block with the paper's inter-layer cool-down: each layer
+    is scanned for steps_per_layer steps of dt (explicit scheme), then cools
+    for `cooldown` seconds on the schedule of cooldown_schedule (implicit
+    scheme, substeps of at most 0.01 s).  Same seeded scan lines as
+    multilayer_block, each layer starting after the previous cool-down."""
+    h = 10e-6
+    grid = Grid(nx, ny, nz, h)
+    rng = np.random.default_rng(seed)
+    width = nx * h
+    n_lines = int(round(ny * h / hatch))
+    active = steps_per_layer * dt
+    rows, phases = [], []
+    for ell in range(n_layers):
+        z_top = -(n_layers - 1 - ell) * layer_thick
+        first = int(rng.integers(0, max(1, n_lines - 1)))
+        t_layer = ell * (active + cooldown)
+        lines = hatch_lines_x(0.0, width, 0.5 * hatch, hatch, n_lines, first)
+        rows += serpentine_layer(t_layer, t_layer + active, z_top, lines, Q_ABS, V_SCAN)
+        phases.append(Phase(t_layer, dt, steps_per_layer, z_top, "explicit"))
+        for (t0, d, k) in cooldown_schedule(t_layer + steps_per_layer * dt, cooldown, dt):
+            phases.append(Phase(t0, d, k, z_top, "implicit"))
+    scan = Scan(np.array(rows, dtype=np.float64), K_W, ALPHA, T0, T_CLAMP, window)
+    return PhasedWorkload("multilayer_cooldown", grid, scan, phases, seed)
+
+
 def island_scan(nx, ny, nz, n_layers, layer_thick, steps_per_layer, dt, seed,
                 island=5e-3, hatch=100e-6, window=2, index=None, name="island_scan"):
     """Island scan: square islands of `island` size tiled over the box top,
