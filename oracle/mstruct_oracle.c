@@ -46,6 +46,11 @@
  *       in both schemes.
  *   R15 subcycling: a step longer than dt_sub is split into the fewest equal
  *       substeps not longer than dt_sub, with T linear in time.
+ *   R16 a switched-off track is the difference of two moving sources that
+ *       share a virtual current position beyond the end point; its field is
+ *       smooth there but the closed form is 0/0 at it, so within 0.5 um of
+ *       that position it is evaluated 0.5 um below it (the clamp applies
+ *       only near a switched-on source).
  */
 #include <math.h>
 #include <stdint.h>
@@ -391,7 +396,8 @@ int64_t orc_step_implicit_n(int64_t n, double *as, double *am, double *b, double
  * T = min(T_clamp, T0 + sum over the last `window` tracks switched on by t).
  */
 
-#define R_EPS 1e-9 /* [m]: closer than this to a source the clamp applies */
+#define R_EPS 1e-9 /* [m]: closer than this to a switched-on source the clamp applies */
+#define R_OFF 5e-7 /* [m]: see reading R16 */
 
 /* erfcx(y) = exp(y^2) erfc(y) for y >= 0: direct product below 25, above it
  * the asymptotic series of Abramowitz & Stegun 7.1.23. */
@@ -460,11 +466,24 @@ double orc_temperature(const double *tracks, int64_t n_tracks, const double *sp,
         double ux = tr[3], uy = tr[4], v = tr[8], dur = tr[6];
         double xs = tr[0] + v * tau * ux, ys = tr[1] + v * tau * uy;
         double dx = x - xs, dy = y - ys, dz = z - tr[2];
-        if (sqrt(dx * dx + dy * dy + dz * dz) < R_EPS) return Tc;
-        double C = orc_source_F(tr, tau, k, alpha, x, y, z);
+        double R = sqrt(dx * dx + dy * dy + dz * dz);
+        double px = x, py = y, pz = z;
+        if (tau > dur) {
+            /* switched off: the current position is virtual and the field is
+             * smooth there (the two singular parts cancel exactly); within
+             * R_OFF of it the contribution is taken at R_OFF below it (R16) */
+            if (R < R_OFF) {
+                px = xs;
+                py = ys;
+                pz = tr[2] - R_OFF;
+            }
+        } else if (R < R_EPS) {
+            return Tc;
+        }
+        double C = orc_source_F(tr, tau, k, alpha, px, py, pz);
         if (tau > dur) {
             double x1 = tr[0] + v * dur * ux, y1 = tr[1] + v * dur * uy;
-            C -= source_F(x1, y1, tr[2], ux, uy, tr[7], v, tau - dur, k, alpha, x, y, z);
+            C -= source_F(x1, y1, tr[2], ux, uy, tr[7], v, tau - dur, k, alpha, px, py, pz);
         }
         T += C;
     }

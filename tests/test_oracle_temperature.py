@@ -89,6 +89,20 @@ def test_switched_off_track_matches_quadrature(orc):
         assert T == pytest.approx(ref, rel=1e-9)
 
 
+def test_switched_off_track_is_smooth_at_its_virtual_position(orc):
+    # after switch-off the closed form is a difference of two sources with a
+    # common (virtual) current position; the field there is finite, matches
+    # the quadrature of the pulses actually emitted, and is not clamped
+    dur = 300e-6
+    sc = _scan([[0, 0, 0, 1, 0, 0.0, dur, Q, V]], window=1)
+    for t in (330e-6, 340e-6, 350e-6, 400e-6):
+        p = (V * t, 0.0, 0.0)
+        T = orc.temperature(sc, np.array(p), t)[0]
+        ref = 300.0 + quad_T(*p, t - dur, t, t=t)
+        assert 300.0 < T < 1928.0
+        assert T - 300.0 == pytest.approx(ref - 300.0, rel=2e-3), (t, T, ref)
+
+
 def test_window_superposition_and_clamp(orc):
     rows = [[0, 0, 0, 1, 0, 0.0, 200e-6, Q, V],
             [2e-4, 1e-4, 0, -1, 0, 200e-6, 200e-6, Q, V],
