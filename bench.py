@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-stepwise", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
+    ap.add_argument("--no-cooldown", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--threads", type=int, default=0)
@@ -173,6 +174,9 @@ def main():
     if not args.no_stepwise:
         result["plain_step"] = bench_stepwise(torch, ms, ctx, wl, dev)
         result["implicit_step"] = bench_implicit(torch, ms, ctx, wl, final_state)
+        result["divergence"] = bench_divergence(torch, ctx, n)
+    if not args.no_cooldown:
+        result["cooldown"], cool_state = bench_cooldown(torch, ms, ctx)
 
     if args.copy_probe:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
@@ -189,6 +193,13 @@ def main():
         result["errors_vs_oracle"] = errors(final_state, st, idx)
         for key, state in sur_states.items():
             result[key]["errors_vs_oracle"] = errors(state, st, idx)
+        if not args.no_cooldown:
+            import oracle
+            pw = workload.multilayer_cooldown()
+            cidx = workload.sample_indices(pw.grid.n, 1e-3, pw.seed)
+            cst, _ = oracle.run_phases(pw, cidx, threads=args.threads or min(16, os.cpu_count() or 1))
+            result["cooldown"]["errors_vs_oracle"] = errors(cool_state, cst, cidx)
+            result["cooldown"]["errors_sample"] = f"{cidx.size} seeded points (p=1e-3)"
 
     print(json.dumps(result))
     ctx.close()
@@ -282,6 +293,88 @@ def bench_implicit(torch, ms, ctx, wl, state):
             entry["valu_frac"] = n * ops / avg / 1e12 / VALU_PEAK_TLANEOPS
         out[key] = entry
     out["unconverged_substeps"] = int(unc.item())
+    return out
+
+
+def bench_cooldown(torch, ms, ctx):
+    """The multi-layer block with the paper's inter-layer cool-down (each
+    layer: 2000 scan steps of 2 us, explicit; then 1 s of cool-down on the
+    doubling schedule, implicit with 0.01 s substeps), one run."""
+    pw = workload.multilayer_cooldown()
+    n = pw.grid.n
+    g = [torch.from_numpy(x).cuda() for x in workload.initial_state(n, np.float32)]
+    ms.run_phases(ctx, pw, *g)  # warm-up
+    for dst, src in zip(g, workload.initial_state(n, np.float32)):
+        dst.copy_(torch.from_numpy(src))
+    ctx.implicit_unconverged(reset=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    ms.run_phases(ctx, pw, *g)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3
+    upd = pw.point_updates()
+    scan_upd = sum((pw.grid.nz - pw.grid.first_active_k(p.z_top)) * pw.grid.nx * pw.grid.ny * p.n_steps
+                   for p in pw.phases if p.scheme == "explicit")
+    return {"value": upd / t, "unit": "point-updates/s", "seconds": t, "point_updates": upd,
+            "scan_point_updates": scan_upd, "simulated_s": pw.phases[-1].t0 + pw.phases[-1].dt * pw.phases[-1].n_steps,
+            "calls": len(pw.phases), "unconverged_substeps": ctx.implicit_unconverged(),
+            "path": "run_phases: fused PLAIN while scanning, fused IMPLICIT while cooling (K = 16)"}, g
+
+
+def bench_divergence(torch, ctx, n):
+    """Cost of branch divergence (the paper's synthetic layouts, Sec. 4.1):
+    points of two kinds that take different branches of the update, laid out
+    alternating, in blocks of 10, 64 (one wave) and 100, or all of one kind.
+    Kind A: a diffusive state at 1050-1150 K (the three rate laws); kind B: pure
+    beta at 1000 K (the closed-form start of diffusion).  Explicit
+    (mstruct_step, HBM-bound) and implicit (mstruct_step_implicit, dt = 1 ms)
+    steps on n points; point-updates/s per layout."""
+    g = torch.Generator(device="cuda")
+    g.manual_seed(77)
+    idx = torch.arange(n, device="cuda")
+    TA0 = 1050.0 + 100.0 * torch.rand(n, device="cuda", generator=g)
+    TA1 = TA0 + 2.0
+    aA = 0.2 + 0.3 * torch.rand(n, device="cuda", generator=g)
+    mA = 0.1 * torch.rand(n, device="cuda", generator=g)
+    layouts = {"uniform_A": torch.zeros(n, dtype=torch.bool, device="cuda"),
+               "uniform_B": torch.ones(n, dtype=torch.bool, device="cuda"),
+               "alternating": (idx % 2) == 1, "blocks_10": ((idx // 10) % 2) == 1,
+               "blocks_64": ((idx // 64) % 2) == 1, "blocks_100": ((idx // 100) % 2) == 1}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = {"points": n, "kinds": "A: diffusive state at 1050-1150 K; B: pure beta at 1000 K (start-up)"}
+    for name, kb in layouts.items():
+        Tp = torch.where(kb, torch.full_like(TA0, 1000.0), TA0)
+        Tn = torch.where(kb, torch.full_like(TA0, 1000.0), TA1)
+        a0 = torch.where(kb, torch.zeros_like(aA), aA)
+        m0 = torch.where(kb, torch.zeros_like(mA), mA)
+        b0 = 1.0 - a0 - m0
+        entry = {}
+        for scheme, dt, reps in (("explicit", 2e-6, 50), ("implicit", 1e-3, 50)):
+            b, a, m = b0.clone(), a0.clone(), m0.clone()
+            call = ctx.step if scheme == "explicit" else ctx.step_implicit
+            call(Tp, Tn, dt, b, a, m)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                b.copy_(b0)
+                a.copy_(a0)
+                m.copy_(m0)
+            e1.record()
+            torch.cuda.synchronize()
+            copies = e0.elapsed_time(e1)
+            e0.record()
+            for _ in range(reps):
+                b.copy_(b0)
+                a.copy_(a0)
+                m.copy_(m0)
+                call(Tp, Tn, dt, b, a, m)
+            e1.record()
+            torch.cuda.synchronize()
+            avg = (e0.elapsed_time(e1) - copies) * 1e-3 / reps
+            entry[scheme] = {"point_updates_per_s": n / avg, "avg_launch_us": avg * 1e6}
+        out[name] = entry
     return out
 
 

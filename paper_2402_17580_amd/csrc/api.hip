@@ -124,6 +124,7 @@ int make_geom(mstruct_ctx* ctx, const mstruct_points* p, int64_t n, PointGeom& p
     pg.nxy = (int32_t)(p->nx * p->ny);
     pg.k0 = (int32_t)k0;
     pg.r2min = (float)((1e-9 / p->h) * (1e-9 / p->h));
+    pg.roff = (float)(5e-7 / p->h);
     if (p->index) {
         pg.first = 0;
         pg.count = n;

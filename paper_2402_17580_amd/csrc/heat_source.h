@@ -78,13 +78,26 @@ __device__ __forceinline__ float scaled_erfcx(float y, float lg) {
 constexpr float kLog2DropK = -13.2877f;  // log2(1e-4)
 
 // Contribution of one slot at grid point (gi, gj, gk) (z grid coordinate -gk).
-// Returns +inf when the point is within sqrt(r2min) of the source (clamp applies).
-__device__ __forceinline__ float source_rise(const SrcRec& s, int gi, int gj, int gk, float r2min) {
-    const float dx = (float)(gi - s.ix) - s.fx;
-    const float dy = (float)(gj - s.iy) - s.fy;
-    const float dz = (float)(-gk - s.iz) - s.fz;
-    const float R2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-    if (R2 < r2min) return __builtin_inff();
+// Returns +inf when the point is within sqrt(r2min) of a switched-on source
+// (the clamp applies).  A switched-off track is the difference of two sources
+// sharing a virtual current position; its field is smooth there, but the
+// closed form is 0/0 at it, so within roff of that position the contribution
+// is taken roff below it.
+__device__ __forceinline__ float source_rise(const SrcRec& s, int gi, int gj, int gk, float r2min, float roff) {
+    float dx = (float)(gi - s.ix) - s.fx;
+    float dy = (float)(gj - s.iy) - s.fy;
+    float dz = (float)(-gk - s.iz) - s.fz;
+    float R2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    if (s.is1 > 0.0f) {
+        if (R2 < roff * roff) {
+            dx = 0.0f;
+            dy = 0.0f;
+            dz = -roff;
+            R2 = roff * roff;
+        }
+    } else if (R2 < r2min) {
+        return __builtin_inff();
+    }
     const float rR = __builtin_amdgcn_rsqf(R2);
     const float R = R2 * rR;
     const float xi = fmaf(dx, s.ux, dy * s.uy);
@@ -136,12 +149,12 @@ __device__ __forceinline__ float source_rise(const SrcRec& s, int gi, int gj, in
 
 template <int W>
 __device__ __forceinline__ float scan_temperature(const SrcRec* __restrict__ recs, int gi, int gj, int gk,
-                                                  float T0, float Tclamp, float r2min) {
+                                                  float T0, float Tclamp, float r2min, float roff) {
     float T = T0;
 #pragma unroll
     for (int w = 0; w < W; ++w) {
         const SrcRec s = recs[w];
-        if (s.lamp > -1e30f) T += source_rise(s, gi, gj, gk, r2min);
+        if (s.lamp > -1e30f) T += source_rise(s, gi, gj, gk, r2min, roff);
     }
     return fminf(T, Tclamp);
 }

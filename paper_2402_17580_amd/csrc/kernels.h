@@ -14,7 +14,8 @@ struct PointGeom {
     int64_t count;         // number of local points processed
     int32_t nx, nxy;       // box dimensions
     int32_t k0;            // points on planes k < k0 are inactive
-    float r2min;           // squared clamp radius [grid units^2]
+    float r2min;           // squared clamp radius around a switched-on source [grid units^2]
+    float roff;            // radius around a switched-off track's virtual position [grid units]
 };
 
 // scan constants of one call

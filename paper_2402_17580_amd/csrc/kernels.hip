@@ -148,7 +148,7 @@ __global__ __launch_bounds__(kBlock) void temperature_kernel(PointGeom pg, const
     const int64_t local = pg.first + g;
     int gi, gj, gk;
     decode_point(pg, local, gi, gj, gk);
-    T[local] = (gk < pg.k0) ? sa.T0 : scan_temperature<W>(rec, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min);
+    T[local] = (gk < pg.k0) ? sa.T0 : scan_temperature<W>(rec, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
 }
 
 // ---------------------------------------------------------------------------
@@ -182,13 +182,13 @@ __global__ __launch_bounds__(kBlock) void fused_plain_kernel(PointGeom pg, const
     }
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
-        Tn[u] = scan_temperature<W>(tab, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min);
+        Tn[u] = scan_temperature<W>(tab, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min, pg.roff);
         xeq_n[u] = alpha_eq(Tn[u]);
     }
     for (int s = 0; s < K; ++s) {
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
-            const float Tn1 = scan_temperature<W>(tab + (s + 1) * W, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min);
+            const float Tn1 = scan_temperature<W>(tab + (s + 1) * W, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min, pg.roff);
             const float xeq_n1 = alpha_eq(Tn1);
             explicit_step<true>(a[u], m[u], alo[u], mlo[u], Tn[u], xeq_n[u], Tn1, xeq_n1, dt);
             Tn[u] = Tn1;
@@ -226,10 +226,10 @@ __global__ __launch_bounds__(kBlock) void fused_implicit_kernel(PointGeom pg, co
     act = act && gk >= pg.k0;
     float a = act ? as[local] : 0.0f, m = act ? am[local] : 0.0f, b = 0.0f, alo = 0.0f, mlo = 0.0f;
     int bad = 0;
-    float Tn = scan_temperature<W>(tab, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min);
+    float Tn = scan_temperature<W>(tab, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
     const float inv = 1.0f / (float)n_sub;
     for (int s = 0; s < K; ++s) {
-        const float Tn1 = scan_temperature<W>(tab + (s + 1) * W, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min);
+        const float Tn1 = scan_temperature<W>(tab + (s + 1) * W, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
         float Ta = Tn;
         for (int k = 0; k < n_sub; ++k) {
             const float Tb = (k + 1 == n_sub) ? Tn1 : fmaf(Tn1 - Tn, (float)(k + 1) * inv, Tn);

@@ -577,6 +577,15 @@ __device__ __forceinline__ bool needs_plain(float T0, float TK, const MlpNorm& n
 
 // tin and tout may be the same buffer (a point's block-start temperature is
 // read before its block-end temperature is written), so they are not restrict.
+// A point at its martensite formation front: within kFrontProbe of the lower
+// block-end temperature the formation law would raise alpha_m, so a dip of the
+// temperature inside the block would form martensite the block ends miss.
+constexpr float kFrontProbe = 5.0f;  // [K]
+__device__ __forceinline__ bool formation_front(float T0, float TK, float a, float m) {
+    const float Tlo = fminf(T0, TK) - kFrontProbe;
+    return Tlo < kTamStart && am0_eq(Tlo) * (kXmax - a) * (1.0f / kXmax) > m;
+}
+
 template <int W, int PPT>
 __global__ __launch_bounds__(256) void surrogate_a_kernel(PointGeom pg, const SrcRec* __restrict__ tab, int K,
                                                          float dt, ScanArgs sa, float* __restrict__ beta,
@@ -617,11 +626,11 @@ __global__ __launch_bounds__(256) void surrogate_a_kernel(PointGeom pg, const Sr
         // block-end temperature: independent of the loads above
 #pragma unroll
         for (int u = 0; u < PPT; ++u)
-            TK[u] = scan_temperature<W>(tab + K * W, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min);
+            TK[u] = scan_temperature<W>(tab + K * W, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min, pg.roff);
         if (!tin) {
 #pragma unroll
             for (int u = 0; u < PPT; ++u)
-                T0[u] = scan_temperature<W>(tab, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min);
+                T0[u] = scan_temperature<W>(tab, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min, pg.roff);
         }
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
@@ -639,11 +648,19 @@ __global__ __launch_bounds__(256) void surrogate_a_kernel(PointGeom pg, const Sr
             if (valid[u]) {
                 float an = a[u], mn = m[u], bn;
                 const float xeq0 = alpha_eq(T0[u]);
-                if (needs_plain(T0[u], TK[u], nrm)) {
+                bool plain = needs_plain(T0[u], TK[u], nrm);
+                if (!plain && formation_front(T0[u], TK[u], a[u], m[u])) {
+                    // martensite forms at the lowest temperature of the block:
+                    // a dip below both ends (probed at the block middle) needs the plain steps
+                    const float Tmid = scan_temperature<W>(tab + (K / 2) * W, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp,
+                                                           pg.r2min, pg.roff);
+                    plain = Tmid < fminf(T0[u], TK[u]);
+                }
+                if (plain) {
                     float alo = 0.0f, mlo = 0.0f, Tn = T0[u], xeq_n = xeq0;
                     for (int s = 0; s < K; ++s) {
                         const float Tn1 = scan_temperature<W>(tab + (s + 1) * W, gi[u], gj[u], gk[u], sa.T0,
-                                                              sa.Tclamp, pg.r2min);
+                                                              sa.Tclamp, pg.r2min, pg.roff);
                         const float xeq_n1 = alpha_eq(Tn1);
                         explicit_step<true>(an, mn, alo, mlo, Tn, xeq_n, Tn1, xeq_n1, dt);
                         Tn = Tn1;
