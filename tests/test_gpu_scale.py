@@ -60,3 +60,34 @@ def test_island_block_plain_and_surrogate(torch, ctx, orc):
             assert mx <= tol, (mode, k, err)
         assert ctx.check_invariants(*g, tol=2e-6) == 0
         del g
+
+
+@pytest.mark.parametrize("weights", ["k8", "k16"])
+def test_multilayer_block_surrogate_sampled(torch, ctx, orc, weights):
+    """The benchmark block with each shipped network; a seeded 1 % sample
+    (83,886 points) against the oracle, bar 1e-3."""
+    import paper_2402_17580_amd as ms
+    from paper_2402_17580_amd import surrogate as S
+    sur = S.Surrogate.load(S.DEFAULT_WEIGHTS if weights == "k8" else S.WEIGHTS_K16)
+    sur.load_into(ctx)
+    wl = workload.multilayer_block()
+    n = wl.grid.n
+    g = [torch.from_numpy(x).cuda() for x in workload.initial_state(n, np.float32)]
+    ms.run_layers(ctx, wl, *g, K=sur.K, mode=ms.MODE_SURROGATE)
+    torch.cuda.synchronize()
+    idx = workload.sample_indices(n, 1e-2, wl.seed)
+    st = _oracle_c2(orc, wl, idx)
+    err = _errors(g, st, idx)
+    print("multilayer block surrogate", weights, idx.size, err, flush=True)
+    for k, (mx, rms) in err.items():
+        assert mx <= 1e-3, (k, err)
+    assert ctx.check_invariants(*g, tol=2e-6) == 0
+
+
+_C2_CACHE = {}
+
+
+def _oracle_c2(orc, wl, idx):
+    if "st" not in _C2_CACHE:
+        _C2_CACHE["st"] = orc.run_workload(wl, idx)
+    return _C2_CACHE["st"]
