@@ -211,9 +211,9 @@ def main():
 # HBM bytes per launch (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0: the factors a
 # plain 1 GiB device copy reads on the same counters).
 FUSED_PROFILE = {
-    "valu_lane_ops_per_update": 210.47,
-    "fp32_flops_per_update": 162.8,
-    "traffic_bytes_per_launch": (29387.88 * 2.0 + 58858.50) * 1024,
+    "valu_lane_ops_per_update": 212.69,
+    "fp32_flops_per_update": 158.5,
+    "traffic_bytes_per_launch": (29391.52 * 2.0 + 58858.50) * 1024,
 }
 
 def bench_stepwise(torch, ms, ctx, wl, dev):
