@@ -1,49 +1,79 @@
 // Device (gfx950) implementation of the Ti-6Al-4V phase model of Proell et
-// al., arXiv 2402.17580, Sec. 2.2 and Sec. 3.1, in float32.
+// al., arXiv 2402.17580, Sec. 2.2 and Sec. 3.1, generic in the real type.
 //
-// Transcendentals go to the hardware units: v_exp_f32 / v_log_f32 are base-2,
-// so powers a^p (eq. power_exp_log) are exp2(p * log2 a); a = 0 gives
-// log2 = -inf and exp2(-inf) = 0, which is the value of the rate factors at
-// a zero fraction.  1 - exp(-x) in the Koistinen-Marburger laws uses a
-// Taylor polynomial for small x so that the equilibria stay accurate near
-// their start temperatures.
+// float (the hot path): transcendentals go to the hardware units; v_exp_f32 /
+// v_log_f32 are base-2, so powers a^p (eq. power_exp_log) are
+// exp2(p * log2 a); a = 0 gives log2 = -inf and exp2(-inf) = 0, which is the
+// value of the rate factors at a zero fraction.  1 - exp(-x) in the
+// Koistinen-Marburger laws uses a Taylor polynomial for small x so that the
+// equilibria stay accurate near their start temperatures.
+//
+// double: the translation unit that instantiates the model in double defines
+// fexp2, flog2, frcp and one_minus_exp_neg for double (declared below) before
+// use, and sets MSTRUCT_MODEL_NS to a namespace of its own, so that each
+// choice of double math is a separate set of functions.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-namespace mstruct {
+#ifndef MSTRUCT_MODEL_NS
+#define MSTRUCT_MODEL_NS mstruct
+#endif
 
-// Table 1 / Table 2 / Table 3 of the paper and T_as,reg = 100 K (Sec. 2.2)
-constexpr float kTsol = 1878.0f;
-constexpr float kTliq = 1928.0f;
-constexpr float kTinf = 293.0f;
-constexpr float kTasStart = 1273.0f;
-constexpr float kTasEnd = 935.0f;
-constexpr float kTamStart = 848.0f;
-constexpr float kKalphaEq = 0.0068f;
-constexpr float kKamEq = 0.00415f;
-constexpr float kCas = 2.51f;
-constexpr float kCbeta = 11.0f;
-constexpr float kK1 = 0.294f;
-constexpr float kK2 = 850.0f;
-constexpr float kK3 = 0.0337f;
-constexpr float kF = 3.8f;
-constexpr float kTreg = 100.0f;
-constexpr float kXmax = 0.9f;            // maximum alpha fraction
-constexpr float kStartupLimit = 1e-15f;  // Appendix A exit test on X~beta * dt
-constexpr float kCnEpsAbs = 1e-10f;      // WRMS weights of the implicit scheme (Sec. 3.1)
-constexpr float kCnEpsRel = 1e-3f;
+namespace MSTRUCT_MODEL_NS {
 
-// exponents (c -/+ 1)/c of the generalised logistic rates
-constexpr float kPa = (kCas - 1.0f) / kCas;
-constexpr float kQa = (kCas + 1.0f) / kCas;
-constexpr float kPb = (kCbeta - 1.0f) / kCbeta;
-constexpr float kQb = (kCbeta + 1.0f) / kCbeta;
-constexpr float kLog2e = 1.4426950408889634f;
+// Table 1 / Table 2 / Table 3 of the paper and T_as,reg = 100 K (Sec. 2.2),
+// in the model's real type
+template <class R>
+struct Const {
+    static constexpr R Tsol = R(1878.0);
+    static constexpr R Tliq = R(1928.0);
+    static constexpr R Tinf = R(293.0);
+    static constexpr R TasStart = R(1273.0);
+    static constexpr R TasEnd = R(935.0);
+    static constexpr R TamStart = R(848.0);
+    static constexpr R KalphaEq = R(0.0068);
+    static constexpr R KamEq = R(0.00415);
+    static constexpr R Cas = R(2.51);
+    static constexpr R Cbeta = R(11.0);
+    static constexpr R K1 = R(0.294);
+    static constexpr R K2 = R(850.0);
+    static constexpr R K3 = R(0.0337);
+    static constexpr R F = R(3.8);
+    static constexpr R Treg = R(100.0);
+    static constexpr R Xmax = R(0.9);            // maximum alpha fraction
+    static constexpr R StartupLimit = R(1e-15);  // Appendix A exit test on X~beta * dt
+    static constexpr R CnEpsAbs = R(1e-10);      // WRMS weights of the implicit scheme (Sec. 3.1)
+    static constexpr R CnEpsRel = R(1e-3);
+    // exponents (c -/+ 1)/c of the generalised logistic rates
+    static constexpr R Pa = (Cas - R(1)) / Cas;
+    static constexpr R Qa = (Cas + R(1)) / Cas;
+    static constexpr R Pb = (Cbeta - R(1)) / Cbeta;
+    static constexpr R Qb = (Cbeta + R(1)) / Cbeta;
+    static constexpr R Log2e = R(1.4426950408889634);
+};
+
+// float constants used by the kernels
+constexpr float kTasStart = Const<float>::TasStart;
+constexpr float kTamStart = Const<float>::TamStart;
+constexpr float kXmax = Const<float>::Xmax;
+constexpr float kLog2e = Const<float>::Log2e;
 
 __device__ __forceinline__ float fexp2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float flog2(float x) { return __builtin_amdgcn_logf(x); }
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fexp2(double x);
+__device__ __forceinline__ double flog2(double x);
+__device__ __forceinline__ double frcp(double x);
+
+__device__ __forceinline__ float vfma(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double vfma(double a, double b, double c) { return fma(a, b, c); }
+__device__ __forceinline__ float vmax(float a, float b) { return fmaxf(a, b); }
+__device__ __forceinline__ double vmax(double a, double b) { return fmax(a, b); }
+__device__ __forceinline__ float vmin(float a, float b) { return fminf(a, b); }
+__device__ __forceinline__ double vmin(double a, double b) { return fmin(a, b); }
+__device__ __forceinline__ float vabs(float a) { return fabsf(a); }
+__device__ __forceinline__ double vabs(double a) { return fabs(a); }
 
 // 1 - exp(-x) for x >= 0, accurate to a few ulp of the result
 __device__ __forceinline__ float one_minus_exp_neg(float x) {
@@ -59,80 +89,90 @@ __device__ __forceinline__ float one_minus_exp_neg(float x) {
     }
     return 1.0f - fexp2(-x * kLog2e);
 }
+__device__ __forceinline__ double one_minus_exp_neg(double x);
 
 // liquid fraction g(T), eq. liquid_fraction; X_sol = 1 - g
-__device__ __forceinline__ float solid_fraction(float T) {
-    if (T < kTsol) return 1.0f;
-    if (T > kTliq) return 0.0f;
-    return 1.0f - (T - kTsol) * (1.0f / (kTliq - kTsol));
+template <class R>
+__device__ __forceinline__ R solid_fraction(R T) {
+    using C = Const<R>;
+    if (T < C::Tsol) return R(1);
+    if (T > C::Tliq) return R(0);
+    return R(1) - (T - C::Tsol) * (R(1) / (C::Tliq - C::Tsol));
 }
 
 // X_alpha^eq(T), eq. equilibrium_phase_as
-__device__ __forceinline__ float alpha_eq(float T) {
-    if (T < kTasEnd) return kXmax;
-    if (T > kTasStart) return 0.0f;
-    return one_minus_exp_neg(kKalphaEq * (kTasStart - T));
+template <class R>
+__device__ __forceinline__ R alpha_eq(R T) {
+    using C = Const<R>;
+    if (T < C::TasEnd) return C::Xmax;
+    if (T > C::TasStart) return R(0);
+    return one_minus_exp_neg(C::KalphaEq * (C::TasStart - T));
 }
 
 // X_alpha_m,0^eq(T), eq. equilibrium_phase_am0 (zero above the martensite start)
-__device__ __forceinline__ float am0_eq(float T) {
-    if (T < kTinf) return kXmax;
-    if (T > kTamStart) return 0.0f;
-    return one_minus_exp_neg(kKamEq * (kTamStart - T));
+template <class R>
+__device__ __forceinline__ R am0_eq(R T) {
+    using C = Const<R>;
+    if (T < C::Tinf) return C::Xmax;
+    if (T > C::TamStart) return R(0);
+    return one_minus_exp_neg(C::KamEq * (C::TamStart - T));
 }
 
 // k_alpha_s(T) = k1 / (1 + exp(-k3 (T - k2)))
-__device__ __forceinline__ float k_alpha_s(float T) {
-    return kK1 * frcp(1.0f + fexp2(-kK3 * kLog2e * (T - kK2)));
+template <class R>
+__device__ __forceinline__ R k_alpha_s(R T) {
+    using C = Const<R>;
+    return C::K1 * frcp(R(1) + fexp2(-C::K3 * C::Log2e * (T - C::K2)));
 }
 
 // Appendix A closed form: fraction X = D xi after dt for
 // xi' = kt xi^((c-1)/c) (1-xi)^((c+1)/c) at constant kt.
-__device__ __forceinline__ float logistic_step(float X, float D, float kt, float c, float inv_c,
-                                               float dt) {
-    if (!(D > 0.0f)) return X;
-    float xi = fmaxf(X, 0.0f) * frcp(D);
-    if (!(xi < 1.0f)) return X;
-    float u = fexp2(inv_c * flog2(xi * frcp(1.0f - xi)));  // (xi/(1-xi))^(1/c); 0 at xi = 0
-    float w = c * frcp(fmaf(kt, dt, c * u));
-    float wc = fexp2(c * flog2(w));  // overflow -> inf -> result 0
-    return D * frcp(1.0f + wc);
+template <class R>
+__device__ __forceinline__ R logistic_step(R X, R D, R kt, R c, R inv_c, R dt) {
+    if (!(D > R(0))) return X;
+    R xi = vmax(X, R(0)) * frcp(D);
+    if (!(xi < R(1))) return X;
+    R u = fexp2(inv_c * flog2(xi * frcp(R(1) - xi)));  // (xi/(1-xi))^(1/c); 0 at xi = 0
+    R w = c * frcp(vfma(kt, dt, c * u));
+    R wc = fexp2(c * flog2(w));  // overflow -> inf -> result 0
+    return D * frcp(R(1) + wc);
 }
 
 // Diffusive increments over one explicit step (eq. explicit_integration) at
 // T^n: beta -> alpha_s, alpha_m -> alpha_s, alpha_s -> beta, with the
 // closed-form start from zero-rate states.  X~beta = 0.9 - X_alpha.
-__device__ __forceinline__ void diffusive_increment(float a, float m, float Tn, float xeq, float dt,
-                                                    float& da, float& dm) {
-    float xa = a + m;
-    da = 0.0f;
-    dm = 0.0f;
-    const bool grow = xa < xeq, dissolve = xa > xeq, marten = m > 0.0f;
+template <class R>
+__device__ __forceinline__ void diffusive_increment(R a, R m, R Tn, R xeq, R dt, R& da, R& dm) {
+    using C = Const<R>;
+    R xa = a + m;
+    da = R(0);
+    dm = R(0);
+    const bool grow = xa < xeq, dissolve = xa > xeq, marten = m > R(0);
     if (!(grow | dissolve | marten)) return;
-    const float kas = k_alpha_s(Tn);
-    const float la = flog2(a);  // -inf at a = 0
+    const R kas = k_alpha_s(Tn);
+    const R la = flog2(a);  // -inf at a = 0
     if (grow) {
-        if (a > 0.0f) {
-            da = dt * kas * fexp2(fmaf(kPa, la, kQa * flog2(xeq - xa)));
+        if (a > R(0)) {
+            da = dt * kas * fexp2(vfma(C::Pa, la, C::Qa * flog2(xeq - xa)));
         } else {
-            const float D = xeq - m;
-            if (D > 0.0f) da = logistic_step(0.0f, D, kas * D, kCas, 1.0f / kCas, dt);
+            const R D = xeq - m;
+            if (D > R(0)) da = logistic_step(R(0), D, kas * D, C::Cas, R(1) / C::Cas, dt);
         }
     }
     if (marten) {
-        const float r2 = kas * fexp2(fmaf(kPa, la, kQa * flog2(m)));
-        da = fmaf(dt, r2, da);
+        const R r2 = kas * fexp2(vfma(C::Pa, la, C::Qa * flog2(m)));
+        da = vfma(dt, r2, da);
         dm = -dt * r2;
     }
     if (dissolve) {
-        const float kb = kF * kas;
-        const float bt = fmaxf(kXmax - xa, 0.0f);
-        if (bt * dt <= kStartupLimit) {
-            const float D = kXmax - xeq;
-            const float nb = logistic_step(bt, D, D * kb, kCbeta, 1.0f / kCbeta, dt);
+        const R kb = C::F * kas;
+        const R bt = vmax(C::Xmax - xa, R(0));
+        if (bt * dt <= C::StartupLimit) {
+            const R D = C::Xmax - xeq;
+            const R nb = logistic_step(bt, D, D * kb, C::Cbeta, R(1) / C::Cbeta, dt);
             da -= (nb - bt);
         } else {
-            da -= dt * kb * fexp2(fmaf(kPb, flog2(bt), kQb * flog2(xa - xeq)));
+            da -= dt * kb * fexp2(vfma(C::Pb, flog2(bt), C::Qb * flog2(xa - xeq)));
         }
     }
 }
@@ -143,30 +183,32 @@ __device__ __forceinline__ void diffusive_increment(float a, float m, float Tn, 
 // inst_martensite_dissolution) and formation (eq. inst_martensite_formation,
 // never lowering alpha_m), the 0.9 cap again, the solid-fraction cap; returns
 // X_beta from the sum rule (eq. beta_post_processing).  xeq = X_alpha^eq(T).
-__device__ __forceinline__ float correct(float T, float xeq, float& a_io, float& m_io) {
-    float a = fmaxf(a_io, 0.0f), m = fmaxf(m_io, 0.0f);
-    float s = a + m;
-    if (s > kXmax) {
-        const float f = kXmax * frcp(s);
+template <class R>
+__device__ __forceinline__ R correct(R T, R xeq, R& a_io, R& m_io) {
+    using C = Const<R>;
+    R a = vmax(a_io, R(0)), m = vmax(m_io, R(0));
+    R s = a + m;
+    if (s > C::Xmax) {
+        const R f = C::Xmax * frcp(s);
         a *= f;
         m *= f;
     }
-    if (T > kTasStart) {
-        const float f = fminf(fmaxf((kTasStart + kTreg - T) * (1.0f / kTreg), 0.0f), 1.0f);
-        a = fminf(a, kXmax * f);
+    if (T > C::TasStart) {
+        const R f = vmin(vmax((C::TasStart + C::Treg - T) * (R(1) / C::Treg), R(0)), R(1));
+        a = vmin(a, C::Xmax * f);
     }
-    if (a + m > xeq) m = fmaxf(xeq - a, 0.0f);
-    if (T < kTamStart) m = fmaxf(m, am0_eq(T) * (kXmax - a) * (1.0f / kXmax));
+    if (a + m > xeq) m = vmax(xeq - a, R(0));
+    if (T < C::TamStart) m = vmax(m, am0_eq(T) * (C::Xmax - a) * (R(1) / C::Xmax));
     s = a + m;
-    if (s > kXmax) {
-        const float f = kXmax * frcp(s);
+    if (s > C::Xmax) {
+        const R f = C::Xmax * frcp(s);
         a *= f;
         m *= f;
     }
-    const float xsol = solid_fraction(T);
+    const R xsol = solid_fraction(T);
     s = a + m;
     if (s > xsol) {
-        const float f = (s > 0.0f) ? xsol * frcp(s) : 0.0f;
+        const R f = (s > R(0)) ? xsol * frcp(s) : R(0);
         a *= f;
         m *= f;
     }
@@ -176,9 +218,10 @@ __device__ __forceinline__ float correct(float T, float xeq, float& a_io, float&
 }
 
 // error-free sum: s + e == a + b exactly (Knuth's two-sum)
-__device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
+template <class R>
+__device__ __forceinline__ void two_sum(R a, R b, R& s, R& e) {
     s = a + b;
-    const float bb = s - a;
+    const R bb = s - a;
     e = (a - (s - bb)) + (b - bb);
 }
 
@@ -186,12 +229,11 @@ __device__ __forceinline__ void two_sum(float a, float b, float& s, float& e) {
 // increments are accumulated in (hi, lo) pairs so that increments below half
 // an ulp of the fraction are not lost; any correction that changes a
 // fraction resets its lo part.  Returns X_beta^{n+1}.
-template <bool COMPENSATED>
-__device__ __forceinline__ float explicit_step(float& a, float& m, float& a_lo, float& m_lo, float Tn,
-                                               float xeq_n, float Tn1, float xeq_n1, float dt) {
-    float da, dm;
+template <bool COMPENSATED, class R>
+__device__ __forceinline__ R explicit_step(R& a, R& m, R& a_lo, R& m_lo, R Tn, R xeq_n, R Tn1, R xeq_n1, R dt) {
+    R da, dm;
     diffusive_increment(a, m, Tn, xeq_n, dt, da, dm);
-    float at, mt;
+    R at, mt;
     if (COMPENSATED) {
         two_sum(a, a_lo + da, at, a_lo);
         two_sum(m, m_lo + dm, mt, m_lo);
@@ -199,11 +241,11 @@ __device__ __forceinline__ float explicit_step(float& a, float& m, float& a_lo, 
         at = a + da;
         mt = m + dm;
     }
-    const float a_before = at, m_before = mt;
-    const float beta = correct(Tn1, xeq_n1, at, mt);
+    const R a_before = at, m_before = mt;
+    const R beta = correct(Tn1, xeq_n1, at, mt);
     if (COMPENSATED) {
-        if (at != a_before) a_lo = 0.0f;
-        if (mt != m_before) m_lo = 0.0f;
+        if (at != a_before) a_lo = R(0);
+        if (mt != m_before) m_lo = R(0);
     }
     a = at;
     m = mt;
@@ -213,20 +255,22 @@ __device__ __forceinline__ float explicit_step(float& a, float& m, float& a_lo, 
 // Diffusive rate vector [alpha_s', alpha_m'] (eqs. beta_to_alpha_s,
 // alpha_m_to_alpha_s, alpha_s_to_beta, split as in eq. diff_inst_split) at a
 // temperature with X_alpha^eq = xeq and k_alpha_s = kas; X~beta = 0.9 - X_alpha.
-__device__ __forceinline__ void diffusive_rates(float a, float m, float xeq, float kas, float& fa, float& fm) {
-    const float xa = a + m;
-    const float la = flog2(a);  // -inf at a = 0: the rates that carry a^p vanish
-    fa = 0.0f;
-    fm = 0.0f;
-    if (xa < xeq) fa = kas * fexp2(fmaf(kPa, la, kQa * flog2(xeq - xa)));
-    if (m > 0.0f) {
-        const float r2 = kas * fexp2(fmaf(kPa, la, kQa * flog2(m)));
+template <class R>
+__device__ __forceinline__ void diffusive_rates(R a, R m, R xeq, R kas, R& fa, R& fm) {
+    using C = Const<R>;
+    const R xa = a + m;
+    const R la = flog2(a);  // -inf at a = 0: the rates that carry a^p vanish
+    fa = R(0);
+    fm = R(0);
+    if (xa < xeq) fa = kas * fexp2(vfma(C::Pa, la, C::Qa * flog2(xeq - xa)));
+    if (m > R(0)) {
+        const R r2 = kas * fexp2(vfma(C::Pa, la, C::Qa * flog2(m)));
         fa += r2;
         fm = -r2;
     }
     if (xa > xeq) {
-        const float bt = fmaxf(kXmax - xa, 0.0f);
-        fa -= kF * kas * fexp2(fmaf(kPb, flog2(bt), kQb * flog2(xa - xeq)));
+        const R bt = vmax(C::Xmax - xa, R(0));
+        fa -= C::F * kas * fexp2(vfma(C::Pb, flog2(bt), C::Qb * flog2(xa - xeq)));
     }
 }
 
@@ -241,28 +285,29 @@ __device__ __forceinline__ void diffusive_rates(float a, float m, float xeq, flo
 // COMPENSATED the increment m^{n+1} - m^n is added to (hi, lo) pairs as in
 // explicit_step.  Returns the iteration count (0 for a start-up step),
 // negated if the stop test failed.
-template <bool COMPENSATED>
-__device__ __forceinline__ int implicit_step(float& a, float& m, float& a_lo, float& m_lo, float& beta, float Tn,
-                                             float Tn1, float dt, int max_iter) {
-    const float xeq_n = alpha_eq(Tn), xeq_1 = alpha_eq(Tn1);
-    const float xa = a + m;
-    if ((xa < xeq_n && !(a > 0.0f)) || (xa > xeq_n && fmaxf(kXmax - xa, 0.0f) * dt <= kStartupLimit)) {
+template <bool COMPENSATED, class R>
+__device__ __forceinline__ int implicit_step(R& a, R& m, R& a_lo, R& m_lo, R& beta, R Tn, R Tn1, R dt,
+                                             int max_iter) {
+    using C = Const<R>;
+    const R xeq_n = alpha_eq(Tn), xeq_1 = alpha_eq(Tn1);
+    const R xa = a + m;
+    if ((xa < xeq_n && !(a > R(0))) || (xa > xeq_n && vmax(C::Xmax - xa, R(0)) * dt <= C::StartupLimit)) {
         beta = explicit_step<COMPENSATED>(a, m, a_lo, m_lo, Tn, xeq_n, Tn1, xeq_1, dt);
         return 0;
     }
-    const float k_1 = k_alpha_s(Tn1);
-    float fa_n, fm_n;
+    const R k_1 = k_alpha_s(Tn1);
+    R fa_n, fm_n;
     diffusive_rates(a, m, xeq_n, k_alpha_s(Tn), fa_n, fm_n);
-    float ai = a, mi = m, ali = 0.0f, mli = 0.0f;
+    R ai = a, mi = m, ali = R(0), mli = R(0);
     beta = correct(Tn1, xeq_1, ai, mi);
-    float fa, fm;
+    R fa, fm;
     diffusive_rates(ai, mi, xeq_1, k_1, fa, fm);
-    const float h = 0.5f * dt;
+    const R h = R(0.5) * dt;
     int it = 0;
     bool converged = false;
     while (it < max_iter) {
-        const float da = h * (fa + fa_n), dm = h * (fm + fm_n);
-        float a1, m1, al1 = 0.0f, ml1 = 0.0f;
+        const R da = h * (fa + fa_n), dm = h * (fm + fm_n);
+        R a1, m1, al1 = R(0), ml1 = R(0);
         if (COMPENSATED) {
             two_sum(a, a_lo + da, a1, al1);
             two_sum(m, m_lo + dm, m1, ml1);
@@ -270,16 +315,16 @@ __device__ __forceinline__ int implicit_step(float& a, float& m, float& a_lo, fl
             a1 = a + da;
             m1 = m + dm;
         }
-        const float a_before = a1, m_before = m1;
+        const R a_before = a1, m_before = m1;
         beta = correct(Tn1, xeq_1, a1, m1);
         if (COMPENSATED) {
-            if (a1 != a_before) al1 = 0.0f;
-            if (m1 != m_before) ml1 = 0.0f;
+            if (a1 != a_before) al1 = R(0);
+            if (m1 != m_before) ml1 = R(0);
         }
-        float fa1, fm1;
+        R fa1, fm1;
         diffusive_rates(a1, m1, xeq_1, k_1, fa1, fm1);
-        const float wa = h * (fa1 - fa) * frcp(fmaf(fabsf(a1), kCnEpsRel, kCnEpsAbs));
-        const float wm = h * (fm1 - fm) * frcp(fmaf(fabsf(m1), kCnEpsRel, kCnEpsAbs));
+        const R wa = h * (fa1 - fa) * frcp(vfma(vabs(a1), C::CnEpsRel, C::CnEpsAbs));
+        const R wm = h * (fm1 - fm) * frcp(vfma(vabs(m1), C::CnEpsRel, C::CnEpsAbs));
         ai = a1;
         mi = m1;
         ali = al1;
@@ -287,7 +332,7 @@ __device__ __forceinline__ int implicit_step(float& a, float& m, float& a_lo, fl
         fa = fa1;
         fm = fm1;
         ++it;
-        if (0.5f * fmaf(wa, wa, wm * wm) < 1.0f) {
+        if (R(0.5) * vfma(wa, wa, wm * wm) < R(1)) {
             converged = true;
             break;
         }
@@ -301,4 +346,4 @@ __device__ __forceinline__ int implicit_step(float& a, float& m, float& a_lo, fl
     return converged ? it : -it;
 }
 
-}  // namespace mstruct
+}  // namespace MSTRUCT_MODEL_NS
