@@ -175,6 +175,7 @@ def main():
         result["plain_step"] = bench_stepwise(torch, ms, ctx, wl, dev)
         result["implicit_step"] = bench_implicit(torch, ms, ctx, wl, final_state)
         result["divergence"] = bench_divergence(torch, ctx, n)
+        result["f64_step"] = bench_f64(torch, ms, ctx, wl, final_state)
     if not args.no_cooldown:
         result["cooldown"], cool_state = bench_cooldown(torch, ms, ctx)
 
@@ -321,6 +322,39 @@ def bench_cooldown(torch, ms, ctx):
             "scan_point_updates": scan_upd, "simulated_s": pw.phases[-1].t0 + pw.phases[-1].dt * pw.phases[-1].n_steps,
             "calls": len(pw.phases), "unconverged_substeps": ctx.implicit_unconverged(),
             "path": "run_phases: fused PLAIN while scanning, fused IMPLICIT while cooling (K = 16)"}, g
+
+
+F64_STEP_BYTES = 56  # float64 step: reads alpha_s, alpha_m, T^n, T^{n+1}; writes beta, alpha_s, alpha_m
+
+
+def bench_f64(torch, ms, ctx, wl, state):
+    """The explicit step in float64 on all 8.4M points (state after the plain
+    run, top-layer temperatures at 2 us apart), with the device math library
+    and with exponent-bit exp2 / log2: HBM-bound at 56 bytes per point."""
+    n = wl.grid.n
+    L = wl.layers[-1]
+    Ta, Tb = torch.empty(n, device="cuda"), torch.empty(n, device="cuda")
+    t = wl.t0(L) + 1000 * wl.dt
+    ctx.temperature(wl.scan, wl.grid, t, Ta, z_top=L.z_top)
+    ctx.temperature(wl.scan, wl.grid, t + wl.dt, Tb, z_top=L.z_top)
+    Ta, Tb = Ta.double(), Tb.double()
+    out = {"path": "mstruct_step_f64 on all points (state after the plain run, cast to float64)"}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for key, math_mode in (("library", ms.F64_LIBRARY), ("synth", ms.F64_SYNTH)):
+        b, a, m = [x.double() for x in state]
+        ctx.step_f64(Ta, Tb, wl.dt, b, a, m, math=math_mode)
+        torch.cuda.synchronize()
+        reps = 100
+        e0.record()
+        for _ in range(reps):
+            ctx.step_f64(Ta, Tb, wl.dt, b, a, m, math=math_mode)
+        e1.record()
+        torch.cuda.synchronize()
+        avg = e0.elapsed_time(e1) * 1e-3 / reps
+        gbs = F64_STEP_BYTES * n / avg / 1e9
+        out[key] = {"avg_launch_us": avg * 1e6, "point_updates_per_s": n / avg, "hbm_GBs": gbs,
+                    "hbm_frac": gbs / HBM_PEAK_GBS}
+    return out
 
 
 def bench_divergence(torch, ctx, n):

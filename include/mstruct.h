@@ -83,6 +83,17 @@ typedef struct {
 
 enum { MSTRUCT_MODE_PLAIN = 0, MSTRUCT_MODE_SURROGATE = 1, MSTRUCT_MODE_IMPLICIT = 2 };
 
+/* Float64 state for mstruct_step_f64 (device arrays of n points, caller-owned). */
+typedef struct {
+    double *beta;
+    double *alpha_s;
+    double *alpha_m;
+    int64_t n;
+} mstruct_phases_f64;
+
+/* exp2 / log2 used by mstruct_step_f64 */
+enum { MSTRUCT_F64_LIBRARY = 0, MSTRUCT_F64_SYNTH = 1 };
+
 /* Create a context on HIP device `device` (the caller's current device is
  * restored).  *out receives the context; free it with mstruct_destroy. */
 int mstruct_init(int device, mstruct_ctx **out);
@@ -105,6 +116,17 @@ const char *mstruct_last_error(const mstruct_ctx *ctx);
  * (16-byte alignment of all five enables vector access). */
 int mstruct_step(mstruct_ctx *ctx, const float *T_prev, const float *T_next, double dt,
                  const mstruct_phases *ph, void *stream);
+
+/* The explicit step of mstruct_step (Algorithm 1 with Algorithm 2) in
+ * float64 for n points, in place: T_prev, T_next and the three fractions are
+ * device float64 arrays (40 bytes read and 24 written per point).  math
+ * MSTRUCT_F64_LIBRARY uses the device math library's exp2, log2 and expm1;
+ * MSTRUCT_F64_SYNTH builds exp2 and log2 from the bit pattern of the double
+ * and a short polynomial on the reduced argument, as the paper does on CPUs
+ * (Sec. 3.3).  Both agree with the reference to a few float64 ulps.  dt > 0
+ * and finite; asynchronous on the stream. */
+int mstruct_step_f64(mstruct_ctx *ctx, const double *T_prev, const double *T_next, double dt,
+                     const mstruct_phases_f64 *ph, int math, void *stream);
 
 /* One step of the implicit scheme (Sec. 3.1, eqs. implicit_integration,
  * implicit_correction, implicit_fp_iteration; the implicit algorithm of

@@ -20,6 +20,8 @@ LIB_PATH = os.path.join(_HERE, "libmstruct.so")
 MODE_PLAIN = 0
 MODE_SURROGATE = 1
 MODE_IMPLICIT = 2
+F64_LIBRARY = 0
+F64_SYNTH = 1
 MLP_NPARAM = 4803
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "HIP device error", -3: "out of memory",
@@ -37,6 +39,11 @@ class PhasesC(ctypes.Structure):
                 ("n", ctypes.c_int64)]
 
 
+class PhasesF64C(ctypes.Structure):
+    _fields_ = [("beta", ctypes.c_void_p), ("alpha_s", ctypes.c_void_p), ("alpha_m", ctypes.c_void_p),
+                ("n", ctypes.c_int64)]
+
+
 class ScanC(ctypes.Structure):
     _fields_ = [("tracks", ctypes.c_void_p), ("n_tracks", ctypes.c_int64), ("conductivity", ctypes.c_double),
                 ("diffusivity", ctypes.c_double), ("T0", ctypes.c_double), ("T_clamp", ctypes.c_double),
@@ -50,7 +57,7 @@ class PointsC(ctypes.Structure):
 
 
 EXPORTS = ("mstruct_init", "mstruct_destroy", "mstruct_status_string", "mstruct_last_error", "mstruct_step",
-           "mstruct_step_implicit", "mstruct_implicit_unconverged", "mstruct_temperature", "mstruct_fused_scan_steps", "mstruct_gather", "mstruct_check_invariants",
+           "mstruct_step_implicit", "mstruct_implicit_unconverged", "mstruct_step_f64", "mstruct_temperature", "mstruct_fused_scan_steps", "mstruct_gather", "mstruct_check_invariants",
            "mstruct_correct", "mstruct_mlp_set_params", "mstruct_mlp_get_params", "mstruct_mlp_forward",
            "mstruct_mlp_grad", "mstruct_mlp_train_step")
 
@@ -70,6 +77,7 @@ def lib() -> ctypes.CDLL:
             "mstruct_last_error": [p], "mstruct_step": [p, p, p, d, p, p],
             "mstruct_step_implicit": [p, p, p, d, d, i, p, p, p],
             "mstruct_implicit_unconverged": [p, p, i, p],
+            "mstruct_step_f64": [p, p, p, d, p, i, p],
             "mstruct_temperature": [p, p, p, d, p, p],
             "mstruct_fused_scan_steps": [p, p, p, d, d, i64, i, i, p, p],
             "mstruct_gather": [p, p, p, i64, p, p], "mstruct_check_invariants": [p, p, p, ctypes.c_float, p, p],
@@ -157,6 +165,17 @@ class Context:
         self._check(lib().mstruct_step(self._h, _dev_ptr(T_prev, torch.float32, ph.n, "T_prev"),
                                        _dev_ptr(T_next, torch.float32, ph.n, "T_next"), float(dt),
                                        ctypes.byref(ph), _stream(stream)), "mstruct_step")
+
+    def step_f64(self, T_prev, T_next, dt, beta, alpha_s, alpha_m, math=F64_LIBRARY, stream=None):
+        """The explicit step in float64 (all arrays float64 CUDA tensors)."""
+        import torch
+        n = beta.numel()
+        f = torch.float64
+        ph = PhasesF64C(_dev_ptr(beta, f, n, "beta"), _dev_ptr(alpha_s, f, n, "alpha_s"),
+                        _dev_ptr(alpha_m, f, n, "alpha_m"), n)
+        self._check(lib().mstruct_step_f64(self._h, _dev_ptr(T_prev, f, n, "T_prev"), _dev_ptr(T_next, f, n, "T_next"),
+                                           float(dt), ctypes.byref(ph), int(math), _stream(stream)),
+                    "mstruct_step_f64")
 
     def step_implicit(self, T_prev, T_next, dt, beta, alpha_s, alpha_m, dt_sub=0.01, max_iter=50,
                       unconverged=None, stream=None):

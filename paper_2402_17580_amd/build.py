@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmstruct.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ("api.hip", "kernels.hip", "mlp.hip")
+SOURCES = ("api.hip", "kernels.hip", "mlp.hip", "step_f64_lib.hip", "step_f64_synth.hip")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # keep packed-FP32 instructions out of the device code

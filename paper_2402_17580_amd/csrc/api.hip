@@ -309,6 +309,24 @@ int mstruct_step(mstruct_ctx* ctx, const float* T_prev, const float* T_next, dou
     return MSTRUCT_OK;
 }
 
+int mstruct_step_f64(mstruct_ctx* ctx, const double* T_prev, const double* T_next, double dt,
+                     const mstruct_phases_f64* ph, int math, void* stream) {
+    if (!ctx) return MSTRUCT_EINVAL;
+    if (!ph) return fail(ctx, MSTRUCT_EINVAL, "phases is NULL");
+    if (ph->n < 0) return fail(ctx, MSTRUCT_EINVAL, "n < 0");
+    if (ph->n > 0 && (!ph->beta || !ph->alpha_s || !ph->alpha_m || !T_prev || !T_next))
+        return fail(ctx, MSTRUCT_EINVAL, "NULL array");
+    if (!finite_pos(dt)) return fail(ctx, MSTRUCT_EINVAL, "dt must be positive and finite");
+    if (math != MSTRUCT_F64_LIBRARY && math != MSTRUCT_F64_SYNTH) return fail(ctx, MSTRUCT_EINVAL, "bad math");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = math == MSTRUCT_F64_LIBRARY
+                       ? launch_step_f64_library(T_prev, T_next, ph->beta, ph->alpha_s, ph->alpha_m, ph->n, dt, st)
+                       : launch_step_f64_synth(T_prev, T_next, ph->beta, ph->alpha_s, ph->alpha_m, ph->n, dt, st);
+    if (e != hipSuccess) return hip_fail(ctx, e, "float64 step launch");
+    return MSTRUCT_OK;
+}
+
 int mstruct_step_implicit(mstruct_ctx* ctx, const float* T_prev, const float* T_next, double dt, double dt_sub,
                           int max_iter, const mstruct_phases* ph, unsigned long long* unconverged, void* stream) {
     if (!ctx) return MSTRUCT_EINVAL;

@@ -28,6 +28,12 @@ hipError_t launch_step(const float* Tp, const float* Tn, float* beta, float* as,
 hipError_t launch_fused_implicit(const PointGeom& pg, int W, const SrcRec* tab, int K, float h, int n_sub,
                                  int max_iter, ScanArgs sa, float* beta, float* as, float* am,
                                  unsigned long long* unconverged, hipStream_t st);
+// float64 explicit step (step_f64_lib.hip: device math library; step_f64_synth.hip:
+// exponent-bit exp2 / log2)
+hipError_t launch_step_f64_library(const double* Tp, const double* Tn, double* beta, double* as, double* am,
+                                   int64_t n, double dt, hipStream_t st);
+hipError_t launch_step_f64_synth(const double* Tp, const double* Tn, double* beta, double* as, double* am,
+                                 int64_t n, double dt, hipStream_t st);
 hipError_t launch_implicit_step(const float* Tp, const float* Tn, float* beta, float* as, float* am, int64_t n,
                                 float h, int n_sub, int max_iter, unsigned long long* unconverged,
                                 hipStream_t st);
