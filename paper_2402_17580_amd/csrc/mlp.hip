@@ -581,6 +581,7 @@ __device__ __forceinline__ bool needs_plain(float T0, float TK, const MlpNorm& n
 // block-end temperature the formation law would raise alpha_m, so a dip of the
 // temperature inside the block would form martensite the block ends miss.
 constexpr float kFrontProbe = 5.0f;  // [K]
+constexpr int kProbeEvery = 8;       // probe spacing inside longer blocks [steps]
 __device__ __forceinline__ bool formation_front(float T0, float TK, float a, float m) {
     const float Tlo = fminf(T0, TK) - kFrontProbe;
     return Tlo < kTamStart && am0_eq(Tlo) * (kXmax - a) * (1.0f / kXmax) > m;
@@ -651,10 +652,17 @@ __global__ __launch_bounds__(256) void surrogate_a_kernel(PointGeom pg, const Sr
                 bool plain = needs_plain(T0[u], TK[u], nrm);
                 if (!plain && formation_front(T0[u], TK[u], a[u], m[u])) {
                     // martensite forms at the lowest temperature of the block:
-                    // a dip below both ends (probed at the block middle) needs the plain steps
+                    // a dip below both ends needs the plain steps.  Probed at
+                    // the block middle and every kProbeEvery steps.
+                    const float Tlo = fminf(T0[u], TK[u]);
                     const float Tmid = scan_temperature<W>(tab + (K / 2) * W, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp,
                                                            pg.r2min, pg.roff);
-                    plain = Tmid < fminf(T0[u], TK[u]);
+                    plain = Tmid < Tlo;
+                    for (int s = kProbeEvery; s < K && !plain; s += kProbeEvery) {
+                        if (s == K / 2) continue;
+                        plain = scan_temperature<W>(tab + s * W, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min,
+                                                    pg.roff) < Tlo;
+                    }
                 }
                 if (plain) {
                     float alo = 0.0f, mlo = 0.0f, Tn = T0[u], xeq_n = xeq0;

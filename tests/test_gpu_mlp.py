@@ -135,3 +135,37 @@ def test_surrogate_mode_with_zero_network(torch, ctx, orc):
     print("zero-network surrogate errors", errs)
     assert max(errs) <= 1e-3
     assert ctx.check_invariants(*g, tol=2e-6) == 0
+
+
+@pytest.mark.parametrize("K,window,masked", [(1, 1, False), (64, 3, False), (8, 2, True), (13, 4, True)])
+def test_surrogate_mode_edge_cases(torch, ctx, orc, K, window, masked):
+    """The shipped K = 8 network in surrogate mode with other block lengths
+    (1, 13 with a partial last block, 64), other window sizes and a masked
+    grid (index list, points above the layers inactive); within the surrogate
+    tolerance of the oracle, inactive points untouched."""
+    import paper_2402_17580_amd as ms
+    from paper_2402_17580_amd import surrogate as S
+    S.Surrogate.load(S.DEFAULT_WEIGHTS).load_into(ctx)
+    if masked:
+        wl0 = workload.island_scan(96, 64, 24, n_layers=3, layer_thick=20e-6, steps_per_layer=303, dt=2e-6,
+                                   seed=77, island=0.5e-3, window=window)
+        idx = workload.cantilever_mask(96, 64, 24, seed=77, top=6, base=6, leg_frac=0.1)
+        wl = workload.Workload("masked", workload.Grid(96, 64, 24, 10e-6, index=idx), wl0.scan, wl0.layers, wl0.dt,
+                               wl0.seed)
+        index = torch.from_numpy(idx).cuda()
+    else:
+        wl = workload.multilayer_block(nx=48, ny=40, nz=12, n_layers=2, layer_thick=30e-6, steps_per_layer=401,
+                                       hatch=100e-6, seed=3, window=window)
+        index = None
+    n = wl.grid.n
+    g = [torch.from_numpy(x).cuda() for x in workload.initial_state(n, np.float32)]
+    ms.run_layers(ctx, wl, *g, K=K, mode=ms.MODE_SURROGATE, index=index)
+    torch.cuda.synchronize()
+    st = orc.run_workload(wl, np.arange(n))
+    errs = [float(np.abs(x.double().cpu().numpy() - y).max()) for x, y in zip(g, (st.beta, st.alpha_s, st.alpha_m))]
+    print("surrogate edge case", K, window, masked, errs)
+    assert max(errs) <= 1e-3
+    assert ctx.check_invariants(*g, tol=2e-6) == 0
+    z = wl.grid.coords(np.arange(n))[:, 2]
+    never = z > wl.layers[-1].z_top + 1e-3 * wl.grid.h
+    assert never.sum() == 0 or np.all(g[1].cpu().numpy()[never] == np.float32(0.9))
