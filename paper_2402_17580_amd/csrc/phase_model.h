@@ -183,8 +183,11 @@ __device__ __forceinline__ void diffusive_increment(R a, R m, R Tn, R xeq, R dt,
 // inst_martensite_dissolution) and formation (eq. inst_martensite_formation,
 // never lowering alpha_m), the 0.9 cap again, the solid-fraction cap; returns
 // X_beta from the sum rule (eq. beta_post_processing).  xeq = X_alpha^eq(T).
+// The correction with its temperature functions given: xeq = X_alpha^eq(T),
+// am0 = X_alpha_m,0^eq(T) (used below the martensite start), xsol = 1 - g(T)
+// (for iterations at a fixed temperature).
 template <class R>
-__device__ __forceinline__ R correct(R T, R xeq, R& a_io, R& m_io) {
+__device__ __forceinline__ R correct_at(R T, R xeq, R am0, R xsol, R& a_io, R& m_io) {
     using C = Const<R>;
     R a = vmax(a_io, R(0)), m = vmax(m_io, R(0));
     R s = a + m;
@@ -198,14 +201,13 @@ __device__ __forceinline__ R correct(R T, R xeq, R& a_io, R& m_io) {
         a = vmin(a, C::Xmax * f);
     }
     if (a + m > xeq) m = vmax(xeq - a, R(0));
-    if (T < C::TamStart) m = vmax(m, am0_eq(T) * (C::Xmax - a) * (R(1) / C::Xmax));
+    if (T < C::TamStart) m = vmax(m, am0 * (C::Xmax - a) * (R(1) / C::Xmax));
     s = a + m;
     if (s > C::Xmax) {
         const R f = C::Xmax * frcp(s);
         a *= f;
         m *= f;
     }
-    const R xsol = solid_fraction(T);
     s = a + m;
     if (s > xsol) {
         const R f = (s > R(0)) ? xsol * frcp(s) : R(0);
@@ -215,6 +217,11 @@ __device__ __forceinline__ R correct(R T, R xeq, R& a_io, R& m_io) {
     a_io = a;
     m_io = m;
     return xsol - a - m;
+}
+
+template <class R>
+__device__ __forceinline__ R correct(R T, R xeq, R& a_io, R& m_io) {
+    return correct_at(T, xeq, T < Const<R>::TamStart ? am0_eq(T) : R(0), solid_fraction(T), a_io, m_io);
 }
 
 // error-free sum: s + e == a + b exactly (Knuth's two-sum)
@@ -296,10 +303,11 @@ __device__ __forceinline__ int implicit_step(R& a, R& m, R& a_lo, R& m_lo, R& be
         return 0;
     }
     const R k_1 = k_alpha_s(Tn1);
+    const R am0_1 = Tn1 < C::TamStart ? am0_eq(Tn1) : R(0), xsol_1 = solid_fraction(Tn1);
     R fa_n, fm_n;
     diffusive_rates(a, m, xeq_n, k_alpha_s(Tn), fa_n, fm_n);
     R ai = a, mi = m, ali = R(0), mli = R(0);
-    beta = correct(Tn1, xeq_1, ai, mi);
+    beta = correct_at(Tn1, xeq_1, am0_1, xsol_1, ai, mi);
     R fa, fm;
     diffusive_rates(ai, mi, xeq_1, k_1, fa, fm);
     const R h = R(0.5) * dt;
@@ -316,7 +324,7 @@ __device__ __forceinline__ int implicit_step(R& a, R& m, R& a_lo, R& m_lo, R& be
             m1 = m + dm;
         }
         const R a_before = a1, m_before = m1;
-        beta = correct(Tn1, xeq_1, a1, m1);
+        beta = correct_at(Tn1, xeq_1, am0_1, xsol_1, a1, m1);
         if (COMPENSATED) {
             if (a1 != a_before) al1 = R(0);
             if (m1 != m_before) ml1 = R(0);
