@@ -11,7 +11,7 @@
  * computational approach for part-scale microstructure predictions in
  * Ti-6Al-4V additive manufacturing" (arXiv 2402.17580) that it follows.
  *
- * Readings taken where the paper is silent or garbled (listed in the design doc):
+ * Readings taken where the paper is silent or garbled:
  *   R1  third case of the martensite pseudo-equilibrium is "0 above the
  *       martensite start temperature" (the printed bound names the alpha_s
  *       start temperature, which would leave (848, 1273] undefined).
