@@ -69,7 +69,8 @@ typedef struct {
 
 /* Material points on a regular box grid: point (i, j, k) sits at
  * (ox + i h, oy + j h, oz - k h) with box linear index i + nx (j + ny k).
- * `index` (device int32, n sorted box linear indices) selects a masked subset;
+ * `index` (device int32, n sorted box linear indices, each in [0, nx*ny*nz);
+ * not checked on the device) selects a masked subset;
  * NULL means all nx*ny*nz box points in linear order (then n must equal
  * nx*ny*nz).  Points with z > z_top + 1e-3 h are inactive: the fused call
  * leaves them untouched (material not yet deposited). */

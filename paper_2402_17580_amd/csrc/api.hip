@@ -122,6 +122,8 @@ int make_geom(mstruct_ctx* ctx, const mstruct_points* p, int64_t n, PointGeom& p
     pg.index = p->index;
     pg.nx = (int32_t)p->nx;
     pg.nxy = (int32_t)(p->nx * p->ny);
+    divide_magic(pg.nx, pg.mag_nx, pg.sh_nx);
+    divide_magic(pg.nxy, pg.mag_nxy, pg.sh_nxy);
     pg.k0 = (int32_t)k0;
     pg.r2min = (float)((1e-9 / p->h) * (1e-9 / p->h));
     pg.roff = (float)(5e-7 / p->h);

@@ -13,10 +13,35 @@ struct PointGeom {
     int64_t first;         // first local point number processed
     int64_t count;         // number of local points processed
     int32_t nx, nxy;       // box dimensions
+    // exact division by nx and nxy for 0 <= n < 2^31: n / d = mulhi(n, mag) >> sh
+    // (sh < 0 marks d = 1); see divide_magic
+    uint32_t mag_nx, mag_nxy;
+    int32_t sh_nx, sh_nxy;
     int32_t k0;            // points on planes k < k0 are inactive
     float r2min;           // squared clamp radius around a switched-on source [grid units^2]
     float roff;            // radius around a switched-off track's virtual position [grid units]
 };
+
+// floor(n / d) for 0 <= n < 2^31 from the multiplier and shift of divide_magic
+__device__ __forceinline__ int32_t divide_by(int32_t n, uint32_t mag, int32_t sh) {
+    return sh < 0 ? n : (int32_t)(__umulhi((uint32_t)n, mag) >> sh);
+}
+
+// Multiplier and shift for exact unsigned division of n < 2^31 by d >= 1:
+// with l = ceil(log2 d) >= 1, mag = ceil(2^(31+l) / d) < 2^32 and
+// n / d = (n mag) >> (31 + l); the error n (mag - 2^(31+l)/d) / 2^(31+l) is
+// below 2^-l <= 1/d, so the floor is exact.  d = 1 gives sh = -1.
+inline void divide_magic(int64_t d, uint32_t& mag, int32_t& sh) {
+    if (d <= 1) {
+        mag = 0;
+        sh = -1;
+        return;
+    }
+    int l = 0;
+    while (((int64_t)1 << l) < d) ++l;
+    mag = (uint32_t)((((uint64_t)1 << (31 + l)) + (uint64_t)d - 1) / (uint64_t)d);
+    sh = l - 1;
+}
 
 // scan constants of one call
 struct ScanArgs {

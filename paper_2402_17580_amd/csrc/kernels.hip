@@ -14,9 +14,9 @@ typedef float vf4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ void decode_point(const PointGeom& pg, int64_t local, int& gi, int& gj, int& gk) {
     const int lin = pg.index ? pg.index[local] : (int)local;
-    gk = lin / pg.nxy;
+    gk = divide_by(lin, pg.mag_nxy, pg.sh_nxy);
     const int rem = lin - gk * pg.nxy;
-    gj = rem / pg.nx;
+    gj = divide_by(rem, pg.mag_nx, pg.sh_nx);
     gi = rem - gj * pg.nx;
 }
 

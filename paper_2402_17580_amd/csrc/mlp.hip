@@ -612,9 +612,9 @@ __global__ __launch_bounds__(256) void surrogate_a_kernel(PointGeom pg, const Sr
             valid[u] = g < pg.count;
             local[u] = pg.first + (valid[u] ? g : 0);
             const int lin = pg.index ? pg.index[local[u]] : (int)local[u];
-            gk[u] = lin / pg.nxy;
+            gk[u] = divide_by(lin, pg.mag_nxy, pg.sh_nxy);
             const int rem = lin - gk[u] * pg.nxy;
-            gj[u] = rem / pg.nx;
+            gj[u] = divide_by(rem, pg.mag_nx, pg.sh_nx);
             gi[u] = rem - gj[u] * pg.nx;
             valid[u] = valid[u] && gk[u] >= pg.k0;
         }
