@@ -212,9 +212,9 @@ def main():
 # HBM bytes per launch (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0: the factors a
 # plain 1 GiB device copy reads on the same counters).
 FUSED_PROFILE = {
-    "valu_lane_ops_per_update": 213.71,
-    "fp32_flops_per_update": 158.5,
-    "traffic_bytes_per_launch": (29390.75 * 2.0 + 58858.50) * 1024,
+    "valu_lane_ops_per_update": 211.08,
+    "fp32_flops_per_update": 158.1,
+    "traffic_bytes_per_launch": (29390.19 * 2.0 + 58858.50) * 1024,
 }
 
 def bench_stepwise(torch, ms, ctx, wl, dev):

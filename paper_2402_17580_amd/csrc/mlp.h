@@ -59,7 +59,8 @@ struct MlpState {
     int64_t queue_entries = 0;
     unsigned* counters = nullptr;
     // block-end temperatures of the previous surrogate block of a call (the
-    // next block's start temperatures), indexed by local point number
+    // next block's start temperatures), indexed by local point number; two
+    // slots of tcache_n floats each, used alternately by consecutive blocks
     float* tcache = nullptr;
     int64_t tcache_n = 0;
     int cu_count = 0;  // compute units of the context's device (pass A grid)

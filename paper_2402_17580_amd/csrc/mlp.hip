@@ -749,7 +749,9 @@ hipError_t surrogate_prepare(MlpState& s, int64_t points, hipStream_t st) {
         if (s.tcache) (void)hipFree(s.tcache);
         s.tcache = nullptr;
         s.tcache_n = 0;
-        if ((e = hipMalloc((void**)&s.tcache, (size_t)points * sizeof(float))) != hipSuccess) return e;
+        // two slots: block b reads slot b & 1 and writes slot (b + 1) & 1, so the
+        // cached temperatures are never read and rewritten in the same buffer
+        if ((e = hipMalloc((void**)&s.tcache, 2 * (size_t)points * sizeof(float))) != hipSuccess) return e;
         s.tcache_n = points;
     }
     // at most one queue entry per wave and point group of pass A
@@ -780,8 +782,8 @@ hipError_t surrogate_prepare(MlpState& s, int64_t points, hipStream_t st) {
 hipError_t launch_surrogate(const MlpState& s, const PointGeom& pg, int W, const SrcRec* tab, int K, float dt,
                             ScanArgs sa, float* beta, float* as, float* am, int64_t block, bool first_block,
                             bool last_block, hipStream_t st) {
-    const float* tin = first_block ? nullptr : s.tcache;
-    float* tout = last_block ? nullptr : s.tcache;
+    const float* tin = first_block ? nullptr : s.tcache + (block & 1) * s.tcache_n;
+    float* tout = last_block ? nullptr : s.tcache + ((block + 1) & 1) * s.tcache_n;
     if (!last_block) beta = nullptr;
     if (pg.count <= 0) return hipSuccess;
     unsigned* cur = s.counters + (block & 1);
