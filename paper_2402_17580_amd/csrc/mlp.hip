@@ -677,6 +677,8 @@ __global__ __launch_bounds__(256) void surrogate_a_kernel(PointGeom pg, const Sr
                     an += alo;
                     mn += mlo;
                     bn = solid_fraction(Tn) - an - mn;
+                } else if (at_rest(a[u], m[u], T0[u], TK[u])) {
+                    bn = 1.0f - an - mn;  // the step of K dt leaves the state as it is
                 } else {
                     float da, dm;
                     diffusive_increment(a[u], m[u], T0[u], xeq0, dt * (float)K, da, dm);

@@ -224,6 +224,20 @@ __device__ __forceinline__ R correct(R T, R xeq, R& a_io, R& m_io) {
     return correct_at(T, xeq, T < Const<R>::TamStart ? am0_eq(T) : R(0), solid_fraction(T), a_io, m_io);
 }
 
+// A fully stable-alpha state (X_alpha_s = 0.9, no martensite) is a fixed point
+// of the update while T^n and T^{n+1} stay below the alpha_s -> beta end
+// temperature: X_alpha = X_alpha^eq = 0.9 there, so every diffusive rate is
+// zero, and the correction leaves it alone (the formation law raises alpha_m
+// to at most X_alpha_m,0^eq (0.9 - X_alpha_s) / 0.9 = 0).  Steps of such a
+// state return it unchanged without evaluating the model; the result is the
+// same as that of the full evaluation, bit for bit.  Away from the laser
+// most of a part is in this state.
+template <class R>
+__device__ __forceinline__ bool at_rest(R a, R m, R Tn, R Tn1) {
+    using C = Const<R>;
+    return a == C::Xmax && m == R(0) && Tn < C::TasEnd && Tn1 < C::TasEnd;
+}
+
 // error-free sum: s + e == a + b exactly (Knuth's two-sum)
 template <class R>
 __device__ __forceinline__ void two_sum(R a, R b, R& s, R& e) {
@@ -235,9 +249,13 @@ __device__ __forceinline__ void two_sum(R a, R b, R& s, R& e) {
 // One explicit step on a register state.  With COMPENSATED the Euler
 // increments are accumulated in (hi, lo) pairs so that increments below half
 // an ulp of the fraction are not lost; any correction that changes a
-// fraction resets its lo part.  Returns X_beta^{n+1}.
+// fraction resets its lo part.  Returns X_beta^{n+1}.  A state at rest is
+// returned as it is: with m == 0 its lo part is 0, and re-adding the (hi, lo)
+// pair of a previous two-sum reproduces it, so the full step would not change
+// it either.
 template <bool COMPENSATED, class R>
 __device__ __forceinline__ R explicit_step(R& a, R& m, R& a_lo, R& m_lo, R Tn, R xeq_n, R Tn1, R xeq_n1, R dt) {
+    if (at_rest(a, m, Tn, Tn1)) return R(1) - a - m;  // X_sol = 1 below T_as,end
     R da, dm;
     diffusive_increment(a, m, Tn, xeq_n, dt, da, dm);
     R at, mt;
@@ -291,11 +309,16 @@ __device__ __forceinline__ void diffusive_rates(R a, R m, R xeq, R kas, R& fa, R
 // the explicit step with its Appendix A closed form instead.  With
 // COMPENSATED the increment m^{n+1} - m^n is added to (hi, lo) pairs as in
 // explicit_step.  Returns the iteration count (0 for a start-up step),
-// negated if the stop test failed.
+// negated if the stop test failed.  A state at rest converges in the first
+// iteration with zero rates and is returned as it is (count 1).
 template <bool COMPENSATED, class R>
 __device__ __forceinline__ int implicit_step(R& a, R& m, R& a_lo, R& m_lo, R& beta, R Tn, R Tn1, R dt,
                                              int max_iter) {
     using C = Const<R>;
+    if (at_rest(a, m, Tn, Tn1)) {
+        beta = R(1) - a - m;
+        return 1;
+    }
     const R xeq_n = alpha_eq(Tn), xeq_1 = alpha_eq(Tn1);
     const R xa = a + m;
     if ((xa < xeq_n && !(a > R(0))) || (xa > xeq_n && vmax(C::Xmax - xa, R(0)) * dt <= C::StartupLimit)) {

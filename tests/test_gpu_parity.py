@@ -241,3 +241,53 @@ def test_cantilever_islands_full_size_sampled(torch, ctx, orc):
     # the scan transformed part of the sample (martensite formed under the tracks)
     assert float(st.alpha_m.max()) > 0.1
     assert ctx.check_invariants(*g, tol=2e-6) == 0
+
+
+@pytest.mark.parametrize("dt", [1e-6, 1e-2, 1.0])
+def test_states_at_rest(torch, ctx, orc, dt):
+    """alpha_s = 0.9 without martensite is a fixed point of both schemes while
+    T^n and T^{n+1} stay below 935 K: the kernels return such states without
+    evaluating the model, so the output must be the input bit for bit there,
+    and match the oracle's full evaluation on both sides of 935 K."""
+    n = 8192
+    rng = np.random.default_rng(21)
+    Tp = rng.uniform(880.0, 990.0, n).astype(np.float32)
+    Tn = np.clip(Tp + rng.normal(0.0, 30.0, n), 300.0, 1100.0).astype(np.float32)
+    Tp[:64] = np.float32(934.99994)  # the largest float32 below 935
+    Tp[64:128] = np.float32(935.0)
+    cold = (Tp < 935.0) & (Tn < 935.0)
+    assert 0.2 * n < cold.sum() < 0.8 * n
+    b0, a0, m0 = workload.initial_state(n, np.float32)
+    for step in ("step", "step_implicit"):
+        g = [torch.from_numpy(x.copy()).cuda() for x in (b0, a0, m0)]
+        getattr(ctx, step)(torch.from_numpy(Tp).cuda(), torch.from_numpy(Tn).cuda(), dt, *g)
+        gb, ga, gm = [x.cpu().numpy() for x in g]
+        assert np.array_equal(ga[cold], a0[cold]) and np.array_equal(gm[cold], m0[cold])
+        assert np.array_equal(gb[cold], np.full(int(cold.sum()), np.float32(1.0) - np.float32(0.9)))
+        st = orc.State(*[x.astype(np.float64) for x in (b0, a0, m0)])
+        if step == "step":
+            orc.step(st, Tp.astype(np.float64), Tn.astype(np.float64), dt)
+        else:
+            orc.step_implicit(st, Tp.astype(np.float64), Tn.astype(np.float64), dt)
+        for x, y in ((gb, st.beta), (ga, st.alpha_s), (gm, st.alpha_m)):
+            assert float(np.abs(x.astype(np.float64) - y).max()) <= 2e-6, (step, dt)
+
+
+def test_fused_body_near_the_alpha_end_temperature(torch, ctx, orc):
+    """A track on a body at 920 K: the whole body starts at rest just below
+    935 K and the track's heat takes a growing region across it, where the
+    fused kernel must leave the shortcut; all points against the oracle."""
+    import dataclasses
+
+    import paper_2402_17580_amd as ms
+    wl0 = workload.single_track(nx=48, ny=32, nz=10)
+    wl = dataclasses.replace(wl0, scan=dataclasses.replace(wl0.scan, T0=920.0))
+    n = wl.grid.n
+    g = _state(torch, n)
+    ms.run_layers(ctx, wl, *g, K=16)
+    torch.cuda.synchronize()
+    st = orc.run_workload(wl, np.arange(n))
+    for k, (mx, rms) in _errors(torch, g, st).items():
+        assert mx <= RUN_TOL, k
+    moved = np.abs(st.alpha_s - np.float32(0.9)) > 1e-3
+    assert 0.01 * n < moved.sum() < 0.9 * n
