@@ -212,9 +212,9 @@ def main():
 # HBM bytes per launch (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0: the factors a
 # plain 1 GiB device copy reads on the same counters).
 FUSED_PROFILE = {
-    "valu_lane_ops_per_update": 211.08,
-    "fp32_flops_per_update": 158.1,
-    "traffic_bytes_per_launch": (29390.19 * 2.0 + 58858.50) * 1024,
+    "valu_lane_ops_per_update": 133.51,
+    "fp32_flops_per_update": 99.5,
+    "traffic_bytes_per_launch": (29383.50 * 2.0 + 58858.50) * 1024,
 }
 
 def bench_stepwise(torch, ms, ctx, wl, dev):
@@ -256,7 +256,7 @@ def bench_stepwise(torch, ms, ctx, wl, dev):
 
 # Per-point VALU lane-ops of the implicit step kernel on the two regimes timed
 # below, from rocprofv3 counter runs of this script (SQ_INSTS_VALU x 64 / points)
-IMPLICIT_PROFILE = {"scan": 293.2, "cooldown": 2350.3}
+IMPLICIT_PROFILE = {"scan": 96.8, "cooldown": 385.8}
 
 
 def bench_implicit(torch, ms, ctx, wl, state):
