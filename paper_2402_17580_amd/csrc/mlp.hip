@@ -564,7 +564,8 @@ hipError_t mlp_adam(MlpState& s, float lr, hipStream_t st) {
 // Pass A (one point per lane, no matrix code, high occupancy): temperatures at
 // the block ends, the error indicator, the K plain steps for flagged points,
 // and for the others one explicit step of K dt, stored; a wave with any
-// non-zero diffusive increment appends its inputs to the queue.
+// point whose increment exceeds kNetMinIncrement appends its inputs to the
+// queue.
 // Pass B (persistent, weights staged in LDS): the network on queued waves,
 // whose output corrects the increment before the block-end correction.
 // ---------------------------------------------------------------------------
@@ -581,6 +582,12 @@ __device__ __forceinline__ bool needs_plain(float T0, float TK, const MlpNorm& n
 // block-end temperature the formation law would raise alpha_m, so a dip of the
 // temperature inside the block would form martensite the block ends miss.
 constexpr float kFrontProbe = 5.0f;  // [K]
+// The network corrects one explicit step of K dt towards K plain steps.  The
+// two differ by the change of the rates over the block times K dt, at most
+// about the increment itself, so increments of at most 2^-20 (about 1e-6) in
+// both fractions are taken as they are.  Away from the laser these are the
+// slow low-temperature rates, e.g. the tempering of martensite.
+constexpr float kNetMinIncrement = 0x1p-20f;
 constexpr int kProbeEvery = 8;       // probe spacing inside longer blocks [steps]
 __device__ __forceinline__ bool formation_front(float T0, float TK, float a, float m) {
     const float Tlo = fminf(T0, TK) - kFrontProbe;
@@ -684,7 +691,7 @@ __global__ __launch_bounds__(256) void surrogate_a_kernel(PointGeom pg, const Sr
                     diffusive_increment(a[u], m[u], T0[u], xeq0, dt * (float)K, da, dm);
                     pa = a[u] + da;
                     pm = m[u] + dm;
-                    need = (da != 0.0f) || (dm != 0.0f);
+                    need = fmaxf(fabsf(da), fabsf(dm)) > kNetMinIncrement;
                     an = pa;
                     mn = pm;
                     bn = correct(TK[u], alpha_eq(TK[u]), an, mn);
