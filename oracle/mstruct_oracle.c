@@ -27,7 +27,10 @@
  *       solid-fraction cap, beta from the sum rule.
  *   R6  alpha_s -> beta start-up (Appendix A) is used while
  *       X_alpha > X_alpha^eq and X~beta * dt <= 1e-15 (dt in seconds), with
- *       T held at T^n over the step; X~beta is carried as its own state.
+ *       T held at T^n over the step; X~beta is carried as its own state and,
+ *       while the closed form is in use, is authoritative: alpha_s is set to
+ *       X_sol - 0.1 - X~beta - X_am (not accumulated from increments, which
+ *       float64 rounds at 1.1e-16 each while they are near 1e-15).
  *   R7  beta -> alpha_s start-up (cited to an absent reference) uses the same
  *       generalised-logistic closed form with X_am frozen:
  *       D' = X_alpha^eq - X_am, k~ = k_as D', c = c_as, from X_as = 0.
@@ -244,7 +247,6 @@ void orc_step(double *as_, double *am_, double *b_, double *bt_, double Tn, doub
             double D = X_ALPHA_MAX - xeq;
             double nb = orc_logistic_step(btp, D, D * kb, C_BETA, dt);
             if (nb != btp) {
-                das -= (nb - btp);
                 bt_new = nb;
                 startup_beta = 1;
             }
@@ -253,8 +255,11 @@ void orc_step(double *as_, double *am_, double *b_, double *bt_, double Tn, doub
         }
     }
 
-    /* forward Euler towards the intermediate state, then the correction */
-    double a = as + das, m = am + dam;
+    /* forward Euler towards the intermediate state, then the correction;
+     * while the start-up form is in use X~beta is authoritative and alpha_s
+     * follows from it (R6): X_alpha = 0.9 - X~beta, alpha_m as updated */
+    double m = am + dam;
+    double a = startup_beta ? X_ALPHA_MAX - bt_new - m : as + das;
     double a_t = a, m_t = m;
     double b = orc_correct(Tn1, &a, &m);
 

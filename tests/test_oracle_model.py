@@ -260,3 +260,27 @@ def test_first_order_in_time_on_smooth_history(orc):
     e = [np.abs(run(dt) - ref).max() for dt in (4e-3, 2e-3, 1e-3)]
     assert e[0] > 1e-6
     assert 1.7 < e[0] / e[1] < 2.3 and 1.7 < e[1] / e[2] < 2.3
+
+
+def test_alpha_s_to_beta_start_converges_through_the_exit(orc):
+    """At constant 1100 K, 10 s from X~beta = 0: the start-up closed form
+    runs until X~beta dt > 1e-15, then Euler.  X~beta grows monotonically
+    across the switch and its error against the Appendix A closed form over
+    the whole hold is first order in dt.  Accumulating alpha_s from the
+    start-up increments (near 1e-15 each, rounded at 1.1e-16 in float64)
+    instead of setting it from X~beta breaks both."""
+    c = orc.constants()
+    T = 1100.0
+    D = 0.9 - orc.alpha_eq(T)
+    exact = orc.logistic_step(0.0, D, c["f"] * orc.k_as(T) * D, c["c_beta"], 10.0)
+    errs = []
+    for dt in (4e-3, 2e-3, 1e-3):
+        st = orc.State.initial(1)
+        prev = 0.0
+        for _ in range(int(round(10.0 / dt))):
+            orc.step(st, T, T, dt)
+            assert st.xbt[0] >= prev
+            prev = st.xbt[0]
+        errs.append(abs(st.xbt[0] - exact) / exact)
+    assert errs[-1] < 1e-2
+    assert all(1.8 < errs[i] / errs[i + 1] < 2.4 for i in range(2)), errs
