@@ -40,12 +40,30 @@ typedef enum {
 
 typedef struct mstruct_ctx mstruct_ctx;
 
-/* Phase fractions of n points, device float32 arrays (structure of arrays). */
+/* Phase fractions of n points, device float32 arrays (structure of arrays).
+ *
+ * xbt is optional (NULL: not used): a device float64 array of n values that
+ * carries the shifted beta fraction X~beta = 0.9 - X_alpha of points whose
+ * alpha_s -> beta transformation is starting.  Its early values are far below
+ * the float32 resolution of X_beta = 0.1 + X~beta (e.g. 1e-80 after one
+ * microsecond at 1200 K), which is why the paper keeps X~beta apart
+ * (Appendix A); without xbt the float32 state cannot leave that start within
+ * holds of seconds at 935-1273 K.  A point is tracked while it has no
+ * martensite, dissolves at T^n (X_alpha > X_alpha^eq) and X~beta < 2^-12;
+ * above that alpha_s itself resolves X~beta.  NaN marks "not tracked": fill
+ * the array with NaN before its first use.  mstruct_step, mstruct_step_implicit
+ * and fused PLAIN and IMPLICIT modes read and write it (8 more bytes per
+ * point each way); fused SURROGATE mode rejects it (MSTRUCT_EUNSUPPORTED).
+ * A value that disagrees with the fractions (martensite present, or alpha_s
+ * not 0.9 - X~beta to float32 rounding) is ignored; after the fractions are
+ * changed by other means (the surrogate, mstruct_correct, the caller) fill
+ * it with NaN again. */
 typedef struct {
     float *beta;    /* X_beta */
     float *alpha_s; /* X_alpha_s (stable alpha) */
     float *alpha_m; /* X_alpha_m (martensite) */
     int64_t n;
+    double *xbt;    /* optional tracked X~beta, see above */
 } mstruct_phases;
 
 /* Laser scan as a host table of straight tracks (row-major n_tracks x 9,

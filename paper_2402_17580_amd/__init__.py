@@ -36,7 +36,7 @@ class MstructError(RuntimeError):
 
 class PhasesC(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_void_p), ("alpha_s", ctypes.c_void_p), ("alpha_m", ctypes.c_void_p),
-                ("n", ctypes.c_int64)]
+                ("n", ctypes.c_int64), ("xbt", ctypes.c_void_p)]
 
 
 class PhasesF64C(ctypes.Structure):
@@ -152,16 +152,18 @@ class Context:
             raise MstructError(rc, f"{what}: {msg}")
 
     @staticmethod
-    def _phases(beta, alpha_s, alpha_m):
+    def _phases(beta, alpha_s, alpha_m, xbt=None):
         import torch
         n = beta.numel()
         return PhasesC(_dev_ptr(beta, torch.float32, n, "beta"), _dev_ptr(alpha_s, torch.float32, n, "alpha_s"),
-                       _dev_ptr(alpha_m, torch.float32, n, "alpha_m"), n)
+                       _dev_ptr(alpha_m, torch.float32, n, "alpha_m"), n, _dev_ptr(xbt, torch.float64, n, "xbt"))
 
     # -- hot path ----------------------------------------------------------
-    def step(self, T_prev, T_next, dt, beta, alpha_s, alpha_m, stream=None):
+    def step(self, T_prev, T_next, dt, beta, alpha_s, alpha_m, xbt=None, stream=None):
+        """Explicit step in place; xbt: optional CUDA float64 tensor carrying
+        the tracked X~beta (NaN-filled before first use, see new_xbt)."""
         import torch
-        ph = self._phases(beta, alpha_s, alpha_m)
+        ph = self._phases(beta, alpha_s, alpha_m, xbt)
         self._check(lib().mstruct_step(self._h, _dev_ptr(T_prev, torch.float32, ph.n, "T_prev"),
                                        _dev_ptr(T_next, torch.float32, ph.n, "T_next"), float(dt),
                                        ctypes.byref(ph), _stream(stream)), "mstruct_step")
@@ -178,12 +180,12 @@ class Context:
                     "mstruct_step_f64")
 
     def step_implicit(self, T_prev, T_next, dt, beta, alpha_s, alpha_m, dt_sub=0.01, max_iter=50,
-                      unconverged=None, stream=None):
+                      unconverged=None, xbt=None, stream=None):
         """Implicit (Crank-Nicolson, fixed-point) step; unconverged: optional
         CUDA int64 tensor of one element, incremented by the number of
-        substeps that hit max_iter."""
+        substeps that hit max_iter; xbt as for step."""
         import torch
-        ph = self._phases(beta, alpha_s, alpha_m)
+        ph = self._phases(beta, alpha_s, alpha_m, xbt)
         up = _dev_ptr(unconverged, torch.int64, 1, "unconverged") if unconverged is not None else None
         self._check(lib().mstruct_step_implicit(self._h, _dev_ptr(T_prev, torch.float32, ph.n, "T_prev"),
                                                 _dev_ptr(T_next, torch.float32, ph.n, "T_next"), float(dt),
@@ -206,8 +208,8 @@ class Context:
                     "mstruct_temperature")
 
     def fused_scan_steps(self, scan, grid, t0, dt, n_steps, K, beta, alpha_s, alpha_m, z_top=math.inf,
-                         mode=MODE_PLAIN, index=None, stream=None):
-        ph = self._phases(beta, alpha_s, alpha_m)
+                         mode=MODE_PLAIN, index=None, xbt=None, stream=None):
+        ph = self._phases(beta, alpha_s, alpha_m, xbt)
         sc, pts = scan_struct(scan), points_struct(grid, ph.n, z_top, index)
         self._check(lib().mstruct_fused_scan_steps(self._h, ctypes.byref(sc), ctypes.byref(pts), float(t0),
                                                    float(dt), int(n_steps), int(K), int(mode), ctypes.byref(ph),
@@ -276,21 +278,27 @@ class Context:
                                                  else None, _stream(stream)), "mstruct_mlp_train_step")
 
 
+def new_xbt(n, device="cuda"):
+    """A tracked-X~beta side array for n points, nothing tracked yet."""
+    import torch
+    return torch.full((n,), float("nan"), dtype=torch.float64, device=device)
+
+
 def run_layers(ctx: Context, wl, beta, alpha_s, alpha_m, K=16, mode=MODE_PLAIN, index=None, layers=None,
-               stream=None):
+               xbt=None, stream=None):
     """Run the layers of a workload with the fused kernel (one call per layer)."""
     for L in (wl.layers if layers is None else layers):
         ctx.fused_scan_steps(wl.scan, wl.grid, wl.t0(L), wl.dt, L.step_end - L.step_begin, K, beta, alpha_s,
-                             alpha_m, z_top=L.z_top, mode=mode, index=index, stream=stream)
+                             alpha_m, z_top=L.z_top, mode=mode, index=index, xbt=xbt, stream=stream)
 
 
-def run_phases(ctx: Context, pw, beta, alpha_s, alpha_m, K=16, stream=None):
+def run_phases(ctx: Context, pw, beta, alpha_s, alpha_m, K=16, xbt=None, stream=None):
     """Run the phases of a phased workload (scan phases with the explicit
     scheme, cool-down phases with the implicit one), one fused call each."""
     for ph in pw.phases:
         mode = MODE_IMPLICIT if ph.scheme == "implicit" else MODE_PLAIN
         ctx.fused_scan_steps(pw.scan, pw.grid, ph.t0, ph.dt, ph.n_steps, K, beta, alpha_s, alpha_m, z_top=ph.z_top,
-                             mode=mode, stream=stream)
+                             mode=mode, xbt=xbt, stream=stream)
 
 
 def run_layers_stepwise(ctx: Context, wl, beta, alpha_s, alpha_m, T_a, T_b, layers=None, stream=None):

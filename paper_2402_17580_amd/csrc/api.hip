@@ -305,7 +305,7 @@ int mstruct_step(mstruct_ctx* ctx, const float* T_prev, const float* T_next, dou
     if (!finite_pos(dt)) return fail(ctx, MSTRUCT_EINVAL, "dt must be positive and finite");
     if (ph->n > 0 && (!T_prev || !T_next)) return fail(ctx, MSTRUCT_EINVAL, "temperature array is NULL");
     DeviceGuard g(ctx->device);
-    hipError_t e = launch_step(T_prev, T_next, ph->beta, ph->alpha_s, ph->alpha_m, ph->n, (float)dt,
+    hipError_t e = launch_step(T_prev, T_next, ph->beta, ph->alpha_s, ph->alpha_m, ph->xbt, ph->n, (float)dt,
                                (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "step launch");
     return MSTRUCT_OK;
@@ -341,7 +341,7 @@ int mstruct_step_implicit(mstruct_ctx* ctx, const float* T_prev, const float* T_
     if (dt / dt_sub > 1e6) return fail(ctx, MSTRUCT_EINVAL, "dt / dt_sub exceeds 1e6 substeps");
     const int n_sub = substeps(dt, dt_sub);
     DeviceGuard g(ctx->device);
-    hipError_t e = launch_implicit_step(T_prev, T_next, ph->beta, ph->alpha_s, ph->alpha_m, ph->n,
+    hipError_t e = launch_implicit_step(T_prev, T_next, ph->beta, ph->alpha_s, ph->alpha_m, ph->xbt, ph->n,
                                         (float)(dt / n_sub), n_sub, max_iter, unconverged, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "implicit step launch");
     return MSTRUCT_OK;
@@ -388,6 +388,8 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
         return fail(ctx, MSTRUCT_EINVAL, "dt / 0.01 s exceeds 1e6 substeps");
     PointGeom pg;
     if ((rc = make_geom(ctx, pts, ph->n, pg))) return rc;
+    if (mode == MSTRUCT_MODE_SURROGATE && ph->xbt)
+        return fail(ctx, MSTRUCT_EUNSUPPORTED, "surrogate mode does not carry the tracked X~beta (xbt)");
     if (mode == MSTRUCT_MODE_SURROGATE && !ctx->mlp.ready)
         return fail(ctx, MSTRUCT_ESTATE, "surrogate mode needs network parameters (mstruct_mlp_set_params)");
     if (n_steps == 0 || pg.count == 0) return MSTRUCT_OK;
@@ -414,11 +416,12 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
         float* beta = last ? ph->beta : nullptr;
         hipError_t e;
         if (mode == MSTRUCT_MODE_PLAIN) {
-            e = launch_fused_plain(pg, W, s->dev + s0 * W, Kb, (float)dt, sa, beta, ph->alpha_s, ph->alpha_m, st);
+            e = launch_fused_plain(pg, W, s->dev + s0 * W, Kb, (float)dt, sa, beta, ph->alpha_s, ph->alpha_m, ph->xbt,
+                                   st);
         } else if (mode == MSTRUCT_MODE_IMPLICIT) {
             const int n_sub = substeps(dt, kImplicitDtSub);
             e = launch_fused_implicit(pg, W, s->dev + s0 * W, Kb, (float)(dt / n_sub), n_sub, kImplicitMaxIter, sa,
-                                      beta, ph->alpha_s, ph->alpha_m, ctx->implicit_bad, st);
+                                      beta, ph->alpha_s, ph->alpha_m, ph->xbt, ctx->implicit_bad, st);
         } else
             e = launch_surrogate(ctx->mlp, pg, W, s->dev + s0 * W, Kb, (float)dt, sa, ph->beta, ph->alpha_s,
                                  ph->alpha_m, s0 / K, s0 == 0, last, st);

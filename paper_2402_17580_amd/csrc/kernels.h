@@ -48,10 +48,11 @@ struct ScanArgs {
     float T0, Tclamp;
 };
 
-hipError_t launch_step(const float* Tp, const float* Tn, float* beta, float* as, float* am, int64_t n,
+// xb: optional tracked X~beta side values (float64 per point), or nullptr
+hipError_t launch_step(const float* Tp, const float* Tn, float* beta, float* as, float* am, double* xb, int64_t n,
                        float dt, hipStream_t st);
 hipError_t launch_fused_implicit(const PointGeom& pg, int W, const SrcRec* tab, int K, float h, int n_sub,
-                                 int max_iter, ScanArgs sa, float* beta, float* as, float* am,
+                                 int max_iter, ScanArgs sa, float* beta, float* as, float* am, double* xb,
                                  unsigned long long* unconverged, hipStream_t st);
 // float64 explicit step (step_f64_lib.hip: device math library; step_f64_synth.hip:
 // exponent-bit exp2 / log2)
@@ -59,13 +60,13 @@ hipError_t launch_step_f64_library(const double* Tp, const double* Tn, double* b
                                    int64_t n, double dt, hipStream_t st);
 hipError_t launch_step_f64_synth(const double* Tp, const double* Tn, double* beta, double* as, double* am,
                                  int64_t n, double dt, hipStream_t st);
-hipError_t launch_implicit_step(const float* Tp, const float* Tn, float* beta, float* as, float* am, int64_t n,
-                                float h, int n_sub, int max_iter, unsigned long long* unconverged,
+hipError_t launch_implicit_step(const float* Tp, const float* Tn, float* beta, float* as, float* am, double* xb,
+                                int64_t n, float h, int n_sub, int max_iter, unsigned long long* unconverged,
                                 hipStream_t st);
 hipError_t launch_temperature(const PointGeom& pg, int W, const SrcRec* rec, ScanArgs sa, float* T,
                               hipStream_t st);
 hipError_t launch_fused_plain(const PointGeom& pg, int W, const SrcRec* tab, int K, float dt, ScanArgs sa,
-                              float* beta, float* as, float* am, hipStream_t st);
+                              float* beta, float* as, float* am, double* xb, hipStream_t st);
 hipError_t launch_gather(const float* src, const int64_t* idx, int64_t m, float* dst, hipStream_t st);
 hipError_t launch_invariants(const float* beta, const float* as, const float* am, const float* T, int64_t n,
                              float tol, unsigned long long* counter, hipStream_t st);

@@ -75,9 +75,30 @@ __global__ __launch_bounds__(kBlock) void step_kernel(const float* __restrict__ 
     }
 }
 
-hipError_t launch_step(const float* Tp, const float* Tn, float* beta, float* as, float* am, int64_t n,
+// the explicit step with the tracked X~beta side value (float64 per point)
+__global__ __launch_bounds__(kBlock) void step_tracked_kernel(const float* __restrict__ Tp,
+                                                             const float* __restrict__ Tn, float* __restrict__ beta,
+                                                             float* __restrict__ as, float* __restrict__ am,
+                                                             double* __restrict__ xbv, int64_t n, float dt) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= n) return;
+    float a = as[g], m = am[g], alo = 0.0f, mlo = 0.0f;
+    double xb = track_check(xbv[g], a, m);
+    const float tp = Tp[g], tn = Tn[g];
+    beta[g] = explicit_step_tracked<false>(a, m, alo, mlo, xb, tp, alpha_eq(tp), tn, alpha_eq(tn), dt);
+    as[g] = a;
+    am[g] = m;
+    xbv[g] = xb;
+}
+
+hipError_t launch_step(const float* Tp, const float* Tn, float* beta, float* as, float* am, double* xb, int64_t n,
                        float dt, hipStream_t st) {
     if (n <= 0) return hipSuccess;
+    if (xb) {
+        hipLaunchKernelGGL(step_tracked_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, Tp,
+                           Tn, beta, as, am, xb, n, dt);
+        return hipGetLastError();
+    }
     const uintptr_t align = (uintptr_t)Tp | (uintptr_t)Tn | (uintptr_t)beta | (uintptr_t)as | (uintptr_t)am;
     if ((align & 15) == 0) {
         const int64_t threads = (n + 3) / 4;
@@ -98,27 +119,33 @@ hipError_t launch_step(const float* Tp, const float* Tn, float* beta, float* as,
 // explicit step; the iteration makes it compute-heavier).  Substeps whose
 // iteration hit max_iter are counted, one atomic per wave.
 // ---------------------------------------------------------------------------
+// TRACK: with the tracked X~beta side value (float64 per point)
+template <bool TRACK>
 __global__ __launch_bounds__(kBlock) void implicit_step_kernel(const float* __restrict__ Tp,
                                                               const float* __restrict__ Tn,
                                                               float* __restrict__ beta, float* __restrict__ as,
-                                                              float* __restrict__ am, int64_t n, float h,
-                                                              int n_sub, int max_iter,
+                                                              float* __restrict__ am, double* __restrict__ xbv,
+                                                              int64_t n, float h, int n_sub, int max_iter,
                                                               unsigned long long* __restrict__ unconverged) {
     const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     int bad = 0;
     if (g < n) {
         float a = as[g], m = am[g], b = 0.0f, alo = 0.0f, mlo = 0.0f;
+        double xb = TRACK ? track_check(xbv[g], a, m) : 0.0;
         const float T0 = Tp[g], dT = Tn[g] - T0;
         const float inv = 1.0f / (float)n_sub;
         float Ta = T0;
         for (int s = 0; s < n_sub; ++s) {
             const float Tb = (s + 1 == n_sub) ? Tn[g] : fmaf(dT, (float)(s + 1) * inv, T0);
-            if (implicit_step<false>(a, m, alo, mlo, b, Ta, Tb, h, max_iter) < 0) ++bad;
+            const int it = TRACK ? implicit_step_tracked<false>(a, m, alo, mlo, xb, b, Ta, Tb, h, max_iter)
+                                 : implicit_step<false>(a, m, alo, mlo, b, Ta, Tb, h, max_iter);
+            if (it < 0) ++bad;
             Ta = Tb;
         }
         as[g] = a;
         am[g] = m;
         beta[g] = b;
+        if (TRACK) xbv[g] = xb;
     }
     if (unconverged) {
         // sum of the per-lane counts over the wave (counts are small)
@@ -128,12 +155,17 @@ __global__ __launch_bounds__(kBlock) void implicit_step_kernel(const float* __re
     }
 }
 
-hipError_t launch_implicit_step(const float* Tp, const float* Tn, float* beta, float* as, float* am, int64_t n,
-                                float h, int n_sub, int max_iter, unsigned long long* unconverged,
+hipError_t launch_implicit_step(const float* Tp, const float* Tn, float* beta, float* as, float* am, double* xb,
+                                int64_t n, float h, int n_sub, int max_iter, unsigned long long* unconverged,
                                 hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(implicit_step_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, Tp,
-                       Tn, beta, as, am, n, h, n_sub, max_iter, unconverged);
+    const dim3 grid((unsigned)((n + kBlock - 1) / kBlock)), block(kBlock);
+    if (xb)
+        hipLaunchKernelGGL(implicit_step_kernel<true>, grid, block, 0, st, Tp, Tn, beta, as, am, xb, n, h, n_sub,
+                           max_iter, unconverged);
+    else
+        hipLaunchKernelGGL(implicit_step_kernel<false>, grid, block, 0, st, Tp, Tn, beta, as, am, xb, n, h, n_sub,
+                           max_iter, unconverged);
     return hipGetLastError();
 }
 
@@ -156,10 +188,11 @@ __global__ __launch_bounds__(kBlock) void temperature_kernel(PointGeom pg, const
 // held in registers (with compensated Euler accumulation); tab holds the
 // K + 1 time points x W window slots of this launch.
 // ---------------------------------------------------------------------------
-template <int W, int PPT>
+template <int W, int PPT, bool TRACK>
 __global__ __launch_bounds__(kBlock) void fused_plain_kernel(PointGeom pg, const SrcRec* __restrict__ tab, int K,
                                                             float dt, ScanArgs sa, float* __restrict__ beta,
-                                                            float* __restrict__ as, float* __restrict__ am) {
+                                                            float* __restrict__ as, float* __restrict__ am,
+                                                            double* __restrict__ xbv) {
     // beta == nullptr: not written (inside a call only the last launch writes
     // it; no kernel reads beta, it follows from the sum rule)
     // PPT points per lane, kBlock apart (coalesced), advanced together for ILP
@@ -168,6 +201,7 @@ __global__ __launch_bounds__(kBlock) void fused_plain_kernel(PointGeom pg, const
     int gi[PPT], gj[PPT], gk[PPT];
     bool act[PPT];
     float a[PPT], m[PPT], alo[PPT], mlo[PPT], Tn[PPT], xeq_n[PPT];
+    double xb[PPT];
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
         const int64_t g = g0 + u * kBlock;
@@ -177,6 +211,7 @@ __global__ __launch_bounds__(kBlock) void fused_plain_kernel(PointGeom pg, const
         act[u] = act[u] && gk[u] >= pg.k0;
         a[u] = act[u] ? as[local[u]] : 0.0f;
         m[u] = act[u] ? am[local[u]] : 0.0f;
+        xb[u] = (TRACK && act[u]) ? track_check(xbv[local[u]], a[u], m[u]) : track_none();
         alo[u] = 0.0f;
         mlo[u] = 0.0f;
     }
@@ -190,7 +225,10 @@ __global__ __launch_bounds__(kBlock) void fused_plain_kernel(PointGeom pg, const
         for (int u = 0; u < PPT; ++u) {
             const float Tn1 = scan_temperature<W>(tab + (s + 1) * W, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min, pg.roff);
             const float xeq_n1 = alpha_eq(Tn1);
-            explicit_step<true>(a[u], m[u], alo[u], mlo[u], Tn[u], xeq_n[u], Tn1, xeq_n1, dt);
+            if (TRACK)
+                explicit_step_tracked<true>(a[u], m[u], alo[u], mlo[u], xb[u], Tn[u], xeq_n[u], Tn1, xeq_n1, dt);
+            else
+                explicit_step<true>(a[u], m[u], alo[u], mlo[u], Tn[u], xeq_n[u], Tn1, xeq_n1, dt);
             Tn[u] = Tn1;
             xeq_n[u] = xeq_n1;
         }
@@ -201,6 +239,7 @@ __global__ __launch_bounds__(kBlock) void fused_plain_kernel(PointGeom pg, const
         const float af = a[u] + alo[u], mf = m[u] + mlo[u];
         as[local[u]] = af;
         am[local[u]] = mf;
+        if (TRACK) xbv[local[u]] = xb[u];
         if (beta) beta[local[u]] = solid_fraction(Tn[u]) - af - mf;
     }
 }
@@ -212,11 +251,11 @@ __global__ __launch_bounds__(kBlock) void fused_plain_kernel(PointGeom pg, const
 // analytic step-end values), with compensated accumulation of the increments
 // inside a launch as in the plain fused kernel.
 // ---------------------------------------------------------------------------
-template <int W>
+template <int W, bool TRACK>
 __global__ __launch_bounds__(kBlock) void fused_implicit_kernel(PointGeom pg, const SrcRec* __restrict__ tab, int K,
                                                                float h, int n_sub, int max_iter, ScanArgs sa,
                                                                float* __restrict__ beta, float* __restrict__ as,
-                                                               float* __restrict__ am,
+                                                               float* __restrict__ am, double* __restrict__ xbv,
                                                                unsigned long long* __restrict__ unconverged) {
     const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     bool act = g < pg.count;
@@ -225,6 +264,7 @@ __global__ __launch_bounds__(kBlock) void fused_implicit_kernel(PointGeom pg, co
     decode_point(pg, local, gi, gj, gk);
     act = act && gk >= pg.k0;
     float a = act ? as[local] : 0.0f, m = act ? am[local] : 0.0f, b = 0.0f, alo = 0.0f, mlo = 0.0f;
+    double xb = (TRACK && act) ? track_check(xbv[local], a, m) : track_none();
     int bad = 0;
     float Tn = scan_temperature<W>(tab, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
     const float inv = 1.0f / (float)n_sub;
@@ -233,7 +273,9 @@ __global__ __launch_bounds__(kBlock) void fused_implicit_kernel(PointGeom pg, co
         float Ta = Tn;
         for (int k = 0; k < n_sub; ++k) {
             const float Tb = (k + 1 == n_sub) ? Tn1 : fmaf(Tn1 - Tn, (float)(k + 1) * inv, Tn);
-            if (implicit_step<true>(a, m, alo, mlo, b, Ta, Tb, h, max_iter) < 0) ++bad;
+            const int it = TRACK ? implicit_step_tracked<true>(a, m, alo, mlo, xb, b, Ta, Tb, h, max_iter)
+                                 : implicit_step<true>(a, m, alo, mlo, b, Ta, Tb, h, max_iter);
+            if (it < 0) ++bad;
             Ta = Tb;
         }
         Tn = Tn1;
@@ -244,6 +286,7 @@ __global__ __launch_bounds__(kBlock) void fused_implicit_kernel(PointGeom pg, co
         as[local] = a;
         am[local] = m;
         if (beta) beta[local] = solid_fraction(Tn) - a - m;
+        if (TRACK) xbv[local] = xb;
     }
     if (!act) bad = 0;
     int total = bad;
@@ -251,19 +294,27 @@ __global__ __launch_bounds__(kBlock) void fused_implicit_kernel(PointGeom pg, co
     if ((threadIdx.x & 63) == 0 && total) atomicAdd(unconverged, (unsigned long long)total);
 }
 
-hipError_t launch_fused_implicit(const PointGeom& pg, int W, const SrcRec* tab, int K, float h, int n_sub,
-                                 int max_iter, ScanArgs sa, float* beta, float* as, float* am,
-                                 unsigned long long* unconverged, hipStream_t st) {
-    if (pg.count <= 0) return hipSuccess;
+template <bool TRACK>
+static hipError_t fused_implicit_w(const PointGeom& pg, int W, const SrcRec* tab, int K, float h, int n_sub,
+                                   int max_iter, ScanArgs sa, float* beta, float* as, float* am, double* xb,
+                                   unsigned long long* unconverged, hipStream_t st) {
     const dim3 grid((unsigned)((pg.count + kBlock - 1) / kBlock)), block(kBlock);
     switch (W) {
-        case 1: hipLaunchKernelGGL(fused_implicit_kernel<1>, grid, block, 0, st, pg, tab, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
-        case 2: hipLaunchKernelGGL(fused_implicit_kernel<2>, grid, block, 0, st, pg, tab, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
-        case 3: hipLaunchKernelGGL(fused_implicit_kernel<3>, grid, block, 0, st, pg, tab, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
-        case 4: hipLaunchKernelGGL(fused_implicit_kernel<4>, grid, block, 0, st, pg, tab, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
+        case 1: hipLaunchKernelGGL((fused_implicit_kernel<1, TRACK>), grid, block, 0, st, pg, tab, K, h, n_sub, max_iter, sa, beta, as, am, xb, unconverged); break;
+        case 2: hipLaunchKernelGGL((fused_implicit_kernel<2, TRACK>), grid, block, 0, st, pg, tab, K, h, n_sub, max_iter, sa, beta, as, am, xb, unconverged); break;
+        case 3: hipLaunchKernelGGL((fused_implicit_kernel<3, TRACK>), grid, block, 0, st, pg, tab, K, h, n_sub, max_iter, sa, beta, as, am, xb, unconverged); break;
+        case 4: hipLaunchKernelGGL((fused_implicit_kernel<4, TRACK>), grid, block, 0, st, pg, tab, K, h, n_sub, max_iter, sa, beta, as, am, xb, unconverged); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_fused_implicit(const PointGeom& pg, int W, const SrcRec* tab, int K, float h, int n_sub,
+                                 int max_iter, ScanArgs sa, float* beta, float* as, float* am, double* xb,
+                                 unsigned long long* unconverged, hipStream_t st) {
+    if (pg.count <= 0) return hipSuccess;
+    return xb ? fused_implicit_w<true>(pg, W, tab, K, h, n_sub, max_iter, sa, beta, as, am, xb, unconverged, st)
+              : fused_implicit_w<false>(pg, W, tab, K, h, n_sub, max_iter, sa, beta, as, am, xb, unconverged, st);
 }
 
 hipError_t launch_temperature(const PointGeom& pg, int W, const SrcRec* rec, ScanArgs sa, float* T,
@@ -282,18 +333,25 @@ hipError_t launch_temperature(const PointGeom& pg, int W, const SrcRec* rec, Sca
 
 constexpr int kFusedPPT = FUSED_PPT;
 
-hipError_t launch_fused_plain(const PointGeom& pg, int W, const SrcRec* tab, int K, float dt, ScanArgs sa,
-                              float* beta, float* as, float* am, hipStream_t st) {
-    if (pg.count <= 0) return hipSuccess;
+template <bool TRACK>
+static hipError_t fused_plain_w(const PointGeom& pg, int W, const SrcRec* tab, int K, float dt, ScanArgs sa,
+                                float* beta, float* as, float* am, double* xb, hipStream_t st) {
     const dim3 grid((unsigned)((pg.count + kBlock * kFusedPPT - 1) / (kBlock * kFusedPPT))), block(kBlock);
     switch (W) {
-        case 1: hipLaunchKernelGGL((fused_plain_kernel<1, kFusedPPT>), grid, block, 0, st, pg, tab, K, dt, sa, beta, as, am); break;
-        case 2: hipLaunchKernelGGL((fused_plain_kernel<2, kFusedPPT>), grid, block, 0, st, pg, tab, K, dt, sa, beta, as, am); break;
-        case 3: hipLaunchKernelGGL((fused_plain_kernel<3, kFusedPPT>), grid, block, 0, st, pg, tab, K, dt, sa, beta, as, am); break;
-        case 4: hipLaunchKernelGGL((fused_plain_kernel<4, kFusedPPT>), grid, block, 0, st, pg, tab, K, dt, sa, beta, as, am); break;
+        case 1: hipLaunchKernelGGL((fused_plain_kernel<1, kFusedPPT, TRACK>), grid, block, 0, st, pg, tab, K, dt, sa, beta, as, am, xb); break;
+        case 2: hipLaunchKernelGGL((fused_plain_kernel<2, kFusedPPT, TRACK>), grid, block, 0, st, pg, tab, K, dt, sa, beta, as, am, xb); break;
+        case 3: hipLaunchKernelGGL((fused_plain_kernel<3, kFusedPPT, TRACK>), grid, block, 0, st, pg, tab, K, dt, sa, beta, as, am, xb); break;
+        case 4: hipLaunchKernelGGL((fused_plain_kernel<4, kFusedPPT, TRACK>), grid, block, 0, st, pg, tab, K, dt, sa, beta, as, am, xb); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_fused_plain(const PointGeom& pg, int W, const SrcRec* tab, int K, float dt, ScanArgs sa,
+                              float* beta, float* as, float* am, double* xb, hipStream_t st) {
+    if (pg.count <= 0) return hipSuccess;
+    return xb ? fused_plain_w<true>(pg, W, tab, K, dt, sa, beta, as, am, xb, st)
+              : fused_plain_w<false>(pg, W, tab, K, dt, sa, beta, as, am, xb, st);
 }
 
 // ---------------------------------------------------------------------------

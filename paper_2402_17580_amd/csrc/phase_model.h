@@ -377,4 +377,143 @@ __device__ __forceinline__ int implicit_step(R& a, R& m, R& a_lo, R& m_lo, R& be
     return converged ? it : -it;
 }
 
+// ---------------------------------------------------------------------------
+// Tracked shifted beta fraction (Appendix A).  When the alpha_s -> beta
+// transformation starts, X~beta = 0.9 - X_alpha is far below what X_beta =
+// 0.1 + X~beta, or X_alpha_s near 0.9, resolves in float32 (and its early
+// values, e.g. 1e-80 after one microsecond at 1200 K, are below the float32
+// range), so the paper keeps it apart.  An optional float64 value per point
+// carries it while the point is in that regime: no martensite, dissolution at
+// T^n (X~beta below D = 0.9 - X_alpha^eq) and X~beta below kTrackMax, above
+// which alpha_s resolves it to 1.2e-4 relative.  NaN: nothing is tracked;
+// X~beta then follows from the fractions.  The regime's only diffusive rate
+// is alpha_s -> beta, so the step is written on X~beta alone, in float64:
+// the closed form while X~beta dt is at most 1e-15, then Euler (or
+// Crank-Nicolson) on X~beta.  alpha_s = 0.9 - X~beta is stored as a float
+// (hi, lo) pair in the compensated kernels, which hands the value over
+// exactly when tracking ends.  0.9 is the float model's cap throughout.
+// (Float only: the float64 model keeps X~beta in its fractions.)
+// ---------------------------------------------------------------------------
+constexpr double kTrackMax = 0x1p-12;
+
+__device__ __forceinline__ double track_none() { return __builtin_nan(""); }
+
+// the side value as loaded with the fractions: kept if it agrees with them
+// (no martensite, 0.9 - alpha_s within 0.6 ulp of 0.9 of it), NaN otherwise
+__device__ __forceinline__ double track_check(double xb, float a, float m) {
+    const double d = (double)(Const<float>::Xmax - a) - xb;
+    return (m == 0.0f && fabs(d) <= 3.6e-8) ? xb : track_none();
+}
+
+// float64 forms of the functions the tracked step needs
+__device__ __forceinline__ double alpha_eq_f64(double T) {
+    if (T < 935.0) return (double)Const<float>::Xmax;
+    if (T > 1273.0) return 0.0;
+    return -expm1(-0.0068 * (1273.0 - T));
+}
+__device__ __forceinline__ double k_beta_f64(double T) {  // f k_alpha_s(T)
+    return 3.8 * 0.294 / (1.0 + exp(-0.0337 * (T - 850.0)));
+}
+// d X~beta / dt = k_b X~beta^((c-1)/c) (D - X~beta)^((c+1)/c), c = 11
+__device__ __forceinline__ double beta_rate_f64(double x, double D, double kb) {
+    return x < D ? kb * pow(x, 10.0 / 11.0) * pow(D - x, 12.0 / 11.0) : 0.0;
+}
+// Appendix A closed form from X~beta = x over dt at constant k~ = D k_b
+__device__ __forceinline__ double beta_startup_f64(double x, double D, double kb, double dt) {
+    const double xi = x / D;
+    const double u = pow(xi / (1.0 - xi), 1.0 / 11.0);
+    const double w = 11.0 / (D * kb * dt + 11.0 * u);
+    return D / (1.0 + pow(w, 11.0));
+}
+
+// X~beta if the point is in the tracked regime at T^n (D > 0), else false
+__device__ __forceinline__ bool track_regime(float a, float m, double xb, double D, double& bt) {
+    bt = (xb == xb) ? xb : (double)fmaxf(Const<float>::Xmax - (a + m), 0.0f);
+    return m == 0.0f && bt < D && bt < kTrackMax;
+}
+
+// alpha_s = 0.9 - X~beta after a tracked step, then g at T^{n+1}; tracking
+// goes on if g left the state alone and X~beta stays below kTrackMax
+template <bool COMPENSATED>
+__device__ __forceinline__ float track_finish(float& a, float& m, float& a_lo, float& m_lo, double& xb, double bn,
+                                              float Tn1, float xeq_n1) {
+    const double av = (double)Const<float>::Xmax - bn;
+    float at = (float)av;
+    const float lo = (float)(av - (double)at);
+    float mt = 0.0f;
+    const float a_before = at;
+    const float beta = correct(Tn1, xeq_n1, at, mt);
+    const bool kept = at == a_before && mt == 0.0f;
+    xb = (kept && bn < kTrackMax) ? bn : track_none();
+    a = at;
+    m = mt;
+    a_lo = (COMPENSATED && kept) ? lo : 0.0f;
+    m_lo = 0.0f;
+    return beta;
+}
+
+// explicit_step with the tracked X~beta
+template <bool COMPENSATED>
+__device__ __forceinline__ float explicit_step_tracked(float& a, float& m, float& a_lo, float& m_lo, double& xb,
+                                                       float Tn, float xeq_n, float Tn1, float xeq_n1, float dt) {
+    double bt;
+    const double D = (double)Const<float>::Xmax - alpha_eq_f64(Tn);
+    if (at_rest(a, m, Tn, Tn1) || !track_regime(a, m, xb, D, bt)) {
+        xb = track_none();
+        return explicit_step<COMPENSATED>(a, m, a_lo, m_lo, Tn, xeq_n, Tn1, xeq_n1, dt);
+    }
+    const double kb = k_beta_f64(Tn), h = dt;
+    const double bn = bt * h <= 1e-15 ? beta_startup_f64(bt, D, kb, h) : bt + h * beta_rate_f64(bt, D, kb);
+    return track_finish<COMPENSATED>(a, m, a_lo, m_lo, xb, bn, Tn1, xeq_n1);
+}
+
+// implicit_step with the tracked X~beta: the start-up takes the tracked
+// explicit step; after it, Crank-Nicolson on X~beta with the same fixed-point
+// iteration and WRMS stop (the alpha_m residual is zero).  If g could act on
+// the state at T^{n+1} (below the martensite start or above the alpha_s
+// start), the value is handed over and the ordinary step is taken.
+template <bool COMPENSATED>
+__device__ __forceinline__ int implicit_step_tracked(float& a, float& m, float& a_lo, float& m_lo, double& xb,
+                                                     float& beta, float Tn, float Tn1, float dt, int max_iter) {
+    using C = Const<float>;
+    double bt;
+    const double D = (double)C::Xmax - alpha_eq_f64(Tn);
+    if (at_rest(a, m, Tn, Tn1) || !track_regime(a, m, xb, D, bt)) {
+        xb = track_none();
+        return implicit_step<COMPENSATED>(a, m, a_lo, m_lo, beta, Tn, Tn1, dt, max_iter);
+    }
+    if (bt * (double)dt <= 1e-15) {
+        xb = bt;
+        beta = explicit_step_tracked<COMPENSATED>(a, m, a_lo, m_lo, xb, Tn, alpha_eq(Tn), Tn1, alpha_eq(Tn1), dt);
+        return 0;
+    }
+    if (!(Tn1 >= C::TamStart && Tn1 <= C::TasStart)) {
+        const double av = (double)C::Xmax - bt;
+        a = (float)av;
+        a_lo = COMPENSATED ? (float)(av - (double)a) : 0.0f;
+        xb = track_none();
+        return implicit_step<COMPENSATED>(a, m, a_lo, m_lo, beta, Tn, Tn1, dt, max_iter);
+    }
+    const double D1 = (double)C::Xmax - alpha_eq_f64(Tn1), kb1 = k_beta_f64(Tn1);
+    const double f_n = beta_rate_f64(bt, D, k_beta_f64(Tn));
+    const double h = 0.5 * (double)dt;
+    double x = bt, f = beta_rate_f64(bt, D1, kb1);  // g(T^{n+1}, m^n) leaves the state alone here
+    int it = 0;
+    bool converged = false;
+    while (it < max_iter) {
+        const double x1 = bt + h * (f_n + f);
+        const double f1 = beta_rate_f64(x1, D1, kb1);
+        const double w = h * (f1 - f) / ((double)C::CnEpsAbs + (double)C::CnEpsRel * fabs((double)C::Xmax - x1));
+        x = x1;
+        f = f1;
+        ++it;
+        if (0.5 * w * w < 1.0) {
+            converged = true;
+            break;
+        }
+    }
+    beta = track_finish<COMPENSATED>(a, m, a_lo, m_lo, xb, x, Tn1, alpha_eq(Tn1));
+    return converged ? it : -it;
+}
+
 }  // namespace MSTRUCT_MODEL_NS

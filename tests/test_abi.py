@@ -77,3 +77,32 @@ def test_product_path_does_not_use_the_oracle():
                 txt = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(import|from)\s+oracle", txt, re.M), f
                 assert "mstruct_oracle" not in txt and "liborc" not in txt, f
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes structures of the binding have the sizes and field offsets
+    that a C compiler gives the header's structs."""
+    import shutil
+    import subprocess
+
+    import paper_2402_17580_amd as ms
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"mstruct_phases": ms.PhasesC, "mstruct_phases_f64": ms.PhasesF64C}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mstruct.h"', "int main(void) {"]
+    for cname, py in structs.items():
+        lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for f, _ in py._fields_:
+            lines.append(f'printf("{cname} {f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    got = dict(l.rsplit(" ", 1) for l in subprocess.run([str(exe)], capture_output=True, text=True,
+                                                        check=True).stdout.splitlines())
+    for cname, py in structs.items():
+        assert int(got[f"{cname} size"]) == ctypes.sizeof(py)
+        for f, _ in py._fields_:
+            assert int(got[f"{cname} {f}"]) == getattr(py, f).offset, (cname, f)
