@@ -300,7 +300,8 @@ def bench_implicit(torch, ms, ctx, wl, state):
 def bench_cooldown(torch, ms, ctx):
     """The multi-layer block with the paper's inter-layer cool-down (each
     layer: 2000 scan steps of 2 us, explicit; then 1 s of cool-down on the
-    doubling schedule, implicit with 0.01 s substeps), one run."""
+    doubling schedule, implicit with 0.01 s substeps) and the final 100 s
+    cool-down in steps of 0.1 s, one run."""
     pw = workload.multilayer_cooldown()
     n = pw.grid.n
     g = [torch.from_numpy(x).cuda() for x in workload.initial_state(n, np.float32)]

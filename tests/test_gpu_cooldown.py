@@ -1,7 +1,8 @@
 """The inter-layer cool-down workload (the paper's schedule: after each
 layer's scan, 2000 steps at the scan step, then the step doubled after every
 ten steps, the microstructure subcycled at 0.01 s; explicit scheme while
-scanning, implicit scheme while cooling) against the oracle."""
+scanning, implicit scheme while cooling; a final 100 s cool-down after the
+last layer) against the oracle."""
 import numpy as np
 import pytest
 
@@ -58,7 +59,8 @@ def test_cooldown_small_all_points(torch, ctx, orc):
 
 def test_multilayer_cooldown_full_size_sampled(torch, ctx, orc):
     """256x256x128, 10 layers of 2000 scan steps, each followed by 1 s of
-    cool-down (2146 steps); a seeded 0.1 % sample against the oracle."""
+    cool-down (2146 steps), then the final 100 s (1000 steps of 0.1 s); a
+    seeded 0.1 % sample against the oracle."""
     pw = workload.multilayer_cooldown()
     g = _run(torch, ctx, pw)
     assert ctx.implicit_unconverged() == 0

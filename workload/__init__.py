@@ -322,11 +322,14 @@ def cooldown_schedule(t_start, duration, dt_first, n_first=2000, double_every=10
 
 
 def multilayer_cooldown(nx=256, ny=256, nz=128, n_layers=10, layer_thick=30e-6, steps_per_layer=2000,
-                        dt=2e-6, hatch=100e-6, cooldown=1.0, seed=1002, window=2) -> PhasedWorkload:
+                        dt=2e-6, hatch=100e-6, cooldown=1.0, final_cooldown=100.0, seed=1002,
+                        window=2) -> PhasedWorkload:
     """The multi-layer block with the paper's inter-layer cool-down: each layer
     is scanned for steps_per_layer steps of dt (explicit scheme), then cools
     for `cooldown` seconds on the schedule of cooldown_schedule (implicit
-    scheme, substeps of at most 0.01 s).  Same seeded scan lines as
+    scheme, substeps of at most 0.01 s).  After the last layer's cool-down
+    the part cools for `final_cooldown` more seconds in steps of 0.1 s, as
+    the paper's examples end (Sec. 4.2).  Same seeded scan lines as
     multilayer_block, each layer starting after the previous cool-down."""
     h = 10e-6
     grid = Grid(nx, ny, nz, h)
@@ -344,6 +347,9 @@ def multilayer_cooldown(nx=256, ny=256, nz=128, n_layers=10, layer_thick=30e-6, 
         phases.append(Phase(t_layer, dt, steps_per_layer, z_top, "explicit"))
         for (t0, d, k) in cooldown_schedule(t_layer + steps_per_layer * dt, cooldown, dt):
             phases.append(Phase(t0, d, k, z_top, "implicit"))
+    if final_cooldown > 0:
+        for (t0, d, k) in cooldown_schedule(n_layers * (active + cooldown), final_cooldown, 0.1, n_first=1 << 40):
+            phases.append(Phase(t0, d, k, phases[-1].z_top, "implicit"))
     scan = Scan(np.array(rows, dtype=np.float64), K_W, ALPHA, T0, T_CLAMP, window)
     return PhasedWorkload("multilayer_cooldown", grid, scan, phases, seed)
 
