@@ -214,7 +214,7 @@ def main():
 FUSED_PROFILE = {
     "valu_lane_ops_per_update": 133.51,
     "fp32_flops_per_update": 99.5,
-    "traffic_bytes_per_launch": (29383.50 * 2.0 + 58858.50) * 1024,
+    "traffic_bytes_per_launch": (29389.55 * 2.0 + 58858.50) * 1024,
 }
 
 def bench_stepwise(torch, ms, ctx, wl, dev):
