@@ -110,8 +110,10 @@ int64_t first_active_plane(const mstruct_points* p) {
 
 int make_geom(mstruct_ctx* ctx, const mstruct_points* p, int64_t n, PointGeom& pg) {
     if (!p) return fail(ctx, MSTRUCT_EINVAL, "points is NULL");
-    if (p->nx <= 0 || p->ny <= 0 || p->nz <= 0 || p->nx * p->ny * p->nz >= ((int64_t)1 << 31))
-        return fail(ctx, MSTRUCT_EINVAL, "bad box dimensions");
+    const int64_t lim = (int64_t)1 << 31;  // each factor below 2^31 first, so no product overflows
+    if (p->nx <= 0 || p->ny <= 0 || p->nz <= 0 || p->nx >= lim || p->ny >= lim || p->nz >= lim ||
+        p->nx * p->ny >= lim || p->nx * p->ny * p->nz >= lim)
+        return fail(ctx, MSTRUCT_EINVAL, "bad box dimensions (at most 2^31 - 1 points)");
     if (!finite_pos(p->h) || !isfinite(p->ox) || !isfinite(p->oy) || !isfinite(p->oz) || isnan(p->z_top))
         return fail(ctx, MSTRUCT_EINVAL, "bad grid geometry");
     if (p->n != n) return fail(ctx, MSTRUCT_EINVAL, "points n differs from phases n");
