@@ -190,6 +190,7 @@ def main():
 
     if not args.no_cpu_baseline:
         base, st, idx = cpu_baseline(wl, args)
+        base["gpu_vs_oracle"] = result["value"] / base["value"]
         result["cpu_baseline"] = base
         result["errors_vs_oracle"] = errors(final_state, st, idx)
         for key, state in sur_states.items():
@@ -427,8 +428,30 @@ def cpu_baseline(wl, args):
     el = time.perf_counter() - t0
     base = {"value": upd / el, "unit": "point-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"{idx.size} seeded points (p={args.sample}) x all 20,000 steps "
-                      f"({upd} point-updates, FP64, {el:.1f} s)"}
+                      f"({upd} point-updates, FP64, {el:.1f} s)",
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count()}
+    # one core, on a 32 times smaller sample
+    idx1 = workload.sample_indices(wl.grid.n, args.sample / 32, wl.seed + 1)
+    xyz1 = wl.grid.coords(idx1)
+    upd1 = sum(int(np.count_nonzero(xyz1[:, 2] <= L.z_top + 1e-3 * wl.grid.h)) * (L.step_end - L.step_begin)
+               for L in wl.layers)
+    t0 = time.perf_counter()
+    oracle.run_workload(wl, idx1, threads=1)
+    el1 = time.perf_counter() - t0
+    base["single_core"] = {"value": upd1 / el1, "sample": f"{idx1.size} seeded points x all 20,000 steps "
+                                                          f"({upd1} point-updates, {el1:.1f} s)"}
     return base, st, idx
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 def errors(state, st, idx):
