@@ -56,6 +56,9 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration under rocprofv3)")
     ap.add_argument("--threads", type=int, default=0)
+    ap.add_argument("--island-block", action="store_true",
+                    help="instead: the 512x512x256 island block (100 layers, 200,000 steps), plain K = 16 and "
+                         "surrogate K = 8 side by side, errors on a 0.1 %% sample")
     return ap.parse_args()
 
 
@@ -69,6 +72,9 @@ def main():
 
     import paper_2402_17580_amd as ms
 
+    if args.island_block:
+        print(json.dumps(bench_island_block(torch, ms, args)))
+        return
     dev = torch.device("cuda:0")
     wl = workload.multilayer_block()
     n = wl.grid.n
@@ -452,6 +458,52 @@ def _cpu_model():
     except OSError:
         pass
     return None
+
+
+def bench_island_block(torch, ms, args):
+    """The 64M-point island block at full length (512x512x256 points, 100
+    layers of 20 um, 2000 steps of 2 us each): the plain fused path (K = 16)
+    and the surrogate (K = 8 network) one after the other on the same GPU,
+    each timed once, and both against the oracle on a seeded 0.1 % sample."""
+    import oracle
+    from paper_2402_17580_amd import surrogate as S
+    wl = workload.island_block()
+    n = wl.grid.n
+    upd = wl.point_updates()
+    ctx = ms.Context(0)
+    out = {"workload": "island_block", "points": n, "layers": len(wl.layers), "time_steps": wl.n_steps,
+           "active_point_updates": upd}
+    states = {}
+    for key, mode, K in (("plain", ms.MODE_PLAIN, 16), ("surrogate", ms.MODE_SURROGATE, 8)):
+        if mode == ms.MODE_SURROGATE:
+            sur = S.Surrogate.load(S.DEFAULT_WEIGHTS)
+            sur.load_into(ctx)
+        g = [torch.from_numpy(x).cuda() for x in workload.initial_state(n, np.float32)]
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ms.run_layers(ctx, wl, *g, K=K, mode=mode)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) * 1e-3
+        out[key] = {"seconds": t, "point_updates_per_s": upd / t, "K": K}
+        print(f"island block {key}: {t:.2f} s", file=sys.stderr, flush=True)
+        states[key] = g
+    out["surrogate"]["speedup_vs_plain"] = out["plain"]["seconds"] / out["surrogate"]["seconds"]
+    idx = workload.sample_indices(n, 1e-3, wl.seed)
+    t0 = time.perf_counter()
+    threads = args.threads or min(16, os.cpu_count() or 1)
+    st = None
+    for first in range(0, len(wl.layers), 10):  # ten layers per call, with a progress line each
+        st = oracle.run_workload(wl, idx, state=st, threads=threads, layers=wl.layers[first:first + 10])
+        print(f"oracle: {first + 10} layers, {time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
+    el = time.perf_counter() - t0
+    out["oracle"] = {"sample": f"{idx.size} seeded points (p=1e-3), all 200,000 steps", "seconds": el,
+                     "threads": threads}
+    for key, g in states.items():
+        out[key]["errors_vs_oracle"] = errors(g, st, idx)
+    ctx.close()
+    return out
 
 
 def errors(state, st, idx):
