@@ -263,7 +263,7 @@ def main(argv=None):
     ap.add_argument("--layers", type=int, default=10)
     ap.add_argument("--steps-per-layer", type=int, default=2000)
     ap.add_argument("--every", type=int, default=512)
-    ap.add_argument("--per-pick", type=int, default=16000)
+    ap.add_argument("--per-pick", type=int, default=93200)  # 10 layers x 4 picks x 3 dt: ~10M transitions
     ap.add_argument("--epochs", type=int, default=6)
     ap.add_argument("--K", type=int, default=8)
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
