@@ -180,7 +180,9 @@ int mstruct_temperature(mstruct_ctx *ctx, const mstruct_scan *scan, const mstruc
  * increments inside a launch).  mode SURROGATE replaces each block of K steps
  * of a point by one explicit step of K dt (rates at the block-start
  * temperature, correction at the block-end temperature) plus the correction
- * to it predicted by the trained network, except where the error
+ * to it predicted by the trained network (applied where the one-step
+ * increment of alpha_s or alpha_m exceeds 2^-20; below that one step of K dt
+ * is taken as it is), except where the error
  * indicator flags the point (temperature window touching the martensite
  * start, beta-transus or melting bands, or a start-up state), which get the
  * K plain steps; requires weights loaded with mstruct_mlp_set_params.
