@@ -153,6 +153,23 @@ def main():
     }
     final_state = [x.clone() for x in (b, a, m)]
 
+    # the same run with every temperature evaluated (cold-wave certificate
+    # off): the same bits, for comparison
+    ctx.set_option(ms.OPTION_SKIP_COLD_WAVES, 0)
+    ms_all, _ = timed(ms.MODE_PLAIN, args.K)
+    ctx.set_option(ms.OPTION_SKIP_COLD_WAVES, 1)
+    avg_all_s = ms_all * 1e-3 / (args.steps * launches)
+    ops_all = FUSED_PROFILE_EVERY_T["valu_lane_ops_per_update"]
+    result["plain_every_temperature"] = {
+        "value": updates * args.steps / (ms_all * 1e-3), "unit": "point-updates/s",
+        "ms_per_step": ms_all / args.steps, "value_speedup": ms_all / ms_total,
+        "bitwise_equal_to_value_run": all(bool(torch.equal(x, y)) for x, y in zip((b, a, m), final_state)),
+        "roofline": {"kernel": f"fused_plain_kernel<{wl.scan.window}>", "bound": "alu",
+                     "achieved": upd_per_launch / avg_all_s * ops_all / 1e12, "peak": VALU_PEAK_TLANEOPS,
+                     "unit": "Tlane-op/s", "frac": upd_per_launch / avg_all_s * ops_all / 1e12 / VALU_PEAK_TLANEOPS,
+                     "lane_ops_per_update": ops_all, "avg_launch_us": avg_all_s * 1e6},
+    }
+
     sur_states = {}
     if not args.no_surrogate:
         from paper_2402_17580_amd import surrogate as S
@@ -171,7 +188,8 @@ def main():
             sur_states[key] = [x.clone() for x in (b, a, m)]
             result[key] = {
                 "value": updates * args.steps / (ms_sur * 1e-3), "unit": "point-updates/s",
-                "ms_per_step": ms_sur / args.steps, "speedup_vs_plain": ms_total / ms_sur, "K": sur.K,
+                "ms_per_step": ms_sur / args.steps, "speedup_vs_plain": ms_total / ms_sur,
+                "speedup_vs_plain_every_temperature": ms_all / ms_sur, "K": sur.K,
                 "path": "mstruct_fused_scan_steps, SURROGATE: one explicit step of K dt + BF16-MFMA network "
                         "correction where the indicator allows, K plain steps elsewhere",
                 "indicator": list(sur.indicator), "trained_in_bench_s": t_tr,
@@ -218,6 +236,8 @@ def main():
 # executed VALU instructions x 64 lanes and FP32 FLOPs per point-update, and
 # HBM bytes per launch (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0: the factors a
 # plain 1 GiB device copy reads on the same counters).
+# the same kernel with every temperature evaluated (MSTRUCT_OPTION_SKIP_COLD_WAVES = 0)
+FUSED_PROFILE_EVERY_T = {"valu_lane_ops_per_update": 133.51}
 FUSED_PROFILE = {
     "valu_lane_ops_per_update": 133.51,
     "fp32_flops_per_update": 99.5,

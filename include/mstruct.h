@@ -188,14 +188,30 @@ int mstruct_temperature(mstruct_ctx *ctx, const mstruct_scan *scan, const mstruc
  * K plain steps; requires weights loaded with mstruct_mlp_set_params.
  * mode IMPLICIT runs the implicit step of mstruct_step_implicit at every
  * step (substep limit 0.01 s, T linear in time between the analytic values
- * at the step ends, at most 50 iterations; no compensated accumulation);
- * substeps that hit the cap are counted in the context (see
- * mstruct_implicit_unconverged).
+ * at the step ends, at most 50 iterations, compensated accumulation of the
+ * increments inside a launch); substeps that hit the cap are counted in the
+ * context (see mstruct_implicit_unconverged).  In PLAIN and IMPLICIT modes
+ * a wave of points that no source of a launch reaches takes T = T0 at every
+ * step without evaluating the source terms, with the same results bit for
+ * bit (see MSTRUCT_OPTION_SKIP_COLD_WAVES).
  * K in 1..64.  pts->n must equal ph->n.  Inside a call beta is not read and
  * is written once, by the last launch (it follows from the sum rule). */
 int mstruct_fused_scan_steps(mstruct_ctx *ctx, const mstruct_scan *scan, const mstruct_points *pts,
                              double t0, double dt, int64_t n_steps, int K, int mode,
                              const mstruct_phases *ph, void *stream);
+
+/* Context options (value 0 or 1).
+ * MSTRUCT_OPTION_SKIP_COLD_WAVES (default 1): before each launch of fused
+ * PLAIN or IMPLICIT mode the host lists every track that occupies a window
+ * slot at any of the launch's time points, with its positions at the first
+ * and last of them.  Each point bounds every term of every listed track over
+ * the whole launch with the drop test of the temperature model (a term
+ * provably below 1e-4 K is dropped); a wave whose points drop them all has
+ * T = T0 throughout and skips their evaluation.  The results are the same
+ * bit for bit as with 0, which evaluates every temperature (for
+ * comparison). */
+enum { MSTRUCT_OPTION_SKIP_COLD_WAVES = 1 };
+int mstruct_set_option(mstruct_ctx *ctx, int option, int value);
 
 /* Number of substeps of fused IMPLICIT runs on this context whose fixed-point
  * iteration hit the cap, since the context was created or last reset

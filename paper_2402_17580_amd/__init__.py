@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libmstruct.so")
 MODE_PLAIN = 0
 MODE_SURROGATE = 1
 MODE_IMPLICIT = 2
+OPTION_SKIP_COLD_WAVES = 1
 F64_LIBRARY = 0
 F64_SYNTH = 1
 MLP_NPARAM = 4803
@@ -57,7 +58,7 @@ class PointsC(ctypes.Structure):
 
 
 EXPORTS = ("mstruct_init", "mstruct_destroy", "mstruct_status_string", "mstruct_last_error", "mstruct_step",
-           "mstruct_step_implicit", "mstruct_implicit_unconverged", "mstruct_step_f64", "mstruct_temperature", "mstruct_fused_scan_steps", "mstruct_gather", "mstruct_check_invariants",
+           "mstruct_step_implicit", "mstruct_implicit_unconverged", "mstruct_set_option", "mstruct_step_f64", "mstruct_temperature", "mstruct_fused_scan_steps", "mstruct_gather", "mstruct_check_invariants",
            "mstruct_correct", "mstruct_mlp_set_params", "mstruct_mlp_get_params", "mstruct_mlp_forward",
            "mstruct_mlp_grad", "mstruct_mlp_train_step")
 
@@ -76,7 +77,7 @@ def lib() -> ctypes.CDLL:
             "mstruct_init": [i, p], "mstruct_destroy": [p], "mstruct_status_string": [i],
             "mstruct_last_error": [p], "mstruct_step": [p, p, p, d, p, p],
             "mstruct_step_implicit": [p, p, p, d, d, i, p, p, p],
-            "mstruct_implicit_unconverged": [p, p, i, p],
+            "mstruct_implicit_unconverged": [p, p, i, p], "mstruct_set_option": [p, i, i],
             "mstruct_step_f64": [p, p, p, d, p, i, p],
             "mstruct_temperature": [p, p, p, d, p, p],
             "mstruct_fused_scan_steps": [p, p, p, d, d, i64, i, i, p, p],
@@ -191,6 +192,9 @@ class Context:
                                                 _dev_ptr(T_next, torch.float32, ph.n, "T_next"), float(dt),
                                                 float(dt_sub), int(max_iter), ctypes.byref(ph), up,
                                                 _stream(stream)), "mstruct_step_implicit")
+
+    def set_option(self, option, value):
+        self._check(lib().mstruct_set_option(self._h, int(option), int(value)), "mstruct_set_option")
 
     def implicit_unconverged(self, reset=False, stream=None) -> int:
         """Substeps of fused IMPLICIT runs that hit the iteration cap."""

@@ -34,6 +34,7 @@ struct mstruct_ctx {
     int next_slot = 0;
     unsigned long long* counter = nullptr;
     unsigned long long* implicit_bad = nullptr;  // substeps of fused implicit runs that hit the cap
+    bool skip_cold = true;                       // MSTRUCT_OPTION_SKIP_COLD_WAVES
     MlpState mlp;
 };
 
@@ -204,6 +205,67 @@ void build_table(SrcRec* out, const mstruct_scan* sc, const mstruct_points* p, d
         const int64_t c = last_on(sc, t);
         for (int w = 0; w < W; ++w) fill_record(out[s * W + w], sc, p, c - w, t);
     }
+}
+
+// Per launch of K steps (time points s0 .. s0 + Kb of the call's table), one
+// EnvRec for every track that occupies a window slot at any of them: its
+// positions at the first and last of those time points and the constants of
+// the last.  env[first[i] .. first[i] + count[i]) belongs to launch i.
+// Returns the number of records written (at most n_launches * (W + K + 1)).
+int64_t build_envelopes(EnvRec* env, std::vector<int32_t>& first, std::vector<int32_t>& count, const SrcRec* recs,
+                        const mstruct_scan* sc, double t0, double dt, int64_t n_steps, int K) {
+    const int W = sc->window;
+    first.clear();
+    count.clear();
+    int64_t total = 0;
+    std::vector<int64_t> ids;
+    std::vector<int64_t> lo, hi;  // first and last time point of each track in this launch
+    for (int64_t s0 = 0; s0 < n_steps; s0 += K) {
+        const int64_t Kb = (n_steps - s0) < K ? (n_steps - s0) : K;
+        ids.clear();
+        lo.clear();
+        hi.clear();
+        for (int64_t s = s0; s <= s0 + Kb; ++s) {
+            const int64_t c = last_on(sc, t0 + (double)s * dt);
+            for (int w = 0; w < W; ++w) {
+                if (!(recs[s * W + w].lamp > -1e30f)) continue;
+                const int64_t j = c - w;
+                size_t k = 0;
+                while (k < ids.size() && ids[k] != j) ++k;
+                if (k == ids.size()) {
+                    ids.push_back(j);
+                    lo.push_back(s * W + w);
+                    hi.push_back(s * W + w);
+                } else {
+                    hi[k] = s * W + w;
+                }
+            }
+        }
+        first.push_back((int32_t)total);
+        count.push_back((int32_t)ids.size());
+        for (size_t k = 0; k < ids.size(); ++k) {
+            const SrcRec& a = recs[lo[k]];
+            const SrcRec& b = recs[hi[k]];
+            EnvRec& e = env[total++];
+            memset(&e, 0, sizeof e);
+            e.px = (float)((double)b.ix + (double)b.fx);
+            e.py = (float)((double)b.iy + (double)b.fy);
+            e.pz = (float)((double)b.iz + (double)b.fz);
+            e.qx = (float)((double)a.ix + (double)a.fx);
+            e.qy = (float)((double)a.iy + (double)a.fy);
+            e.ux = b.ux;
+            e.uy = b.uy;
+            e.lamp = b.lamp;
+            e.c1 = b.c1;
+            e.e2 = b.e2;
+            e.vt = b.vt;
+            if (b.is1 > 0.0f) {
+                e.e21 = b.e21;
+                e.vt1 = b.vt1;
+            }
+        }
+    }
+    return total;
 }
 
 // acquire a table slot with room for `records` entries; waits until its
@@ -399,10 +461,18 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
     hipStream_t st = (hipStream_t)stream;
     const int W = scan->window;
     const size_t recs = (size_t)(n_steps + 1) * W;
+    const int64_t n_launches = (n_steps + K - 1) / K;
+    const size_t env_cap = (size_t)n_launches * (W + K + 1);
     TableSlot* s;
-    if ((rc = acquire_slot(ctx, recs, s))) return rc;
+    if ((rc = acquire_slot(ctx, recs + env_cap, s))) return rc;
     build_table(s->host, scan, pts, t0, dt, n_steps + 1);
-    HIP_CHECK(ctx, hipMemcpyAsync(s->dev, s->host, recs * sizeof(SrcRec), hipMemcpyHostToDevice, st));
+    // launch envelopes after the records (EnvRec has the size of SrcRec)
+    std::vector<int32_t> env_first, env_count;
+    EnvRec* env_host = reinterpret_cast<EnvRec*>(s->host + recs);
+    const EnvRec* env_dev = reinterpret_cast<const EnvRec*>(s->dev + recs);
+    const int64_t n_env = build_envelopes(env_host, env_first, env_count, s->host, scan, t0, dt, n_steps, K);
+    HIP_CHECK(ctx, hipMemcpyAsync(s->dev, s->host, (recs + (size_t)n_env) * sizeof(SrcRec), hipMemcpyHostToDevice,
+                                  st));
     const ScanArgs sa{(float)scan->T0, (float)scan->T_clamp};
     if (mode == MSTRUCT_MODE_SURROGATE) {
         hipError_t e = surrogate_prepare(ctx->mlp, pg.first + pg.count, st);
@@ -417,22 +487,32 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
         // beta is written by the last launch only (no kernel reads it)
         float* beta = last ? ph->beta : nullptr;
         hipError_t e;
+        const int64_t li = s0 / K;
+        const EnvSet es{env_dev + env_first[li], ctx->skip_cold ? env_count[li] : -1};
         if (mode == MSTRUCT_MODE_PLAIN) {
-            e = launch_fused_plain(pg, W, s->dev + s0 * W, Kb, (float)dt, sa, beta, ph->alpha_s, ph->alpha_m, ph->xbt,
-                                   st);
+            e = launch_fused_plain(pg, W, s->dev + s0 * W, es, Kb, (float)dt, sa, beta, ph->alpha_s, ph->alpha_m,
+                                   ph->xbt, st);
         } else if (mode == MSTRUCT_MODE_IMPLICIT) {
             const int n_sub = substeps(dt, kImplicitDtSub);
-            e = launch_fused_implicit(pg, W, s->dev + s0 * W, Kb, (float)(dt / n_sub), n_sub, kImplicitMaxIter, sa,
-                                      beta, ph->alpha_s, ph->alpha_m, ph->xbt, ctx->implicit_bad, st);
+            e = launch_fused_implicit(pg, W, s->dev + s0 * W, es, Kb, (float)(dt / n_sub), n_sub, kImplicitMaxIter,
+                                      sa, beta, ph->alpha_s, ph->alpha_m, ph->xbt, ctx->implicit_bad, st);
         } else
             e = launch_surrogate(ctx->mlp, pg, W, s->dev + s0 * W, Kb, (float)dt, sa, ph->beta, ph->alpha_s,
-                                 ph->alpha_m, s0 / K, s0 == 0, last, st);
+                                 ph->alpha_m, li, s0 == 0, last, st);
         if (e != hipSuccess) {
             (void)release_slot(ctx, s, st);
             return hip_fail(ctx, e, "fused launch");
         }
     }
     return release_slot(ctx, s, st);
+}
+
+int mstruct_set_option(mstruct_ctx* ctx, int option, int value) {
+    if (!ctx) return MSTRUCT_EINVAL;
+    switch (option) {
+        case MSTRUCT_OPTION_SKIP_COLD_WAVES: ctx->skip_cold = value != 0; return MSTRUCT_OK;
+        default: return fail(ctx, MSTRUCT_EINVAL, "unknown option");
+    }
 }
 
 int mstruct_implicit_unconverged(mstruct_ctx* ctx, int64_t* count, int reset, void* stream) {

@@ -147,6 +147,67 @@ __device__ __forceinline__ float source_rise(const SrcRec& s, int gi, int gj, in
     return rR * acc;
 }
 
+// One track over the time points of one launch (a K-step block): its
+// current (or, after switch-off, virtual) position at the first and at the
+// last time point where it is in the window, and the slot constants at the
+// last one, where each drop test of source_rise is least strict (64 bytes).
+struct EnvRec {
+    float px, py, pz;  // position at the last time point [grid units from the origin]
+    float qx, qy;      // position at the first time point (same z)
+    float ux, uy;      // unit direction of motion
+    float lamp, c1;    // as in SrcRec
+    float e2, vt;      // at the last time point (e2 is smallest there)
+    float e21, vt1;    // at the last time point if the track is then switched off, else 0
+    float pad[3];
+};
+static_assert(sizeof(EnvRec) == 64, "EnvRec layout");
+
+// True if, at grid point (gi, gj, gk), source_rise drops every term of this
+// track at every time point the record covers, so that the track adds
+// exactly 0 to T there.  Each bound follows a drop test of source_rise:
+// over the launch xi (along the motion) only decreases, so xi + R is
+// smallest at the last position; e2 and e21 only decrease; the
+// start-point distances |x - P0| and |x - P_end| are fixed; and R is at least
+// the distance to the segment between the two positions, which bounds the
+// threshold from below.  1 % of R^2 and 0.25 in the base-2 exponents cover
+// float32 rounding of both computations (and the hardware rsq and rcp here).
+__device__ __forceinline__ bool env_negligible(const EnvRec& e, int gi, int gj, int gk) {
+    const float x = (float)gi, y = (float)gj, dz = (float)(-gk) - e.pz;
+    const float dx = x - e.px, dy = y - e.py;
+    const float xi = fmaf(dx, e.ux, dy * e.uy);
+    const float cr = fmaf(dx, e.uy, -dy * e.ux);
+    const float rho2 = fmaf(cr, cr, dz * dz);
+    const float R2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+    const float qx = x - e.qx, qy = y - e.qy;
+    const float xi0 = fmaf(qx, e.ux, qy * e.uy);
+    const float R02 = fmaf(qx, qx, fmaf(qy, qy, dz * dz));
+    const float Rmin2 = 0.99f * ((xi0 >= 0.0f && xi <= 0.0f) ? rho2 : fminf(R2, R02));
+    if (!(Rmin2 >= 1.0f)) return false;
+    const float cut = kLog2DropK - 1.25f + 0.5f * (float)(__builtin_amdgcn_frexp_expf(Rmin2) - 1);
+    const float R = R2 * __builtin_amdgcn_rsqf(R2);
+    const float xr = xi >= 0.0f ? xi + R : rho2 * frcp(R - xi);
+    if (fmaf(-e.c1, 0.999f * xr, e.lamp) > cut) return false;
+    const float s0 = xi + e.vt;
+    if (fmaf(-e.e2, 0.999f * fmaf(s0, s0, rho2), e.lamp) > cut) return false;
+    if (e.e21 > 0.0f) {
+        const float s1 = xi + e.vt1;
+        if (fmaf(-e.e21, 0.999f * fmaf(s1, s1, rho2), e.lamp) > cut) return false;
+    }
+    return true;
+}
+
+// all points of the calling wave certified cold for the launch: every track
+// of env drops out at every one of them (inactive lanes count as cold).
+// n_env < 0: no certificate, every wave evaluates the temperature.
+__device__ __forceinline__ bool wave_cold(const EnvRec* __restrict__ env, int n_env, bool act, int gi, int gj,
+                                          int gk) {
+    if (n_env < 0) return false;
+    bool cold = true;
+    if (act)
+        for (int e = 0; e < n_env && cold; ++e) cold = env_negligible(env[e], gi, gj, gk);
+    return __ballot(!cold) == 0;
+}
+
 template <int W>
 __device__ __forceinline__ float scan_temperature(const SrcRec* __restrict__ recs, int gi, int gj, int gk,
                                                   float T0, float Tclamp, float r2min, float roff) {

@@ -48,10 +48,16 @@ struct ScanArgs {
     float T0, Tclamp;
 };
 
+// the envelope records of one launch (see EnvRec)
+struct EnvSet {
+    const EnvRec* rec;
+    int32_t n;
+};
+
 // xb: optional tracked X~beta side values (float64 per point), or nullptr
 hipError_t launch_step(const float* Tp, const float* Tn, float* beta, float* as, float* am, double* xb, int64_t n,
                        float dt, hipStream_t st);
-hipError_t launch_fused_implicit(const PointGeom& pg, int W, const SrcRec* tab, int K, float h, int n_sub,
+hipError_t launch_fused_implicit(const PointGeom& pg, int W, const SrcRec* tab, EnvSet env, int K, float h, int n_sub,
                                  int max_iter, ScanArgs sa, float* beta, float* as, float* am, double* xb,
                                  unsigned long long* unconverged, hipStream_t st);
 // float64 explicit step (step_f64_lib.hip: device math library; step_f64_synth.hip:
@@ -65,7 +71,7 @@ hipError_t launch_implicit_step(const float* Tp, const float* Tn, float* beta, f
                                 hipStream_t st);
 hipError_t launch_temperature(const PointGeom& pg, int W, const SrcRec* rec, ScanArgs sa, float* T,
                               hipStream_t st);
-hipError_t launch_fused_plain(const PointGeom& pg, int W, const SrcRec* tab, int K, float dt, ScanArgs sa,
+hipError_t launch_fused_plain(const PointGeom& pg, int W, const SrcRec* tab, EnvSet env, int K, float dt, ScanArgs sa,
                               float* beta, float* as, float* am, double* xb, hipStream_t st);
 hipError_t launch_gather(const float* src, const int64_t* idx, int64_t m, float* dst, hipStream_t st);
 hipError_t launch_invariants(const float* beta, const float* as, const float* am, const float* T, int64_t n,

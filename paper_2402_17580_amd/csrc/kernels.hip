@@ -189,10 +189,10 @@ __global__ __launch_bounds__(kBlock) void temperature_kernel(PointGeom pg, const
 // K + 1 time points x W window slots of this launch.
 // ---------------------------------------------------------------------------
 template <int W, int PPT, bool TRACK>
-__global__ __launch_bounds__(kBlock) void fused_plain_kernel(PointGeom pg, const SrcRec* __restrict__ tab, int K,
-                                                            float dt, ScanArgs sa, float* __restrict__ beta,
-                                                            float* __restrict__ as, float* __restrict__ am,
-                                                            double* __restrict__ xbv) {
+__global__ __launch_bounds__(kBlock) void fused_plain_kernel(PointGeom pg, const SrcRec* __restrict__ tab,
+                                                            EnvSet env, int K, float dt, ScanArgs sa,
+                                                            float* __restrict__ beta, float* __restrict__ as,
+                                                            float* __restrict__ am, double* __restrict__ xbv) {
     // beta == nullptr: not written (inside a call only the last launch writes
     // it; no kernel reads beta, it follows from the sum rule)
     // PPT points per lane, kBlock apart (coalesced), advanced together for ILP
@@ -215,15 +215,27 @@ __global__ __launch_bounds__(kBlock) void fused_plain_kernel(PointGeom pg, const
         alo[u] = 0.0f;
         mlo[u] = 0.0f;
     }
+    // a wave that no source of this launch reaches (every term of every
+    // track dropped at every time point) has T = T0 throughout
+    bool cold[PPT], still[PPT];
+    const float T0c = fminf(sa.T0, sa.Tclamp);
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
-        Tn[u] = scan_temperature<W>(tab, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min, pg.roff);
+        cold[u] = wave_cold(env.rec, env.n, act[u], gi[u], gj[u], gk[u]);
+        Tn[u] = cold[u] ? T0c : scan_temperature<W>(tab, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min, pg.roff);
         xeq_n[u] = alpha_eq(Tn[u]);
+        // a cold wave whose points are all at rest at T0 is left as it is by
+        // every step of the launch
+        still[u] = cold[u] && __ballot(act[u] && !at_rest(a[u], m[u], T0c, T0c)) == 0;
+        if (TRACK && still[u]) xb[u] = track_none();
     }
     for (int s = 0; s < K; ++s) {
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
-            const float Tn1 = scan_temperature<W>(tab + (s + 1) * W, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min, pg.roff);
+            if (still[u]) continue;
+            const float Tn1 = cold[u] ? T0c
+                                      : scan_temperature<W>(tab + (s + 1) * W, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp,
+                                                            pg.r2min, pg.roff);
             const float xeq_n1 = alpha_eq(Tn1);
             if (TRACK)
                 explicit_step_tracked<true>(a[u], m[u], alo[u], mlo[u], xb[u], Tn[u], xeq_n[u], Tn1, xeq_n1, dt);
@@ -252,8 +264,9 @@ __global__ __launch_bounds__(kBlock) void fused_plain_kernel(PointGeom pg, const
 // inside a launch as in the plain fused kernel.
 // ---------------------------------------------------------------------------
 template <int W, bool TRACK>
-__global__ __launch_bounds__(kBlock) void fused_implicit_kernel(PointGeom pg, const SrcRec* __restrict__ tab, int K,
-                                                               float h, int n_sub, int max_iter, ScanArgs sa,
+__global__ __launch_bounds__(kBlock) void fused_implicit_kernel(PointGeom pg, const SrcRec* __restrict__ tab,
+                                                               EnvSet env, int K, float h, int n_sub, int max_iter,
+                                                               ScanArgs sa,
                                                                float* __restrict__ beta, float* __restrict__ as,
                                                                float* __restrict__ am, double* __restrict__ xbv,
                                                                unsigned long long* __restrict__ unconverged) {
@@ -266,10 +279,16 @@ __global__ __launch_bounds__(kBlock) void fused_implicit_kernel(PointGeom pg, co
     float a = act ? as[local] : 0.0f, m = act ? am[local] : 0.0f, b = 0.0f, alo = 0.0f, mlo = 0.0f;
     double xb = (TRACK && act) ? track_check(xbv[local], a, m) : track_none();
     int bad = 0;
-    float Tn = scan_temperature<W>(tab, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
+    const bool cold = wave_cold(env.rec, env.n, act, gi, gj, gk);  // T = T0 throughout (see fused_plain_kernel)
+    const float T0c = fminf(sa.T0, sa.Tclamp);
+    float Tn = cold ? T0c : scan_temperature<W>(tab, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
     const float inv = 1.0f / (float)n_sub;
-    for (int s = 0; s < K; ++s) {
-        const float Tn1 = scan_temperature<W>(tab + (s + 1) * W, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
+    // a cold wave whose points are all at rest at T0 is left as it is
+    const bool still = cold && __ballot(act && !at_rest(a, m, T0c, T0c)) == 0;
+    if (TRACK && still) xb = track_none();
+    for (int s = 0; s < K && !still; ++s) {
+        const float Tn1 =
+            cold ? T0c : scan_temperature<W>(tab + (s + 1) * W, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
         float Ta = Tn;
         for (int k = 0; k < n_sub; ++k) {
             const float Tb = (k + 1 == n_sub) ? Tn1 : fmaf(Tn1 - Tn, (float)(k + 1) * inv, Tn);
@@ -295,26 +314,26 @@ __global__ __launch_bounds__(kBlock) void fused_implicit_kernel(PointGeom pg, co
 }
 
 template <bool TRACK>
-static hipError_t fused_implicit_w(const PointGeom& pg, int W, const SrcRec* tab, int K, float h, int n_sub,
-                                   int max_iter, ScanArgs sa, float* beta, float* as, float* am, double* xb,
+static hipError_t fused_implicit_w(const PointGeom& pg, int W, const SrcRec* tab, EnvSet env, int K, float h,
+                                   int n_sub, int max_iter, ScanArgs sa, float* beta, float* as, float* am, double* xb,
                                    unsigned long long* unconverged, hipStream_t st) {
     const dim3 grid((unsigned)((pg.count + kBlock - 1) / kBlock)), block(kBlock);
     switch (W) {
-        case 1: hipLaunchKernelGGL((fused_implicit_kernel<1, TRACK>), grid, block, 0, st, pg, tab, K, h, n_sub, max_iter, sa, beta, as, am, xb, unconverged); break;
-        case 2: hipLaunchKernelGGL((fused_implicit_kernel<2, TRACK>), grid, block, 0, st, pg, tab, K, h, n_sub, max_iter, sa, beta, as, am, xb, unconverged); break;
-        case 3: hipLaunchKernelGGL((fused_implicit_kernel<3, TRACK>), grid, block, 0, st, pg, tab, K, h, n_sub, max_iter, sa, beta, as, am, xb, unconverged); break;
-        case 4: hipLaunchKernelGGL((fused_implicit_kernel<4, TRACK>), grid, block, 0, st, pg, tab, K, h, n_sub, max_iter, sa, beta, as, am, xb, unconverged); break;
+        case 1: hipLaunchKernelGGL((fused_implicit_kernel<1, TRACK>), grid, block, 0, st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, xb, unconverged); break;
+        case 2: hipLaunchKernelGGL((fused_implicit_kernel<2, TRACK>), grid, block, 0, st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, xb, unconverged); break;
+        case 3: hipLaunchKernelGGL((fused_implicit_kernel<3, TRACK>), grid, block, 0, st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, xb, unconverged); break;
+        case 4: hipLaunchKernelGGL((fused_implicit_kernel<4, TRACK>), grid, block, 0, st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, xb, unconverged); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_fused_implicit(const PointGeom& pg, int W, const SrcRec* tab, int K, float h, int n_sub,
+hipError_t launch_fused_implicit(const PointGeom& pg, int W, const SrcRec* tab, EnvSet env, int K, float h, int n_sub,
                                  int max_iter, ScanArgs sa, float* beta, float* as, float* am, double* xb,
                                  unsigned long long* unconverged, hipStream_t st) {
     if (pg.count <= 0) return hipSuccess;
-    return xb ? fused_implicit_w<true>(pg, W, tab, K, h, n_sub, max_iter, sa, beta, as, am, xb, unconverged, st)
-              : fused_implicit_w<false>(pg, W, tab, K, h, n_sub, max_iter, sa, beta, as, am, xb, unconverged, st);
+    return xb ? fused_implicit_w<true>(pg, W, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, xb, unconverged, st)
+              : fused_implicit_w<false>(pg, W, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, xb, unconverged, st);
 }
 
 hipError_t launch_temperature(const PointGeom& pg, int W, const SrcRec* rec, ScanArgs sa, float* T,
@@ -334,24 +353,24 @@ hipError_t launch_temperature(const PointGeom& pg, int W, const SrcRec* rec, Sca
 constexpr int kFusedPPT = FUSED_PPT;
 
 template <bool TRACK>
-static hipError_t fused_plain_w(const PointGeom& pg, int W, const SrcRec* tab, int K, float dt, ScanArgs sa,
-                                float* beta, float* as, float* am, double* xb, hipStream_t st) {
+static hipError_t fused_plain_w(const PointGeom& pg, int W, const SrcRec* tab, EnvSet env, int K, float dt,
+                                ScanArgs sa, float* beta, float* as, float* am, double* xb, hipStream_t st) {
     const dim3 grid((unsigned)((pg.count + kBlock * kFusedPPT - 1) / (kBlock * kFusedPPT))), block(kBlock);
     switch (W) {
-        case 1: hipLaunchKernelGGL((fused_plain_kernel<1, kFusedPPT, TRACK>), grid, block, 0, st, pg, tab, K, dt, sa, beta, as, am, xb); break;
-        case 2: hipLaunchKernelGGL((fused_plain_kernel<2, kFusedPPT, TRACK>), grid, block, 0, st, pg, tab, K, dt, sa, beta, as, am, xb); break;
-        case 3: hipLaunchKernelGGL((fused_plain_kernel<3, kFusedPPT, TRACK>), grid, block, 0, st, pg, tab, K, dt, sa, beta, as, am, xb); break;
-        case 4: hipLaunchKernelGGL((fused_plain_kernel<4, kFusedPPT, TRACK>), grid, block, 0, st, pg, tab, K, dt, sa, beta, as, am, xb); break;
+        case 1: hipLaunchKernelGGL((fused_plain_kernel<1, kFusedPPT, TRACK>), grid, block, 0, st, pg, tab, env, K, dt, sa, beta, as, am, xb); break;
+        case 2: hipLaunchKernelGGL((fused_plain_kernel<2, kFusedPPT, TRACK>), grid, block, 0, st, pg, tab, env, K, dt, sa, beta, as, am, xb); break;
+        case 3: hipLaunchKernelGGL((fused_plain_kernel<3, kFusedPPT, TRACK>), grid, block, 0, st, pg, tab, env, K, dt, sa, beta, as, am, xb); break;
+        case 4: hipLaunchKernelGGL((fused_plain_kernel<4, kFusedPPT, TRACK>), grid, block, 0, st, pg, tab, env, K, dt, sa, beta, as, am, xb); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_fused_plain(const PointGeom& pg, int W, const SrcRec* tab, int K, float dt, ScanArgs sa,
+hipError_t launch_fused_plain(const PointGeom& pg, int W, const SrcRec* tab, EnvSet env, int K, float dt, ScanArgs sa,
                               float* beta, float* as, float* am, double* xb, hipStream_t st) {
     if (pg.count <= 0) return hipSuccess;
-    return xb ? fused_plain_w<true>(pg, W, tab, K, dt, sa, beta, as, am, xb, st)
-              : fused_plain_w<false>(pg, W, tab, K, dt, sa, beta, as, am, xb, st);
+    return xb ? fused_plain_w<true>(pg, W, tab, env, K, dt, sa, beta, as, am, xb, st)
+              : fused_plain_w<false>(pg, W, tab, env, K, dt, sa, beta, as, am, xb, st);
 }
 
 // ---------------------------------------------------------------------------

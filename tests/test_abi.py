@@ -56,6 +56,7 @@ def test_null_context_rejected_without_device(L):
     assert L.mstruct_step(None, None, None, 1e-6, None, None) == -1
     assert L.mstruct_step_implicit(None, None, None, 1e-3, 0.01, 50, None, None, None) == -1
     assert L.mstruct_implicit_unconverged(None, None, 0, None) == -1
+    assert L.mstruct_set_option(None, 1, 0) == -1
     assert L.mstruct_step_f64(None, None, None, 1e-6, None, 0, None) == -1
     assert L.mstruct_temperature(None, None, None, 0.0, None, None) == -1
     assert L.mstruct_fused_scan_steps(None, None, None, 0.0, 1e-6, 1, 1, 0, None, None) == -1

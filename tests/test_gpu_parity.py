@@ -291,3 +291,45 @@ def test_fused_body_near_the_alpha_end_temperature(torch, ctx, orc):
         assert mx <= RUN_TOL, k
     moved = np.abs(st.alpha_s - np.float32(0.9)) > 1e-3
     assert 0.01 * n < moved.sum() < 0.9 * n
+
+
+def _cold_cases():
+    import dataclasses
+    cases = [("block_w2", workload.multilayer_block(nx=64, ny=64, nz=24, n_layers=3, steps_per_layer=600, seed=5)),
+             ("block_w4", workload.multilayer_block(nx=48, ny=40, nz=12, n_layers=2, steps_per_layer=400, seed=3,
+                                                    window=4)),
+             ("islands", workload.island_scan(96, 64, 24, n_layers=3, layer_thick=20e-6, steps_per_layer=300,
+                                              dt=2e-6, seed=78, island=0.5e-3))]
+    wl0 = workload.single_track(nx=48, ny=32, nz=10)
+    cases.append(("preheated", dataclasses.replace(wl0, scan=dataclasses.replace(wl0.scan, T0=1250.0))))
+    return cases
+
+
+@pytest.mark.parametrize("mode", ["plain", "implicit"])
+def test_cold_waves_skip_is_bit_exact(torch, ctx, mode):
+    """Fused PLAIN and IMPLICIT runs give the same bits with the cold-wave
+    certificate on (default) and off (every temperature evaluated), on
+    scans with windows of 2 and 4 tracks, an island scan, a masked grid and
+    a preheated body."""
+    import paper_2402_17580_amd as ms
+    m = ms.MODE_PLAIN if mode == "plain" else ms.MODE_IMPLICIT
+    cases = _cold_cases()
+    wl0 = workload.island_scan(96, 64, 24, n_layers=3, layer_thick=20e-6, steps_per_layer=300, dt=2e-6,
+                               seed=77, island=0.5e-3)
+    idx = workload.cantilever_mask(96, 64, 24, seed=77, top=6, base=6, leg_frac=0.1)
+    cases.append(("masked", workload.Workload("masked", workload.Grid(96, 64, 24, 10e-6, index=idx), wl0.scan,
+                                              wl0.layers, wl0.dt, wl0.seed)))
+    try:
+        for name, wl in cases:
+            index = torch.from_numpy(wl.grid.index).cuda() if wl.grid.index is not None else None
+            outs = []
+            for skip in (1, 0):
+                ctx.set_option(ms.OPTION_SKIP_COLD_WAVES, skip)
+                g = [torch.from_numpy(x).cuda() for x in workload.initial_state(wl.grid.n, np.float32)]
+                ms.run_layers(ctx, wl, *g, K=16, mode=m, index=index)
+                outs.append([x.cpu().numpy() for x in g])
+            for x, y in zip(*outs):
+                assert np.array_equal(x.view(np.uint32), y.view(np.uint32)), (name, mode)
+            assert np.any(outs[0][1] != np.float32(0.9)), name  # the run changed something
+    finally:
+        ctx.set_option(ms.OPTION_SKIP_COLD_WAVES, 1)
