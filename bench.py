@@ -237,11 +237,11 @@ def main():
 # HBM bytes per launch (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0: the factors a
 # plain 1 GiB device copy reads on the same counters).
 # the same kernel with every temperature evaluated (MSTRUCT_OPTION_SKIP_COLD_WAVES = 0)
-FUSED_PROFILE_EVERY_T = {"valu_lane_ops_per_update": 133.51}
+FUSED_PROFILE_EVERY_T = {"valu_lane_ops_per_update": 134.83}
 FUSED_PROFILE = {
-    "valu_lane_ops_per_update": 133.51,
-    "fp32_flops_per_update": 99.5,
-    "traffic_bytes_per_launch": (29389.55 * 2.0 + 58858.50) * 1024,
+    "valu_lane_ops_per_update": 54.48,
+    "fp32_flops_per_update": 43.1,
+    "traffic_bytes_per_launch": (29398.68 * 2.0 + 58858.50) * 1024,
 }
 
 def bench_stepwise(torch, ms, ctx, wl, dev):
