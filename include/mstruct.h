@@ -191,9 +191,10 @@ int mstruct_temperature(mstruct_ctx *ctx, const mstruct_scan *scan, const mstruc
  * at the step ends, at most 50 iterations, compensated accumulation of the
  * increments inside a launch); substeps that hit the cap are counted in the
  * context (see mstruct_implicit_unconverged).  In PLAIN and IMPLICIT modes
- * a wave of points that no source of a launch reaches takes T = T0 at every
- * step without evaluating the source terms, with the same results bit for
- * bit (see MSTRUCT_OPTION_SKIP_COLD_WAVES).
+ * a wave of points at rest that provably stays below 935 K through a launch
+ * skips it, and a wave that no source of a launch reaches takes T = T0 at
+ * every step without evaluating the source terms, with the same results bit
+ * for bit (see MSTRUCT_OPTION_SKIP_COLD_WAVES).
  * K in 1..64.  pts->n must equal ph->n.  Inside a call beta is not read and
  * is written once, by the last launch (it follows from the sum rule). */
 int mstruct_fused_scan_steps(mstruct_ctx *ctx, const mstruct_scan *scan, const mstruct_points *pts,
@@ -204,11 +205,15 @@ int mstruct_fused_scan_steps(mstruct_ctx *ctx, const mstruct_scan *scan, const m
  * MSTRUCT_OPTION_SKIP_COLD_WAVES (default 1): before each launch of fused
  * PLAIN or IMPLICIT mode the host lists every track that occupies a window
  * slot at any of the launch's time points, with its positions at the first
- * and last of them.  Each point bounds every term of every listed track over
- * the whole launch with the drop test of the temperature model (a term
- * provably below 1e-4 K is dropped); a wave whose points drop them all has
- * T = T0 throughout and skips their evaluation.  The results are the same
- * bit for bit as with 0, which evaluates every temperature (for
+ * and last of them.  Each point bounds every track over the whole launch in
+ * two ways.  (1) A wave whose points are all at rest (alpha_s = 0.9, no
+ * martensite) and whose temperatures provably stay below 935 K, where both
+ * schemes leave such a state unchanged, skips the launch: no temperature, no
+ * step and no store of alpha_s, alpha_m.  (2) A wave whose points drop every
+ * term of every track by the drop test of the temperature model (a term
+ * provably below 1e-4 K is dropped) has T = T0 throughout and skips the
+ * evaluation of the sources.  The results are the same bit for bit as with
+ * 0, which evaluates every temperature and takes every step (for
  * comparison). */
 enum { MSTRUCT_OPTION_SKIP_COLD_WAVES = 1 };
 int mstruct_set_option(mstruct_ctx *ctx, int option, int value);

@@ -259,6 +259,7 @@ int64_t build_envelopes(EnvRec* env, std::vector<int32_t>& first, std::vector<in
             e.c1 = b.c1;
             e.e2 = b.e2;
             e.vt = b.vt;
+            e.is = b.is;
             if (b.is1 > 0.0f) {
                 e.e21 = b.e21;
                 e.vt1 = b.vt1;

@@ -158,54 +158,106 @@ struct EnvRec {
     float lamp, c1;    // as in SrcRec
     float e2, vt;      // at the last time point (e2 is smallest there)
     float e21, vt1;    // at the last time point if the track is then switched off, else 0
-    float pad[3];
+    float is;          // as in SrcRec, at the last time point (is is smallest there)
+    float pad[2];
 };
 static_assert(sizeof(EnvRec) == 64, "EnvRec layout");
 
-// True if, at grid point (gi, gj, gk), source_rise drops every term of this
-// track at every time point the record covers, so that the track adds
-// exactly 0 to T there.  Each bound follows a drop test of source_rise:
-// over the launch xi (along the motion) only decreases, so xi + R is
-// smallest at the last position; e2 and e21 only decrease; the
-// start-point distances |x - P0| and |x - P_end| are fixed; and R is at least
-// the distance to the segment between the two positions, which bounds the
-// threshold from below.  1 % of R^2 and 0.25 in the base-2 exponents cover
-// float32 rounding of both computations (and the hardware rsq and rcp here).
-__device__ __forceinline__ bool env_negligible(const EnvRec& e, int gi, int gj, int gk) {
+// Distances from grid point (gi, gj, gk) to one track over the time points an
+// EnvRec covers.  Over a launch the current (or virtual) position moves along
+// the straight segment from (qx, qy) to (px, py), so R is at least the
+// distance to that segment; along the motion xi only decreases, so xi + R is
+// smallest at the last position; the start-point distance |x - P0| is fixed.
+struct EnvGeom {
+    float Rmin2;  // 0.99 x the squared distance to the segment (a lower bound of R^2 at every time point)
+    float xi;     // along the motion from the last position
+    float rho2;   // squared distance from the line of motion
+    float xr;     // xi + R at the last position (a lower bound over the launch)
+};
+
+__device__ __forceinline__ EnvGeom env_geometry(const EnvRec& e, int gi, int gj, int gk) {
     const float x = (float)gi, y = (float)gj, dz = (float)(-gk) - e.pz;
     const float dx = x - e.px, dy = y - e.py;
-    const float xi = fmaf(dx, e.ux, dy * e.uy);
+    EnvGeom g;
+    g.xi = fmaf(dx, e.ux, dy * e.uy);
     const float cr = fmaf(dx, e.uy, -dy * e.ux);
-    const float rho2 = fmaf(cr, cr, dz * dz);
+    g.rho2 = fmaf(cr, cr, dz * dz);
     const float R2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
     const float qx = x - e.qx, qy = y - e.qy;
     const float xi0 = fmaf(qx, e.ux, qy * e.uy);
     const float R02 = fmaf(qx, qx, fmaf(qy, qy, dz * dz));
-    const float Rmin2 = 0.99f * ((xi0 >= 0.0f && xi <= 0.0f) ? rho2 : fminf(R2, R02));
-    if (!(Rmin2 >= 1.0f)) return false;
-    const float cut = kLog2DropK - 1.25f + 0.5f * (float)(__builtin_amdgcn_frexp_expf(Rmin2) - 1);
+    g.Rmin2 = 0.99f * ((xi0 >= 0.0f && g.xi <= 0.0f) ? g.rho2 : fminf(R2, R02));
     const float R = R2 * __builtin_amdgcn_rsqf(R2);
-    const float xr = xi >= 0.0f ? xi + R : rho2 * frcp(R - xi);
-    if (fmaf(-e.c1, 0.999f * xr, e.lamp) > cut) return false;
-    const float s0 = xi + e.vt;
-    if (fmaf(-e.e2, 0.999f * fmaf(s0, s0, rho2), e.lamp) > cut) return false;
+    g.xr = g.xi >= 0.0f ? g.xi + R : g.rho2 * frcp(R - g.xi);
+    return g;
+}
+
+// True if, at grid point (gi, gj, gk), source_rise drops every term of this
+// track at every time point the record covers, so that the track adds
+// exactly 0 to T there.  Each bound follows a drop test of source_rise, with
+// the distances of env_geometry and e2, e21 (which only decrease) at the last
+// time point; R is at least sqrt(Rmin2), which bounds the threshold from
+// below.  rlim2 >= 1 keeps the point outside the clamp radius and the
+// switched-off offset radius of source_rise.  1 % of R^2, 0.25 in the base-2
+// exponents and 0.1 % of the exponents' distances cover float32 rounding of
+// both computations (and the hardware rsq and rcp here).
+__device__ __forceinline__ bool env_negligible(const EnvRec& e, int gi, int gj, int gk, float rlim2) {
+    const EnvGeom g = env_geometry(e, gi, gj, gk);
+    if (!(g.Rmin2 >= rlim2)) return false;
+    const float cut = kLog2DropK - 1.25f + 0.5f * (float)(__builtin_amdgcn_frexp_expf(g.Rmin2) - 1);
+    if (fmaf(-e.c1, 0.999f * g.xr, e.lamp) > cut) return false;
+    const float s0 = g.xi + e.vt;
+    if (fmaf(-e.e2, 0.999f * fmaf(s0, s0, g.rho2), e.lamp) > cut) return false;
     if (e.e21 > 0.0f) {
-        const float s1 = xi + e.vt1;
-        if (fmaf(-e.e21, 0.999f * fmaf(s1, s1, rho2), e.lamp) > cut) return false;
+        const float s1 = g.xi + e.vt1;
+        if (fmaf(-e.e21, 0.999f * fmaf(s1, s1, g.rho2), e.lamp) > cut) return false;
     }
     return true;
+}
+
+// An upper bound of source_rise of this track at (gi, gj, gk) at every time
+// point the record covers (+inf if the point may come within rlim2 of it).
+// The leading term is 2^lg1 / R times a difference of erfc values in
+// [0, 2], and at most 2^lg1 e^{-y^2} / R when y = (R - v tau) s^-1 >= 0
+// (erfc(y) <= e^{-y^2}; a switched-off track only subtracts from it); y is
+// bounded below with R >= sqrt(Rmin2), v tau at most vt and 1/s at least is
+// of the last time point.  The start-point term is at most 2^lg2 / R
+// (erfcx <= 1 for a non-negative argument), and a switched-off track's
+// end-point term is subtracted.  The margins cover float32 rounding of both
+// computations and the 1.2e-7 relative error of the erfc form.
+__device__ __forceinline__ float env_rise_bound(const EnvRec& e, int gi, int gj, int gk, float rlim2) {
+    const EnvGeom g = env_geometry(e, gi, gj, gk);
+    if (!(g.Rmin2 >= rlim2)) return __builtin_inff();
+    const float rR = __builtin_amdgcn_rsqf(g.Rmin2);
+    const float lg1 = fmaf(-e.c1, 0.999f * g.xr, e.lamp);
+    const float y = fmaf(g.Rmin2, rR, -e.vt) * e.is;
+    const float t1 = y > 0.0f ? fexp2(fmaf(-0.999f * y * y, kLog2e, lg1)) : 2.0f * fexp2(lg1);
+    const float s0 = g.xi + e.vt;
+    const float t2 = fexp2(fmaf(-e.e2, 0.999f * fmaf(s0, s0, g.rho2), e.lamp));
+    return 1.002f * rR * (t1 + t2);
 }
 
 // all points of the calling wave certified cold for the launch: every track
 // of env drops out at every one of them (inactive lanes count as cold).
 // n_env < 0: no certificate, every wave evaluates the temperature.
 __device__ __forceinline__ bool wave_cold(const EnvRec* __restrict__ env, int n_env, bool act, int gi, int gj,
-                                          int gk) {
+                                          int gk, float rlim2) {
     if (n_env < 0) return false;
     bool cold = true;
     if (act)
-        for (int e = 0; e < n_env && cold; ++e) cold = env_negligible(env[e], gi, gj, gk);
+        for (int e = 0; e < n_env && cold; ++e) cold = env_negligible(env[e], gi, gj, gk, rlim2);
     return __ballot(!cold) == 0;
+}
+
+// all points of the calling wave certified to stay below Tlim at every time
+// point of the launch: T0 plus the rise bound of every track of env is below
+// it (inactive lanes pass).  The caller checks n_env >= 0.
+__device__ __forceinline__ bool wave_below(const EnvRec* __restrict__ env, int n_env, bool act, int gi, int gj,
+                                           int gk, float rlim2, float T0, float Tlim) {
+    float T = T0;
+    if (act)
+        for (int e = 0; e < n_env && T < Tlim; ++e) T += env_rise_bound(env[e], gi, gj, gk, rlim2);
+    return __ballot(act && !(T < Tlim)) == 0;
 }
 
 template <int W>

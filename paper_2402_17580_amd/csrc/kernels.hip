@@ -183,6 +183,24 @@ __global__ __launch_bounds__(kBlock) void temperature_kernel(PointGeom pg, const
     T[local] = (gk < pg.k0) ? sa.T0 : scan_temperature<W>(rec, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
 }
 
+// squared distance [grid units^2] within which the envelope tests certify
+// nothing: one grid unit, and at least the clamp radius and the offset
+// radius of source_rise
+__device__ __forceinline__ float envelope_radius2(const PointGeom& pg) {
+    return fmaxf(1.0f, fmaxf(pg.roff * pg.roff, pg.r2min));
+}
+
+// limit of the still test: the alpha_s -> beta end temperature of at_rest,
+// with 0.5 K to spare for float32 rounding of the computed temperatures
+constexpr float kRestBelow = Const<float>::TasEnd - 0.5f;
+
+// whether the still test can succeed (wave-uniform): certificates enabled,
+// T0 below the limit and every point of the wave at rest at the start of
+// the launch
+__device__ __forceinline__ bool wave_may_rest(const EnvSet& env, bool act, float a, float m, float T0) {
+    return env.n >= 0 && T0 < kRestBelow && __ballot(act && !(a == kXmax && m == 0.0f)) == 0;
+}
+
 // ---------------------------------------------------------------------------
 // fused K steps with the analytic temperature: one point per lane, its state
 // held in registers (with compensated Euler accumulation); tab holds the
@@ -215,18 +233,24 @@ __global__ __launch_bounds__(kBlock) void fused_plain_kernel(PointGeom pg, const
         alo[u] = 0.0f;
         mlo[u] = 0.0f;
     }
-    // a wave that no source of this launch reaches (every term of every
-    // track dropped at every time point) has T = T0 throughout
+    // A wave whose points are all at rest and provably stay below the
+    // alpha_s -> beta end temperature at every time point of the launch is
+    // left as it is by every step (still).  Otherwise, a wave that no source
+    // of this launch reaches (every term of every track dropped at every time
+    // point) has T = T0 throughout (cold).
     bool cold[PPT], still[PPT];
     const float T0c = fminf(sa.T0, sa.Tclamp);
+    const float rlim2 = envelope_radius2(pg);
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
-        cold[u] = wave_cold(env.rec, env.n, act[u], gi[u], gj[u], gk[u]);
+        const bool tried = wave_may_rest(env, act[u], a[u], m[u], T0c);
+        still[u] = tried && wave_below(env.rec, env.n, act[u], gi[u], gj[u], gk[u], rlim2, T0c, kRestBelow);
+        // an all-at-rest wave that is not below the limit everywhere is not cold either
+        cold[u] = still[u] || (!tried && wave_cold(env.rec, env.n, act[u], gi[u], gj[u], gk[u], rlim2));
         Tn[u] = cold[u] ? T0c : scan_temperature<W>(tab, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min, pg.roff);
         xeq_n[u] = alpha_eq(Tn[u]);
-        // a cold wave whose points are all at rest at T0 is left as it is by
-        // every step of the launch
-        still[u] = cold[u] && __ballot(act[u] && !at_rest(a[u], m[u], T0c, T0c)) == 0;
+        // a cold wave whose points are all at rest at T0 is still as well
+        still[u] = still[u] || (cold[u] && __ballot(act[u] && !at_rest(a[u], m[u], T0c, T0c)) == 0);
         if (TRACK && still[u]) xb[u] = track_none();
     }
     for (int s = 0; s < K; ++s) {
@@ -249,8 +273,11 @@ __global__ __launch_bounds__(kBlock) void fused_plain_kernel(PointGeom pg, const
     for (int u = 0; u < PPT; ++u) {
         if (!act[u]) continue;
         const float af = a[u] + alo[u], mf = m[u] + mlo[u];
-        as[local[u]] = af;
-        am[local[u]] = mf;
+        // a still wave's fractions are those in memory
+        if (!still[u]) {
+            as[local[u]] = af;
+            am[local[u]] = mf;
+        }
         if (TRACK) xbv[local[u]] = xb[u];
         if (beta) beta[local[u]] = solid_fraction(Tn[u]) - af - mf;
     }
@@ -279,12 +306,15 @@ __global__ __launch_bounds__(kBlock) void fused_implicit_kernel(PointGeom pg, co
     float a = act ? as[local] : 0.0f, m = act ? am[local] : 0.0f, b = 0.0f, alo = 0.0f, mlo = 0.0f;
     double xb = (TRACK && act) ? track_check(xbv[local], a, m) : track_none();
     int bad = 0;
-    const bool cold = wave_cold(env.rec, env.n, act, gi, gj, gk);  // T = T0 throughout (see fused_plain_kernel)
+    // still and cold waves as in fused_plain_kernel
     const float T0c = fminf(sa.T0, sa.Tclamp);
+    const float rlim2 = envelope_radius2(pg);
+    const bool tried = wave_may_rest(env, act, a, m, T0c);
+    bool still = tried && wave_below(env.rec, env.n, act, gi, gj, gk, rlim2, T0c, kRestBelow);
+    const bool cold = still || (!tried && wave_cold(env.rec, env.n, act, gi, gj, gk, rlim2));
     float Tn = cold ? T0c : scan_temperature<W>(tab, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
     const float inv = 1.0f / (float)n_sub;
-    // a cold wave whose points are all at rest at T0 is left as it is
-    const bool still = cold && __ballot(act && !at_rest(a, m, T0c, T0c)) == 0;
+    still = still || (cold && __ballot(act && !at_rest(a, m, T0c, T0c)) == 0);
     if (TRACK && still) xb = track_none();
     for (int s = 0; s < K && !still; ++s) {
         const float Tn1 =
@@ -302,8 +332,10 @@ __global__ __launch_bounds__(kBlock) void fused_implicit_kernel(PointGeom pg, co
     if (act) {
         a += alo;
         m += mlo;
-        as[local] = a;
-        am[local] = m;
+        if (!still) {  // a still wave's fractions are those in memory
+            as[local] = a;
+            am[local] = m;
+        }
         if (beta) beta[local] = solid_fraction(Tn) - a - m;
         if (TRACK) xbv[local] = xb;
     }

@@ -302,15 +302,20 @@ def _cold_cases():
                                               dt=2e-6, seed=78, island=0.5e-3))]
     wl0 = workload.single_track(nx=48, ny=32, nz=10)
     cases.append(("preheated", dataclasses.replace(wl0, scan=dataclasses.replace(wl0.scan, T0=1250.0))))
+    # bodies just below the 935 K limit of the still test (934.5 K): rises of
+    # 14.5 and 0.5 K already leave it
+    for T0 in (920.0, 934.0):
+        cases.append((f"warm_{T0:.0f}", dataclasses.replace(wl0, scan=dataclasses.replace(wl0.scan, T0=T0))))
     return cases
 
 
 @pytest.mark.parametrize("mode", ["plain", "implicit"])
 def test_cold_waves_skip_is_bit_exact(torch, ctx, mode):
-    """Fused PLAIN and IMPLICIT runs give the same bits with the cold-wave
-    certificate on (default) and off (every temperature evaluated), on
-    scans with windows of 2 and 4 tracks, an island scan, a masked grid and
-    a preheated body."""
+    """Fused PLAIN and IMPLICIT runs give the same bits with the launch
+    certificates on (default: cold waves take T = T0, waves at rest below
+    935 K skip the launch) and off (every temperature evaluated), on scans
+    with windows of 2 and 4 tracks, an island scan, a masked grid, a body
+    preheated to 1250 K and bodies at 920 and 934 K."""
     import paper_2402_17580_amd as ms
     m = ms.MODE_PLAIN if mode == "plain" else ms.MODE_IMPLICIT
     cases = _cold_cases()
