@@ -35,6 +35,10 @@ struct mstruct_ctx {
     unsigned long long* counter = nullptr;
     unsigned long long* implicit_bad = nullptr;  // substeps of fused implicit runs that hit the cap
     bool skip_cold = true;                       // MSTRUCT_OPTION_SKIP_COLD_WAVES
+    // per-wave flags of fused calls on box grids: rest flags, then the still
+    // flags of a chunk of launches
+    uint8_t* wave_flags = nullptr;
+    size_t wave_flags_cap = 0;
     MlpState mlp;
 };
 
@@ -160,6 +164,9 @@ int substeps(double dt, double dt_sub) { return dt > dt_sub ? (int)ceil(dt / dt_
 // substep limit and iteration cap of the implicit scheme in the fused path (Sec. 3.1)
 constexpr double kImplicitDtSub = 0.01;
 constexpr int kImplicitMaxIter = 50;
+
+// bytes of still flags per chunk of launches of a fused call
+constexpr int64_t kWaveFlagBudget = (int64_t)64 << 20;
 
 void split(double g, int32_t& i, float& f) {
     const double fl = floor(g);
@@ -357,6 +364,7 @@ int mstruct_destroy(mstruct_ctx* ctx) {
     }
     if (ctx->counter) (void)hipFree(ctx->counter);
     if (ctx->implicit_bad) (void)hipFree(ctx->implicit_bad);
+    if (ctx->wave_flags) (void)hipFree(ctx->wave_flags);
     mlp_free(ctx->mlp);
     delete ctx;
     return MSTRUCT_OK;
@@ -464,16 +472,46 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
     const size_t recs = (size_t)(n_steps + 1) * W;
     const int64_t n_launches = (n_steps + K - 1) / K;
     const size_t env_cap = (size_t)n_launches * (W + K + 1);
+    // (first, count) of each launch's envelopes, as int32 pairs after them
+    const size_t fc_recs = ((size_t)n_launches * 2 * sizeof(int32_t) + sizeof(SrcRec) - 1) / sizeof(SrcRec);
+    // Wave flags on box grids (one point per lane, 64 per wave): still flags
+    // for chunks of launches from a box pre-pass, rest flags kept by the
+    // fused kernels.  Not with the tracked X~beta, whose store every launch
+    // takes.
+    const bool wave_flags = ctx->skip_cold && !ph->xbt && !pts->index && mode != MSTRUCT_MODE_SURROGATE;
+    const int64_t n_waves = (pg.count + kWave - 1) / kWave;
+    int64_t chunk = kWaveFlagBudget / n_waves;
+    chunk = chunk < 1 ? 1 : (chunk > n_launches ? n_launches : chunk);
+    if (wave_flags) {
+        const size_t need = (size_t)n_waves * (size_t)(1 + chunk);
+        if (ctx->wave_flags_cap < need) {
+            HIP_CHECK(ctx, hipStreamSynchronize(st));
+            if (ctx->wave_flags) HIP_CHECK(ctx, hipFree(ctx->wave_flags));
+            ctx->wave_flags = nullptr;
+            ctx->wave_flags_cap = 0;
+            if (hipMalloc((void**)&ctx->wave_flags, need) != hipSuccess) {
+                ctx->wave_flags = nullptr;
+                return fail(ctx, MSTRUCT_ENOMEM, "wave flag allocation failed");
+            }
+            ctx->wave_flags_cap = need;
+        }
+    }
     TableSlot* s;
-    if ((rc = acquire_slot(ctx, recs + env_cap, s))) return rc;
+    if ((rc = acquire_slot(ctx, recs + env_cap + fc_recs, s))) return rc;
     build_table(s->host, scan, pts, t0, dt, n_steps + 1);
     // launch envelopes after the records (EnvRec has the size of SrcRec)
     std::vector<int32_t> env_first, env_count;
     EnvRec* env_host = reinterpret_cast<EnvRec*>(s->host + recs);
     const EnvRec* env_dev = reinterpret_cast<const EnvRec*>(s->dev + recs);
     const int64_t n_env = build_envelopes(env_host, env_first, env_count, s->host, scan, t0, dt, n_steps, K);
-    HIP_CHECK(ctx, hipMemcpyAsync(s->dev, s->host, (recs + (size_t)n_env) * sizeof(SrcRec), hipMemcpyHostToDevice,
-                                  st));
+    int32_t* fc_host = reinterpret_cast<int32_t*>(s->host + recs + n_env);
+    const int32_t* fc_dev = reinterpret_cast<const int32_t*>(s->dev + recs + n_env);
+    for (int64_t li = 0; li < n_launches; ++li) {
+        fc_host[2 * li] = env_first[li];
+        fc_host[2 * li + 1] = env_count[li];
+    }
+    HIP_CHECK(ctx, hipMemcpyAsync(s->dev, s->host, (recs + (size_t)n_env + fc_recs) * sizeof(SrcRec),
+                                  hipMemcpyHostToDevice, st));
     const ScanArgs sa{(float)scan->T0, (float)scan->T_clamp};
     if (mode == MSTRUCT_MODE_SURROGATE) {
         hipError_t e = surrogate_prepare(ctx->mlp, pg.first + pg.count, st);
@@ -489,7 +527,21 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
         float* beta = last ? ph->beta : nullptr;
         hipError_t e;
         const int64_t li = s0 / K;
-        const EnvSet es{env_dev + env_first[li], ctx->skip_cold ? env_count[li] : -1};
+        uint8_t* below = nullptr;
+        if (wave_flags) {
+            below = ctx->wave_flags + n_waves * (1 + li % chunk);
+            if (li % chunk == 0) {
+                const int64_t nl = (n_launches - li) < chunk ? (n_launches - li) : chunk;
+                e = launch_still_flags(pg, env_dev, fc_dev, li, nl, n_waves, fminf(sa.T0, sa.Tclamp),
+                                       ctx->wave_flags + n_waves, st);
+                if (e != hipSuccess) {
+                    (void)release_slot(ctx, s, st);
+                    return hip_fail(ctx, e, "still flags launch");
+                }
+            }
+        }
+        const EnvSet es{env_dev + env_first[li], ctx->skip_cold ? env_count[li] : -1, below,
+                        wave_flags ? ctx->wave_flags : nullptr, n_waves, li > 0};
         if (mode == MSTRUCT_MODE_PLAIN) {
             e = launch_fused_plain(pg, W, s->dev + s0 * W, es, Kb, (float)dt, sa, beta, ph->alpha_s, ph->alpha_m,
                                    ph->xbt, st);

@@ -237,6 +237,54 @@ __device__ __forceinline__ float env_rise_bound(const EnvRec& e, int gi, int gj,
     return 1.002f * rR * (t1 + t2);
 }
 
+// An axis-aligned box of grid positions (x = i, y = j, z = -k).
+struct GridBox {
+    float xl, xh, yl, yh, zl, zh;
+};
+
+// distance from [lo, hi] to c along one axis: nearest and farthest
+__device__ __forceinline__ float axis_near(float lo, float hi, float c) { return fmaxf(0.0f, fmaxf(lo - c, c - hi)); }
+__device__ __forceinline__ float axis_far(float lo, float hi, float c) { return fmaxf(fabsf(lo - c), fabsf(hi - c)); }
+
+// env_rise_bound for every point of a box at once: the same terms, with the
+// distances bounded over the box.  R is at least the distance from the box
+// to the bounding box of the segment Q..P.  For d = x - P, xi + R is |d| or
+// more where d points along the motion, and rho^2 / (|d| - xi) >=
+// rho^2 / (2 |d|) behind it, so it is at least the smaller of the least |d|
+// and the least rho^2 over twice the largest |d| (rho is the distance from
+// the line of motion, whose cross-track part is linear in x and y and is
+// bounded at the corners).  |x - P0|, P0 = P - vt u the start point, is at
+// least the distance from the box to P0.
+__device__ __forceinline__ float env_box_rise_bound(const EnvRec& e, const GridBox& b, float rlim2) {
+    // gap between the box and the segment's bounding box along each axis
+    const float gx = fmaxf(0.0f, fmaxf(fminf(e.qx, e.px) - b.xh, b.xl - fmaxf(e.qx, e.px)));
+    const float gy = fmaxf(0.0f, fmaxf(fminf(e.qy, e.py) - b.yh, b.yl - fmaxf(e.qy, e.py)));
+    const float nz = axis_near(b.zl, b.zh, e.pz);
+    const float Rmin2 = 0.99f * fmaf(gx, gx, fmaf(gy, gy, nz * nz));
+    // (P is inside the segment's bounding box, so below dmin2 >= Rmin2 >= 1)
+    if (!(Rmin2 >= rlim2)) return __builtin_inff();
+    const float nx = axis_near(b.xl, b.xh, e.px), ny = axis_near(b.yl, b.yh, e.py);
+    const float fx = axis_far(b.xl, b.xh, e.px), fy = axis_far(b.yl, b.yh, e.py), fz = axis_far(b.zl, b.zh, e.pz);
+    const float dmin2 = 0.99f * fmaf(nx, nx, fmaf(ny, ny, nz * nz));
+    const float dmax2 = 1.01f * fmaf(fx, fx, fmaf(fy, fy, fz * fz));
+    // cross-track offset dx uy - dy ux at the four corners
+    const float xl = b.xl - e.px, xh = b.xh - e.px, yl = b.yl - e.py, yh = b.yh - e.py;
+    const float c0 = fmaf(xl, e.uy, -yl * e.ux), c1 = fmaf(xl, e.uy, -yh * e.ux);
+    const float c2 = fmaf(xh, e.uy, -yl * e.ux), c3 = fmaf(xh, e.uy, -yh * e.ux);
+    const float cmin = fminf(fminf(c0, c1), fminf(c2, c3)), cmax = fmaxf(fmaxf(c0, c1), fmaxf(c2, c3));
+    const float cr = (cmin <= 0.0f && cmax >= 0.0f) ? 0.0f : 0.99f * fminf(fabsf(cmin), fabsf(cmax));
+    const float rho2 = fmaf(cr, cr, nz * nz);
+    const float xr = fminf(dmin2 * __builtin_amdgcn_rsqf(dmin2), 0.5f * rho2 * __builtin_amdgcn_rsqf(dmax2));
+    const float rR = __builtin_amdgcn_rsqf(Rmin2);
+    const float lg1 = fmaf(-e.c1, 0.999f * fmaxf(xr, 0.0f), e.lamp);
+    const float y = fmaf(Rmin2, rR, -e.vt) * e.is;
+    const float t1 = y > 0.0f ? fexp2(fmaf(-0.999f * y * y, kLog2e, lg1)) : 2.0f * fexp2(lg1);
+    const float ax = axis_near(b.xl, b.xh, fmaf(-e.vt, e.ux, e.px)), ay = axis_near(b.yl, b.yh, fmaf(-e.vt, e.uy, e.py));
+    const float d02 = 0.99f * fmaf(ax, ax, fmaf(ay, ay, nz * nz));
+    const float t2 = fexp2(fmaf(-e.e2, 0.999f * d02, e.lamp));
+    return 1.002f * rR * (t1 + t2);
+}
+
 // all points of the calling wave certified cold for the launch: every track
 // of env drops out at every one of them (inactive lanes count as cold).
 // n_env < 0: no certificate, every wave evaluates the temperature.

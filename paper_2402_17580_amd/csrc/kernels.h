@@ -48,11 +48,30 @@ struct ScanArgs {
     float T0, Tclamp;
 };
 
-// the envelope records of one launch (see EnvRec)
+// the envelope records of one launch (see EnvRec), and the per-wave flags of
+// a box grid (below == nullptr: not used; never with a tracked X~beta):
+// below[w] != 0 when still_flags bounded every point of wave w below the
+// still limit through this launch; rest[w] != 0 when every point of wave w
+// was at rest after the last launch that took its steps.  rest is read only
+// when read_rest (from the second launch of a call) and written by every
+// wave that takes its steps.
 struct EnvSet {
     const EnvRec* rec;
     int32_t n;
+    const uint8_t* below;
+    uint8_t* rest;
+    int64_t n_waves;
+    int32_t read_rest;
 };
+
+// points per wave of the fused kernels (one point per lane)
+constexpr int kWave = 64;
+
+// still_flags for launches l0 .. l0 + nl - 1 of a call on a box grid:
+// flags[(l - l0) * n_waves + w] for wave w = points 64 w .. 64 w + 63 of pg;
+// env_fc holds (first record, count) of each launch's envelopes in env.
+hipError_t launch_still_flags(const PointGeom& pg, const EnvRec* env, const int32_t* env_fc, int64_t l0, int64_t nl,
+                              int64_t n_waves, float T0, uint8_t* flags, hipStream_t st);
 
 // xb: optional tracked X~beta side values (float64 per point), or nullptr
 hipError_t launch_step(const float* Tp, const float* Tn, float* beta, float* as, float* am, double* xb, int64_t n,

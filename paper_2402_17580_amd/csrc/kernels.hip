@@ -186,7 +186,7 @@ __global__ __launch_bounds__(kBlock) void temperature_kernel(PointGeom pg, const
 // squared distance [grid units^2] within which the envelope tests certify
 // nothing: one grid unit, and at least the clamp radius and the offset
 // radius of source_rise
-__device__ __forceinline__ float envelope_radius2(const PointGeom& pg) {
+__host__ __device__ __forceinline__ float envelope_radius2(const PointGeom& pg) {
     return fmaxf(1.0f, fmaxf(pg.roff * pg.roff, pg.r2min));
 }
 
@@ -194,11 +194,84 @@ __device__ __forceinline__ float envelope_radius2(const PointGeom& pg) {
 // with 0.5 K to spare for float32 rounding of the computed temperatures
 constexpr float kRestBelow = Const<float>::TasEnd - 0.5f;
 
+// a state at rest with alpha_m = +0.0 exactly: steps at rest store m + 0 =
+// +0.0, so a wave of such states may skip its stores
+__device__ __forceinline__ bool rest_bits(float a, float m) { return a == kXmax && __float_as_uint(m) == 0u; }
+
 // whether the still test can succeed (wave-uniform): certificates enabled,
 // T0 below the limit and every point of the wave at rest at the start of
 // the launch
 __device__ __forceinline__ bool wave_may_rest(const EnvSet& env, bool act, float a, float m, float T0) {
-    return env.n >= 0 && T0 < kRestBelow && __ballot(act && !(a == kXmax && m == 0.0f)) == 0;
+    return env.n >= 0 && T0 < kRestBelow && __ballot(act && !rest_bits(a, m)) == 0;
+}
+
+// the box of grid positions holding the points of wave w (points 64 w ..
+// 64 w + 63 of pg, a box grid): the wave's part of one row, or whole rows
+// of one plane, or whole planes
+__device__ __forceinline__ GridBox wave_box(const PointGeom& pg, int64_t w) {
+    const int64_t g1 = w * kWave + kWave - 1 < pg.count ? w * kWave + kWave - 1 : pg.count - 1;
+    int i0, j0, k0, i1, j1, k1;
+    decode_point(pg, pg.first + w * kWave, i0, j0, k0);
+    decode_point(pg, pg.first + g1, i1, j1, k1);
+    GridBox b;
+    const bool row = k0 == k1 && j0 == j1;
+    b.xl = row ? (float)i0 : 0.0f;
+    b.xh = row ? (float)i1 : (float)(pg.nx - 1);
+    b.yl = k0 == k1 ? (float)j0 : 0.0f;
+    b.yh = k0 == k1 ? (float)j1 : (float)(pg.nxy / pg.nx - 1);
+    b.zl = -(float)k1;
+    b.zh = -(float)k0;
+    return b;
+}
+
+// one lane per (launch, wave): whether T0 plus the box bounds of every track
+// of the launch stay below the still limit at every point of the wave
+__global__ __launch_bounds__(kBlock) void still_flags_kernel(PointGeom pg, const EnvRec* __restrict__ env,
+                                                            const int32_t* __restrict__ env_fc, int64_t nl,
+                                                            int64_t n_waves, float T0, float rlim2,
+                                                            uint8_t* __restrict__ flags) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t >= nl * n_waves) return;
+    const int64_t l = t / n_waves, w = t - l * n_waves;
+    const GridBox b = wave_box(pg, w);
+    const EnvRec* e = env + env_fc[2 * l];
+    const int n = env_fc[2 * l + 1];
+    float T = T0;
+    for (int k = 0; k < n && T < kRestBelow; ++k) T += env_box_rise_bound(e[k], b, rlim2);
+    flags[t] = T < kRestBelow ? 1 : 0;
+}
+
+hipError_t launch_still_flags(const PointGeom& pg, const EnvRec* env, const int32_t* env_fc, int64_t l0, int64_t nl,
+                              int64_t n_waves, float T0, uint8_t* flags, hipStream_t st) {
+    const int64_t lanes = nl * n_waves;
+    if (lanes <= 0) return hipSuccess;
+    hipLaunchKernelGGL(still_flags_kernel, dim3((unsigned)((lanes + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, pg,
+                       env, env_fc + 2 * l0, nl, n_waves, T0, envelope_radius2(pg), flags);
+    return hipGetLastError();
+}
+
+// wave index of the calling lane in a fused launch (uniform across the wave)
+__device__ __forceinline__ int64_t fused_wave() {
+    return (int64_t)blockIdx.x * (kBlock / kWave) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+}
+
+// A wave whose flags say still from the pre-pass and the previous launch:
+// its state is at rest and stays as it is, so only beta (last launch of a
+// call) is written, with the value every step would give.
+__device__ __forceinline__ bool wave_flag_still(const EnvSet& env, int64_t wv) {
+    return env.below && env.read_rest && wv < env.n_waves && env.below[wv] && env.rest[wv];
+}
+
+__device__ __forceinline__ void still_wave_beta(const PointGeom& pg, float T0c, float* beta) {
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (beta && g < pg.count) beta[pg.first + g] = solid_fraction(T0c) - kXmax - 0.0f;
+}
+
+// record whether every point of the wave is at rest after the launch
+__device__ __forceinline__ void record_rest(const EnvSet& env, int64_t wv, bool act, float a, float m) {
+    if (!env.below || wv >= env.n_waves) return;
+    const bool r = __ballot(act && !rest_bits(a, m)) == 0;
+    if ((threadIdx.x & (kWave - 1)) == 0) env.rest[wv] = r ? 1 : 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -214,6 +287,12 @@ __global__ __launch_bounds__(kBlock) void fused_plain_kernel(PointGeom pg, const
     // beta == nullptr: not written (inside a call only the last launch writes
     // it; no kernel reads beta, it follows from the sum rule)
     // PPT points per lane, kBlock apart (coalesced), advanced together for ILP
+    const float T0c = fminf(sa.T0, sa.Tclamp);
+    const int64_t wv = fused_wave();
+    if (PPT == 1 && !TRACK && wave_flag_still(env, wv)) {
+        still_wave_beta(pg, T0c, beta);
+        return;
+    }
     const int64_t g0 = (int64_t)blockIdx.x * kBlock * PPT + threadIdx.x;
     int64_t local[PPT];
     int gi[PPT], gj[PPT], gk[PPT];
@@ -239,7 +318,6 @@ __global__ __launch_bounds__(kBlock) void fused_plain_kernel(PointGeom pg, const
     // of this launch reaches (every term of every track dropped at every time
     // point) has T = T0 throughout (cold).
     bool cold[PPT], still[PPT];
-    const float T0c = fminf(sa.T0, sa.Tclamp);
     const float rlim2 = envelope_radius2(pg);
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
@@ -250,7 +328,7 @@ __global__ __launch_bounds__(kBlock) void fused_plain_kernel(PointGeom pg, const
         Tn[u] = cold[u] ? T0c : scan_temperature<W>(tab, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min, pg.roff);
         xeq_n[u] = alpha_eq(Tn[u]);
         // a cold wave whose points are all at rest at T0 is still as well
-        still[u] = still[u] || (cold[u] && __ballot(act[u] && !at_rest(a[u], m[u], T0c, T0c)) == 0);
+        still[u] = still[u] || (cold[u] && T0c < Const<float>::TasEnd && __ballot(act[u] && !rest_bits(a[u], m[u])) == 0);
         if (TRACK && still[u]) xb[u] = track_none();
     }
     for (int s = 0; s < K; ++s) {
@@ -281,6 +359,7 @@ __global__ __launch_bounds__(kBlock) void fused_plain_kernel(PointGeom pg, const
         if (TRACK) xbv[local[u]] = xb[u];
         if (beta) beta[local[u]] = solid_fraction(Tn[u]) - af - mf;
     }
+    if (PPT == 1 && !TRACK) record_rest(env, wv, act[0], a[0] + alo[0], m[0] + mlo[0]);
 }
 
 // ---------------------------------------------------------------------------
@@ -297,6 +376,12 @@ __global__ __launch_bounds__(kBlock) void fused_implicit_kernel(PointGeom pg, co
                                                                float* __restrict__ beta, float* __restrict__ as,
                                                                float* __restrict__ am, double* __restrict__ xbv,
                                                                unsigned long long* __restrict__ unconverged) {
+    const float T0c = fminf(sa.T0, sa.Tclamp);
+    const int64_t wv = fused_wave();
+    if (!TRACK && wave_flag_still(env, wv)) {  // see fused_plain_kernel
+        still_wave_beta(pg, T0c, beta);
+        return;
+    }
     const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     bool act = g < pg.count;
     const int64_t local = pg.first + (act ? g : 0);
@@ -307,14 +392,13 @@ __global__ __launch_bounds__(kBlock) void fused_implicit_kernel(PointGeom pg, co
     double xb = (TRACK && act) ? track_check(xbv[local], a, m) : track_none();
     int bad = 0;
     // still and cold waves as in fused_plain_kernel
-    const float T0c = fminf(sa.T0, sa.Tclamp);
     const float rlim2 = envelope_radius2(pg);
     const bool tried = wave_may_rest(env, act, a, m, T0c);
     bool still = tried && wave_below(env.rec, env.n, act, gi, gj, gk, rlim2, T0c, kRestBelow);
     const bool cold = still || (!tried && wave_cold(env.rec, env.n, act, gi, gj, gk, rlim2));
     float Tn = cold ? T0c : scan_temperature<W>(tab, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
     const float inv = 1.0f / (float)n_sub;
-    still = still || (cold && __ballot(act && !at_rest(a, m, T0c, T0c)) == 0);
+    still = still || (cold && T0c < Const<float>::TasEnd && __ballot(act && !rest_bits(a, m)) == 0);
     if (TRACK && still) xb = track_none();
     for (int s = 0; s < K && !still; ++s) {
         const float Tn1 =
@@ -339,6 +423,7 @@ __global__ __launch_bounds__(kBlock) void fused_implicit_kernel(PointGeom pg, co
         if (beta) beta[local] = solid_fraction(Tn) - a - m;
         if (TRACK) xbv[local] = xb;
     }
+    if (!TRACK) record_rest(env, wv, act, a, m);
     if (!act) bad = 0;
     int total = bad;
     for (int o = 32; o > 0; o >>= 1) total += __shfl_xor(total, o);

@@ -306,6 +306,12 @@ def _cold_cases():
     # 14.5 and 0.5 K already leave it
     for T0 in (920.0, 934.0):
         cases.append((f"warm_{T0:.0f}", dataclasses.replace(wl0, scan=dataclasses.replace(wl0.scan, T0=T0))))
+    # planes of 60 points: every wave of 64 spans two planes (the track moved
+    # over them)
+    wt = workload.single_track(nx=20, ny=3, nz=40, n_steps=400)
+    tracks = wt.scan.tracks.copy()
+    tracks[:, 1] = 15e-6
+    cases.append(("thin", dataclasses.replace(wt, scan=dataclasses.replace(wt.scan, tracks=tracks))))
     return cases
 
 
