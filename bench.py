@@ -35,12 +35,13 @@ K_SURROGATE = 8
 STEP_BYTES = 28  # plain step: reads alpha_s, alpha_m, T^n, T^{n+1}; writes beta, alpha_s, alpha_m (float32)
 
 
-def fused_bytes_per_point(launches, calls, written):
-    """Algorithmic HBM bytes per active point and fused launch: every launch
-    reads alpha_s, alpha_m (8 B) and writes them (8 B) for the fraction
-    `written` of the points whose wave is not still; the last launch of each
-    call also writes beta (4 B)."""
-    return 8.0 + 8.0 * written + 4.0 * calls / launches
+def fused_bytes_per_point(launches, calls, read, written):
+    """Algorithmic HBM bytes per active point and fused launch: alpha_s,
+    alpha_m are read (8 B) for the fraction `read` of the points whose wave
+    does not exit on its flags, and written (8 B) for the fraction `written`
+    whose wave is not still; the last launch of each call also writes beta
+    (4 B)."""
+    return 8.0 * read + 8.0 * written + 4.0 * calls / launches
 
 
 def parse():
@@ -113,8 +114,8 @@ def main():
     # kernel is the only kernel in it besides three state resets per step)
     avg_launch_s = ms_total * 1e-3 / (args.steps * launches)
     upd_per_launch = updates / launches
-    bytes_per_launch = fused_bytes_per_point(launches, len(wl.layers), FUSED_PROFILE["written_fraction"]) * \
-        upd_per_launch / args.K
+    bytes_per_launch = fused_bytes_per_point(launches, len(wl.layers), FUSED_PROFILE["read_fraction"],
+                                             FUSED_PROFILE["written_fraction"]) * upd_per_launch / args.K
 
     result = {
         "metric": "microstructure point-updates/s @8.4M pts (256x256x128 block, 10 layers, 20k steps): FP32 plain",
@@ -237,15 +238,17 @@ def main():
 # counter runs of this script (profiles/fused_plain_kernel_multilayer_block.txt):
 # executed VALU instructions x 64 lanes and FP32 FLOPs per point-update, and
 # HBM bytes per launch (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0: the factors a
-# plain 1 GiB device copy reads on the same counters), and the fraction of the
-# points whose state the kernel writes (waves that are not still, at K = 16).
+# plain 1 GiB device copy reads on the same counters), and the fractions of
+# the points whose state the kernel reads (waves that do not exit on their
+# flags) and writes (waves that are not still), at K = 16.
 # the same kernel with every temperature evaluated (MSTRUCT_OPTION_SKIP_COLD_WAVES = 0)
-FUSED_PROFILE_EVERY_T = {"valu_lane_ops_per_update": 135.33}
+FUSED_PROFILE_EVERY_T = {"valu_lane_ops_per_update": 135.58}
 FUSED_PROFILE = {
-    "valu_lane_ops_per_update": 23.19,
-    "fp32_flops_per_update": 15.75,
-    "traffic_bytes_per_launch": (29403.92 * 2.0 + 2662.87) * 1024,
-    "written_fraction": 0.0414,
+    "valu_lane_ops_per_update": 11.03,
+    "fp32_flops_per_update": 8.58,
+    "traffic_bytes_per_launch": (2658.51 * 2.0 + 2724.55) * 1024,
+    "read_fraction": 0.0907,
+    "written_fraction": 0.0425,
 }
 
 def bench_stepwise(torch, ms, ctx, wl, dev):
