@@ -476,9 +476,9 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
     const size_t fc_recs = ((size_t)n_launches * 2 * sizeof(int32_t) + sizeof(SrcRec) - 1) / sizeof(SrcRec);
     // Wave flags on box grids (one point per lane, 64 per wave): still flags
     // for chunks of launches from a box pre-pass, rest flags kept by the
-    // fused kernels.  Not with the tracked X~beta, whose store every launch
-    // takes.
-    const bool wave_flags = ctx->skip_cold && !ph->xbt && !pts->index && mode != MSTRUCT_MODE_SURROGATE;
+    // fused kernels and surrogate pass A.  Not with the tracked X~beta, whose
+    // store every launch takes.
+    const bool wave_flags = ctx->skip_cold && !ph->xbt && !pts->index;
     const int64_t n_waves = (pg.count + kWave - 1) / kWave;
     int64_t chunk = kWaveFlagBudget / n_waves;
     chunk = chunk < 1 ? 1 : (chunk > n_launches ? n_launches : chunk);
@@ -550,7 +550,7 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
             e = launch_fused_implicit(pg, W, s->dev + s0 * W, es, Kb, (float)(dt / n_sub), n_sub, kImplicitMaxIter,
                                       sa, beta, ph->alpha_s, ph->alpha_m, ph->xbt, ctx->implicit_bad, st);
         } else
-            e = launch_surrogate(ctx->mlp, pg, W, s->dev + s0 * W, Kb, (float)dt, sa, ph->beta, ph->alpha_s,
+            e = launch_surrogate(ctx->mlp, pg, W, s->dev + s0 * W, es, Kb, (float)dt, sa, ph->beta, ph->alpha_s,
                                  ph->alpha_m, li, s0 == 0, last, st);
         if (e != hipSuccess) {
             (void)release_slot(ctx, s, st);

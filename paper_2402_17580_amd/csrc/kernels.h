@@ -67,6 +67,16 @@ struct EnvSet {
 // points per wave of the fused kernels (one point per lane)
 constexpr int kWave = 64;
 
+// a state at rest with alpha_m = +0.0 exactly: steps at rest store m + 0 =
+// +0.0, so a wave of such states may skip its stores
+__device__ __forceinline__ bool rest_bits(float a, float m) { return a == kXmax && __float_as_uint(m) == 0u; }
+
+// wave wv (points 64 wv .. 64 wv + 63) is still by its flags: bounded below
+// the still limit through this launch and at rest after the previous one
+__device__ __forceinline__ bool wave_flag_still(const EnvSet& env, int64_t wv) {
+    return env.below && env.read_rest && wv < env.n_waves && env.below[wv] && env.rest[wv];
+}
+
 // still_flags for launches l0 .. l0 + nl - 1 of a call on a box grid:
 // flags[(l - l0) * n_waves + w] for wave w = points 64 w .. 64 w + 63 of pg;
 // env_fc holds (first record, count) of each launch's envelopes in env.

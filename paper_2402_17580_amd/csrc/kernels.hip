@@ -194,10 +194,6 @@ __host__ __device__ __forceinline__ float envelope_radius2(const PointGeom& pg) 
 // with 0.5 K to spare for float32 rounding of the computed temperatures
 constexpr float kRestBelow = Const<float>::TasEnd - 0.5f;
 
-// a state at rest with alpha_m = +0.0 exactly: steps at rest store m + 0 =
-// +0.0, so a wave of such states may skip its stores
-__device__ __forceinline__ bool rest_bits(float a, float m) { return a == kXmax && __float_as_uint(m) == 0u; }
-
 // whether the still test can succeed (wave-uniform): certificates enabled,
 // T0 below the limit and every point of the wave at rest at the start of
 // the launch
@@ -255,13 +251,9 @@ __device__ __forceinline__ int64_t fused_wave() {
     return (int64_t)blockIdx.x * (kBlock / kWave) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
 }
 
-// A wave whose flags say still from the pre-pass and the previous launch:
-// its state is at rest and stays as it is, so only beta (last launch of a
-// call) is written, with the value every step would give.
-__device__ __forceinline__ bool wave_flag_still(const EnvSet& env, int64_t wv) {
-    return env.below && env.read_rest && wv < env.n_waves && env.below[wv] && env.rest[wv];
-}
-
+// A wave whose flags say still (wave_flag_still): its state is at rest and
+// stays as it is, so only beta (last launch of a call) is written, with the
+// value every step would give.
 __device__ __forceinline__ void still_wave_beta(const PointGeom& pg, float T0c, float* beta) {
     const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (beta && g < pg.count) beta[pg.first + g] = solid_fraction(T0c) - kXmax - 0.0f;

@@ -76,8 +76,10 @@ hipError_t mlp_grad(MlpState& s, const float* X, const float* Y, int64_t B, floa
                     hipStream_t st);
 hipError_t mlp_adam(MlpState& s, float lr, hipStream_t st);
 hipError_t surrogate_prepare(MlpState& s, int64_t points, hipStream_t st);
-hipError_t launch_surrogate(const MlpState& s, const PointGeom& pg, int W, const SrcRec* tab, int K, float dt,
-                            ScanArgs sa, float* beta, float* as, float* am, int64_t block, bool first_block,
+// env: the wave flags of the launch (env.below == nullptr: not used; the
+// envelope records themselves are not used by the surrogate)
+hipError_t launch_surrogate(const MlpState& s, const PointGeom& pg, int W, const SrcRec* tab, EnvSet env, int K,
+                            float dt, ScanArgs sa, float* beta, float* as, float* am, int64_t block, bool first_block,
                             bool last_block, hipStream_t st);
 hipError_t launch_correct(const float* T, float* beta, float* as, float* am, int64_t n, hipStream_t st);
 

@@ -595,8 +595,8 @@ __device__ __forceinline__ bool formation_front(float T0, float TK, float a, flo
 }
 
 template <int W, int PPT>
-__global__ __launch_bounds__(256) void surrogate_a_kernel(PointGeom pg, const SrcRec* __restrict__ tab, int K,
-                                                         float dt, ScanArgs sa, float* __restrict__ beta,
+__global__ __launch_bounds__(256) void surrogate_a_kernel(PointGeom pg, const SrcRec* __restrict__ tab, EnvSet env,
+                                                         int K, float dt, ScanArgs sa, float* __restrict__ beta,
                                                          float* __restrict__ as, float* __restrict__ am,
                                                          MlpNorm nrm, float* __restrict__ queue,
                                                          unsigned* __restrict__ counter, const float* tin,
@@ -606,12 +606,23 @@ __global__ __launch_bounds__(256) void surrogate_a_kernel(PointGeom pg, const Sr
     // (coalesced); their loads are issued together and their temperatures
     // computed side by side.
     const int lane = threadIdx.x & 63;
+    const int wib = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
     for (int64_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
         const int64_t g0 = chunk * 256 * PPT + threadIdx.x;
-        int64_t local[PPT];
+        int64_t local[PPT], wv[PPT];
         int gi[PPT], gj[PPT], gk[PPT];
-        bool valid[PPT];
+        bool valid[PPT], still[PPT];
         float a[PPT], m[PPT], T0[PPT], TK[PPT];
+        // 64 points of a wave whose flags say still (at rest, below 935 K
+        // through the block): every branch below would leave them as they
+        // are and write beta = 1 - 0.9 - 0, and none would be queued; only
+        // the block-end temperature is not computed (NaN in the cache makes
+        // the next block compute its start temperature, the same value)
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+            wv[u] = chunk * (256 * PPT / 64) + wib + u * (256 / 64);
+            still[u] = wave_flag_still(env, wv[u]);
+        }
         // indices, then every load issued before any arithmetic that needs it
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
@@ -627,6 +638,14 @@ __global__ __launch_bounds__(256) void surrogate_a_kernel(PointGeom pg, const Sr
         }
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
+            if (still[u]) {
+                if (valid[u]) {
+                    if (tout) tout[local[u]] = __builtin_nanf("");
+                    if (beta) beta[local[u]] = 1.0f - kXmax - 0.0f;
+                }
+                valid[u] = false;
+                continue;
+            }
             a[u] = as[local[u]];
             m[u] = am[local[u]];
             T0[u] = tin ? tin[local[u]] : 0.0f;
@@ -634,12 +653,14 @@ __global__ __launch_bounds__(256) void surrogate_a_kernel(PointGeom pg, const Sr
         // block-end temperature: independent of the loads above
 #pragma unroll
         for (int u = 0; u < PPT; ++u)
-            TK[u] = scan_temperature<W>(tab + K * W, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min, pg.roff);
-        if (!tin) {
+            if (!still[u])
+                TK[u] = scan_temperature<W>(tab + K * W, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min, pg.roff);
+        // block start: computed in the first block of a call, and where the
+        // previous block left no value (NaN)
 #pragma unroll
-            for (int u = 0; u < PPT; ++u)
+        for (int u = 0; u < PPT; ++u)
+            if (!still[u] && (!tin || T0[u] != T0[u]))
                 T0[u] = scan_temperature<W>(tab, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min, pg.roff);
-        }
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
             if (valid[u]) {
@@ -651,7 +672,7 @@ __global__ __launch_bounds__(256) void surrogate_a_kernel(PointGeom pg, const Sr
         }
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
-            float pa = 0.0f, pm = 0.0f;
+            float pa = 0.0f, pm = 0.0f, fa = 0.0f, fm = 0.0f;
             bool need = false;
             if (valid[u]) {
                 float an = a[u], mn = m[u], bn;
@@ -699,6 +720,8 @@ __global__ __launch_bounds__(256) void surrogate_a_kernel(PointGeom pg, const Sr
                 as[local[u]] = an;
                 am[local[u]] = mn;
                 if (beta) beta[local[u]] = bn;
+                fa = an;
+                fm = mn;
             }
             if (__ballot(need) != 0) {
                 unsigned slot = 0;
@@ -712,6 +735,12 @@ __global__ __launch_bounds__(256) void surrogate_a_kernel(PointGeom pg, const Sr
                 e[256 + lane] = m[u];
                 e[320 + lane] = pa;
                 e[384 + lane] = pm;
+            }
+            // rest flag of the wave after this block (a queued point is
+            // corrected by pass B and does not count as at rest)
+            if (env.below && !still[u] && wv[u] < env.n_waves) {
+                const bool r = __ballot(valid[u] && !(rest_bits(fa, fm) && !need)) == 0;
+                if (lane == 0) env.rest[wv[u]] = r ? 1 : 0;
             }
         }
     }
@@ -788,8 +817,8 @@ hipError_t surrogate_prepare(MlpState& s, int64_t points, hipStream_t st) {
     return hipGetLastError();
 }
 
-hipError_t launch_surrogate(const MlpState& s, const PointGeom& pg, int W, const SrcRec* tab, int K, float dt,
-                            ScanArgs sa, float* beta, float* as, float* am, int64_t block, bool first_block,
+hipError_t launch_surrogate(const MlpState& s, const PointGeom& pg, int W, const SrcRec* tab, EnvSet env, int K,
+                            float dt, ScanArgs sa, float* beta, float* as, float* am, int64_t block, bool first_block,
                             bool last_block, hipStream_t st) {
     const float* tin = first_block ? nullptr : s.tcache + (block & 1) * s.tcache_n;
     float* tout = last_block ? nullptr : s.tcache + ((block + 1) & 1) * s.tcache_n;
@@ -802,10 +831,10 @@ hipError_t launch_surrogate(const MlpState& s, const PointGeom& pg, int W, const
     const int64_t cap = (int64_t)s.cu_count * SURROGATE_BLOCKS_PER_CU;
     const dim3 grid((unsigned)(cap > 0 && cap < n_chunks ? cap : n_chunks)), blk(256);
     switch (W) {
-        case 1: hipLaunchKernelGGL((surrogate_a_kernel<1, P>), grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, tout, n_chunks); break;
-        case 2: hipLaunchKernelGGL((surrogate_a_kernel<2, P>), grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, tout, n_chunks); break;
-        case 3: hipLaunchKernelGGL((surrogate_a_kernel<3, P>), grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, tout, n_chunks); break;
-        case 4: hipLaunchKernelGGL((surrogate_a_kernel<4, P>), grid, blk, 0, st, pg, tab, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, tout, n_chunks); break;
+        case 1: hipLaunchKernelGGL((surrogate_a_kernel<1, P>), grid, blk, 0, st, pg, tab, env, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, tout, n_chunks); break;
+        case 2: hipLaunchKernelGGL((surrogate_a_kernel<2, P>), grid, blk, 0, st, pg, tab, env, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, tout, n_chunks); break;
+        case 3: hipLaunchKernelGGL((surrogate_a_kernel<3, P>), grid, blk, 0, st, pg, tab, env, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, tout, n_chunks); break;
+        case 4: hipLaunchKernelGGL((surrogate_a_kernel<4, P>), grid, blk, 0, st, pg, tab, env, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, tout, n_chunks); break;
         default: return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();

@@ -315,15 +315,21 @@ def _cold_cases():
     return cases
 
 
-@pytest.mark.parametrize("mode", ["plain", "implicit"])
+@pytest.mark.parametrize("mode", ["plain", "implicit", "surrogate"])
 def test_cold_waves_skip_is_bit_exact(torch, ctx, mode):
-    """Fused PLAIN and IMPLICIT runs give the same bits with the launch
-    certificates on (default: cold waves take T = T0, waves at rest below
-    935 K skip the launch) and off (every temperature evaluated), on scans
+    """Fused PLAIN, IMPLICIT and SURROGATE runs give the same bits with the
+    launch certificates on (default: cold waves take T = T0, waves at rest
+    below 935 K skip the launch) and off (every temperature evaluated), on scans
     with windows of 2 and 4 tracks, an island scan, a masked grid, a body
     preheated to 1250 K and bodies at 920 and 934 K."""
     import paper_2402_17580_amd as ms
-    m = ms.MODE_PLAIN if mode == "plain" else ms.MODE_IMPLICIT
+    m = {"plain": ms.MODE_PLAIN, "implicit": ms.MODE_IMPLICIT, "surrogate": ms.MODE_SURROGATE}[mode]
+    K = 16
+    if mode == "surrogate":  # the shipped K = 8 network (pass A uses the wave flags)
+        from paper_2402_17580_amd import surrogate as S
+        sur = S.Surrogate.load(S.DEFAULT_WEIGHTS)
+        sur.load_into(ctx)
+        K = sur.K
     cases = _cold_cases()
     wl0 = workload.island_scan(96, 64, 24, n_layers=3, layer_thick=20e-6, steps_per_layer=300, dt=2e-6,
                                seed=77, island=0.5e-3)
@@ -337,7 +343,7 @@ def test_cold_waves_skip_is_bit_exact(torch, ctx, mode):
             for skip in (1, 0):
                 ctx.set_option(ms.OPTION_SKIP_COLD_WAVES, skip)
                 g = [torch.from_numpy(x).cuda() for x in workload.initial_state(wl.grid.n, np.float32)]
-                ms.run_layers(ctx, wl, *g, K=16, mode=m, index=index)
+                ms.run_layers(ctx, wl, *g, K=K, mode=m, index=index)
                 outs.append([x.cpu().numpy() for x in g])
             for x, y in zip(*outs):
                 assert np.array_equal(x.view(np.uint32), y.view(np.uint32)), (name, mode)
