@@ -474,16 +474,16 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
     const size_t env_cap = (size_t)n_launches * (W + K + 1);
     // (first, count) of each launch's envelopes, as int32 pairs after them
     const size_t fc_recs = ((size_t)n_launches * 2 * sizeof(int32_t) + sizeof(SrcRec) - 1) / sizeof(SrcRec);
-    // Wave flags on box grids (one point per lane, 64 per wave): still flags
-    // for chunks of launches from a box pre-pass, rest flags kept by the
-    // fused kernels and surrogate pass A.  Not with the tracked X~beta, whose
+    // Wave flags on box grids (one point per lane, 64 per wave): rest flags
+    // kept by the fused kernels and surrogate pass A, pass A's tcached
+    // flags, then still flags for chunks of launches from a box pre-pass.  Not with the tracked X~beta, whose
     // store every launch takes.
     const bool wave_flags = ctx->skip_cold && !ph->xbt && !pts->index;
     const int64_t n_waves = (pg.count + kWave - 1) / kWave;
     int64_t chunk = kWaveFlagBudget / n_waves;
     chunk = chunk < 1 ? 1 : (chunk > n_launches ? n_launches : chunk);
     if (wave_flags) {
-        const size_t need = (size_t)n_waves * (size_t)(1 + chunk);
+        const size_t need = (size_t)n_waves * (size_t)(2 + chunk);
         if (ctx->wave_flags_cap < need) {
             HIP_CHECK(ctx, hipStreamSynchronize(st));
             if (ctx->wave_flags) HIP_CHECK(ctx, hipFree(ctx->wave_flags));
@@ -529,11 +529,11 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
         const int64_t li = s0 / K;
         uint8_t* below = nullptr;
         if (wave_flags) {
-            below = ctx->wave_flags + n_waves * (1 + li % chunk);
+            below = ctx->wave_flags + n_waves * (2 + li % chunk);
             if (li % chunk == 0) {
                 const int64_t nl = (n_launches - li) < chunk ? (n_launches - li) : chunk;
                 e = launch_still_flags(pg, env_dev, fc_dev, li, nl, n_waves, fminf(sa.T0, sa.Tclamp),
-                                       ctx->wave_flags + n_waves, st);
+                                       ctx->wave_flags + 2 * n_waves, st);
                 if (e != hipSuccess) {
                     (void)release_slot(ctx, s, st);
                     return hip_fail(ctx, e, "still flags launch");
@@ -541,7 +541,8 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
             }
         }
         const EnvSet es{env_dev + env_first[li], ctx->skip_cold ? env_count[li] : -1, below,
-                        wave_flags ? ctx->wave_flags : nullptr, n_waves, li > 0};
+                        wave_flags ? ctx->wave_flags : nullptr, n_waves, li > 0,
+                        wave_flags && mode == MSTRUCT_MODE_SURROGATE ? ctx->wave_flags + n_waves : nullptr};
         if (mode == MSTRUCT_MODE_PLAIN) {
             e = launch_fused_plain(pg, W, s->dev + s0 * W, es, Kb, (float)dt, sa, beta, ph->alpha_s, ph->alpha_m,
                                    ph->xbt, st);

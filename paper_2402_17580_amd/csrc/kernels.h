@@ -62,6 +62,9 @@ struct EnvSet {
     uint8_t* rest;
     int64_t n_waves;
     int32_t read_rest;
+    // surrogate pass A only: tcached[w] != 0 when the previous block left
+    // wave w's block-end temperatures in the cache (a still group leaves none)
+    uint8_t* tcached;
 };
 
 // points per wave of the fused kernels (one point per lane)

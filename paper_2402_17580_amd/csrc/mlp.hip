@@ -616,8 +616,8 @@ __global__ __launch_bounds__(256) void surrogate_a_kernel(PointGeom pg, const Sr
         // 64 points of a wave whose flags say still (at rest, below 935 K
         // through the block): every branch below would leave them as they
         // are and write beta = 1 - 0.9 - 0, and none would be queued; only
-        // the block-end temperature is not computed (NaN in the cache makes
-        // the next block compute its start temperature, the same value)
+        // the block-end temperature is not computed (the wave's tcached byte
+        // makes the next block compute its start temperature, the same value)
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
             wv[u] = chunk * (256 * PPT / 64) + wib + u * (256 / 64);
@@ -639,10 +639,7 @@ __global__ __launch_bounds__(256) void surrogate_a_kernel(PointGeom pg, const Sr
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
             if (still[u]) {
-                if (valid[u]) {
-                    if (tout) tout[local[u]] = __builtin_nanf("");
-                    if (beta) beta[local[u]] = 1.0f - kXmax - 0.0f;
-                }
+                if (valid[u] && beta) beta[local[u]] = 1.0f - kXmax - 0.0f;
                 valid[u] = false;
                 continue;
             }
@@ -656,10 +653,10 @@ __global__ __launch_bounds__(256) void surrogate_a_kernel(PointGeom pg, const Sr
             if (!still[u])
                 TK[u] = scan_temperature<W>(tab + K * W, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min, pg.roff);
         // block start: computed in the first block of a call, and where the
-        // previous block left no value (NaN)
+        // previous block left no value
 #pragma unroll
         for (int u = 0; u < PPT; ++u)
-            if (!still[u] && (!tin || T0[u] != T0[u]))
+            if (!still[u] && (!tin || (env.tcached && wv[u] < env.n_waves && !env.tcached[wv[u]])))
                 T0[u] = scan_temperature<W>(tab, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min, pg.roff);
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
@@ -669,6 +666,7 @@ __global__ __launch_bounds__(256) void surrogate_a_kernel(PointGeom pg, const Sr
                 a[u] = m[u] = 0.0f;
                 T0[u] = TK[u] = sa.T0;
             }
+            if (tout && env.tcached && wv[u] < env.n_waves && lane == 0) env.tcached[wv[u]] = still[u] ? 0 : 1;
         }
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
