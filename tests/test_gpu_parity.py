@@ -315,6 +315,41 @@ def _cold_cases():
     return cases
 
 
+def test_wave_flags_follow_changes_between_calls(torch, ctx):
+    """The rest flags of the wave flags live in the context; a call must not
+    trust them from an earlier one.  Between the layers of a block scan the
+    state of points far from the scan is changed from at rest (alpha_s =
+    0.9) to a transformed state and back, and of some waves only one point;
+    the results stay the same bit for bit as with every step taken."""
+    import paper_2402_17580_amd as ms
+    wl = workload.multilayer_block(nx=64, ny=64, nz=24, n_layers=3, steps_per_layer=600, seed=5)
+    n = wl.grid.n
+    far = np.arange(n - 64 * 64 * 4, n)  # the bottom planes, far below the scanned layers
+    one = np.arange(n - 64 * 64 * 8, n - 64 * 64 * 4, 64 * 3)  # one point in every third wave
+    outs = []
+    try:
+        for skip in (1, 0):
+            ctx.set_option(ms.OPTION_SKIP_COLD_WAVES, skip)
+            g = [torch.from_numpy(x).cuda() for x in workload.initial_state(n, np.float32)]
+            for i, layer in enumerate(wl.layers):
+                ms.run_layers(ctx, wl, *g, K=16, layers=[layer])
+                if i == 1 and skip:  # the points set to the transformed state were stepped
+                    stepped = g[2][torch.from_numpy(far).cuda()].cpu().numpy()
+                idx = torch.from_numpy(np.concatenate([far, one])).cuda()
+                if i % 2 == 0:  # beta 0.3, alpha_s 0.6, alpha_m 0.1: at 300 K beta turns to martensite
+                    g[1][idx] = 0.6
+                    g[2][idx] = 0.1
+                else:  # back to at rest
+                    g[1][idx] = 0.9
+                    g[2][idx] = 0.0
+            outs.append([x.cpu().numpy() for x in g])
+    finally:
+        ctx.set_option(ms.OPTION_SKIP_COLD_WAVES, 1)
+    for x, y in zip(*outs):
+        assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
+    assert np.all(stepped > np.float32(0.2))  # the correction at 300 K formed martensite from beta
+
+
 @pytest.mark.parametrize("mode", ["plain", "implicit", "surrogate"])
 def test_cold_waves_skip_is_bit_exact(torch, ctx, mode):
     """Fused PLAIN, IMPLICIT and SURROGATE runs give the same bits with the
