@@ -5,8 +5,9 @@ MI355X.
 One benchmark step = one whole run of the workload from the initial state
 through every layer (all 20,000 time steps; 150,077,440,000 active
 point-updates) with the temperature evaluated from the scan inside the fused
-kernel (K = 16 steps per launch).  `value` is the plain float32 path; the
-`surrogate` entry is the same workload with the learned surrogate (K = 8).
+kernel (K = 64 steps per launch).  `value` is the plain float32 path; the
+`surrogate` entries are the same workload with the learned surrogate (K = 8
+and K = 16 networks).
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -30,18 +31,22 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 # VALU ceiling in lane-ops: the FP32 vector peak counts 2 FLOPs per FMA lane-op,
 # i.e. 256 CUs x 128 lane-ops/clock x 2.4 GHz = 78.6 T lane-ops/s
 VALU_PEAK_TLANEOPS = FP32_VECTOR_PEAK_TFLOPS / 2
-K_FUSED = 16
+K_FUSED = 64
 K_SURROGATE = 8
 STEP_BYTES = 28  # plain step: reads alpha_s, alpha_m, T^n, T^{n+1}; writes beta, alpha_s, alpha_m (float32)
 
 
-def fused_bytes_per_point(launches, calls, read, written):
-    """Algorithmic HBM bytes per active point and fused launch: alpha_s,
-    alpha_m are read (8 B) for the fraction `read` of the points whose wave
-    does not exit on its flags, and written (8 B) for the fraction `written`
-    whose wave is not still; the last launch of each call also writes beta
-    (4 B)."""
-    return 8.0 * read + 8.0 * written + 4.0 * calls / launches
+def fused_bytes_per_launch(wl, K, read, written):
+    """Algorithmic HBM bytes per fused launch, averaged over the run: alpha_s,
+    alpha_m are read (8 B) for the fraction `read` of the active points whose
+    wave does not exit on its flags, and written (8 B) for the fraction
+    `written` whose wave is not still; the last launch of each call (one per
+    layer) also writes beta (4 B per active point)."""
+    g = wl.grid
+    pts = [(g.nz - g.first_active_k(L.z_top)) * g.nx * g.ny for L in wl.layers]
+    launches = [math.ceil((L.step_end - L.step_begin) / K) for L in wl.layers]
+    state = sum(n * p for n, p in zip(launches, pts)) * (8.0 * read + 8.0 * written)
+    return (state + 4.0 * sum(pts)) / sum(launches)
 
 
 def parse():
@@ -114,8 +119,8 @@ def main():
     # kernel is the only kernel in it besides three state resets per step)
     avg_launch_s = ms_total * 1e-3 / (args.steps * launches)
     upd_per_launch = updates / launches
-    bytes_per_launch = fused_bytes_per_point(launches, len(wl.layers), FUSED_PROFILE["read_fraction"],
-                                             FUSED_PROFILE["written_fraction"]) * upd_per_launch / args.K
+    bytes_per_launch = fused_bytes_per_launch(wl, args.K, FUSED_PROFILE["read_fraction"],
+                                              FUSED_PROFILE["written_fraction"])
 
     result = {
         "metric": "microstructure point-updates/s @8.4M pts (256x256x128 block, 10 layers, 20k steps): FP32 plain",
@@ -240,15 +245,15 @@ def main():
 # HBM bytes per launch (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0: the factors a
 # plain 1 GiB device copy reads on the same counters), and the fractions of
 # the points whose state the kernel reads (waves that do not exit on their
-# flags) and writes (waves that are not still), at K = 16.
+# flags) and writes (waves that are not still), at K = 64.
 # the same kernel with every temperature evaluated (MSTRUCT_OPTION_SKIP_COLD_WAVES = 0)
-FUSED_PROFILE_EVERY_T = {"valu_lane_ops_per_update": 135.58}
+FUSED_PROFILE_EVERY_T = {"valu_lane_ops_per_update": 128.07}
 FUSED_PROFILE = {
-    "valu_lane_ops_per_update": 11.03,
-    "fp32_flops_per_update": 8.58,
-    "traffic_bytes_per_launch": (2658.51 * 2.0 + 2724.55) * 1024,
-    "read_fraction": 0.0907,
-    "written_fraction": 0.0425,
+    "valu_lane_ops_per_update": 10.19,
+    "fp32_flops_per_update": 8.30,
+    "traffic_bytes_per_launch": (3361.80 * 2.0 + 3472.90) * 1024,
+    "read_fraction": 0.1147,
+    "written_fraction": 0.0436,
 }
 
 def bench_stepwise(torch, ms, ctx, wl, dev):
