@@ -72,7 +72,7 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; the multi-GPU path is a design note only",
+        print(json.dumps({"error": "this implementation runs on one GPU; the multi-GPU path is a design note only",
                           "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
