@@ -251,9 +251,9 @@ FUSED_PROFILE_EVERY_T = {"valu_lane_ops_per_update": 128.07}
 FUSED_PROFILE = {
     "valu_lane_ops_per_update": 10.19,
     "fp32_flops_per_update": 8.30,
-    "traffic_bytes_per_launch": (3361.80 * 2.0 + 3472.90) * 1024,
-    "read_fraction": 0.1147,
-    "written_fraction": 0.0436,
+    "traffic_bytes_per_launch": (3359.98 * 2.0 + 3477.09) * 1024,
+    "read_fraction": 0.1146,
+    "written_fraction": 0.0437,
 }
 
 def bench_stepwise(torch, ms, ctx, wl, dev):
