@@ -7,9 +7,16 @@
 namespace mstruct {
 
 constexpr int kBlock = 256;
-// workgroup of the fused kernels: two waves, so that the few waves that step
-// in a launch spread over more CUs (6 % faster than four on the block scan)
-constexpr int kFusedBlock = 128;
+// workgroup of the fused kernels
+constexpr int kFusedBlock = 256;
+// wave slots per wave of the persistent fused kernels (see fused_slots),
+// and the launch size (in waves) from which they run in workgroups of four
+// waves instead of two: on large, mostly still grids the occupancy of four
+// pays (island block, 1M waves: 2.2 s against 2.7 s), on smaller ones two
+// spread the waves that step over more CUs (block scan, 131k waves: 9 %
+// faster)
+constexpr int kSlotsPerWave = 4;
+constexpr int64_t kSlotsLargeGrid = (int64_t)1 << 18;
 #ifndef FUSED_PPT
 #define FUSED_PPT 1
 #endif
@@ -257,9 +264,40 @@ __device__ __forceinline__ int64_t fused_wave() {
 // A wave whose flags say still (wave_flag_still): its state is at rest and
 // stays as it is, so only beta (last launch of a call) is written, with the
 // value every step would give.
-__device__ __forceinline__ void still_wave_beta(const PointGeom& pg, float T0c, float* beta) {
-    const int64_t g = (int64_t)blockIdx.x * kFusedBlock + threadIdx.x;
+__device__ __forceinline__ void still_wave_beta(const PointGeom& pg, float T0c, float* beta, int64_t g) {
     if (beta && g < pg.count) beta[pg.first + g] = solid_fraction(T0c) - kXmax - 0.0f;
+}
+
+// The persistent form of a fused launch, used from the second launch of a
+// call when the wave flags are kept: a grid of about one wave per
+// kSlotsPerWave waves of the launch, in which wave p takes the wave slots p,
+// p + P, p + 2P, ... (P waves in the grid).  Each lane loads the flags of
+// one slot; the wave then runs body(w) for every slot w that is not still
+// (all 64 lanes, one point each) and writes beta for the still ones.  No
+// wave is launched only to find its flags set, and the interleaved slots
+// spread the few waves that step evenly over the grid.
+template <int BS, class Body>
+__device__ __forceinline__ void fused_slots(const PointGeom& pg, const EnvSet& env, float T0c, float* beta,
+                                            Body body) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t P = (int64_t)gridDim.x * (BS / kWave);
+    const int64_t p = (int64_t)blockIdx.x * (BS / kWave) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    for (int64_t r = 0; p + r * kWave * P < env.n_waves; ++r) {
+        const int64_t w = p + (r * kWave + lane) * P;
+        const bool in = w < env.n_waves;
+        const bool still = in && env.below[w] && env.rest[w];
+        uint64_t todo = __ballot(in && !still), quiet = beta ? __ballot(still) : 0;
+        while (todo) {
+            const int i = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            body(p + (r * kWave + i) * P);
+        }
+        while (quiet) {
+            const int i = __builtin_ctzll(quiet);
+            quiet &= quiet - 1;
+            still_wave_beta(pg, T0c, beta, (p + (r * kWave + i) * P) * kWave + lane);
+        }
+    }
 }
 
 // record whether every point of the wave is at rest after the launch
@@ -274,21 +312,17 @@ __device__ __forceinline__ void record_rest(const EnvSet& env, int64_t wv, bool 
 // held in registers (with compensated Euler accumulation); tab holds the
 // K + 1 time points x W window slots of this launch.
 // ---------------------------------------------------------------------------
+// The points g0 + u kFusedBlock (u < PPT) of the calling lane; wv is the
+// wave of the points for PPT = 1.  beta == nullptr: not written (inside a
+// call only the last launch writes it; no kernel reads beta, it follows from
+// the sum rule).
 template <int W, int PPT, bool TRACK>
-__global__ __launch_bounds__(kFusedBlock) void fused_plain_kernel(PointGeom pg, const SrcRec* __restrict__ tab,
-                                                            EnvSet env, int K, float dt, ScanArgs sa,
-                                                            float* __restrict__ beta, float* __restrict__ as,
-                                                            float* __restrict__ am, double* __restrict__ xbv) {
-    // beta == nullptr: not written (inside a call only the last launch writes
-    // it; no kernel reads beta, it follows from the sum rule)
-    // PPT points per lane, kFusedBlock apart (coalesced), advanced together for ILP
+__device__ __forceinline__ void fused_plain_body(const PointGeom& pg, const SrcRec* __restrict__ tab,
+                                                 const EnvSet& env, int K, float dt, const ScanArgs& sa,
+                                                 float* __restrict__ beta, float* __restrict__ as,
+                                                 float* __restrict__ am, double* __restrict__ xbv, int64_t g0,
+                                                 int64_t wv) {
     const float T0c = fminf(sa.T0, sa.Tclamp);
-    const int64_t wv = fused_wave();
-    if (PPT == 1 && !TRACK && wave_flag_still(env, wv)) {
-        still_wave_beta(pg, T0c, beta);
-        return;
-    }
-    const int64_t g0 = (int64_t)blockIdx.x * kFusedBlock * PPT + threadIdx.x;
     int64_t local[PPT];
     int gi[PPT], gj[PPT], gk[PPT];
     bool act[PPT];
@@ -357,6 +391,33 @@ __global__ __launch_bounds__(kFusedBlock) void fused_plain_kernel(PointGeom pg, 
     if (PPT == 1 && !TRACK) record_rest(env, wv, act[0], a[0] + alo[0], m[0] + mlo[0]);
 }
 
+// PPT points per lane, kFusedBlock apart (coalesced), advanced together for ILP
+template <int W, int PPT, bool TRACK>
+__global__ __launch_bounds__(kFusedBlock) void fused_plain_kernel(PointGeom pg, const SrcRec* __restrict__ tab,
+                                                                  EnvSet env, int K, float dt, ScanArgs sa,
+                                                                  float* __restrict__ beta, float* __restrict__ as,
+                                                                  float* __restrict__ am, double* __restrict__ xbv) {
+    const int64_t wv = fused_wave();
+    if (PPT == 1 && !TRACK && wave_flag_still(env, wv)) {
+        still_wave_beta(pg, fminf(sa.T0, sa.Tclamp), beta, (int64_t)blockIdx.x * kFusedBlock + threadIdx.x);
+        return;
+    }
+    fused_plain_body<W, PPT, TRACK>(pg, tab, env, K, dt, sa, beta, as, am, xbv,
+                                    (int64_t)blockIdx.x * kFusedBlock * PPT + threadIdx.x, wv);
+}
+
+template <int W, int BS>
+__global__ __launch_bounds__(BS) void fused_plain_slots_kernel(PointGeom pg, const SrcRec* __restrict__ tab,
+                                                                        EnvSet env, int K, float dt, ScanArgs sa,
+                                                                        float* __restrict__ beta,
+                                                                        float* __restrict__ as,
+                                                                        float* __restrict__ am) {
+    const int lane = threadIdx.x & (kWave - 1);
+    fused_slots<BS>(pg, env, fminf(sa.T0, sa.Tclamp), beta, [&](int64_t w) {
+        fused_plain_body<W, 1, false>(pg, tab, env, K, dt, sa, beta, as, am, nullptr, w * kWave + lane, w);
+    });
+}
+
 // ---------------------------------------------------------------------------
 // fused K steps with the implicit scheme: as the plain fused kernel, with the
 // Crank-Nicolson fixed-point step at every step (n_sub equal substeps of
@@ -365,19 +426,14 @@ __global__ __launch_bounds__(kFusedBlock) void fused_plain_kernel(PointGeom pg, 
 // inside a launch as in the plain fused kernel.
 // ---------------------------------------------------------------------------
 template <int W, bool TRACK>
-__global__ __launch_bounds__(kFusedBlock) void fused_implicit_kernel(PointGeom pg, const SrcRec* __restrict__ tab,
-                                                               EnvSet env, int K, float h, int n_sub, int max_iter,
-                                                               ScanArgs sa,
-                                                               float* __restrict__ beta, float* __restrict__ as,
-                                                               float* __restrict__ am, double* __restrict__ xbv,
-                                                               unsigned long long* __restrict__ unconverged) {
+__device__ __forceinline__ void fused_implicit_body(const PointGeom& pg, const SrcRec* __restrict__ tab,
+                                                    const EnvSet& env, int K, float h, int n_sub, int max_iter,
+                                                    const ScanArgs& sa, float* __restrict__ beta,
+                                                    float* __restrict__ as, float* __restrict__ am,
+                                                    double* __restrict__ xbv,
+                                                    unsigned long long* __restrict__ unconverged, int64_t g,
+                                                    int64_t wv) {
     const float T0c = fminf(sa.T0, sa.Tclamp);
-    const int64_t wv = fused_wave();
-    if (!TRACK && wave_flag_still(env, wv)) {  // see fused_plain_kernel
-        still_wave_beta(pg, T0c, beta);
-        return;
-    }
-    const int64_t g = (int64_t)blockIdx.x * kFusedBlock + threadIdx.x;
     bool act = g < pg.count;
     const int64_t local = pg.first + (act ? g : 0);
     int gi, gj, gk;
@@ -425,6 +481,34 @@ __global__ __launch_bounds__(kFusedBlock) void fused_implicit_kernel(PointGeom p
     if ((threadIdx.x & 63) == 0 && total) atomicAdd(unconverged, (unsigned long long)total);
 }
 
+template <int W, bool TRACK>
+__global__ __launch_bounds__(kFusedBlock) void fused_implicit_kernel(PointGeom pg, const SrcRec* __restrict__ tab,
+                                                                     EnvSet env, int K, float h, int n_sub,
+                                                                     int max_iter, ScanArgs sa,
+                                                                     float* __restrict__ beta, float* __restrict__ as,
+                                                                     float* __restrict__ am, double* __restrict__ xbv,
+                                                                     unsigned long long* __restrict__ unconverged) {
+    const int64_t wv = fused_wave();
+    const int64_t g = (int64_t)blockIdx.x * kFusedBlock + threadIdx.x;
+    if (!TRACK && wave_flag_still(env, wv)) {  // see fused_plain_kernel
+        still_wave_beta(pg, fminf(sa.T0, sa.Tclamp), beta, g);
+        return;
+    }
+    fused_implicit_body<W, TRACK>(pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, xbv, unconverged, g, wv);
+}
+
+template <int W, int BS>
+__global__ __launch_bounds__(BS) void fused_implicit_slots_kernel(
+    PointGeom pg, const SrcRec* __restrict__ tab, EnvSet env, int K, float h, int n_sub, int max_iter, ScanArgs sa,
+    float* __restrict__ beta, float* __restrict__ as, float* __restrict__ am,
+    unsigned long long* __restrict__ unconverged) {
+    const int lane = threadIdx.x & (kWave - 1);
+    fused_slots<BS>(pg, env, fminf(sa.T0, sa.Tclamp), beta, [&](int64_t w) {
+        fused_implicit_body<W, false>(pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, nullptr, unconverged,
+                                      w * kWave + lane, w);
+    });
+}
+
 template <bool TRACK>
 static hipError_t fused_implicit_w(const PointGeom& pg, int W, const SrcRec* tab, EnvSet env, int K, float h,
                                    int n_sub, int max_iter, ScanArgs sa, float* beta, float* as, float* am, double* xb,
@@ -440,10 +524,36 @@ static hipError_t fused_implicit_w(const PointGeom& pg, int W, const SrcRec* tab
     return hipGetLastError();
 }
 
+// grid of the persistent (slot) fused kernels in workgroups of bs threads:
+// one wave per kSlotsPerWave waves of the launch
+static dim3 slots_grid(int64_t n_waves, int bs) {
+    const int64_t waves = (n_waves + kSlotsPerWave - 1) / kSlotsPerWave;
+    return dim3((unsigned)((waves + bs / kWave - 1) / (bs / kWave)));
+}
+
+// launch a slot kernel instantiated for workgroups of 128 and 256 threads
+#define LAUNCH_SLOTS(kernel, W, n_waves, st, ...)                                                          \
+    do {                                                                                                    \
+        if ((n_waves) >= kSlotsLargeGrid)                                                                   \
+            hipLaunchKernelGGL((kernel<W, 256>), slots_grid(n_waves, 256), dim3(256), 0, st, __VA_ARGS__); \
+        else                                                                                                \
+            hipLaunchKernelGGL((kernel<W, 128>), slots_grid(n_waves, 128), dim3(128), 0, st, __VA_ARGS__); \
+    } while (0)
+
 hipError_t launch_fused_implicit(const PointGeom& pg, int W, const SrcRec* tab, EnvSet env, int K, float h, int n_sub,
                                  int max_iter, ScanArgs sa, float* beta, float* as, float* am, double* xb,
                                  unsigned long long* unconverged, hipStream_t st) {
     if (pg.count <= 0) return hipSuccess;
+    if (!xb && env.below && env.read_rest) {
+        switch (W) {
+            case 1: LAUNCH_SLOTS(fused_implicit_slots_kernel, 1, env.n_waves, st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
+            case 2: LAUNCH_SLOTS(fused_implicit_slots_kernel, 2, env.n_waves, st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
+            case 3: LAUNCH_SLOTS(fused_implicit_slots_kernel, 3, env.n_waves, st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
+            case 4: LAUNCH_SLOTS(fused_implicit_slots_kernel, 4, env.n_waves, st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     return xb ? fused_implicit_w<true>(pg, W, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, xb, unconverged, st)
               : fused_implicit_w<false>(pg, W, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, xb, unconverged, st);
 }
@@ -481,6 +591,16 @@ static hipError_t fused_plain_w(const PointGeom& pg, int W, const SrcRec* tab, E
 hipError_t launch_fused_plain(const PointGeom& pg, int W, const SrcRec* tab, EnvSet env, int K, float dt, ScanArgs sa,
                               float* beta, float* as, float* am, double* xb, hipStream_t st) {
     if (pg.count <= 0) return hipSuccess;
+    if (kFusedPPT == 1 && !xb && env.below && env.read_rest) {
+        switch (W) {
+            case 1: LAUNCH_SLOTS(fused_plain_slots_kernel, 1, env.n_waves, st, pg, tab, env, K, dt, sa, beta, as, am); break;
+            case 2: LAUNCH_SLOTS(fused_plain_slots_kernel, 2, env.n_waves, st, pg, tab, env, K, dt, sa, beta, as, am); break;
+            case 3: LAUNCH_SLOTS(fused_plain_slots_kernel, 3, env.n_waves, st, pg, tab, env, K, dt, sa, beta, as, am); break;
+            case 4: LAUNCH_SLOTS(fused_plain_slots_kernel, 4, env.n_waves, st, pg, tab, env, K, dt, sa, beta, as, am); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     return xb ? fused_plain_w<true>(pg, W, tab, env, K, dt, sa, beta, as, am, xb, st)
               : fused_plain_w<false>(pg, W, tab, env, K, dt, sa, beta, as, am, xb, st);
 }
