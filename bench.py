@@ -143,7 +143,8 @@ def main():
     rate = upd_per_launch / avg_launch_s  # point-updates/s inside one launch
     ops = FUSED_PROFILE["valu_lane_ops_per_update"]
     result["roofline"] = {
-        "kernel": f"fused_plain_kernel<{wl.scan.window}>",
+        "kernel": f"fused_plain_kernel<{wl.scan.window}> (first launch of each call) + "
+                  f"fused_plain_slots_kernel<{wl.scan.window}> (the others)",
         "bound": "alu",
         "achieved": rate * ops / 1e12,
         "peak": VALU_PEAK_TLANEOPS,
@@ -249,10 +250,10 @@ def main():
 # the same kernel with every temperature evaluated (MSTRUCT_OPTION_SKIP_COLD_WAVES = 0)
 FUSED_PROFILE_EVERY_T = {"valu_lane_ops_per_update": 128.07}
 FUSED_PROFILE = {
-    "valu_lane_ops_per_update": 10.19,
-    "fp32_flops_per_update": 8.30,
-    "traffic_bytes_per_launch": (3359.98 * 2.0 + 3477.09) * 1024,
-    "read_fraction": 0.1146,
+    "valu_lane_ops_per_update": 10.21,
+    "fp32_flops_per_update": 8.31,
+    "traffic_bytes_per_launch": (3363.40 * 2.0 + 3476.92) * 1024,
+    "read_fraction": 0.1147,
     "written_fraction": 0.0437,
 }
 
