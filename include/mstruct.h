@@ -212,13 +212,13 @@ int mstruct_fused_scan_steps(mstruct_ctx *ctx, const mstruct_scan *scan, const m
  * step and no store of alpha_s, alpha_m.  (2) A wave whose points drop every
  * term of every track by the drop test of the temperature model (a term
  * provably below 1e-4 K is dropped) has T = T0 throughout and skips the
- * evaluation of the sources.  On a box grid (no index list) without xbt,
- * each call also bounds the box of every 64 consecutive points against
+ * evaluation of the sources.  Without xbt, each call also bounds the box
+ * of every 64 consecutive points (of the box, or of the index list) against
  * every launch's tracks in a pre-pass, and the context remembers which such
  * waves were at rest: from the second launch of a call such a wave reads
- * neither its state nor a track.  For this the context keeps n/64 bytes
- * plus at most 64 MiB of still flags per call on the device, until
- * mstruct_destroy.  The results are the same bit for bit as with 0, which
+ * neither its state nor a track.  For this the context keeps 2 n/64 bytes
+ * (and 24 n/64 bytes of boxes with an index list) plus at most 64 MiB of
+ * still flags per call on the device, until mstruct_destroy.  The results are the same bit for bit as with 0, which
  * evaluates every temperature and takes every step (for comparison). */
 enum { MSTRUCT_OPTION_SKIP_COLD_WAVES = 1 };
 int mstruct_set_option(mstruct_ctx *ctx, int option, int value);

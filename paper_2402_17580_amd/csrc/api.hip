@@ -39,6 +39,9 @@ struct mstruct_ctx {
     // flags of a chunk of launches
     uint8_t* wave_flags = nullptr;
     size_t wave_flags_cap = 0;
+    // the box of each wave of a call on an index list
+    GridBox* wave_boxes = nullptr;
+    size_t wave_boxes_cap = 0;
     MlpState mlp;
 };
 
@@ -365,6 +368,7 @@ int mstruct_destroy(mstruct_ctx* ctx) {
     if (ctx->counter) (void)hipFree(ctx->counter);
     if (ctx->implicit_bad) (void)hipFree(ctx->implicit_bad);
     if (ctx->wave_flags) (void)hipFree(ctx->wave_flags);
+    if (ctx->wave_boxes) (void)hipFree(ctx->wave_boxes);
     mlp_free(ctx->mlp);
     delete ctx;
     return MSTRUCT_OK;
@@ -474,11 +478,12 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
     const size_t env_cap = (size_t)n_launches * (W + K + 1);
     // (first, count) of each launch's envelopes, as int32 pairs after them
     const size_t fc_recs = ((size_t)n_launches * 2 * sizeof(int32_t) + sizeof(SrcRec) - 1) / sizeof(SrcRec);
-    // Wave flags on box grids (one point per lane, 64 per wave): rest flags
-    // kept by the fused kernels and surrogate pass A, pass A's tcached
-    // flags, then still flags for chunks of launches from a box pre-pass.  Not with the tracked X~beta, whose
-    // store every launch takes.
-    const bool wave_flags = ctx->skip_cold && !ph->xbt && !pts->index;
+    // Wave flags (one point per lane, 64 per wave): rest flags kept by the
+    // fused kernels and surrogate pass A, pass A's tcached flags, then still
+    // flags for chunks of launches from a box pre-pass (on an index list the
+    // boxes of the waves are computed first).  Not with the tracked X~beta,
+    // whose store every launch takes.
+    const bool wave_flags = ctx->skip_cold && !ph->xbt;
     const int64_t n_waves = (pg.count + kWave - 1) / kWave;
     int64_t chunk = kWaveFlagBudget / n_waves;
     chunk = chunk < 1 ? 1 : (chunk > n_launches ? n_launches : chunk);
@@ -494,6 +499,17 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
                 return fail(ctx, MSTRUCT_ENOMEM, "wave flag allocation failed");
             }
             ctx->wave_flags_cap = need;
+        }
+        if (pts->index && ctx->wave_boxes_cap < (size_t)n_waves) {
+            HIP_CHECK(ctx, hipStreamSynchronize(st));
+            if (ctx->wave_boxes) HIP_CHECK(ctx, hipFree(ctx->wave_boxes));
+            ctx->wave_boxes = nullptr;
+            ctx->wave_boxes_cap = 0;
+            if (hipMalloc((void**)&ctx->wave_boxes, (size_t)n_waves * sizeof(GridBox)) != hipSuccess) {
+                ctx->wave_boxes = nullptr;
+                return fail(ctx, MSTRUCT_ENOMEM, "wave box allocation failed");
+            }
+            ctx->wave_boxes_cap = (size_t)n_waves;
         }
     }
     TableSlot* s;
@@ -532,11 +548,15 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
             below = ctx->wave_flags + n_waves * (2 + li % chunk);
             if (li % chunk == 0) {
                 const int64_t nl = (n_launches - li) < chunk ? (n_launches - li) : chunk;
-                e = launch_still_flags(pg, env_dev, fc_dev, li, nl, n_waves, fminf(sa.T0, sa.Tclamp),
-                                       ctx->wave_flags + 2 * n_waves, st);
-                if (e != hipSuccess) {
+                const GridBox* boxes = pts->index ? ctx->wave_boxes : nullptr;
+                hipError_t fe = hipSuccess;
+                if (li == 0 && boxes) fe = launch_wave_boxes(pg, n_waves, ctx->wave_boxes, st);
+                if (fe == hipSuccess)
+                    fe = launch_still_flags(pg, env_dev, fc_dev, li, nl, n_waves, fminf(sa.T0, sa.Tclamp), boxes,
+                                            ctx->wave_flags + 2 * n_waves, st);
+                if (fe != hipSuccess) {
                     (void)release_slot(ctx, s, st);
-                    return hip_fail(ctx, e, "still flags launch");
+                    return hip_fail(ctx, fe, "still flags launch");
                 }
             }
         }

@@ -83,8 +83,14 @@ __device__ __forceinline__ bool wave_flag_still(const EnvSet& env, int64_t wv) {
 // still_flags for launches l0 .. l0 + nl - 1 of a call on a box grid:
 // flags[(l - l0) * n_waves + w] for wave w = points 64 w .. 64 w + 63 of pg;
 // env_fc holds (first record, count) of each launch's envelopes in env.
+// boxes: the box of each wave (launch_wave_boxes), or nullptr on a box grid
+// without an index list, where it follows from the wave's first and last point.
 hipError_t launch_still_flags(const PointGeom& pg, const EnvRec* env, const int32_t* env_fc, int64_t l0, int64_t nl,
-                              int64_t n_waves, float T0, uint8_t* flags, hipStream_t st);
+                              int64_t n_waves, float T0, const GridBox* boxes, uint8_t* flags, hipStream_t st);
+
+// boxes[w]: the box of grid positions of the points 64 w .. 64 w + 63 of pg
+// (any index list: the least and greatest coordinates of its points)
+hipError_t launch_wave_boxes(const PointGeom& pg, int64_t n_waves, GridBox* boxes, hipStream_t st);
 
 // xb: optional tracked X~beta side values (float64 per point), or nullptr
 hipError_t launch_step(const float* Tp, const float* Tn, float* beta, float* as, float* am, double* xb, int64_t n,

@@ -235,11 +235,12 @@ __device__ __forceinline__ GridBox wave_box(const PointGeom& pg, int64_t w) {
 __global__ __launch_bounds__(kBlock) void still_flags_kernel(PointGeom pg, const EnvRec* __restrict__ env,
                                                             const int32_t* __restrict__ env_fc, int64_t nl,
                                                             int64_t n_waves, float T0, float rlim2,
+                                                            const GridBox* __restrict__ boxes,
                                                             uint8_t* __restrict__ flags) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t >= nl * n_waves) return;
     const int64_t l = t / n_waves, w = t - l * n_waves;
-    const GridBox b = wave_box(pg, w);
+    const GridBox b = boxes ? boxes[w] : wave_box(pg, w);
     const EnvRec* e = env + env_fc[2 * l];
     const int n = env_fc[2 * l + 1];
     float T = T0;
@@ -248,11 +249,45 @@ __global__ __launch_bounds__(kBlock) void still_flags_kernel(PointGeom pg, const
 }
 
 hipError_t launch_still_flags(const PointGeom& pg, const EnvRec* env, const int32_t* env_fc, int64_t l0, int64_t nl,
-                              int64_t n_waves, float T0, uint8_t* flags, hipStream_t st) {
+                              int64_t n_waves, float T0, const GridBox* boxes, uint8_t* flags, hipStream_t st) {
     const int64_t lanes = nl * n_waves;
     if (lanes <= 0) return hipSuccess;
     hipLaunchKernelGGL(still_flags_kernel, dim3((unsigned)((lanes + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, pg,
-                       env, env_fc + 2 * l0, nl, n_waves, T0, envelope_radius2(pg), flags);
+                       env, env_fc + 2 * l0, nl, n_waves, T0, envelope_radius2(pg), boxes, flags);
+    return hipGetLastError();
+}
+
+// one wave per wave of points: each lane decodes one point, the wave takes
+// the least and greatest coordinates
+__global__ __launch_bounds__(kBlock) void wave_boxes_kernel(PointGeom pg, int64_t n_waves,
+                                                           GridBox* __restrict__ boxes) {
+    const int64_t w = (int64_t)blockIdx.x * (kBlock / kWave) + (threadIdx.x / kWave);
+    if (w >= n_waves) return;  // uniform per wave
+    const int64_t g = w * kWave + (threadIdx.x & (kWave - 1));
+    int i0 = INT32_MAX, i1 = INT32_MIN, j0 = INT32_MAX, j1 = INT32_MIN, k0 = INT32_MAX, k1 = INT32_MIN;
+    if (g < pg.count) {
+        int gi, gj, gk;
+        decode_point(pg, pg.first + g, gi, gj, gk);
+        i0 = i1 = gi;
+        j0 = j1 = gj;
+        k0 = k1 = gk;
+    }
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+        i0 = min(i0, __shfl_xor(i0, o));
+        i1 = max(i1, __shfl_xor(i1, o));
+        j0 = min(j0, __shfl_xor(j0, o));
+        j1 = max(j1, __shfl_xor(j1, o));
+        k0 = min(k0, __shfl_xor(k0, o));
+        k1 = max(k1, __shfl_xor(k1, o));
+    }
+    if ((threadIdx.x & (kWave - 1)) == 0)
+        boxes[w] = GridBox{(float)i0, (float)i1, (float)j0, (float)j1, -(float)k1, -(float)k0};
+}
+
+hipError_t launch_wave_boxes(const PointGeom& pg, int64_t n_waves, GridBox* boxes, hipStream_t st) {
+    if (n_waves <= 0) return hipSuccess;
+    const int64_t blocks = (n_waves + kBlock / kWave - 1) / (kBlock / kWave);
+    hipLaunchKernelGGL(wave_boxes_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st, pg, n_waves, boxes);
     return hipGetLastError();
 }
 
@@ -264,8 +299,17 @@ __device__ __forceinline__ int64_t fused_wave() {
 // A wave whose flags say still (wave_flag_still): its state is at rest and
 // stays as it is, so only beta (last launch of a call) is written, with the
 // value every step would give.
+// On an index list, points above the current surface are inactive and left
+// alone (on a box grid every point of a call is active).
 __device__ __forceinline__ void still_wave_beta(const PointGeom& pg, float T0c, float* beta, int64_t g) {
-    if (beta && g < pg.count) beta[pg.first + g] = solid_fraction(T0c) - kXmax - 0.0f;
+    if (!beta || g >= pg.count) return;
+    const int64_t local = pg.first + g;
+    if (pg.index) {
+        int gi, gj, gk;
+        decode_point(pg, local, gi, gj, gk);
+        if (gk < pg.k0) return;
+    }
+    beta[local] = solid_fraction(T0c) - kXmax - 0.0f;
 }
 
 // The persistent form of a fused launch, used from the second launch of a
