@@ -250,10 +250,10 @@ def main():
 # the same kernel with every temperature evaluated (MSTRUCT_OPTION_SKIP_COLD_WAVES = 0)
 FUSED_PROFILE_EVERY_T = {"valu_lane_ops_per_update": 128.07}
 FUSED_PROFILE = {
-    "valu_lane_ops_per_update": 10.21,
+    "valu_lane_ops_per_update": 10.26,
     "fp32_flops_per_update": 8.31,
-    "traffic_bytes_per_launch": (3363.40 * 2.0 + 3476.92) * 1024,
-    "read_fraction": 0.1147,
+    "traffic_bytes_per_launch": (3364.18 * 2.0 + 3476.92) * 1024,
+    "read_fraction": 0.1148,
     "written_fraction": 0.0437,
 }
 
