@@ -68,16 +68,18 @@ def test_largest_point_count_steps(torch, ctx, orc):
 
 
 def test_largest_box_fused(torch, ctx, orc):
-    """The fused kernel on a 2047 x 1024 x 1024 box (2,146,435,072 points,
+    """The fused kernels on a 2047 x 1024 x 1024 box (2,146,435,072 points,
     the largest box below 2^31 with these factors): the single track on its
-    top surface, 16 steps of 1 us in one launch; sampled points including the
-    track's neighbourhood and the last planes, against the oracle."""
+    top surface, 32 steps of 1 us in two launches of 16 (the second on the
+    slot kernel, with the wave flags of 33.5M waves); sampled points
+    including the track's neighbourhood and the last planes, against the
+    oracle."""
     import dataclasses
 
     import paper_2402_17580_amd as ms
     wl0 = workload.single_track()
     grid = workload.Grid(2047, 1024, 1024, wl0.grid.h)
-    wl = dataclasses.replace(wl0, grid=grid, layers=[workload.Layer(0, 16, 0.0)])
+    wl = dataclasses.replace(wl0, grid=grid, layers=[workload.Layer(0, 32, 0.0)])
     n = grid.n
     assert n < 1 << 31
     g = [torch.full((n,), v, device="cuda") for v in (0.1, 0.9, 0.0)]
