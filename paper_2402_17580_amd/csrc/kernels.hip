@@ -7,7 +7,7 @@
 namespace mstruct {
 
 constexpr int kBlock = 256;
-// workgroup of the fused kernels
+// workgroup of the fused grid kernels (one wave per 64 points)
 constexpr int kFusedBlock = 256;
 // wave slots per wave of the persistent fused kernels (see fused_slots),
 // and the launch size (in waves) from which they run in workgroups of four
