@@ -46,7 +46,9 @@
  *       absolute value of the newest iterate; at most max_iter iterations.
  *   R14 a state in a start-up regime at T^n takes the explicit step with its
  *       closed form, since the paper initiates diffusion with the closed form
- *       in both schemes.
+ *       in both schemes; the alpha_s -> beta start counts only where its
+ *       closed form can act (D > 0, i.e. above the alpha_s -> beta end
+ *       temperature).
  *   R15 subcycling: a step longer than dt_sub is split into the fewest equal
  *       substeps not longer than dt_sub, with T linear in time.
  *   R16 a switched-off track is the difference of two moving sources that
@@ -295,12 +297,15 @@ static void diff_rates(double as, double am, double T, double *fa, double *fm)
     *fm = -r2;
 }
 
-/* the zero-rate start of either transformation at T^n (R6, R7, R14) */
+/* the zero-rate start of either transformation at T^n (R6, R7, R14).  The
+ * alpha_s -> beta start needs D = 0.9 - X_alpha^eq > 0 (Appendix A; R8):
+ * below the alpha_s -> beta end temperature X_alpha^eq = 0.9, and a state
+ * whose alpha total exceeds it only by rounding is not starting anything. */
 static int startup_regime(double as, double am, double bt, double T, double dt)
 {
     double xa = as + am, xeq = orc_alpha_eq(T);
     if (xa < xeq && !(as > 0.0)) return 1;
-    if (xa > xeq && (bt > 0.0 ? bt : 0.0) * dt <= STARTUP_LIMIT) return 1;
+    if (xa > xeq && xeq < X_ALPHA_MAX && (bt > 0.0 ? bt : 0.0) * dt <= STARTUP_LIMIT) return 1;
     return 0;
 }
 

@@ -321,7 +321,10 @@ __device__ __forceinline__ int implicit_step(R& a, R& m, R& a_lo, R& m_lo, R& be
     }
     const R xeq_n = alpha_eq(Tn), xeq_1 = alpha_eq(Tn1);
     const R xa = a + m;
-    if ((xa < xeq_n && !(a > R(0))) || (xa > xeq_n && vmax(C::Xmax - xa, R(0)) * dt <= C::StartupLimit)) {
+    // (the alpha_s -> beta start needs D = 0.9 - X_alpha^eq > 0: below the
+    // alpha_s -> beta end temperature X_alpha > X_alpha^eq = 0.9 is rounding)
+    if ((xa < xeq_n && !(a > R(0))) ||
+        (xa > xeq_n && xeq_n < C::Xmax && vmax(C::Xmax - xa, R(0)) * dt <= C::StartupLimit)) {
         beta = explicit_step<COMPENSATED>(a, m, a_lo, m_lo, Tn, xeq_n, Tn1, xeq_1, dt);
         return 0;
     }

@@ -195,3 +195,19 @@ def test_scan_run_implicit_is_stepping_with_the_scan_temperature(orc):
         orc.step_implicit(st2, T, T1, 4e-6)
         T = T1
     assert np.array_equal(st1.alpha_s, st2.alpha_s) and np.array_equal(st1.alpha_m, st2.alpha_m)
+
+
+def test_second_order_alpha_m_to_alpha_s_at_constant_T(orc):
+    # pure tempering (eq. alpha_m_to_alpha_s) at 900 K with X_as + X_am = 0.9:
+    # the Appendix A form with D = 0.9, k~ = 0.9 k_as, c = c_as is exact
+    # (derivation beside the explicit test of the same equation)
+    T, a0, m0, t_end = 900.0, 0.3, 0.6, 2.0
+    c = orc.constants()
+    exact = orc.logistic_step(a0, 0.9, 0.9 * orc.k_as(T), c["c_as"], t_end)
+    errs = []
+    for h in (0.04, 0.02, 0.01):
+        st = _run_cn(orc, a0, m0, lambda t: T, t_end, h, **TIGHT)
+        assert st.alpha_s[0] + st.alpha_m[0] == pytest.approx(0.9, abs=1e-14)
+        errs.append(abs(st.alpha_s[0] - exact))
+    order = _order(errs)
+    assert all(1.85 < o < 2.15 for o in order), (errs, order)

@@ -284,3 +284,60 @@ def test_alpha_s_to_beta_start_converges_through_the_exit(orc):
         errs.append(abs(st.xbt[0] - exact) / exact)
     assert errs[-1] < 1e-2
     assert all(1.8 < errs[i] / errs[i + 1] < 2.4 for i in range(2)), errs
+
+
+# ---- eq. alpha_m_to_alpha_s (tempering of martensite into stable alpha) ----
+# At constant T below the alpha_s -> beta end temperature (935 K) the
+# equilibrium is X_alpha^eq = 0.9; a state with X_as + X_am = 0.9 then has
+# neither beta -> alpha_s nor alpha_s -> beta, and the formation law cannot
+# raise alpha_m (X_am,0^eq < 1).  Only the tempering rate acts, and it keeps
+# X_as + X_am = 0.9, so X_as' = k_as X_as^p (0.9 - X_as)^q: with xi = X_as/0.9
+# this is the Appendix A equation with D = 0.9, k~ = 0.9 k_as(T), c = c_as,
+# whose closed form is exact.  A debit of alpha_s instead of a credit, k_beta
+# in place of k_as, or swapped exponents all leave this solution.
+
+def _tempering_run(orc, step, T, a0, m0, dt, t_end):
+    st = orc.State(np.array([1.0 - a0 - m0]), np.array([a0]), np.array([m0]))
+    for _ in range(int(round(t_end / dt))):
+        step(st, T, T, dt)
+    return st
+
+
+@pytest.mark.parametrize("key,T,t_end,dts", [
+    ("tempering_900K_2s", 900.0, 2.0, (4e-3, 2e-3, 1e-3)),
+    ("tempering_700K_20s", 700.0, 20.0, (4e-2, 2e-2, 1e-2)),
+])
+def test_alpha_m_to_alpha_s_explicit_converges_to_closed_form(orc, key, T, t_end, dts):
+    want = _gold("derived_values.json")[key]
+    c = orc.constants()
+    # the oracle's own closed form agrees with the hand-derived value
+    assert orc.logistic_step(0.3, 0.9, 0.9 * orc.k_as(T), c["c_as"], t_end) == pytest.approx(
+        want["value"], rel=want["rtol"])
+    errs = []
+    for dt in dts:
+        st = _tempering_run(orc, orc.step, T, 0.3, 0.6, dt, t_end)
+        # the transformation conserves the alpha total and leaves beta at 0.1
+        assert st.alpha_s[0] + st.alpha_m[0] == pytest.approx(0.9, abs=1e-14)
+        assert st.beta[0] == pytest.approx(0.1, abs=1e-14)
+        errs.append(abs(st.alpha_s[0] - want["value"]))
+    # the hold moves alpha_s by > 0.005; the explicit error is first order
+    assert abs(want["value"] - 0.3) > 5e-3
+    assert errs[-1] < 1e-4 * (t_end / 2.0)
+    assert all(1.8 < errs[i] / errs[i + 1] < 2.2 for i in range(2)), errs
+
+
+def test_alpha_m_to_alpha_s_rate_value(orc):
+    # r2 = k_as X_as^p X_am^q with p = (c-1)/c, q = (c+1)/c, c = c_as; the
+    # other two rates vanish at X_alpha = X_alpha^eq = 0.9 (up to the rounding
+    # of 0.3 + 0.6 in float64)
+    T, a, m = 900.0, 0.3, 0.6
+    r1, r2, r3 = orc.rates(a, m, 0.0, T)
+    kas = 0.294 / (1.0 + math.exp(-0.0337 * (T - 850.0)))
+    p, q = (2.51 - 1) / 2.51, (2.51 + 1) / 2.51
+    assert r1 < 1e-20 and r3 == 0.0
+    assert r2 == pytest.approx(kas * a ** p * m ** q, rel=1e-13)
+    # one small explicit step credits alpha_s with exactly what it takes from alpha_m
+    st = orc.State(np.array([0.1]), np.array([a]), np.array([m]))
+    orc.step(st, T, T, 1e-6)
+    assert st.alpha_s[0] - a == pytest.approx(1e-6 * r2, rel=1e-9)
+    assert m - st.alpha_m[0] == pytest.approx(1e-6 * r2, rel=1e-9)
