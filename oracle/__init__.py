@@ -74,8 +74,40 @@ def lib():
         L.orc_scan_run_implicit.argtypes = [p, i64, p, p, i64, d, d, d, d, i64, d, ctypes.c_int, p, p, p, p,
                                             ctypes.c_int]
         L.orc_step_implicit_n.argtypes = [i64, p, p, p, p, p, p, d, d, ctypes.c_int, d, d, p]
+        L.orc_set_readings.restype = None
+        L.orc_set_readings.argtypes = [ctypes.c_int, ctypes.c_int]
+        L.orc_get_readings.restype = ctypes.c_int
+        L.orc_get_readings.argtypes = []
         _lib = L
     return _lib
+
+
+CORRECTION_T = {"next": 0, "prev": 1}
+MARTENSITE = {"max": 0, "assign": 1}
+
+
+def set_readings(correction_T="next", martensite="max"):
+    """Switch the two readings of the paper that the library exposes: the
+    temperature of the explicit correction ("next": T^{n+1} of eq.
+    explicit_correction; "prev": the T^n Algorithm 2 passes) and the
+    martensite formation law ("max": never lowers alpha_m; "assign": the
+    literal "=" of eq. inst_martensite_formation)."""
+    lib().orc_set_readings(CORRECTION_T[correction_T], MARTENSITE[martensite])
+
+
+class readings:
+    """Context manager: the given readings inside, the defaults after."""
+
+    def __init__(self, correction_T="next", martensite="max"):
+        self.args = (correction_T, martensite)
+
+    def __enter__(self):
+        set_readings(*self.args)
+        return self
+
+    def __exit__(self, *exc):
+        set_readings()
+        return False
 
 
 def _ptr(a: np.ndarray):

@@ -21,6 +21,10 @@
  *       explicit_correction), rates at T^n (eq. explicit_integration).
  *   R4  instantaneous martensite formation never lowers alpha_m:
  *       X_am <- max(X_am, X_am^eq) below the martensite start temperature.
+ *   R3 and R4 are the defaults of two switches (orc_set_readings): the
+ *   explicit correction at T^n (the argument Algorithm 2 passes) instead of
+ *   T^{n+1}, and the formation law's "=" taken literally (X_am <- X_am^eq,
+ *   which lowers alpha_m on reheating below the martensite start).
  *   R5  order inside g: clip at 0, cap alpha at 0.9 keeping the ratio,
  *       regularisation, martensite dissolution, martensite formation, the
  *       0.9 cap again (formation can overshoot it just above T_inf), the
@@ -83,6 +87,21 @@ static const double F_BETA = 3.8;
 static const double T_AS_REG = 100.0;    /* regularisation width chosen in Sec. 2.2 [K] */
 static const double X_ALPHA_MAX = 0.9;   /* maximum alpha fraction (first case of X_alpha^eq) */
 static const double STARTUP_LIMIT = 1e-15; /* Appendix A exit criterion on X~beta * dt */
+
+/* the readings of the paper that can be switched (0: the defaults R3, R4) */
+static int g_correction_prev = 0;  /* 1: explicit correction at T^n */
+static int g_martensite_assign = 0; /* 1: X_am <- X_am^eq below the martensite start */
+
+void orc_set_readings(int correction_prev, int martensite_assign)
+{
+    g_correction_prev = correction_prev != 0;
+    g_martensite_assign = martensite_assign != 0;
+}
+
+int orc_get_readings(void)
+{
+    return g_correction_prev | (g_martensite_assign << 1);
+}
 
 int orc_constants(double *out, int n)
 {
@@ -185,10 +204,12 @@ double orc_correct(double T, double *as_, double *am_)
         if (m < 0.0) m = 0.0;
     }
     /* instantaneous martensite formation below the martensite start (R4),
-     * towards the corrected pseudo-equilibrium of eq. equilibrium_phase_am */
+     * towards the corrected pseudo-equilibrium of eq. equilibrium_phase_am;
+     * with the literal reading of eq. inst_martensite_formation alpha_m is
+     * set to it, also where that lowers it */
     if (T < T_AM_START) {
         double meq = orc_am0_eq(T) * (X_ALPHA_MAX - a) / X_ALPHA_MAX;
-        if (m < meq) m = meq;
+        if (m < meq || g_martensite_assign) m = meq;
     }
     /* the pseudo-equilibrium can exceed 0.9 just above T_inf: cap again */
     s = a + m;
@@ -211,8 +232,9 @@ double orc_correct(double T, double *as_, double *am_)
 
 /* one explicit step (eqs. explicit_integration, explicit_correction) for one
  * point; the start of diffusion from zero-rate states follows Sec. 3.1 and
- * Appendix A (readings R6-R8).  State: alpha_s, alpha_m, beta, X~beta. */
-void orc_step(double *as_, double *am_, double *b_, double *bt_, double Tn, double Tn1, double dt)
+ * Appendix A (readings R6-R8).  State: alpha_s, alpha_m, beta, X~beta.  The
+ * correction is taken at Tc (T^{n+1}, or T^n with the switched reading R3). */
+static void step_at(double *as_, double *am_, double *b_, double *bt_, double Tn, double Tc, double dt)
 {
     const double pa = (C_AS - 1.0) / C_AS, qa = (C_AS + 1.0) / C_AS;
     const double pb = (C_BETA - 1.0) / C_BETA, qb = (C_BETA + 1.0) / C_BETA;
@@ -263,7 +285,7 @@ void orc_step(double *as_, double *am_, double *b_, double *bt_, double Tn, doub
     double m = am + dam;
     double a = startup_beta ? X_ALPHA_MAX - bt_new - m : as + das;
     double a_t = a, m_t = m;
-    double b = orc_correct(Tn1, &a, &m);
+    double b = orc_correct(Tc, &a, &m);
 
     /* X~beta stays authoritative while the start-up form is in use and the
      * correction left the state alone; otherwise it follows the sum rule */
@@ -275,6 +297,11 @@ void orc_step(double *as_, double *am_, double *b_, double *bt_, double Tn, doub
     *am_ = m;
     *b_ = b;
     *bt_ = bt;
+}
+
+void orc_step(double *as_, double *am_, double *b_, double *bt_, double Tn, double Tn1, double dt)
+{
+    step_at(as_, am_, b_, bt_, Tn, g_correction_prev ? Tn : Tn1, dt);
 }
 
 void orc_step_n(int64_t n, double *as, double *am, double *b, double *bt,
@@ -318,7 +345,8 @@ int orc_step_cn(double *as_, double *am_, double *b_, double *bt_, double Tn, do
 {
     const double as = *as_, am = *am_;
     if (startup_regime(as, am, *bt_, Tn, dt)) {
-        orc_step(as_, am_, b_, bt_, Tn, Tn1, dt);
+        /* the implicit scheme corrects at T^{n+1} (eq. implicit_correction) */
+        step_at(as_, am_, b_, bt_, Tn, Tn1, dt);
         return 0;
     }
     double fa_n, fm_n;
