@@ -5,7 +5,6 @@
 #include <string.h>
 
 #include <string>
-#include <vector>
 
 #include "../../include/mstruct.h"
 #include "kernels.h"
@@ -217,43 +216,46 @@ void build_table(SrcRec* out, const mstruct_scan* sc, const mstruct_points* p, d
     }
 }
 
+// the most distinct tracks one launch can see: K + 1 time points with W
+// window slots each (several tracks may switch on within one step)
+constexpr int kMaxLaunchTracks = (64 + 1) * 4;
+
 // Per launch of K steps (time points s0 .. s0 + Kb of the call's table), one
 // EnvRec for every track that occupies a window slot at any of them: its
 // positions at the first and last of those time points and the constants of
-// the last.  env[first[i] .. first[i] + count[i]) belongs to launch i.
-// Returns the number of records written (at most n_launches * (W + K + 1)).
-int64_t build_envelopes(EnvRec* env, std::vector<int32_t>& first, std::vector<int32_t>& count, const SrcRec* recs,
-                        const mstruct_scan* sc, double t0, double dt, int64_t n_steps, int K) {
+// the last.  env[fc[2 i] .. fc[2 i] + fc[2 i + 1]) belongs to launch i.
+// Returns the number of records written, or -1 if more than cap would be
+// needed (at most n_launches (K + 1) W are).
+int64_t build_envelopes(EnvRec* env, int64_t cap, int32_t* fc, const SrcRec* recs, const mstruct_scan* sc,
+                        double t0, double dt, int64_t n_steps, int K) {
     const int W = sc->window;
-    first.clear();
-    count.clear();
     int64_t total = 0;
-    std::vector<int64_t> ids;
-    std::vector<int64_t> lo, hi;  // first and last time point of each track in this launch
-    for (int64_t s0 = 0; s0 < n_steps; s0 += K) {
+    int64_t ids[kMaxLaunchTracks], lo[kMaxLaunchTracks], hi[kMaxLaunchTracks];
+    int64_t li = 0;
+    for (int64_t s0 = 0; s0 < n_steps; s0 += K, ++li) {
         const int64_t Kb = (n_steps - s0) < K ? (n_steps - s0) : K;
-        ids.clear();
-        lo.clear();
-        hi.clear();
+        int n = 0;  // each (time point, slot) adds at most one track: n <= (Kb + 1) W
         for (int64_t s = s0; s <= s0 + Kb; ++s) {
             const int64_t c = last_on(sc, t0 + (double)s * dt);
             for (int w = 0; w < W; ++w) {
                 if (!(recs[s * W + w].lamp > -1e30f)) continue;
                 const int64_t j = c - w;
-                size_t k = 0;
-                while (k < ids.size() && ids[k] != j) ++k;
-                if (k == ids.size()) {
-                    ids.push_back(j);
-                    lo.push_back(s * W + w);
-                    hi.push_back(s * W + w);
+                int k = 0;
+                while (k < n && ids[k] != j) ++k;
+                if (k == n) {
+                    ids[n] = j;
+                    lo[n] = s * W + w;
+                    hi[n] = s * W + w;
+                    ++n;
                 } else {
                     hi[k] = s * W + w;
                 }
             }
         }
-        first.push_back((int32_t)total);
-        count.push_back((int32_t)ids.size());
-        for (size_t k = 0; k < ids.size(); ++k) {
+        if (total + n > cap) return -1;
+        fc[2 * li] = (int32_t)total;
+        fc[2 * li + 1] = n;
+        for (int k = 0; k < n; ++k) {
             const SrcRec& a = recs[lo[k]];
             const SrcRec& b = recs[hi[k]];
             EnvRec& e = env[total++];
@@ -450,8 +452,48 @@ int mstruct_temperature(mstruct_ctx* ctx, const mstruct_scan* scan, const mstruc
     return release_slot(ctx, s, st);
 }
 
-int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const mstruct_points* pts, double t0,
-                             double dt, int64_t n_steps, int K, int mode, const mstruct_phases* ph, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Sizes of one fused call: its table (records of n_steps + 1 time points x
+// W slots, then (first, count) int32 pairs of each launch's envelopes, then
+// at most (K + 1) W envelope records per launch) and its waves of 64 points.
+struct FusedPlan {
+    int W;
+    int64_t n_launches, n_waves;
+    size_t recs, fc_recs, env_cap;
+    size_t table() const { return recs + fc_recs + env_cap; }
+};
+
+FusedPlan fused_plan(const mstruct_scan* scan, const PointGeom& pg, int64_t n_steps, int K) {
+    FusedPlan p;
+    p.W = scan->window;
+    p.n_launches = (n_steps + K - 1) / K;
+    p.n_waves = (pg.count + kWave - 1) / kWave;
+    p.recs = (size_t)(n_steps + 1) * p.W;
+    p.fc_recs = ((size_t)p.n_launches * 2 * sizeof(int32_t) + sizeof(SrcRec) - 1) / sizeof(SrcRec);
+    p.env_cap = (size_t)p.n_launches * (K + 1) * p.W;
+    return p;
+}
+
+// The buffers a fused call works in: the table's host staging and its
+// device copy (cap records each), and the wave flags (2 n_waves bytes of
+// rest and tcached flags, then still flags for chunks of `chunk` launches;
+// flags == nullptr: none) with the waves' boxes on an index list.
+struct FusedBufs {
+    SrcRec* host = nullptr;
+    SrcRec* dev = nullptr;
+    size_t cap = 0;
+    uint8_t* flags = nullptr;
+    int64_t chunk = 0;
+    GridBox* boxes = nullptr;
+};
+
+// Argument checks shared by the fused entry points; fills pg.  Returns
+// MSTRUCT_OK, an error status, or 1 when there is nothing to do.
+int fused_check(mstruct_ctx* ctx, const mstruct_scan* scan, const mstruct_points* pts, double t0, double dt,
+                int64_t n_steps, int K, int mode, const mstruct_phases* ph, PointGeom& pg) {
     if (!ctx) return MSTRUCT_EINVAL;
     int rc = check_phases(ctx, ph);
     if (rc) return rc;
@@ -463,32 +505,103 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
         return fail(ctx, MSTRUCT_EINVAL, "bad mode");
     if (mode == MSTRUCT_MODE_IMPLICIT && dt / kImplicitDtSub > 1e6)
         return fail(ctx, MSTRUCT_EINVAL, "dt / 0.01 s exceeds 1e6 substeps");
-    PointGeom pg;
     if ((rc = make_geom(ctx, pts, ph->n, pg))) return rc;
     if (mode == MSTRUCT_MODE_SURROGATE && ph->xbt)
         return fail(ctx, MSTRUCT_EUNSUPPORTED, "surrogate mode does not carry the tracked X~beta (xbt)");
     if (mode == MSTRUCT_MODE_SURROGATE && !ctx->mlp.ready)
         return fail(ctx, MSTRUCT_ESTATE, "surrogate mode needs network parameters (mstruct_mlp_set_params)");
-    if (n_steps == 0 || pg.count == 0) return MSTRUCT_OK;
+    if (n_steps == 0 || pg.count == 0) return 1;
+    return MSTRUCT_OK;
+}
+
+// The body of a fused call: scan table and launch envelopes built on the
+// host into b.host, uploaded to b.dev (then `uploaded`, if given, is
+// recorded on the stream), the still-flag pre-passes and the launches of K
+// steps.  Nothing is enqueued if the table does not fit.
+int fused_run(mstruct_ctx* ctx, const mstruct_scan* scan, const mstruct_points* pts, const PointGeom& pg,
+              const FusedPlan& p, double t0, double dt, int64_t n_steps, int K, int mode, const mstruct_phases* ph,
+              const FusedBufs& b, hipEvent_t uploaded, hipStream_t st) {
+    const int W = p.W;
+    if (p.recs + p.fc_recs > b.cap) return fail(ctx, MSTRUCT_EINVAL, "scan table larger than the table buffer");
+    build_table(b.host, scan, pts, t0, dt, n_steps + 1);
+    int32_t* fc_host = reinterpret_cast<int32_t*>(b.host + p.recs);
+    const int32_t* fc_dev = reinterpret_cast<const int32_t*>(b.dev + p.recs);
+    EnvRec* env_host = reinterpret_cast<EnvRec*>(b.host + p.recs + p.fc_recs);
+    const EnvRec* env_dev = reinterpret_cast<const EnvRec*>(b.dev + p.recs + p.fc_recs);
+    const int64_t n_env = build_envelopes(env_host, (int64_t)(b.cap - p.recs - p.fc_recs), fc_host, b.host, scan, t0,
+                                          dt, n_steps, K);
+    if (n_env < 0) return fail(ctx, MSTRUCT_EINVAL, "launch envelopes larger than the table buffer");
+    HIP_CHECK(ctx, hipMemcpyAsync(b.dev, b.host, (p.recs + p.fc_recs + (size_t)n_env) * sizeof(SrcRec),
+                                  hipMemcpyHostToDevice, st));
+    if (uploaded) HIP_CHECK(ctx, hipEventRecord(uploaded, st));
+    const ScanArgs sa{(float)scan->T0, (float)scan->T_clamp};
+    const bool wave_flags = b.flags != nullptr;
+    const int64_t n_waves = p.n_waves, n_launches = p.n_launches, chunk = b.chunk;
+    if (mode == MSTRUCT_MODE_SURROGATE) {
+        hipError_t e = surrogate_prepare(ctx->mlp, pg.first + pg.count, st);
+        if (e != hipSuccess) return hip_fail(ctx, e, "surrogate queue");
+    }
+    for (int64_t s0 = 0; s0 < n_steps; s0 += K) {
+        const int Kb = (int)((n_steps - s0) < K ? (n_steps - s0) : K);
+        const bool last = s0 + Kb >= n_steps;
+        // beta is written by the last launch only (no kernel reads it)
+        float* beta = last ? ph->beta : nullptr;
+        hipError_t e;
+        const int64_t li = s0 / K;
+        uint8_t* below = nullptr;
+        if (wave_flags) {
+            below = b.flags + n_waves * (2 + li % chunk);
+            if (li % chunk == 0) {
+                const int64_t nl = (n_launches - li) < chunk ? (n_launches - li) : chunk;
+                const GridBox* boxes = pts->index ? b.boxes : nullptr;
+                hipError_t fe = hipSuccess;
+                if (li == 0 && boxes) fe = launch_wave_boxes(pg, n_waves, b.boxes, st);
+                if (fe == hipSuccess)
+                    fe = launch_still_flags(pg, env_dev, fc_dev, li, nl, n_waves, fminf(sa.T0, sa.Tclamp), boxes,
+                                            b.flags + 2 * n_waves, st);
+                if (fe != hipSuccess) return hip_fail(ctx, fe, "still flags launch");
+            }
+        }
+        const EnvSet es{env_dev + fc_host[2 * li], ctx->skip_cold ? fc_host[2 * li + 1] : -1, below,
+                        wave_flags ? b.flags : nullptr, n_waves, li > 0,
+                        wave_flags && mode == MSTRUCT_MODE_SURROGATE ? b.flags + n_waves : nullptr};
+        if (mode == MSTRUCT_MODE_PLAIN) {
+            e = launch_fused_plain(pg, W, b.dev + s0 * W, es, Kb, (float)dt, sa, beta, ph->alpha_s, ph->alpha_m,
+                                   ph->xbt, st);
+        } else if (mode == MSTRUCT_MODE_IMPLICIT) {
+            const int n_sub = substeps(dt, kImplicitDtSub);
+            e = launch_fused_implicit(pg, W, b.dev + s0 * W, es, Kb, (float)(dt / n_sub), n_sub, kImplicitMaxIter,
+                                      sa, beta, ph->alpha_s, ph->alpha_m, ph->xbt, ctx->implicit_bad, st);
+        } else
+            e = launch_surrogate(ctx->mlp, pg, W, b.dev + s0 * W, es, Kb, (float)dt, sa, ph->beta, ph->alpha_s,
+                                 ph->alpha_m, li, s0 == 0, last, st);
+        if (e != hipSuccess) return hip_fail(ctx, e, "fused launch");
+    }
+    return MSTRUCT_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const mstruct_points* pts, double t0,
+                             double dt, int64_t n_steps, int K, int mode, const mstruct_phases* ph, void* stream) {
+    PointGeom pg;
+    int rc = fused_check(ctx, scan, pts, t0, dt, n_steps, K, mode, ph, pg);
+    if (rc) return rc > 0 ? MSTRUCT_OK : rc;
     DeviceGuard g(ctx->device);
     hipStream_t st = (hipStream_t)stream;
-    const int W = scan->window;
-    const size_t recs = (size_t)(n_steps + 1) * W;
-    const int64_t n_launches = (n_steps + K - 1) / K;
-    const size_t env_cap = (size_t)n_launches * (W + K + 1);
-    // (first, count) of each launch's envelopes, as int32 pairs after them
-    const size_t fc_recs = ((size_t)n_launches * 2 * sizeof(int32_t) + sizeof(SrcRec) - 1) / sizeof(SrcRec);
+    const FusedPlan p = fused_plan(scan, pg, n_steps, K);
+    FusedBufs b;
     // Wave flags (one point per lane, 64 per wave): rest flags kept by the
     // fused kernels and surrogate pass A, pass A's tcached flags, then still
     // flags for chunks of launches from a box pre-pass (on an index list the
     // boxes of the waves are computed first).  Not with the tracked X~beta,
     // whose store every launch takes.
-    const bool wave_flags = ctx->skip_cold && !ph->xbt;
-    const int64_t n_waves = (pg.count + kWave - 1) / kWave;
-    int64_t chunk = kWaveFlagBudget / n_waves;
-    chunk = chunk < 1 ? 1 : (chunk > n_launches ? n_launches : chunk);
-    if (wave_flags) {
-        const size_t need = (size_t)n_waves * (size_t)(2 + chunk);
+    if (ctx->skip_cold && !ph->xbt) {
+        int64_t chunk = kWaveFlagBudget / p.n_waves;
+        chunk = chunk < 1 ? 1 : (chunk > p.n_launches ? p.n_launches : chunk);
+        const size_t need = (size_t)p.n_waves * (size_t)(2 + chunk);
         if (ctx->wave_flags_cap < need) {
             HIP_CHECK(ctx, hipStreamSynchronize(st));
             if (ctx->wave_flags) HIP_CHECK(ctx, hipFree(ctx->wave_flags));
@@ -500,85 +613,29 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
             }
             ctx->wave_flags_cap = need;
         }
-        if (pts->index && ctx->wave_boxes_cap < (size_t)n_waves) {
+        if (pts->index && ctx->wave_boxes_cap < (size_t)p.n_waves) {
             HIP_CHECK(ctx, hipStreamSynchronize(st));
             if (ctx->wave_boxes) HIP_CHECK(ctx, hipFree(ctx->wave_boxes));
             ctx->wave_boxes = nullptr;
             ctx->wave_boxes_cap = 0;
-            if (hipMalloc((void**)&ctx->wave_boxes, (size_t)n_waves * sizeof(GridBox)) != hipSuccess) {
+            if (hipMalloc((void**)&ctx->wave_boxes, (size_t)p.n_waves * sizeof(GridBox)) != hipSuccess) {
                 ctx->wave_boxes = nullptr;
                 return fail(ctx, MSTRUCT_ENOMEM, "wave box allocation failed");
             }
-            ctx->wave_boxes_cap = (size_t)n_waves;
+            ctx->wave_boxes_cap = (size_t)p.n_waves;
         }
+        b.flags = ctx->wave_flags;
+        b.chunk = chunk;
+        b.boxes = ctx->wave_boxes;
     }
     TableSlot* s;
-    if ((rc = acquire_slot(ctx, recs + env_cap + fc_recs, s))) return rc;
-    build_table(s->host, scan, pts, t0, dt, n_steps + 1);
-    // launch envelopes after the records (EnvRec has the size of SrcRec)
-    std::vector<int32_t> env_first, env_count;
-    EnvRec* env_host = reinterpret_cast<EnvRec*>(s->host + recs);
-    const EnvRec* env_dev = reinterpret_cast<const EnvRec*>(s->dev + recs);
-    const int64_t n_env = build_envelopes(env_host, env_first, env_count, s->host, scan, t0, dt, n_steps, K);
-    int32_t* fc_host = reinterpret_cast<int32_t*>(s->host + recs + n_env);
-    const int32_t* fc_dev = reinterpret_cast<const int32_t*>(s->dev + recs + n_env);
-    for (int64_t li = 0; li < n_launches; ++li) {
-        fc_host[2 * li] = env_first[li];
-        fc_host[2 * li + 1] = env_count[li];
-    }
-    HIP_CHECK(ctx, hipMemcpyAsync(s->dev, s->host, (recs + (size_t)n_env + fc_recs) * sizeof(SrcRec),
-                                  hipMemcpyHostToDevice, st));
-    const ScanArgs sa{(float)scan->T0, (float)scan->T_clamp};
-    if (mode == MSTRUCT_MODE_SURROGATE) {
-        hipError_t e = surrogate_prepare(ctx->mlp, pg.first + pg.count, st);
-        if (e != hipSuccess) {
-            (void)release_slot(ctx, s, st);
-            return hip_fail(ctx, e, "surrogate queue");
-        }
-    }
-    for (int64_t s0 = 0; s0 < n_steps; s0 += K) {
-        const int Kb = (int)((n_steps - s0) < K ? (n_steps - s0) : K);
-        const bool last = s0 + Kb >= n_steps;
-        // beta is written by the last launch only (no kernel reads it)
-        float* beta = last ? ph->beta : nullptr;
-        hipError_t e;
-        const int64_t li = s0 / K;
-        uint8_t* below = nullptr;
-        if (wave_flags) {
-            below = ctx->wave_flags + n_waves * (2 + li % chunk);
-            if (li % chunk == 0) {
-                const int64_t nl = (n_launches - li) < chunk ? (n_launches - li) : chunk;
-                const GridBox* boxes = pts->index ? ctx->wave_boxes : nullptr;
-                hipError_t fe = hipSuccess;
-                if (li == 0 && boxes) fe = launch_wave_boxes(pg, n_waves, ctx->wave_boxes, st);
-                if (fe == hipSuccess)
-                    fe = launch_still_flags(pg, env_dev, fc_dev, li, nl, n_waves, fminf(sa.T0, sa.Tclamp), boxes,
-                                            ctx->wave_flags + 2 * n_waves, st);
-                if (fe != hipSuccess) {
-                    (void)release_slot(ctx, s, st);
-                    return hip_fail(ctx, fe, "still flags launch");
-                }
-            }
-        }
-        const EnvSet es{env_dev + env_first[li], ctx->skip_cold ? env_count[li] : -1, below,
-                        wave_flags ? ctx->wave_flags : nullptr, n_waves, li > 0,
-                        wave_flags && mode == MSTRUCT_MODE_SURROGATE ? ctx->wave_flags + n_waves : nullptr};
-        if (mode == MSTRUCT_MODE_PLAIN) {
-            e = launch_fused_plain(pg, W, s->dev + s0 * W, es, Kb, (float)dt, sa, beta, ph->alpha_s, ph->alpha_m,
-                                   ph->xbt, st);
-        } else if (mode == MSTRUCT_MODE_IMPLICIT) {
-            const int n_sub = substeps(dt, kImplicitDtSub);
-            e = launch_fused_implicit(pg, W, s->dev + s0 * W, es, Kb, (float)(dt / n_sub), n_sub, kImplicitMaxIter,
-                                      sa, beta, ph->alpha_s, ph->alpha_m, ph->xbt, ctx->implicit_bad, st);
-        } else
-            e = launch_surrogate(ctx->mlp, pg, W, s->dev + s0 * W, es, Kb, (float)dt, sa, ph->beta, ph->alpha_s,
-                                 ph->alpha_m, li, s0 == 0, last, st);
-        if (e != hipSuccess) {
-            (void)release_slot(ctx, s, st);
-            return hip_fail(ctx, e, "fused launch");
-        }
-    }
-    return release_slot(ctx, s, st);
+    if ((rc = acquire_slot(ctx, p.table(), s))) return rc;
+    b.host = s->host;
+    b.dev = s->dev;
+    b.cap = s->cap;
+    rc = fused_run(ctx, scan, pts, pg, p, t0, dt, n_steps, K, mode, ph, b, nullptr, st);
+    const int rc2 = release_slot(ctx, s, st);
+    return rc ? rc : rc2;
 }
 
 int mstruct_set_option(mstruct_ctx* ctx, int option, int value) {

@@ -388,3 +388,32 @@ def test_cold_waves_skip_is_bit_exact(torch, ctx, mode):
             assert np.any(outs[0][1] != np.float32(0.9)), name  # the run changed something
     finally:
         ctx.set_option(ms.OPTION_SKIP_COLD_WAVES, 1)
+
+
+def test_tracks_switching_within_a_step(torch, ctx, orc):
+    """A window of 4 tracks, each switched on for 0.1 us, ten per step of
+    1 us (3 kW, so that the 0.4 us the window spans melts points next to the
+    path): a launch of 64 steps sees up to (64 + 1) x 4 distinct tracks, all
+    listed for its launch certificates.  Fused PLAIN at K = 64 with the
+    certificates on and off gives the same bits, within 1e-4 of the oracle."""
+    import paper_2402_17580_amd as ms
+    n_tr = 2100
+    rows = np.array([[20e-6 + 0.1e-6 * j, 75e-6, 0.0, 1.0, 0.0, 1e-7 * j, 1e-7, 3000.0, 1.0] for j in range(n_tr)])
+    base = workload.single_track(nx=24, ny=16, nz=4, n_steps=200)
+    scan = workload.Scan(rows, base.scan.conductivity, base.scan.diffusivity, base.scan.T0, base.scan.T_clamp, 4)
+    wl = workload.Workload("short_tracks", base.grid, scan, base.layers, base.dt, base.seed)
+    outs = []
+    try:
+        for skip in (1, 0):
+            ctx.set_option(ms.OPTION_SKIP_COLD_WAVES, skip)
+            g = _state(torch, wl.grid.n)
+            ms.run_layers(ctx, wl, *g, K=64)
+            outs.append([x.cpu().numpy() for x in g])
+    finally:
+        ctx.set_option(ms.OPTION_SKIP_COLD_WAVES, 1)
+    for x, y in zip(*outs):
+        assert np.array_equal(x.view(np.uint32), y.view(np.uint32))
+    st = orc.run_workload(wl, np.arange(wl.grid.n))
+    for name, x, o in zip(("beta", "alpha_s", "alpha_m"), outs[0], (st.beta, st.alpha_s, st.alpha_m)):
+        assert float(np.abs(x.astype(np.float64) - o).max()) <= RUN_TOL, name
+    assert np.count_nonzero(outs[0][2]) > 10  # martensite formed where the sources melted the body
