@@ -201,6 +201,28 @@ int mstruct_fused_scan_steps(mstruct_ctx *ctx, const mstruct_scan *scan, const m
                              double t0, double dt, int64_t n_steps, int K, int mode,
                              const mstruct_phases *ph, void *stream);
 
+/* For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): mstruct_fused_scan_steps in PLAIN or
+ * IMPLICIT mode (SURROGATE: MSTRUCT_EUNSUPPORTED) with the same arguments,
+ * kernels and results, bit for bit, that allocates nothing.  Its per-call
+ * buffers -- the scan table with the launch envelopes, the waves' boxes and
+ * the wave flags -- live in one 32 MiB device array per GPU, which the
+ * library holds until the process ends; the table is uploaded from a static
+ * host array.  Limit: the table of a call, (n_steps + 1) * window records of
+ * 64 bytes plus the envelopes (at most (K + 1) * window records per launch)
+ * and 8 bytes per launch, must fit in 4 MiB (65,536 records), else
+ * MSTRUCT_EINVAL and nothing is enqueued; wave flags are used when at least
+ * one launch of them fits in the remaining 28 MiB (3 bytes per 64 points,
+ * plus 24 bytes per 64 points with an index list), otherwise the call runs
+ * without them (same results).  Every call on a GPU uses that GPU's one
+ * array: calls on different streams, or from different host threads, that
+ * overlap in time race on it; calls on one stream are ordered.  The host
+ * part of these calls is serialised by a lock, and each waits until the
+ * previous call's table upload has completed. */
+int mstruct_fused_scan_steps_noalloc(mstruct_ctx *ctx, const mstruct_scan *scan, const mstruct_points *pts,
+                                     double t0, double dt, int64_t n_steps, int K, int mode,
+                                     const mstruct_phases *ph, void *stream);
+
 /* Context options (value 0 or 1).
  * MSTRUCT_OPTION_SKIP_COLD_WAVES (default 1): before each launch of fused
  * PLAIN or IMPLICIT mode the host lists every track that occupies a window

@@ -58,7 +58,8 @@ class PointsC(ctypes.Structure):
 
 
 EXPORTS = ("mstruct_init", "mstruct_destroy", "mstruct_status_string", "mstruct_last_error", "mstruct_step",
-           "mstruct_step_implicit", "mstruct_implicit_unconverged", "mstruct_set_option", "mstruct_step_f64", "mstruct_temperature", "mstruct_fused_scan_steps", "mstruct_gather", "mstruct_check_invariants",
+           "mstruct_step_implicit", "mstruct_implicit_unconverged", "mstruct_set_option", "mstruct_step_f64", "mstruct_temperature", "mstruct_fused_scan_steps",
+           "mstruct_fused_scan_steps_noalloc", "mstruct_gather", "mstruct_check_invariants",
            "mstruct_correct", "mstruct_mlp_set_params", "mstruct_mlp_get_params", "mstruct_mlp_forward",
            "mstruct_mlp_grad", "mstruct_mlp_train_step")
 
@@ -81,6 +82,7 @@ def lib() -> ctypes.CDLL:
             "mstruct_step_f64": [p, p, p, d, p, i, p],
             "mstruct_temperature": [p, p, p, d, p, p],
             "mstruct_fused_scan_steps": [p, p, p, d, d, i64, i, i, p, p],
+            "mstruct_fused_scan_steps_noalloc": [p, p, p, d, d, i64, i, i, p, p],
             "mstruct_gather": [p, p, p, i64, p, p], "mstruct_check_invariants": [p, p, p, ctypes.c_float, p, p],
             "mstruct_correct": [p, p, p, p],
             "mstruct_mlp_set_params": [p, p, p, p, p, p], "mstruct_mlp_get_params": [p, p],
@@ -218,6 +220,17 @@ class Context:
         self._check(lib().mstruct_fused_scan_steps(self._h, ctypes.byref(sc), ctypes.byref(pts), float(t0),
                                                    float(dt), int(n_steps), int(K), int(mode), ctypes.byref(ph),
                                                    _stream(stream)), "mstruct_fused_scan_steps")
+
+    def fused_scan_steps_noalloc(self, scan, grid, t0, dt, n_steps, K, beta, alpha_s, alpha_m, z_top=math.inf,
+                                 mode=MODE_PLAIN, index=None, xbt=None, stream=None):
+        """fused_scan_steps without device allocations (PLAIN and IMPLICIT
+        modes; the library's fixed per-GPU array holds the call's buffers)."""
+        ph = self._phases(beta, alpha_s, alpha_m, xbt)
+        sc, pts = scan_struct(scan), points_struct(grid, ph.n, z_top, index)
+        self._check(lib().mstruct_fused_scan_steps_noalloc(self._h, ctypes.byref(sc), ctypes.byref(pts), float(t0),
+                                                           float(dt), int(n_steps), int(K), int(mode),
+                                                           ctypes.byref(ph), _stream(stream)),
+                    "mstruct_fused_scan_steps_noalloc")
 
     def gather(self, src, idx, dst, stream=None):
         import torch

@@ -4,6 +4,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 
 #include "../../include/mstruct.h"
@@ -15,6 +16,9 @@ using namespace mstruct;
 namespace {
 
 constexpr int kSlots = 4;  // tables in flight per context
+
+// set-up of the allocation-free fused call's device array (see below)
+int scratch_setup(int device);
 
 struct TableSlot {
     SrcRec* host = nullptr;  // pinned staging
@@ -348,7 +352,8 @@ int mstruct_init(int device, mstruct_ctx** out) {
         return MSTRUCT_ENOMEM;
     }
     const unsigned long long zero = 0;
-    if (hipMemcpy(ctx->implicit_bad, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess) {
+    if (hipMemcpy(ctx->implicit_bad, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess ||
+        scratch_setup(device) != MSTRUCT_OK) {
         (void)hipFree(ctx->counter);
         (void)hipFree(ctx->implicit_bad);
         delete ctx;
@@ -580,6 +585,40 @@ int fused_run(mstruct_ctx* ctx, const mstruct_scan* scan, const mstruct_points* 
     return MSTRUCT_OK;
 }
 
+// ---- the device array of the allocation-free fused call ----
+// One array per GPU, for the life of the process (a static __device__
+// variable; the host code reaches it only through the address
+// hipGetSymbolAddress gives on each device): the scan table (kScratchTable
+// bytes), then the waves' boxes and the wave flags.  Its table is uploaded
+// from a static host array of the same size, one call at a time.
+constexpr size_t kScratchTable = (size_t)4 << 20;
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
+
+struct ScratchState {
+    std::mutex lock;                             // the host staging array, one call at a time
+    uint8_t* dev[kScratchDevices] = {};          // address of `scratch` on each device (nullptr: not set up)
+    hipEvent_t uploaded[kScratchDevices] = {};   // the last upload from the staging array on each device
+    hipEvent_t pending = nullptr;                // the last upload that may still read the staging array
+};
+ScratchState g_scratch;
+alignas(256) SrcRec g_scratch_stage[kScratchTable / sizeof(SrcRec)];
+
+// once per device, with the device current (called by mstruct_init)
+int scratch_setup(int device) {
+    if (device >= kScratchDevices) return MSTRUCT_OK;  // the allocation-free call is not available there
+    std::lock_guard<std::mutex> g(g_scratch.lock);
+    if (g_scratch.dev[device]) return MSTRUCT_OK;
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return MSTRUCT_EDEVICE;
+    hipEvent_t ev = nullptr;
+    if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return MSTRUCT_EDEVICE;
+    g_scratch.uploaded[device] = ev;
+    g_scratch.dev[device] = static_cast<uint8_t*>(ptr);
+    return MSTRUCT_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -636,6 +675,56 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
     rc = fused_run(ctx, scan, pts, pg, p, t0, dt, n_steps, K, mode, ph, b, nullptr, st);
     const int rc2 = release_slot(ctx, s, st);
     return rc ? rc : rc2;
+}
+
+int mstruct_fused_scan_steps_noalloc(mstruct_ctx* ctx, const mstruct_scan* scan, const mstruct_points* pts,
+                                     double t0, double dt, int64_t n_steps, int K, int mode, const mstruct_phases* ph,
+                                     void* stream) {
+    if (ctx && mode == MSTRUCT_MODE_SURROGATE)
+        return fail(ctx, MSTRUCT_EUNSUPPORTED, "the allocation-free call runs PLAIN and IMPLICIT modes only");
+    PointGeom pg;
+    int rc = fused_check(ctx, scan, pts, t0, dt, n_steps, K, mode, ph, pg);
+    if (rc < 0) return rc;
+    const FusedPlan p = rc > 0 ? FusedPlan{} : fused_plan(scan, pg, n_steps, K);
+    // the table must fit; the exact envelope count is checked as it is built
+    if (rc == 0 && (p.recs + p.fc_recs) * sizeof(SrcRec) > kScratchTable) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "%zu table records exceed the allocation-free limit of %zu",
+                 p.recs + p.fc_recs, kScratchTable / sizeof(SrcRec));
+        return fail(ctx, MSTRUCT_EINVAL, "%s", buf);
+    }
+    if (ctx->device >= kScratchDevices || !g_scratch.dev[ctx->device])
+        return fail(ctx, MSTRUCT_EUNSUPPORTED, "no allocation-free array on this device");
+    if (rc > 0) return MSTRUCT_OK;
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    uint8_t* base = g_scratch.dev[ctx->device];
+    FusedBufs b;
+    b.host = g_scratch_stage;
+    b.dev = reinterpret_cast<SrcRec*>(base);
+    b.cap = kScratchTable / sizeof(SrcRec);
+    // wave boxes (index lists) and flags in the rest of the array, as many
+    // launches of still flags per chunk as fit; without room for one launch
+    // the call runs without wave flags (the same results bit for bit)
+    if (ctx->skip_cold && !ph->xbt) {
+        const size_t box_bytes = pts->index ? (((size_t)p.n_waves * sizeof(GridBox) + 255) & ~(size_t)255) : 0;
+        const size_t room = kScratchBytes - kScratchTable;
+        const int64_t per_wave = box_bytes < room ? (int64_t)((room - box_bytes) / (size_t)p.n_waves) : 0;
+        int64_t chunk = per_wave - 2;
+        if (chunk >= 1) {
+            b.boxes = pts->index ? reinterpret_cast<GridBox*>(base + kScratchTable) : nullptr;
+            b.flags = base + kScratchTable + box_bytes;
+            b.chunk = chunk > p.n_launches ? p.n_launches : chunk;
+        }
+    }
+    std::lock_guard<std::mutex> lk(g_scratch.lock);
+    // the staging array is rewritten only after the last upload from it is done
+    if (g_scratch.pending) HIP_CHECK(ctx, hipEventSynchronize(g_scratch.pending));
+    g_scratch.pending = nullptr;
+    rc = fused_run(ctx, scan, pts, pg, p, t0, dt, n_steps, K, mode, ph, b, g_scratch.uploaded[ctx->device], st);
+    // (if the upload was not enqueued, the event holds an earlier, harmless record)
+    g_scratch.pending = g_scratch.uploaded[ctx->device];
+    return rc;
 }
 
 int mstruct_set_option(mstruct_ctx* ctx, int option, int value) {
