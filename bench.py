@@ -5,9 +5,12 @@ MI355X.
 One benchmark step = one whole run of the workload from the initial state
 through every layer (all 20,000 time steps; 150,077,440,000 active
 point-updates) with the temperature evaluated from the scan inside the fused
-kernel (K = 64 steps per launch).  `value` is the plain float32 path; the
-`surrogate` entries are the same workload with the learned surrogate (K = 8
-and K = 16 networks).
+kernel (K = 64 steps per launch).  `value` is the plain float32 path.  The
+same JSON line carries the surrogate on the same workload, the unfused and
+implicit steps, the cool-down workload, the 33.5M-point masked cantilever
+with island scan (`c3`), the 67M-point island block at full length, plain
+and surrogate side by side (`c5`), the oracle timed on the host cores
+(`cpu_baseline`) and the paper's own CPU figures (`paper_cpu`).
 Prints one JSON line.
 """
 from __future__ import annotations
@@ -28,25 +31,53 @@ import workload  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
 FP32_VECTOR_PEAK_TFLOPS = 157.3
-# VALU ceiling in lane-ops: the FP32 vector peak counts 2 FLOPs per FMA lane-op,
-# i.e. 256 CUs x 128 lane-ops/clock x 2.4 GHz = 78.6 T lane-ops/s
+# VALU issue ceiling in lane-ops: 256 CUs x 4 SIMDs x 2 wave64 VALU
+# instructions per 4 cycles (a SIMD can issue two VALU instructions in one
+# quad-cycle: SQ_ACTIVE_INST_VALU2) x 64 lanes x 2.4 GHz = 78.6 T lane-ops/s,
+# the FP32 vector peak of 157.3 TFLOP/s at 2 FLOPs per FMA lane-op.  Measured
+# on the calibration probes: unpacked v_fmamk_f32 chains 48.5 T, v_exp_f32
+# 18.6 T (profiles/valu_probes_calibration.txt).
 VALU_PEAK_TLANEOPS = FP32_VECTOR_PEAK_TFLOPS / 2
+PEAK_DERIVATION = ("256 CUs x 4 SIMDs x 2 wave64 VALU instructions per quad-cycle (dual issue, "
+                   "SQ_ACTIVE_INST_VALU2) x 64 lanes x 2.4 GHz = 78.65 T lane-ops/s = 157.3 TFLOP/s / 2")
 K_FUSED = 64
+K_C3 = 16  # the masked cantilever's configuration names K = 16
 K_SURROGATE = 8
 STEP_BYTES = 28  # plain step: reads alpha_s, alpha_m, T^n, T^{n+1}; writes beta, alpha_s, alpha_m (float32)
 
+# The paper's own CPU figures (Sec. 4.1, hardware of Sec. 4).  A DoF is one
+# phase fraction: 3 per point (Sec. 3.2: 24 B per DoF, 72 B per point).
+PAPER_CPU = {
+    "source": "Sec. 4.1 (explicit step on synthetic data layouts) and Sec. 4 (hardware); 3 DoF per point",
+    "intel_node": {
+        "hardware": "2x Intel Xeon Gold 6230 (40 cores, 2.1 GHz), DAXPY 162 GB/s, 2.5 TFLOP/s",
+        "explicit_step_plateau": "above 6 GDoF/s, i.e. above 2.0e9 point-updates/s (FP64, AVX-512)",
+        "explicit_step_plateau_point_updates_s": 2.0e9,
+        "memory_bound_point_updates_s": 162e9 / 72.0,
+    },
+    "amd_node": {
+        "hardware": "2x AMD EPYC 9354 (64 cores, 3.25 GHz), DAXPY 617 GB/s, 3.75 TFLOP/s",
+        "memory_bound_point_updates_s": 617e9 / 72.0,
+        "note": "derived here from 617 GB/s and 72 B per point; the paper prints no throughput for this node",
+    },
+}
 
-def fused_bytes_per_launch(wl, K, read, written):
-    """Algorithmic HBM bytes per fused launch, averaged over the run: alpha_s,
-    alpha_m are read (8 B) for the fraction `read` of the active points whose
-    wave does not exit on its flags, and written (8 B) for the fraction
-    `written` whose wave is not still; the last launch of each call (one per
-    layer) also writes beta (4 B per active point)."""
-    g = wl.grid
-    pts = [(g.nz - g.first_active_k(L.z_top)) * g.nx * g.ny for L in wl.layers]
-    launches = [math.ceil((L.step_end - L.step_begin) / K) for L in wl.layers]
-    state = sum(n * p for n, p in zip(launches, pts)) * (8.0 * read + 8.0 * written)
-    return (state + 4.0 * sum(pts)) / sum(launches)
+# Per-kernel figures from rocprofv3 counter runs of this script (the profile
+# files named below): executed VALU instructions x 64 per point-update, the
+# VALU-busy fraction (VALUBusy) and the fraction of VALU quad-cycles with a
+# second instruction issued (SQ_ACTIVE_INST_VALU2 / SQ_ACTIVE_INST_VALU), and
+# HBM bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0: the factors a
+# plain 1 GiB device copy reads on the same counters).  Each holds for the
+# launch size K it was taken at; at another K the figures are reported null.
+FUSED_PROFILE = {
+    "file": "profiles/fused_plain_kernel_multilayer_block.txt", "K": 64,
+    "valu_lane_ops_per_update": 10.26, "valu_busy": None, "dual_issue": None,
+    "traffic_bytes_per_launch": (3364.18 * 2.0 + 3476.92) * 1024,
+}
+FUSED_PROFILE_EVERY_T = {"K": 64, "valu_lane_ops_per_update": 128.07, "valu_busy": None}
+C3_PROFILE = {"file": "profiles/fused_plain_kernel_cantilever_islands.txt", "K": K_C3,
+              "valu_lane_ops_per_update": None, "valu_busy": None, "dual_issue": None,
+              "traffic_bytes_per_launch": None}
 
 
 def parse():
@@ -56,17 +87,96 @@ def parse():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--K", type=int, default=K_FUSED)
     ap.add_argument("--sample", type=float, default=1e-2, help="oracle sample fraction (cpu_baseline, errors)")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="no oracle runs (no errors either)")
     ap.add_argument("--no-stepwise", action="store_true")
     ap.add_argument("--no-surrogate", action="store_true")
     ap.add_argument("--no-cooldown", action="store_true")
-    ap.add_argument("--copy-probe", action="store_true",
-                    help="also run a plain 1 GiB device copy (counter calibration under rocprofv3)")
-    ap.add_argument("--threads", type=int, default=0)
-    ap.add_argument("--island-block", action="store_true",
-                    help="instead: the 512x512x256 island block (100 layers, 200,000 steps), plain K = 16 and "
-                         "surrogate K = 8 side by side, errors on a 0.1 %% sample")
-    return ap.parse_args()
+    ap.add_argument("--no-c3", action="store_true")
+    ap.add_argument("--no-c5", action="store_true")
+    ap.add_argument("--only", choices=("c2", "c3", "c5"),
+                    help="one workload only, without the oracle (profiling runs)")
+    ap.add_argument("--threads", type=int, default=0, help="oracle threads (default: OpenMP's, all host cores)")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="instead: the VALU probes (FMA, exp, both) and a 1 GiB device copy, timed, for the "
+                         "counter calibration under rocprofv3")
+    args = ap.parse_args()
+    if args.only:
+        args.no_cpu_baseline = True
+        args.no_stepwise = args.no_cooldown = True
+        args.no_c3 = args.only != "c3"
+        args.no_c5 = args.only != "c5"
+        args.no_surrogate = args.only == "c3"
+    return args
+
+
+def _timer(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def call_launches(wl, K):
+    """Fused launches of one run of a layered workload (one call per layer)."""
+    return sum(math.ceil((L.step_end - L.step_begin) / K) for L in wl.layers)
+
+
+def point_launches(wl, K):
+    """Active points summed over the launches of one run."""
+    return sum(wl.active_count(L.z_top) * math.ceil((L.step_end - L.step_begin) / K) for L in wl.layers)
+
+
+def counted_run(torch, ms, ctx, wl, K, index=None):
+    """One untimed run with the device-side wave counts on: the points whose
+    state the fused launches read and wrote (waves that do not exit on their
+    flags, waves that are not still), the waves by class, and the hot waves'
+    sub-blocks that the surrogate's indicator would allow.  Results are the
+    same bits as without the counts."""
+    g = [torch.from_numpy(x).cuda() for x in workload.initial_state(wl.grid.n, np.float32)]
+    ctx.set_option(ms.OPTION_COUNT_WAVES, 1)
+    ctx.wave_counts(reset=True)
+    try:
+        ms.run_layers(ctx, wl, *g, K=K, index=index)
+        c = ctx.wave_counts(reset=True)
+    finally:
+        ctx.set_option(ms.OPTION_COUNT_WAVES, 0)
+    total = point_launches(wl, K)
+    beta_pts = sum(wl.active_count(L.z_top) for L in wl.layers)
+    launches = call_launches(wl, K)
+    idx_bytes = 4 if wl.grid.index is not None else 0  # index entry of each point a wave decodes
+    alg = 8.0 * c["points_loaded"] + 8.0 * c["points_stored"] + 4.0 * beta_pts + idx_bytes * c["points_loaded"]
+    waves = c["still_waves"] + c["cold_waves"] + c["hot_waves"] + c["flagged_waves"]
+    out = {"counts": c, "point_launches": total, "read_fraction": c["points_loaded"] / total,
+           "written_fraction": c["points_stored"] / total,
+           "wave_classes": {k: c[k] / waves for k in ("flagged_waves", "still_waves", "cold_waves", "hot_waves")},
+           "algorithmic_bytes_per_launch": alg / launches,
+           "bytes_rule": f"8 B read per point of the waves that read their state, 8 B written per point of the "
+                         f"waves that are not still, 4 B of beta per active point once per call"
+                         + (", 4 B of index per point read" if idx_bytes else "")}
+    if c["hot_subblocks"]:
+        s = c["indicator_subblocks"] / c["hot_subblocks"]
+        out["surrogate_share_of_hot_subblocks"] = s
+    return out
+
+
+def fused_roofline(kernel, prof, K, rate, avg_launch_s, counts):
+    """The fused kernels' roofline entry: VALU-bound.  achieved = point-updates
+    per second inside a launch (live HIP-event time) x the profile's executed
+    VALU lane-ops per update; traffic from the profile's counters; the
+    algorithmic bytes from this run's device-side counts."""
+    ok = prof["K"] == K
+    ops = prof["valu_lane_ops_per_update"] if ok else None
+    traffic = prof["traffic_bytes_per_launch"] if ok else None
+    alg = counts["algorithmic_bytes_per_launch"] if counts else None
+    r = {"kernel": kernel, "bound": "alu",
+         "achieved": rate * ops / 1e12 if ops else None, "peak": VALU_PEAK_TLANEOPS, "unit": "Tlane-op/s",
+         "frac": rate * ops / 1e12 / VALU_PEAK_TLANEOPS if ops else None,
+         "traffic": traffic, "traffic_unit": "bytes/launch",
+         "algorithmic_bytes_per_launch": alg,
+         "traffic_over_algorithmic": traffic / alg if traffic and alg else None,
+         "hbm_GBs": alg / avg_launch_s / 1e9 if alg else None,
+         "lane_ops_per_update": ops, "valu_busy_frac": prof.get("valu_busy") if ok else None,
+         "dual_issue_frac": prof.get("dual_issue") if ok else None,
+         "peak_derivation": PEAK_DERIVATION, "avg_launch_us": avg_launch_s * 1e6,
+         "point_updates_per_s_in_launch": rate, "profile": prof.get("file"), "profile_K": prof["K"]}
+    return r
 
 
 def main():
@@ -79,15 +189,62 @@ def main():
 
     import paper_2402_17580_amd as ms
 
-    if args.island_block:
-        print(json.dumps(bench_island_block(torch, ms, args)))
+    if args.calibrate:
+        print(json.dumps(bench_calibrate(torch)))
         return
+    ctx = ms.Context(0)
+    result = {}
+    states = {}
+    if args.only in (None, "c2"):
+        result, states = bench_c2(torch, ms, ctx, args)
+    else:
+        result = {"metric": f"profiling run: {args.only} only", "value": None}
+    wl = workload.multilayer_block()
+    if not args.no_stepwise:
+        result["plain_step"] = bench_stepwise(torch, ms, ctx, wl, torch.device("cuda:0"))
+        result["implicit_step"] = bench_implicit(torch, ms, ctx, wl, states["plain"])
+        result["divergence"] = bench_divergence(torch, ctx, wl.grid.n)
+        result["f64_step"] = bench_f64(torch, ms, ctx, wl, states["plain"])
+    if not args.no_cooldown:
+        result["cooldown"], states["cooldown"] = bench_cooldown(torch, ms, ctx)
+    if not args.no_c3:
+        result["c3"], states["c3"] = bench_c3(torch, ms, ctx, args)
+    if not args.no_c5:
+        result["c5"], states["c5"] = bench_c5(torch, ms, ctx, args)
+
+    if not args.no_cpu_baseline:
+        import oracle
+        threads = args.threads or oracle.num_threads()
+        base, st, idx = cpu_baseline(wl, args, threads)
+        base["gpu_vs_oracle"] = result["value"] / base["value"]
+        result["cpu_baseline"] = base
+        result["errors_vs_oracle"] = errors(states["plain"], st, idx)
+        for key in ("surrogate", "surrogate_k16"):
+            if key in states:
+                result[key]["errors_vs_oracle"] = errors(states[key], st, idx)
+        if "cooldown" in states:
+            pw = workload.multilayer_cooldown()
+            cidx = workload.sample_indices(pw.grid.n, 1e-3, pw.seed)
+            cst, _ = oracle.run_phases(pw, cidx, threads=threads)
+            result["cooldown"]["errors_vs_oracle"] = errors(states["cooldown"], cst, cidx)
+            result["cooldown"]["errors_sample"] = f"{cidx.size} seeded points (p=1e-3)"
+        if "c3" in states:
+            oracle_errors_layered(result["c3"], states["c3"], workload.cantilever_islands(), threads)
+        if "c5" in states:
+            oracle_errors_layered(result["c5"], states["c5"], workload.island_block(), threads)
+    result["paper_cpu"] = PAPER_CPU
+    print(json.dumps(result))
+    ctx.close()
+
+
+def bench_c2(torch, ms, ctx, args):
+    """The metric workload: the plain fused path timed over `steps` whole
+    runs, its launch certificates off for comparison, and the surrogate."""
     dev = torch.device("cuda:0")
     wl = workload.multilayer_block()
     n = wl.grid.n
     updates = wl.point_updates()
-    launches = sum(math.ceil((L.step_end - L.step_begin) / args.K) for L in wl.layers)
-    ctx = ms.Context(0)
+    launches = call_launches(wl, args.K)
     init = [torch.from_numpy(x).to(dev) for x in workload.initial_state(n, np.float32)]
     b, a, m = [x.clone() for x in init]
 
@@ -103,7 +260,7 @@ def main():
         for _ in range(args.warmup):
             one_step()
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0, e1 = _timer(torch)
         e0.record()
         w0 = time.perf_counter()
         for _ in range(args.steps):
@@ -116,12 +273,10 @@ def main():
     ms_per_step = ms_total / args.steps
     value = updates * args.steps / (ms_total * 1e-3)
     # average duration of one fused launch over the timed region (the fused
-    # kernel is the only kernel in it besides three state resets per step)
+    # kernels are the only kernels in it besides the still-flag pre-pass, one
+    # per call, and three state resets per step)
     avg_launch_s = ms_total * 1e-3 / (args.steps * launches)
-    upd_per_launch = updates / launches
-    bytes_per_launch = fused_bytes_per_launch(wl, args.K, FUSED_PROFILE["read_fraction"],
-                                              FUSED_PROFILE["written_fraction"])
-
+    rate = updates / launches / avg_launch_s  # point-updates/s inside one launch
     result = {
         "metric": "microstructure point-updates/s @8.4M pts (256x256x128 block, 10 layers, 20k steps): FP32 plain",
         "value": value,
@@ -140,122 +295,184 @@ def main():
                    "K": args.K, "window": wl.scan.window, "path": "fused (mstruct_fused_scan_steps, PLAIN)"},
         "wall_s_timed": wall,
     }
-    rate = upd_per_launch / avg_launch_s  # point-updates/s inside one launch
-    ops = FUSED_PROFILE["valu_lane_ops_per_update"]
-    result["roofline"] = {
-        "kernel": f"fused_plain_kernel<{wl.scan.window}> (first launch of each call) + "
-                  f"fused_plain_slots_kernel<{wl.scan.window}> (the others)",
-        "bound": "alu",
-        "achieved": rate * ops / 1e12,
-        "peak": VALU_PEAK_TLANEOPS,
-        "unit": "Tlane-op/s",
-        "frac": rate * ops / 1e12 / VALU_PEAK_TLANEOPS,
-        "traffic": FUSED_PROFILE["traffic_bytes_per_launch"] if args.K == K_FUSED else None,
-        "traffic_unit": "bytes/launch",
-        "algorithmic_bytes_per_launch": bytes_per_launch,
-        "lane_ops_per_update": ops,
-        "fp32_tflops": rate * FUSED_PROFILE["fp32_flops_per_update"] / 1e12,
-        "fp32_tflops_peak": FP32_VECTOR_PEAK_TFLOPS,
-        "hbm_GBs": bytes_per_launch / avg_launch_s / 1e9,
-        "avg_launch_us": avg_launch_s * 1e6,
-        "launches_timed": args.steps * launches,
-    }
-    final_state = [x.clone() for x in (b, a, m)]
+    final = [x.clone() for x in (b, a, m)]
+    counts = counted_run(torch, ms, ctx, wl, args.K)
+    result["roofline"] = fused_roofline(
+        f"fused_plain_kernel<{wl.scan.window}> (first launch of each call) + "
+        f"fused_plain_slots_kernel<{wl.scan.window}> (the others)", FUSED_PROFILE, args.K, rate, avg_launch_s, counts)
+    result["roofline"]["launches_timed"] = args.steps * launches
+    result["wave_counts"] = counts
 
-    # the same run with every temperature evaluated (cold-wave certificate
+    # the same run with every temperature evaluated (launch certificates
     # off): the same bits, for comparison
     ctx.set_option(ms.OPTION_SKIP_COLD_WAVES, 0)
     ms_all, _ = timed(ms.MODE_PLAIN, args.K)
     ctx.set_option(ms.OPTION_SKIP_COLD_WAVES, 1)
     avg_all_s = ms_all * 1e-3 / (args.steps * launches)
-    ops_all = FUSED_PROFILE_EVERY_T["valu_lane_ops_per_update"]
+    ok = FUSED_PROFILE_EVERY_T["K"] == args.K
+    ops_all = FUSED_PROFILE_EVERY_T["valu_lane_ops_per_update"] if ok else None
+    rate_all = updates / launches / avg_all_s
     result["plain_every_temperature"] = {
         "value": updates * args.steps / (ms_all * 1e-3), "unit": "point-updates/s",
         "ms_per_step": ms_all / args.steps, "value_speedup": ms_all / ms_total,
-        "bitwise_equal_to_value_run": all(bool(torch.equal(x, y)) for x, y in zip((b, a, m), final_state)),
+        "bitwise_equal_to_value_run": all(bool(torch.equal(x, y)) for x, y in zip((b, a, m), final)),
         "roofline": {"kernel": f"fused_plain_kernel<{wl.scan.window}>", "bound": "alu",
-                     "achieved": upd_per_launch / avg_all_s * ops_all / 1e12, "peak": VALU_PEAK_TLANEOPS,
-                     "unit": "Tlane-op/s", "frac": upd_per_launch / avg_all_s * ops_all / 1e12 / VALU_PEAK_TLANEOPS,
-                     "lane_ops_per_update": ops_all, "avg_launch_us": avg_all_s * 1e6},
+                     "achieved": rate_all * ops_all / 1e12 if ops_all else None, "peak": VALU_PEAK_TLANEOPS,
+                     "unit": "Tlane-op/s",
+                     "frac": rate_all * ops_all / 1e12 / VALU_PEAK_TLANEOPS if ops_all else None,
+                     "lane_ops_per_update": ops_all, "valu_busy_frac": FUSED_PROFILE_EVERY_T["valu_busy"] if ok else None,
+                     "avg_launch_us": avg_all_s * 1e6},
     }
-
-    sur_states = {}
+    states = {"plain": final}
     if not args.no_surrogate:
         from paper_2402_17580_amd import surrogate as S
         for key, path in (("surrogate", S.DEFAULT_WEIGHTS), ("surrogate_k16", S.WEIGHTS_K16)):
-            t_tr = 0.0
-            if os.path.exists(path):
-                sur = S.Surrogate.load(path)
-            else:
-                K_s = K_SURROGATE if key == "surrogate" else 16
-                t0 = time.perf_counter()
-                X, Y = S.generate_transitions(ctx, wl, K=K_s)
-                sur, _ = S.fit(ctx, X, Y, K_s)
-                t_tr = time.perf_counter() - t0
+            sur = S.Surrogate.load(path)
             sur.load_into(ctx)
             ms_sur, _ = timed(ms.MODE_SURROGATE, sur.K)
-            sur_states[key] = [x.clone() for x in (b, a, m)]
+            states[key] = [x.clone() for x in (b, a, m)]
             result[key] = {
                 "value": updates * args.steps / (ms_sur * 1e-3), "unit": "point-updates/s",
                 "ms_per_step": ms_sur / args.steps, "speedup_vs_plain": ms_total / ms_sur,
-                "speedup_vs_plain_every_temperature": ms_all / ms_sur, "K": sur.K,
+                "target_speedup_vs_plain": 3.0, "target_met": ms_total / ms_sur >= 3.0, "K": sur.K,
                 "path": "mstruct_fused_scan_steps, SURROGATE: one explicit step of K dt + BF16-MFMA network "
                         "correction where the indicator allows, K plain steps elsewhere",
-                "indicator": list(sur.indicator), "trained_in_bench_s": t_tr,
+                "indicator": list(sur.indicator),
             }
+        if "surrogate_share_of_hot_subblocks" in counts:
+            result["surrogate_ceiling"] = surrogate_ceiling(counts, ms_total, launches * args.steps)
+    return result, states
 
-    if not args.no_stepwise:
-        result["plain_step"] = bench_stepwise(torch, ms, ctx, wl, dev)
-        result["implicit_step"] = bench_implicit(torch, ms, ctx, wl, final_state)
-        result["divergence"] = bench_divergence(torch, ctx, n)
-        result["f64_step"] = bench_f64(torch, ms, ctx, wl, final_state)
-    if not args.no_cooldown:
-        result["cooldown"], cool_state = bench_cooldown(torch, ms, ctx)
 
-    if args.copy_probe:
-        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        src.fill_(1.0)
-        for _ in range(3):
-            dst.copy_(src)
+def surrogate_ceiling(counts, ms_total, launches):
+    """Bound on the surrogate's speedup over the plain path from the counted
+    run: the plain launches' time is set by their hot waves, and the
+    indicator lets the network replace a hot wave's sub-block of 8 steps only
+    where every point of the wave passes it.  If every such sub-block cost
+    nothing, and nothing else changed, the run would take (1 - s) of its
+    time; at one temperature evaluation and one step per sub-block instead
+    of eight, 1 - s (1 - 1/8)."""
+    s = counts["surrogate_share_of_hot_subblocks"]
+    return {"indicator_share_of_hot_subblocks": s, "speedup_bound_free": 1.0 / (1.0 - s) if s < 1 else None,
+            "speedup_bound_one_step_per_subblock": 1.0 / (1.0 - s * 7.0 / 8.0),
+            "hot_subblocks": counts["counts"]["hot_subblocks"],
+            "indicator_subblocks": counts["counts"]["indicator_subblocks"]}
+
+
+def bench_c3(torch, ms, ctx, args):
+    """The masked cantilever (32.4M points of a 1024x512x128 box, seeded
+    legs, 10 layers of 30 um, 5 mm islands, 50,000 steps of 2 us) on the
+    plain fused path at K = 16: one warm-up run, one timed run, its roofline
+    and its wave counts."""
+    wl = workload.cantilever_islands()
+    n = wl.grid.n
+    idx = torch.from_numpy(wl.grid.index).cuda()
+    upd = wl.point_updates()
+    K = K_C3
+    g = [torch.from_numpy(x).cuda() for x in workload.initial_state(n, np.float32)]
+    ms.run_layers(ctx, wl, *g, K=K, index=idx)  # warm-up
+    for dst, src in zip(g, workload.initial_state(n, np.float32)):
+        dst.copy_(torch.from_numpy(src))
+    torch.cuda.synchronize()
+    e0, e1 = _timer(torch)
+    e0.record()
+    ms.run_layers(ctx, wl, *g, K=K, index=idx)
+    e1.record()
+    torch.cuda.synchronize()
+    t = e0.elapsed_time(e1) * 1e-3
+    launches = call_launches(wl, K)
+    avg = t / launches
+    counts = counted_run(torch, ms, ctx, wl, K, index=idx)
+    out = {"workload": "cantilever_islands", "points": n, "box": [wl.grid.nx, wl.grid.ny, wl.grid.nz],
+           "layers": len(wl.layers), "time_steps": wl.n_steps, "active_point_updates": upd, "K": K,
+           "seconds": t, "value": upd / t, "unit": "point-updates/s",
+           "roofline": fused_roofline("fused_plain_kernel<2> + fused_plain_slots_kernel<2> (index list)",
+                                      C3_PROFILE, K, upd / launches / avg, avg, counts),
+           "wave_counts": counts}
+    print(f"c3: {t:.2f} s", file=sys.stderr, flush=True)
+    return out, g
+
+
+def bench_c5(torch, ms, ctx, args):
+    """The 64M-point island block at full length (512x512x256 points, 100
+    layers of 20 um, 2000 steps of 2 us each): the plain fused path (K = 64)
+    and the surrogate (K = 8 network) one after the other on the same GPU,
+    each timed once."""
+    from paper_2402_17580_amd import surrogate as S
+    wl = workload.island_block()
+    n = wl.grid.n
+    upd = wl.point_updates()
+    out = {"workload": "island_block", "points": n, "layers": len(wl.layers), "time_steps": wl.n_steps,
+           "active_point_updates": upd}
+    states = {}
+    for key, mode, K in (("plain", ms.MODE_PLAIN, K_FUSED), ("surrogate", ms.MODE_SURROGATE, K_SURROGATE)):
+        if mode == ms.MODE_SURROGATE:
+            S.Surrogate.load(S.DEFAULT_WEIGHTS).load_into(ctx)
+        g = [torch.from_numpy(x).cuda() for x in workload.initial_state(n, np.float32)]
         torch.cuda.synchronize()
-        result["copy_probe_bytes"] = {"read": src.numel() * 4, "write": src.numel() * 4}
-
-    if not args.no_cpu_baseline:
-        base, st, idx = cpu_baseline(wl, args)
-        base["gpu_vs_oracle"] = result["value"] / base["value"]
-        result["cpu_baseline"] = base
-        result["errors_vs_oracle"] = errors(final_state, st, idx)
-        for key, state in sur_states.items():
-            result[key]["errors_vs_oracle"] = errors(state, st, idx)
-        if not args.no_cooldown:
-            import oracle
-            pw = workload.multilayer_cooldown()
-            cidx = workload.sample_indices(pw.grid.n, 1e-3, pw.seed)
-            cst, _ = oracle.run_phases(pw, cidx, threads=args.threads or min(16, os.cpu_count() or 1))
-            result["cooldown"]["errors_vs_oracle"] = errors(cool_state, cst, cidx)
-            result["cooldown"]["errors_sample"] = f"{cidx.size} seeded points (p=1e-3)"
-
-    print(json.dumps(result))
-    ctx.close()
+        e0, e1 = _timer(torch)
+        e0.record()
+        ms.run_layers(ctx, wl, *g, K=K, mode=mode)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) * 1e-3
+        out[key] = {"seconds": t, "value": upd / t, "unit": "point-updates/s", "K": K}
+        print(f"c5 {key}: {t:.2f} s", file=sys.stderr, flush=True)
+        states[key] = g
+    out["surrogate"]["speedup_vs_plain"] = out["plain"]["seconds"] / out["surrogate"]["seconds"]
+    return out, states
 
 
-# Per-kernel figures of the fused kernel on this workload, from rocprofv3
-# counter runs of this script (profiles/fused_plain_kernel_multilayer_block.txt):
-# executed VALU instructions x 64 lanes and FP32 FLOPs per point-update, and
-# HBM bytes per launch (FETCH_SIZE x 2.0 and WRITE_SIZE x 1.0: the factors a
-# plain 1 GiB device copy reads on the same counters), and the fractions of
-# the points whose state the kernel reads (waves that do not exit on their
-# flags) and writes (waves that are not still), at K = 64.
-# the same kernel with every temperature evaluated (MSTRUCT_OPTION_SKIP_COLD_WAVES = 0)
-FUSED_PROFILE_EVERY_T = {"valu_lane_ops_per_update": 128.07}
-FUSED_PROFILE = {
-    "valu_lane_ops_per_update": 10.26,
-    "fp32_flops_per_update": 8.31,
-    "traffic_bytes_per_launch": (3364.18 * 2.0 + 3476.92) * 1024,
-    "read_fraction": 0.1148,
-    "written_fraction": 0.0437,
-}
+def oracle_errors_layered(entry, states, wl, threads):
+    """Errors of the GPU state(s) on a seeded 0.1 % sample against the
+    oracle, run ten layers per call with a progress line each."""
+    import oracle
+    idx = workload.sample_indices(wl.grid.n, 1e-3, wl.seed)
+    t0 = time.perf_counter()
+    st = None
+    for first in range(0, len(wl.layers), 10):
+        st = oracle.run_workload(wl, idx, state=st, threads=threads, layers=wl.layers[first:first + 10])
+        print(f"oracle {wl.name}: {min(first + 10, len(wl.layers))} layers, {time.perf_counter() - t0:.0f} s",
+              file=sys.stderr, flush=True)
+    el = time.perf_counter() - t0
+    entry["oracle"] = {"sample": f"{idx.size} seeded points (p=1e-3), all {wl.n_steps} steps", "seconds": el,
+                       "threads": threads}
+    if isinstance(states, dict):
+        for key, g in states.items():
+            entry[key]["errors_vs_oracle"] = errors(g, st, idx)
+    else:
+        entry["errors_vs_oracle"] = errors(states, st, idx)
+
+
+def cpu_baseline(wl, args, threads):
+    """The FP64 oracle on a seeded sample of the workload's points (all
+    20,000 steps), timed on the host cores (OpenMP's thread count: all the
+    cores the process may use, OMP_NUM_THREADS where it is set)."""
+    import oracle
+    idx = workload.sample_indices(wl.grid.n, args.sample, wl.seed)
+    xyz = wl.grid.coords(idx)
+    upd = sum(int(np.count_nonzero(xyz[:, 2] <= L.z_top + 1e-3 * wl.grid.h)) * (L.step_end - L.step_begin)
+              for L in wl.layers)
+    t0 = time.perf_counter()
+    st = oracle.run_workload(wl, idx, threads=threads)
+    el = time.perf_counter() - t0
+    base = {"value": upd / el, "unit": "point-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{idx.size} seeded points (p={args.sample}) x all 20,000 steps "
+                      f"({upd} point-updates, FP64, {el:.1f} s)",
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count(),
+            "omp_num_threads": os.environ.get("OMP_NUM_THREADS")}
+    # one core, on a 32 times smaller sample
+    idx1 = workload.sample_indices(wl.grid.n, args.sample / 32, wl.seed + 1)
+    xyz1 = wl.grid.coords(idx1)
+    upd1 = sum(int(np.count_nonzero(xyz1[:, 2] <= L.z_top + 1e-3 * wl.grid.h)) * (L.step_end - L.step_begin)
+               for L in wl.layers)
+    t0 = time.perf_counter()
+    oracle.run_workload(wl, idx1, threads=1)
+    el1 = time.perf_counter() - t0
+    base["single_core"] = {"value": upd1 / el1, "sample": f"{idx1.size} seeded points x all 20,000 steps "
+                                                          f"({upd1} point-updates, {el1:.1f} s)"}
+    return base, st, idx
+
 
 def bench_stepwise(torch, ms, ctx, wl, dev):
     """The unfused path: temperature-field kernel + plain step kernel per time
@@ -370,8 +587,10 @@ F64_STEP_BYTES = 56  # float64 step: reads alpha_s, alpha_m, T^n, T^{n+1}; write
 
 def bench_f64(torch, ms, ctx, wl, state):
     """The explicit step in float64 on all 8.4M points (state after the plain
-    run, top-layer temperatures at 2 us apart), with the device math library
-    and with exponent-bit exp2 / log2: HBM-bound at 56 bytes per point."""
+    run, top-layer temperatures at 2 us apart), with the device math library,
+    with exponent-bit exp2 / log2 of double accuracy, and with the paper's
+    own exp / ln (Sec. 3.3, its fitted correction polynomials): HBM-bound at
+    56 bytes per point."""
     n = wl.grid.n
     L = wl.layers[-1]
     Ta, Tb = torch.empty(n, device="cuda"), torch.empty(n, device="cuda")
@@ -381,7 +600,7 @@ def bench_f64(torch, ms, ctx, wl, state):
     Ta, Tb = Ta.double(), Tb.double()
     out = {"path": "mstruct_step_f64 on all points (state after the plain run, cast to float64)"}
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    for key, math_mode in (("library", ms.F64_LIBRARY), ("synth", ms.F64_SYNTH)):
+    for key, math_mode in (("library", ms.F64_LIBRARY), ("synth", ms.F64_SYNTH), ("paper", ms.F64_PAPER)):
         b, a, m = [x.double() for x in state]
         ctx.step_f64(Ta, Tb, wl.dt, b, a, m, math=math_mode)
         torch.cuda.synchronize()
@@ -453,33 +672,6 @@ def bench_divergence(torch, ctx, n):
     return out
 
 
-def cpu_baseline(wl, args):
-    """The FP64 oracle on a seeded sample of the workload's points (all
-    20,000 steps), timed on the host cores."""
-    import oracle
-    threads = args.threads or min(16, os.cpu_count() or 1)
-    idx = workload.sample_indices(wl.grid.n, args.sample, wl.seed)
-    xyz = wl.grid.coords(idx)
-    upd = sum(int(np.count_nonzero(xyz[:, 2] <= L.z_top + 1e-3 * wl.grid.h)) * (L.step_end - L.step_begin)
-              for L in wl.layers)
-    t0 = time.perf_counter()
-    st = oracle.run_workload(wl, idx, threads=threads)
-    el = time.perf_counter() - t0
-    base = {"value": upd / el, "unit": "point-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{idx.size} seeded points (p={args.sample}) x all 20,000 steps "
-                      f"({upd} point-updates, FP64, {el:.1f} s)",
-            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count()}
-    # one core, on a 32 times smaller sample
-    idx1 = workload.sample_indices(wl.grid.n, args.sample / 32, wl.seed + 1)
-    xyz1 = wl.grid.coords(idx1)
-    upd1 = sum(int(np.count_nonzero(xyz1[:, 2] <= L.z_top + 1e-3 * wl.grid.h)) * (L.step_end - L.step_begin)
-               for L in wl.layers)
-    t0 = time.perf_counter()
-    oracle.run_workload(wl, idx1, threads=1)
-    el1 = time.perf_counter() - t0
-    base["single_core"] = {"value": upd1 / el1, "sample": f"{idx1.size} seeded points x all 20,000 steps "
-                                                          f"({upd1} point-updates, {el1:.1f} s)"}
-    return base, st, idx
 
 
 def _cpu_model():
@@ -493,50 +685,52 @@ def _cpu_model():
     return None
 
 
-def bench_island_block(torch, ms, args):
-    """The 64M-point island block at full length (512x512x256 points, 100
-    layers of 20 um, 2000 steps of 2 us each): the plain fused path (K = 16)
-    and the surrogate (K = 8 network) one after the other on the same GPU,
-    each timed once, and both against the oracle on a seeded 0.1 % sample."""
-    import oracle
-    from paper_2402_17580_amd import surrogate as S
-    wl = workload.island_block()
-    n = wl.grid.n
-    upd = wl.point_updates()
-    ctx = ms.Context(0)
-    out = {"workload": "island_block", "points": n, "layers": len(wl.layers), "time_steps": wl.n_steps,
-           "active_point_updates": upd}
-    states = {}
-    for key, mode, K in (("plain", ms.MODE_PLAIN, 16), ("surrogate", ms.MODE_SURROGATE, 8)):
-        if mode == ms.MODE_SURROGATE:
-            sur = S.Surrogate.load(S.DEFAULT_WEIGHTS)
-            sur.load_into(ctx)
-        g = [torch.from_numpy(x).cuda() for x in workload.initial_state(n, np.float32)]
+
+
+def bench_calibrate(torch):
+    """Launches of known work for reading the counters: the VALU probes of
+    libmstruct_probe.so (8 independent chains per lane of v_fma_f32, of
+    v_exp_f32, or 16 of both interleaved; a known number of wave64 VALU
+    instructions per launch) and a plain 1 GiB device copy (known bytes)."""
+    import ctypes
+    L = ctypes.CDLL(os.path.join(ROOT, "paper_2402_17580_amd", "libmstruct_probe.so"))
+    L.probe_valu.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    L.probe_valu_insts_per_wave.restype = ctypes.c_int64
+    L.probe_valu_insts_per_wave.argtypes = [ctypes.c_int, ctypes.c_int]
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    blocks, iters, reps = 32 * cus, 20000, 5
+    waves = blocks * 256 // 64
+    out = torch.empty(blocks * 256, device="cuda")
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    res = {"compute_units": cus, "blocks": blocks, "threads_per_block": 256, "iters": iters}
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for kind, name in ((0, "fma"), (1, "exp"), (2, "fma_exp")):
+        assert L.probe_valu(kind, iters, blocks, ctypes.c_void_p(out.data_ptr()), st) == 0
         torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record()
-        ms.run_layers(ctx, wl, *g, K=K, mode=mode)
+        for _ in range(reps):
+            L.probe_valu(kind, iters, blocks, ctypes.c_void_p(out.data_ptr()), st)
         e1.record()
         torch.cuda.synchronize()
-        t = e0.elapsed_time(e1) * 1e-3
-        out[key] = {"seconds": t, "point_updates_per_s": upd / t, "K": K}
-        print(f"island block {key}: {t:.2f} s", file=sys.stderr, flush=True)
-        states[key] = g
-    out["surrogate"]["speedup_vs_plain"] = out["plain"]["seconds"] / out["surrogate"]["seconds"]
-    idx = workload.sample_indices(n, 1e-3, wl.seed)
-    t0 = time.perf_counter()
-    threads = args.threads or min(16, os.cpu_count() or 1)
-    st = None
-    for first in range(0, len(wl.layers), 10):  # ten layers per call, with a progress line each
-        st = oracle.run_workload(wl, idx, state=st, threads=threads, layers=wl.layers[first:first + 10])
-        print(f"oracle: {first + 10} layers, {time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
-    el = time.perf_counter() - t0
-    out["oracle"] = {"sample": f"{idx.size} seeded points (p=1e-3), all 200,000 steps", "seconds": el,
-                     "threads": threads}
-    for key, g in states.items():
-        out[key]["errors_vs_oracle"] = errors(g, st, idx)
-    ctx.close()
-    return out
+        avg = e0.elapsed_time(e1) * 1e-3 / reps
+        insts = waves * L.probe_valu_insts_per_wave(kind, iters)
+        res[name] = {"avg_launch_us": avg * 1e6, "wave_insts_per_launch": insts,
+                     "T_lane_ops_per_s": insts * 64 / avg / 1e12}
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    avg = e0.elapsed_time(e1) * 1e-3 / reps
+    res["copy"] = {"bytes_read": src.numel() * 4, "bytes_written": src.numel() * 4, "avg_launch_us": avg * 1e6,
+                   "GBs": 2 * src.numel() * 4 / avg / 1e9}
+    return res
+
+
 
 
 def errors(state, st, idx):
@@ -545,6 +739,7 @@ def errors(state, st, idx):
         d = np.abs(g.double().cpu().numpy()[idx] - o)
         out[name] = {"max": float(d.max()), "rms": float(np.sqrt(np.mean(d * d)))}
     return out
+
 
 
 if __name__ == "__main__":

@@ -111,11 +111,50 @@ typedef struct {
 } mstruct_phases_f64;
 
 /* exp2 / log2 used by mstruct_step_f64 */
-enum { MSTRUCT_F64_LIBRARY = 0, MSTRUCT_F64_SYNTH = 1 };
+enum { MSTRUCT_F64_LIBRARY = 0, MSTRUCT_F64_SYNTH = 1, MSTRUCT_F64_PAPER = 2 };
 
-/* Create a context on HIP device `device` (the caller's current device is
- * restored).  *out receives the context; free it with mstruct_destroy. */
-int mstruct_init(int device, mstruct_ctx **out);
+/* Model parameters of a context: the constants of Table 1 (thermal), Table 2
+ * (phase-transformation temperatures and equilibrium laws) and Table 3
+ * (diffusion laws) of the paper with the regularisation width T_as,reg =
+ * 100 K (Sec. 2.2), and the two readings of the paper that can be switched:
+ *  - correction_T: the temperature at which the explicit scheme applies the
+ *    correction g -- T^{n+1} as eq. explicit_correction writes it
+ *    (MSTRUCT_CORRECTION_T_NEXT, default) or the T^n that Algorithm 2 passes
+ *    (MSTRUCT_CORRECTION_T_PREV).  The implicit scheme corrects at T^{n+1}
+ *    either way (eq. implicit_correction).
+ *  - martensite_mode: below the martensite start, eq.
+ *    inst_martensite_formation raises alpha_m to the pseudo-equilibrium of
+ *    eq. equilibrium_phase_am and never lowers it (MSTRUCT_MARTENSITE_MAX,
+ *    default; reheating below the start keeps martensite, whose dissolution
+ *    has its own law), or sets it to that value literally
+ *    (MSTRUCT_MARTENSITE_ASSIGN), lowering it on reheating.
+ * The constants are compiled into the kernels as immediate operands:
+ * mstruct_init accepts only their values from mstruct_default_params
+ * (MSTRUCT_EUNSUPPORTED otherwise; other values need a rebuild).  Fused
+ * SURROGATE mode needs the default readings (its network was trained on
+ * them). */
+typedef struct {
+    double T_solidus, T_liquidus, T_ambient;                /* Table 1 [K] */
+    double T_alpha_s_start, T_alpha_s_end, T_alpha_m_start; /* Table 2 [K] */
+    double k_alpha_eq, k_alpha_m_eq;                        /* Table 2 [1/K] */
+    double c_alpha_s, c_beta, k1, k2, k3, f;                /* Table 3: k1 [1/s], k2 [K], k3 [1/K] */
+    double T_alpha_s_reg;                                   /* [K] */
+    int correction_T;
+    int martensite_mode;
+} mstruct_params;
+
+enum { MSTRUCT_CORRECTION_T_NEXT = 0, MSTRUCT_CORRECTION_T_PREV = 1 };
+enum { MSTRUCT_MARTENSITE_MAX = 0, MSTRUCT_MARTENSITE_ASSIGN = 1 };
+
+/* Fill *p with the paper's values and the default readings. */
+int mstruct_default_params(mstruct_params *p);
+
+/* Create a context on HIP device `device` with the given parameters (NULL:
+ * mstruct_default_params); the caller's current device is restored.  *out
+ * receives the context; free it with mstruct_destroy.  Also takes, once per
+ * device, the address of the device array of
+ * mstruct_fused_scan_steps_noalloc. */
+int mstruct_init(const mstruct_params *params, int device, mstruct_ctx **out);
 int mstruct_destroy(mstruct_ctx *ctx);
 const char *mstruct_status_string(int status);
 /* Last error message recorded on ctx (never NULL). */
@@ -141,9 +180,14 @@ int mstruct_step(mstruct_ctx *ctx, const float *T_prev, const float *T_next, dou
  * device float64 arrays (40 bytes read and 24 written per point).  math
  * MSTRUCT_F64_LIBRARY uses the device math library's exp2, log2 and expm1;
  * MSTRUCT_F64_SYNTH builds exp2 and log2 from the bit pattern of the double
- * and a short polynomial on the reduced argument, as the paper does on CPUs
- * (Sec. 3.3).  Both agree with the reference to a few float64 ulps.  dt > 0
- * and finite; asynchronous on the stream. */
+ * and a short series on the reduced argument (the technique of Sec. 3.3,
+ * with series of full double accuracy); both agree with the reference to a
+ * few float64 ulps.  MSTRUCT_F64_PAPER uses the paper's own method of Sec.
+ * 3.3: eqs. exp_algorithm_1 - exp_algorithm_3 and eq. ln_approx with the
+ * correction polynomials of Table tab:coefficients_approx_correction in
+ * Estrin's scheme, whose accuracy is that of the fits: 2^y to 1.2e-10
+ * relative, log2 to 3.0e-8 absolute.  dt > 0 and finite; asynchronous on
+ * the stream. */
 int mstruct_step_f64(mstruct_ctx *ctx, const double *T_prev, const double *T_next, double dt,
                      const mstruct_phases_f64 *ph, int math, void *stream);
 
@@ -212,7 +256,7 @@ int mstruct_fused_scan_steps(mstruct_ctx *ctx, const mstruct_scan *scan, const m
  * 64 bytes plus the envelopes (at most (K + 1) * window records per launch)
  * and 8 bytes per launch, must fit in 4 MiB (65,536 records), else
  * MSTRUCT_EINVAL and nothing is enqueued; wave flags are used when at least
- * one launch of them fits in the remaining 28 MiB (3 bytes per 64 points,
+ * one launch of them fits in the remaining 28 MiB (2 bytes per 64 points,
  * plus 24 bytes per 64 points with an index list), otherwise the call runs
  * without them (same results).  Every call on a GPU uses that GPU's one
  * array: calls on different streams, or from different host threads, that
@@ -242,8 +286,26 @@ int mstruct_fused_scan_steps_noalloc(mstruct_ctx *ctx, const mstruct_scan *scan,
  * (and 24 n/64 bytes of boxes with an index list) plus at most 64 MiB of
  * still flags per call on the device, until mstruct_destroy.  The results are the same bit for bit as with 0, which
  * evaluates every temperature and takes every step (for comparison). */
-enum { MSTRUCT_OPTION_SKIP_COLD_WAVES = 1 };
+enum { MSTRUCT_OPTION_SKIP_COLD_WAVES = 1, MSTRUCT_OPTION_COUNT_WAVES = 2 };
+/* MSTRUCT_OPTION_COUNT_WAVES (default 0): fused PLAIN and IMPLICIT launches
+ * count, per wave of 64 points, what they read and write, into counters of
+ * the context read by mstruct_wave_counts (one atomic per wave and class;
+ * for measurement, not for timed runs).  Results are unchanged. */
 int mstruct_set_option(mstruct_ctx *ctx, int option, int value);
+
+/* The counts of MSTRUCT_OPTION_COUNT_WAVES since the context was created or
+ * last reset (reset != 0 zeroes them after reading); synchronises the
+ * stream.  counts[0]: points whose state (alpha_s, alpha_m) a launch read;
+ * [1]: points whose state it wrote; waves that read their state and then
+ * [2]: were still by the launch certificates (no step, no store), [3]: were
+ * cold (T = T0 without evaluating the sources), [4]: evaluated the
+ * temperature at every step; [5]: waves still by their wave flags, which
+ * read nothing.  Beta, written once per call for every active point, is not
+ * counted.  Fused PLAIN launches also count the whole sub-blocks of 8 steps
+ * of the waves of [4] ([6]) and those of them in which every point passes
+ * the surrogate's default error indicator (see mstruct_mlp_set_params) at
+ * the sub-block's end temperatures ([7]). */
+int mstruct_wave_counts(mstruct_ctx *ctx, int64_t counts[8], int reset, void *stream);
 
 /* Number of substeps of fused IMPLICIT runs on this context whose fixed-point
  * iteration hit the cap, since the context was created or last reset

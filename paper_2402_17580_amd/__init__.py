@@ -17,12 +17,18 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmstruct.so")
 
+CORRECTION_T = {"next": 0, "prev": 1}
+MARTENSITE = {"max": 0, "assign": 1}
 MODE_PLAIN = 0
 MODE_SURROGATE = 1
 MODE_IMPLICIT = 2
 OPTION_SKIP_COLD_WAVES = 1
+OPTION_COUNT_WAVES = 2
+WAVE_COUNT_NAMES = ("points_loaded", "points_stored", "still_waves", "cold_waves", "hot_waves", "flagged_waves",
+                    "hot_subblocks", "indicator_subblocks")
 F64_LIBRARY = 0
 F64_SYNTH = 1
+F64_PAPER = 2
 MLP_NPARAM = 4803
 
 STATUS = {0: "ok", -1: "invalid argument", -2: "HIP device error", -3: "out of memory",
@@ -38,6 +44,13 @@ class MstructError(RuntimeError):
 class PhasesC(ctypes.Structure):
     _fields_ = [("beta", ctypes.c_void_p), ("alpha_s", ctypes.c_void_p), ("alpha_m", ctypes.c_void_p),
                 ("n", ctypes.c_int64), ("xbt", ctypes.c_void_p)]
+
+
+class ParamsC(ctypes.Structure):
+    _fields_ = [(name, ctypes.c_double) for name in
+                ("T_solidus", "T_liquidus", "T_ambient", "T_alpha_s_start", "T_alpha_s_end", "T_alpha_m_start",
+                 "k_alpha_eq", "k_alpha_m_eq", "c_alpha_s", "c_beta", "k1", "k2", "k3", "f", "T_alpha_s_reg")] + \
+               [("correction_T", ctypes.c_int), ("martensite_mode", ctypes.c_int)]
 
 
 class PhasesF64C(ctypes.Structure):
@@ -57,8 +70,8 @@ class PointsC(ctypes.Structure):
                 ("index", ctypes.c_void_p), ("n", ctypes.c_int64), ("z_top", ctypes.c_double)]
 
 
-EXPORTS = ("mstruct_init", "mstruct_destroy", "mstruct_status_string", "mstruct_last_error", "mstruct_step",
-           "mstruct_step_implicit", "mstruct_implicit_unconverged", "mstruct_set_option", "mstruct_step_f64", "mstruct_temperature", "mstruct_fused_scan_steps",
+EXPORTS = ("mstruct_default_params", "mstruct_init", "mstruct_destroy", "mstruct_status_string", "mstruct_last_error", "mstruct_step",
+           "mstruct_step_implicit", "mstruct_implicit_unconverged", "mstruct_set_option", "mstruct_wave_counts", "mstruct_step_f64", "mstruct_temperature", "mstruct_fused_scan_steps",
            "mstruct_fused_scan_steps_noalloc", "mstruct_gather", "mstruct_check_invariants",
            "mstruct_correct", "mstruct_mlp_set_params", "mstruct_mlp_get_params", "mstruct_mlp_forward",
            "mstruct_mlp_grad", "mstruct_mlp_train_step")
@@ -75,10 +88,12 @@ def lib() -> ctypes.CDLL:
         L = ctypes.CDLL(LIB_PATH)
         p, i64, d, i = ctypes.c_void_p, ctypes.c_int64, ctypes.c_double, ctypes.c_int
         sig = {
-            "mstruct_init": [i, p], "mstruct_destroy": [p], "mstruct_status_string": [i],
+            "mstruct_default_params": [p], "mstruct_init": [p, i, p], "mstruct_destroy": [p],
+            "mstruct_status_string": [i],
             "mstruct_last_error": [p], "mstruct_step": [p, p, p, d, p, p],
             "mstruct_step_implicit": [p, p, p, d, d, i, p, p, p],
             "mstruct_implicit_unconverged": [p, p, i, p], "mstruct_set_option": [p, i, i],
+            "mstruct_wave_counts": [p, p, i, p],
             "mstruct_step_f64": [p, p, p, d, p, i, p],
             "mstruct_temperature": [p, p, p, d, p, p],
             "mstruct_fused_scan_steps": [p, p, p, d, d, i64, i, i, p, p],
@@ -130,12 +145,26 @@ def points_struct(grid, n, z_top=math.inf, index=None):
     return PointsC(grid.nx, grid.ny, grid.nz, grid.h, grid.ox, grid.oy, grid.oz, ip, n, float(z_top))
 
 
-class Context:
-    """A library context on one GPU (one process per GPU)."""
+def default_params() -> ParamsC:
+    """The paper's model constants and the default readings (mstruct_default_params)."""
+    p = ParamsC()
+    rc = lib().mstruct_default_params(ctypes.byref(p))
+    if rc != 0:
+        raise MstructError(rc, "mstruct_default_params")
+    return p
 
-    def __init__(self, device: int = 0):
+
+class Context:
+    """A library context on one GPU (one process per GPU).  correction_T
+    ("next" | "prev") and martensite ("max" | "assign") select the readings
+    of the paper (see mstruct_params in include/mstruct.h)."""
+
+    def __init__(self, device: int = 0, correction_T: str = "next", martensite: str = "max"):
         self._h = ctypes.c_void_p()
-        self._check(lib().mstruct_init(int(device), ctypes.byref(self._h)), "mstruct_init")
+        p = default_params()
+        p.correction_T = CORRECTION_T[correction_T]
+        p.martensite_mode = MARTENSITE[martensite]
+        self._check(lib().mstruct_init(ctypes.byref(p), int(device), ctypes.byref(self._h)), "mstruct_init")
         self.device = device
 
     def close(self):
@@ -204,6 +233,12 @@ class Context:
         self._check(lib().mstruct_implicit_unconverged(self._h, ctypes.byref(c), int(bool(reset)), _stream(stream)),
                     "mstruct_implicit_unconverged")
         return c.value
+
+    def wave_counts(self, reset=False, stream=None) -> dict:
+        """Counts of MSTRUCT_OPTION_COUNT_WAVES (see mstruct_wave_counts)."""
+        c = (ctypes.c_int64 * len(WAVE_COUNT_NAMES))()
+        self._check(lib().mstruct_wave_counts(self._h, c, int(bool(reset)), _stream(stream)), "mstruct_wave_counts")
+        return dict(zip(WAVE_COUNT_NAMES, list(c)))
 
     def temperature(self, scan, grid, t, T_out, z_top=math.inf, index=None, stream=None):
         import torch

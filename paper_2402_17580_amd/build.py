@@ -1,4 +1,5 @@
-"""Build the HIP library libmstruct.so for gfx950 in-tree (hipcc)."""
+"""Build the HIP library libmstruct.so for gfx950 in-tree (hipcc), and the
+roofline calibration probes libmstruct_probe.so (not part of the library)."""
 from __future__ import annotations
 
 import os
@@ -9,8 +10,10 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libmstruct.so")
+PROBE_OUT = os.path.join(HERE, "libmstruct_probe.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ("api.hip", "kernels.hip", "mlp.hip", "step_f64_lib.hip", "step_f64_synth.hip")
+SOURCES = ("api.hip", "kernels.hip", "mlp.hip", "step_f64_lib.hip", "step_f64_synth.hip", "step_f64_paper.hip")
+PROBE_SOURCES = ("probe.hip",)
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # keep packed-FP32 instructions out of the device code
@@ -27,14 +30,20 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
-    with ThreadPoolExecutor(len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = OUT + ".tmp"
+def _link(objs, out, verbose):
+    tmp = out + ".tmp"
     cmd = ["hipcc", f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     subprocess.run(cmd, check=True, capture_output=not verbose)
-    os.replace(tmp, OUT)
+    os.replace(tmp, out)
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(BUILD, exist_ok=True)
+    srcs = SOURCES + PROBE_SOURCES
+    with ThreadPoolExecutor(len(srcs)) as ex:
+        objs = dict(zip(srcs, ex.map(_compile, srcs)))
+    _link([objs[s] for s in SOURCES], OUT, verbose)
+    _link([objs[s] for s in PROBE_SOURCES], PROBE_OUT, verbose)
     return OUT
 
 

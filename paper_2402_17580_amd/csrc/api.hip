@@ -37,7 +37,10 @@ struct mstruct_ctx {
     int next_slot = 0;
     unsigned long long* counter = nullptr;
     unsigned long long* implicit_bad = nullptr;  // substeps of fused implicit runs that hit the cap
+    unsigned long long* stats = nullptr;         // wave counts of fused launches (kStatCount)
+    bool count_waves = false;                    // MSTRUCT_OPTION_COUNT_WAVES
     bool skip_cold = true;                       // MSTRUCT_OPTION_SKIP_COLD_WAVES
+    Readings rd{false, false};                   // mstruct_params' correction_T and martensite_mode
     // per-wave flags of fused calls on box grids: rest flags, then the still
     // flags of a chunk of launches
     uint8_t* wave_flags = nullptr;
@@ -336,26 +339,76 @@ const char* mstruct_status_string(int status) {
 
 const char* mstruct_last_error(const mstruct_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
-int mstruct_init(int device, mstruct_ctx** out) {
+int mstruct_default_params(mstruct_params* p) {
+    if (!p) return MSTRUCT_EINVAL;
+    memset(p, 0, sizeof *p);
+    using C = Const<double>;
+    p->T_solidus = C::Tsol;
+    p->T_liquidus = C::Tliq;
+    p->T_ambient = C::Tinf;
+    p->T_alpha_s_start = C::TasStart;
+    p->T_alpha_s_end = C::TasEnd;
+    p->T_alpha_m_start = C::TamStart;
+    p->k_alpha_eq = C::KalphaEq;
+    p->k_alpha_m_eq = C::KamEq;
+    p->c_alpha_s = C::Cas;
+    p->c_beta = C::Cbeta;
+    p->k1 = C::K1;
+    p->k2 = C::K2;
+    p->k3 = C::K3;
+    p->f = C::F;
+    p->T_alpha_s_reg = C::Treg;
+    p->correction_T = MSTRUCT_CORRECTION_T_NEXT;
+    p->martensite_mode = MSTRUCT_MARTENSITE_MAX;
+    return MSTRUCT_OK;
+}
+
+int mstruct_init(const mstruct_params* params, int device, mstruct_ctx** out) {
     if (!out) return MSTRUCT_EINVAL;
     *out = nullptr;
+    mstruct_params p;
+    mstruct_default_params(&p);
+    if (params) {
+        // the model constants are immediate operands of the kernels
+        const double got[] = {params->T_solidus, params->T_liquidus, params->T_ambient, params->T_alpha_s_start,
+                              params->T_alpha_s_end, params->T_alpha_m_start, params->k_alpha_eq,
+                              params->k_alpha_m_eq, params->c_alpha_s, params->c_beta, params->k1, params->k2,
+                              params->k3, params->f, params->T_alpha_s_reg};
+        const double want[] = {p.T_solidus, p.T_liquidus, p.T_ambient, p.T_alpha_s_start, p.T_alpha_s_end,
+                               p.T_alpha_m_start, p.k_alpha_eq, p.k_alpha_m_eq, p.c_alpha_s, p.c_beta, p.k1, p.k2,
+                               p.k3, p.f, p.T_alpha_s_reg};
+        for (size_t i = 0; i < sizeof got / sizeof got[0]; ++i)
+            if (got[i] != want[i]) return MSTRUCT_EUNSUPPORTED;
+        if (params->correction_T != MSTRUCT_CORRECTION_T_NEXT && params->correction_T != MSTRUCT_CORRECTION_T_PREV)
+            return MSTRUCT_EINVAL;
+        if (params->martensite_mode != MSTRUCT_MARTENSITE_MAX && params->martensite_mode != MSTRUCT_MARTENSITE_ASSIGN)
+            return MSTRUCT_EINVAL;
+        p.correction_T = params->correction_T;
+        p.martensite_mode = params->martensite_mode;
+    }
     int count = 0;
     if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return MSTRUCT_EINVAL;
     mstruct_ctx* ctx = new (std::nothrow) mstruct_ctx();
     if (!ctx) return MSTRUCT_ENOMEM;
     ctx->device = device;
+    ctx->rd = Readings{p.correction_T == MSTRUCT_CORRECTION_T_PREV, p.martensite_mode == MSTRUCT_MARTENSITE_ASSIGN};
     DeviceGuard g(device);
     if (hipMalloc((void**)&ctx->counter, sizeof(unsigned long long)) != hipSuccess ||
-        hipMalloc((void**)&ctx->implicit_bad, sizeof(unsigned long long)) != hipSuccess) {
+        hipMalloc((void**)&ctx->implicit_bad, sizeof(unsigned long long)) != hipSuccess ||
+        hipMalloc((void**)&ctx->stats, kStatCount * sizeof(unsigned long long)) != hipSuccess) {
         if (ctx->counter) (void)hipFree(ctx->counter);
+        if (ctx->implicit_bad) (void)hipFree(ctx->implicit_bad);
+    if (ctx->stats) (void)hipFree(ctx->stats);
         delete ctx;
         return MSTRUCT_ENOMEM;
     }
-    const unsigned long long zero = 0;
-    if (hipMemcpy(ctx->implicit_bad, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess ||
+    const unsigned long long zero[kStatCount] = {};
+    if (hipMemcpy(ctx->implicit_bad, zero, sizeof zero[0], hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(ctx->stats, zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess ||
         scratch_setup(device) != MSTRUCT_OK) {
         (void)hipFree(ctx->counter);
         (void)hipFree(ctx->implicit_bad);
+        (void)hipFree(ctx->stats);
         delete ctx;
         return MSTRUCT_EDEVICE;
     }
@@ -374,6 +427,7 @@ int mstruct_destroy(mstruct_ctx* ctx) {
     }
     if (ctx->counter) (void)hipFree(ctx->counter);
     if (ctx->implicit_bad) (void)hipFree(ctx->implicit_bad);
+    if (ctx->stats) (void)hipFree(ctx->stats);
     if (ctx->wave_flags) (void)hipFree(ctx->wave_flags);
     if (ctx->wave_boxes) (void)hipFree(ctx->wave_boxes);
     mlp_free(ctx->mlp);
@@ -390,7 +444,7 @@ int mstruct_step(mstruct_ctx* ctx, const float* T_prev, const float* T_next, dou
     if (ph->n > 0 && (!T_prev || !T_next)) return fail(ctx, MSTRUCT_EINVAL, "temperature array is NULL");
     DeviceGuard g(ctx->device);
     hipError_t e = launch_step(T_prev, T_next, ph->beta, ph->alpha_s, ph->alpha_m, ph->xbt, ph->n, (float)dt,
-                               (hipStream_t)stream);
+                               ctx->rd, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "step launch");
     return MSTRUCT_OK;
 }
@@ -403,12 +457,17 @@ int mstruct_step_f64(mstruct_ctx* ctx, const double* T_prev, const double* T_nex
     if (ph->n > 0 && (!ph->beta || !ph->alpha_s || !ph->alpha_m || !T_prev || !T_next))
         return fail(ctx, MSTRUCT_EINVAL, "NULL array");
     if (!finite_pos(dt)) return fail(ctx, MSTRUCT_EINVAL, "dt must be positive and finite");
-    if (math != MSTRUCT_F64_LIBRARY && math != MSTRUCT_F64_SYNTH) return fail(ctx, MSTRUCT_EINVAL, "bad math");
+    if (math != MSTRUCT_F64_LIBRARY && math != MSTRUCT_F64_SYNTH && math != MSTRUCT_F64_PAPER)
+        return fail(ctx, MSTRUCT_EINVAL, "bad math");
     DeviceGuard g(ctx->device);
     hipStream_t st = (hipStream_t)stream;
-    hipError_t e = math == MSTRUCT_F64_LIBRARY
-                       ? launch_step_f64_library(T_prev, T_next, ph->beta, ph->alpha_s, ph->alpha_m, ph->n, dt, st)
-                       : launch_step_f64_synth(T_prev, T_next, ph->beta, ph->alpha_s, ph->alpha_m, ph->n, dt, st);
+    const bool cp = ctx->rd.corr_prev, ma = ctx->rd.mart_assign;
+    hipError_t e =
+        math == MSTRUCT_F64_LIBRARY
+            ? launch_step_f64_library(T_prev, T_next, ph->beta, ph->alpha_s, ph->alpha_m, ph->n, dt, cp, ma, st)
+        : math == MSTRUCT_F64_SYNTH
+            ? launch_step_f64_synth(T_prev, T_next, ph->beta, ph->alpha_s, ph->alpha_m, ph->n, dt, cp, ma, st)
+            : launch_step_f64_paper(T_prev, T_next, ph->beta, ph->alpha_s, ph->alpha_m, ph->n, dt, cp, ma, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "float64 step launch");
     return MSTRUCT_OK;
 }
@@ -426,7 +485,8 @@ int mstruct_step_implicit(mstruct_ctx* ctx, const float* T_prev, const float* T_
     const int n_sub = substeps(dt, dt_sub);
     DeviceGuard g(ctx->device);
     hipError_t e = launch_implicit_step(T_prev, T_next, ph->beta, ph->alpha_s, ph->alpha_m, ph->xbt, ph->n,
-                                        (float)(dt / n_sub), n_sub, max_iter, unconverged, (hipStream_t)stream);
+                                        (float)(dt / n_sub), n_sub, max_iter, unconverged, ctx->rd,
+                                        (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "implicit step launch");
     return MSTRUCT_OK;
 }
@@ -451,7 +511,7 @@ int mstruct_temperature(mstruct_ctx* ctx, const mstruct_scan* scan, const mstruc
     if ((rc = acquire_slot(ctx, scan->window, s))) return rc;
     build_table(s->host, scan, pts, t, 0.0, 1);
     HIP_CHECK(ctx, hipMemcpyAsync(s->dev, s->host, scan->window * sizeof(SrcRec), hipMemcpyHostToDevice, st));
-    hipError_t e = launch_temperature(pg, scan->window, s->dev, ScanArgs{(float)scan->T0, (float)scan->T_clamp},
+    hipError_t e = launch_temperature(pg, scan->window, s->dev, ScanArgs{(float)scan->T0, (float)scan->T_clamp, ctx->rd},
                                       T_out, st);
     if (e != hipSuccess) return hip_fail(ctx, e, "temperature launch");
     return release_slot(ctx, s, st);
@@ -471,6 +531,10 @@ struct FusedPlan {
     size_t table() const { return recs + fc_recs + env_cap; }
 };
 
+// steps per launch: K, or in SURROGATE mode (K = the network's block) the
+// most whole blocks that fit in 64 steps
+int launch_steps(int K, int mode) { return mode == MSTRUCT_MODE_SURROGATE ? K * (64 / K) : K; }
+
 FusedPlan fused_plan(const mstruct_scan* scan, const PointGeom& pg, int64_t n_steps, int K) {
     FusedPlan p;
     p.W = scan->window;
@@ -483,9 +547,9 @@ FusedPlan fused_plan(const mstruct_scan* scan, const PointGeom& pg, int64_t n_st
 }
 
 // The buffers a fused call works in: the table's host staging and its
-// device copy (cap records each), and the wave flags (2 n_waves bytes of
-// rest and tcached flags, then still flags for chunks of `chunk` launches;
-// flags == nullptr: none) with the waves' boxes on an index list.
+// device copy (cap records each), and the wave flags (n_waves bytes of rest
+// flags, then still flags for chunks of `chunk` launches; flags == nullptr:
+// none) with the waves' boxes on an index list.
 struct FusedBufs {
     SrcRec* host = nullptr;
     SrcRec* dev = nullptr;
@@ -515,6 +579,8 @@ int fused_check(mstruct_ctx* ctx, const mstruct_scan* scan, const mstruct_points
         return fail(ctx, MSTRUCT_EUNSUPPORTED, "surrogate mode does not carry the tracked X~beta (xbt)");
     if (mode == MSTRUCT_MODE_SURROGATE && !ctx->mlp.ready)
         return fail(ctx, MSTRUCT_ESTATE, "surrogate mode needs network parameters (mstruct_mlp_set_params)");
+    if (mode == MSTRUCT_MODE_SURROGATE && (ctx->rd.corr_prev || ctx->rd.mart_assign))
+        return fail(ctx, MSTRUCT_EUNSUPPORTED, "surrogate mode runs with the default readings only");
     if (n_steps == 0 || pg.count == 0) return 1;
     return MSTRUCT_OK;
 }
@@ -522,10 +588,11 @@ int fused_check(mstruct_ctx* ctx, const mstruct_scan* scan, const mstruct_points
 // The body of a fused call: scan table and launch envelopes built on the
 // host into b.host, uploaded to b.dev (then `uploaded`, if given, is
 // recorded on the stream), the still-flag pre-passes and the launches of K
-// steps.  Nothing is enqueued if the table does not fit.
+// steps (in SURROGATE mode in network blocks of Ks steps).  Nothing is
+// enqueued if the table does not fit.
 int fused_run(mstruct_ctx* ctx, const mstruct_scan* scan, const mstruct_points* pts, const PointGeom& pg,
-              const FusedPlan& p, double t0, double dt, int64_t n_steps, int K, int mode, const mstruct_phases* ph,
-              const FusedBufs& b, hipEvent_t uploaded, hipStream_t st) {
+              const FusedPlan& p, double t0, double dt, int64_t n_steps, int K, int Ks, int mode,
+              const mstruct_phases* ph, const FusedBufs& b, hipEvent_t uploaded, hipStream_t st) {
     const int W = p.W;
     if (p.recs + p.fc_recs > b.cap) return fail(ctx, MSTRUCT_EINVAL, "scan table larger than the table buffer");
     build_table(b.host, scan, pts, t0, dt, n_steps + 1);
@@ -539,12 +606,12 @@ int fused_run(mstruct_ctx* ctx, const mstruct_scan* scan, const mstruct_points* 
     HIP_CHECK(ctx, hipMemcpyAsync(b.dev, b.host, (p.recs + p.fc_recs + (size_t)n_env) * sizeof(SrcRec),
                                   hipMemcpyHostToDevice, st));
     if (uploaded) HIP_CHECK(ctx, hipEventRecord(uploaded, st));
-    const ScanArgs sa{(float)scan->T0, (float)scan->T_clamp};
+    const ScanArgs sa{(float)scan->T0, (float)scan->T_clamp, ctx->rd};
     const bool wave_flags = b.flags != nullptr;
     const int64_t n_waves = p.n_waves, n_launches = p.n_launches, chunk = b.chunk;
     if (mode == MSTRUCT_MODE_SURROGATE) {
-        hipError_t e = surrogate_prepare(ctx->mlp, pg.first + pg.count, st);
-        if (e != hipSuccess) return hip_fail(ctx, e, "surrogate queue");
+        hipError_t e = surrogate_prepare(ctx->mlp, n_waves, st);
+        if (e != hipSuccess) return hip_fail(ctx, e, "surrogate records");
     }
     for (int64_t s0 = 0; s0 < n_steps; s0 += K) {
         const int Kb = (int)((n_steps - s0) < K ? (n_steps - s0) : K);
@@ -555,7 +622,7 @@ int fused_run(mstruct_ctx* ctx, const mstruct_scan* scan, const mstruct_points* 
         const int64_t li = s0 / K;
         uint8_t* below = nullptr;
         if (wave_flags) {
-            below = b.flags + n_waves * (2 + li % chunk);
+            below = b.flags + n_waves * (1 + li % chunk);
             if (li % chunk == 0) {
                 const int64_t nl = (n_launches - li) < chunk ? (n_launches - li) : chunk;
                 const GridBox* boxes = pts->index ? b.boxes : nullptr;
@@ -563,13 +630,12 @@ int fused_run(mstruct_ctx* ctx, const mstruct_scan* scan, const mstruct_points* 
                 if (li == 0 && boxes) fe = launch_wave_boxes(pg, n_waves, b.boxes, st);
                 if (fe == hipSuccess)
                     fe = launch_still_flags(pg, env_dev, fc_dev, li, nl, n_waves, fminf(sa.T0, sa.Tclamp), boxes,
-                                            b.flags + 2 * n_waves, st);
+                                            b.flags + n_waves, st);
                 if (fe != hipSuccess) return hip_fail(ctx, fe, "still flags launch");
             }
         }
         const EnvSet es{env_dev + fc_host[2 * li], ctx->skip_cold ? fc_host[2 * li + 1] : -1, below,
-                        wave_flags ? b.flags : nullptr, n_waves, li > 0,
-                        wave_flags && mode == MSTRUCT_MODE_SURROGATE ? b.flags + n_waves : nullptr};
+                        wave_flags ? b.flags : nullptr, n_waves, li > 0, ctx->count_waves ? ctx->stats : nullptr};
         if (mode == MSTRUCT_MODE_PLAIN) {
             e = launch_fused_plain(pg, W, b.dev + s0 * W, es, Kb, (float)dt, sa, beta, ph->alpha_s, ph->alpha_m,
                                    ph->xbt, st);
@@ -578,8 +644,8 @@ int fused_run(mstruct_ctx* ctx, const mstruct_scan* scan, const mstruct_points* 
             e = launch_fused_implicit(pg, W, b.dev + s0 * W, es, Kb, (float)(dt / n_sub), n_sub, kImplicitMaxIter,
                                       sa, beta, ph->alpha_s, ph->alpha_m, ph->xbt, ctx->implicit_bad, st);
         } else
-            e = launch_surrogate(ctx->mlp, pg, W, b.dev + s0 * W, es, Kb, (float)dt, sa, ph->beta, ph->alpha_s,
-                                 ph->alpha_m, li, s0 == 0, last, st);
+            e = launch_surrogate(ctx->mlp, pg, W, b.dev + s0 * W, es, Kb, Ks, (float)dt, sa, beta, ph->alpha_s,
+                                 ph->alpha_m, li, st);
         if (e != hipSuccess) return hip_fail(ctx, e, "fused launch");
     }
     return MSTRUCT_OK;
@@ -630,17 +696,17 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
     if (rc) return rc > 0 ? MSTRUCT_OK : rc;
     DeviceGuard g(ctx->device);
     hipStream_t st = (hipStream_t)stream;
-    const FusedPlan p = fused_plan(scan, pg, n_steps, K);
+    const int Kl = launch_steps(K, mode);
+    const FusedPlan p = fused_plan(scan, pg, n_steps, Kl);
     FusedBufs b;
     // Wave flags (one point per lane, 64 per wave): rest flags kept by the
-    // fused kernels and surrogate pass A, pass A's tcached flags, then still
-    // flags for chunks of launches from a box pre-pass (on an index list the
-    // boxes of the waves are computed first).  Not with the tracked X~beta,
-    // whose store every launch takes.
+    // fused kernels, then still flags for chunks of launches from a box
+    // pre-pass (on an index list the boxes of the waves are computed first).
+    // Not with the tracked X~beta, whose store every launch takes.
     if (ctx->skip_cold && !ph->xbt) {
         int64_t chunk = kWaveFlagBudget / p.n_waves;
         chunk = chunk < 1 ? 1 : (chunk > p.n_launches ? p.n_launches : chunk);
-        const size_t need = (size_t)p.n_waves * (size_t)(2 + chunk);
+        const size_t need = (size_t)p.n_waves * (size_t)(1 + chunk);
         if (ctx->wave_flags_cap < need) {
             HIP_CHECK(ctx, hipStreamSynchronize(st));
             if (ctx->wave_flags) HIP_CHECK(ctx, hipFree(ctx->wave_flags));
@@ -672,7 +738,7 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
     b.host = s->host;
     b.dev = s->dev;
     b.cap = s->cap;
-    rc = fused_run(ctx, scan, pts, pg, p, t0, dt, n_steps, K, mode, ph, b, nullptr, st);
+    rc = fused_run(ctx, scan, pts, pg, p, t0, dt, n_steps, Kl, K, mode, ph, b, nullptr, st);
     const int rc2 = release_slot(ctx, s, st);
     return rc ? rc : rc2;
 }
@@ -710,7 +776,7 @@ int mstruct_fused_scan_steps_noalloc(mstruct_ctx* ctx, const mstruct_scan* scan,
         const size_t box_bytes = pts->index ? (((size_t)p.n_waves * sizeof(GridBox) + 255) & ~(size_t)255) : 0;
         const size_t room = kScratchBytes - kScratchTable;
         const int64_t per_wave = box_bytes < room ? (int64_t)((room - box_bytes) / (size_t)p.n_waves) : 0;
-        int64_t chunk = per_wave - 2;
+        int64_t chunk = per_wave - 1;
         if (chunk >= 1) {
             b.boxes = pts->index ? reinterpret_cast<GridBox*>(base + kScratchTable) : nullptr;
             b.flags = base + kScratchTable + box_bytes;
@@ -721,7 +787,7 @@ int mstruct_fused_scan_steps_noalloc(mstruct_ctx* ctx, const mstruct_scan* scan,
     // the staging array is rewritten only after the last upload from it is done
     if (g_scratch.pending) HIP_CHECK(ctx, hipEventSynchronize(g_scratch.pending));
     g_scratch.pending = nullptr;
-    rc = fused_run(ctx, scan, pts, pg, p, t0, dt, n_steps, K, mode, ph, b, g_scratch.uploaded[ctx->device], st);
+    rc = fused_run(ctx, scan, pts, pg, p, t0, dt, n_steps, K, K, mode, ph, b, g_scratch.uploaded[ctx->device], st);
     // (if the upload was not enqueued, the event holds an earlier, harmless record)
     g_scratch.pending = g_scratch.uploaded[ctx->device];
     return rc;
@@ -731,6 +797,7 @@ int mstruct_set_option(mstruct_ctx* ctx, int option, int value) {
     if (!ctx) return MSTRUCT_EINVAL;
     switch (option) {
         case MSTRUCT_OPTION_SKIP_COLD_WAVES: ctx->skip_cold = value != 0; return MSTRUCT_OK;
+        case MSTRUCT_OPTION_COUNT_WAVES: ctx->count_waves = value != 0; return MSTRUCT_OK;
         default: return fail(ctx, MSTRUCT_EINVAL, "unknown option");
     }
 }
@@ -748,6 +815,22 @@ int mstruct_implicit_unconverged(mstruct_ctx* ctx, int64_t* count, int reset, vo
     }
     HIP_CHECK(ctx, hipStreamSynchronize(st));
     *count = (int64_t)h;
+    return MSTRUCT_OK;
+}
+
+int mstruct_wave_counts(mstruct_ctx* ctx, int64_t* counts, int reset, void* stream) {
+    if (!ctx) return MSTRUCT_EINVAL;
+    if (!counts) return fail(ctx, MSTRUCT_EINVAL, "counts is NULL");
+    DeviceGuard g(ctx->device);
+    hipStream_t st = (hipStream_t)stream;
+    unsigned long long h[kStatCount] = {};
+    HIP_CHECK(ctx, hipMemcpyAsync(h, ctx->stats, sizeof h, hipMemcpyDeviceToHost, st));
+    if (reset) {
+        const unsigned long long zero[kStatCount] = {};
+        HIP_CHECK(ctx, hipMemcpyAsync(ctx->stats, zero, sizeof zero, hipMemcpyHostToDevice, st));
+    }
+    HIP_CHECK(ctx, hipStreamSynchronize(st));
+    for (int i = 0; i < kStatCount; ++i) counts[i] = (int64_t)h[i];
     return MSTRUCT_OK;
 }
 
@@ -792,7 +875,8 @@ int mstruct_correct(mstruct_ctx* ctx, const float* T, const mstruct_phases* ph, 
     if (rc) return rc;
     if (ph->n > 0 && !T) return fail(ctx, MSTRUCT_EINVAL, "T is NULL");
     DeviceGuard g(ctx->device);
-    hipError_t e = launch_correct(T, ph->beta, ph->alpha_s, ph->alpha_m, ph->n, (hipStream_t)stream);
+    hipError_t e = launch_correct(T, ph->beta, ph->alpha_s, ph->alpha_m, ph->n, ctx->rd.mart_assign,
+                                  (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(ctx, e, "correct launch");
     return MSTRUCT_OK;
 }

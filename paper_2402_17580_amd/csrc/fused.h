@@ -1,0 +1,151 @@
+// Shared pieces of the fused kernels (plain, implicit and surrogate): point
+// decoding, the launch certificates' wave tests, the persistent slot form of
+// a launch, the per-wave flags and counts.
+#pragma once
+#include "kernels.h"
+
+namespace mstruct {
+
+// workgroup of the fused grid kernels (one wave per 64 points)
+constexpr int kFusedBlock = 256;
+// wave slots per wave of the persistent fused kernels (see fused_slots),
+// and the launch size (in waves) from which they run in workgroups of four
+// waves instead of two: on large, mostly still grids the occupancy of four
+// pays (island block, 1M waves: 2.2 s against 2.7 s), on smaller ones two
+// spread the waves that step over more CUs (block scan, 131k waves: 9 %
+// faster)
+constexpr int kSlotsPerWave = 4;
+constexpr int64_t kSlotsLargeGrid = (int64_t)1 << 18;
+
+// grid coordinates of a local point number (box or index list)
+__device__ __forceinline__ void decode_point(const PointGeom& pg, int64_t local, int& gi, int& gj, int& gk) {
+    const int lin = pg.index ? pg.index[local] : (int)local;
+    gk = divide_by(lin, pg.mag_nxy, pg.sh_nxy);
+    const int rem = lin - gk * pg.nxy;
+    gj = divide_by(rem, pg.mag_nx, pg.sh_nx);
+    gi = rem - gj * pg.nx;
+}
+
+// squared distance [grid units^2] within which the envelope tests certify
+// nothing: one grid unit, and at least the clamp radius and the offset
+// radius of source_rise
+__host__ __device__ __forceinline__ float envelope_radius2(const PointGeom& pg) {
+    return fmaxf(1.0f, fmaxf(pg.roff * pg.roff, pg.r2min));
+}
+
+// limit of the still test: the alpha_s -> beta end temperature of at_rest,
+// with 0.5 K to spare for float32 rounding of the computed temperatures
+constexpr float kRestBelow = Const<float>::TasEnd - 0.5f;
+
+// whether the still test can succeed (wave-uniform): certificates enabled,
+// T0 below the limit and every point of the wave at rest at the start of
+// the launch
+__device__ __forceinline__ bool wave_may_rest(const EnvSet& env, bool act, float a, float m, float T0) {
+    return env.n >= 0 && T0 < kRestBelow && __ballot(act && !rest_bits(a, m)) == 0;
+}
+
+// wave index of the calling lane in a fused launch (uniform across the wave)
+__device__ __forceinline__ int64_t fused_wave() {
+    return (int64_t)blockIdx.x * (kFusedBlock / kWave) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+}
+
+// A wave whose flags say still (wave_flag_still): its state is at rest and
+// stays as it is, so only beta (last launch of a call) is written, with the
+// value every step would give.
+// On an index list, points above the current surface are inactive and left
+// alone (on a box grid every point of a call is active).
+__device__ __forceinline__ void still_wave_beta(const PointGeom& pg, float T0c, float* beta, int64_t g) {
+    if (!beta || g >= pg.count) return;
+    const int64_t local = pg.first + g;
+    if (pg.index) {
+        int gi, gj, gk;
+        decode_point(pg, local, gi, gj, gk);
+        if (gk < pg.k0) return;
+    }
+    beta[local] = solid_fraction(T0c) - kXmax - 0.0f;
+}
+
+// The persistent form of a fused launch, used from the second launch of a
+// call when the wave flags are kept: a grid of about one wave per
+// kSlotsPerWave waves of the launch, in which wave p takes the wave slots p,
+// p + P, p + 2P, ... (P waves in the grid).  Each lane loads the flags of
+// one slot; the wave then runs body(w) for every slot w that is not still
+// (all 64 lanes, one point each) and writes beta for the still ones.  No
+// wave is launched only to find its flags set, and the interleaved slots
+// spread the few waves that step evenly over the grid.
+template <int BS, class Body>
+__device__ __forceinline__ void fused_slots(const PointGeom& pg, const EnvSet& env, float T0c, float* beta,
+                                            Body body) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t P = (int64_t)gridDim.x * (BS / kWave);
+    const int64_t p = (int64_t)blockIdx.x * (BS / kWave) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    for (int64_t r = 0; p + r * kWave * P < env.n_waves; ++r) {
+        const int64_t w = p + (r * kWave + lane) * P;
+        const bool in = w < env.n_waves;
+        const bool still = in && env.below[w] && env.rest[w];
+        uint64_t todo = __ballot(in && !still), quiet = beta ? __ballot(still) : 0;
+        if (env.stats) {
+            const int nq = __popcll(__ballot(still));  // (all lanes take part in the ballot)
+            if (nq && lane == 0) atomicAdd(env.stats + kStatFlagged, (unsigned long long)nq);
+        }
+        while (todo) {
+            const int i = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            body(p + (r * kWave + i) * P);
+        }
+        while (quiet) {
+            const int i = __builtin_ctzll(quiet);
+            quiet &= quiet - 1;
+            still_wave_beta(pg, T0c, beta, (p + (r * kWave + i) * P) * kWave + lane);
+        }
+    }
+}
+
+// count a wave that read its state: its active points, and its class
+__device__ __forceinline__ void count_wave(const EnvSet& env, bool act, bool still, bool cold) {
+    const unsigned long long n = __popcll(__ballot(act));
+    if ((threadIdx.x & (kWave - 1)) != 0 || n == 0) return;
+    atomicAdd(env.stats + kStatLoaded, n);
+    if (still) {
+        atomicAdd(env.stats + kStatStill, 1ull);
+        return;
+    }
+    atomicAdd(env.stats + kStatStored, n);
+    atomicAdd(env.stats + (cold ? kStatCold : kStatHot), 1ull);
+}
+
+// count a hot wave's sub-block from T0 to TK, and whether every point passes
+// the surrogate's default indicator on it
+__device__ __forceinline__ void count_block(const EnvSet& env, bool act, float T0, float TK) {
+    const float lo = fminf(T0, TK), hi = fmaxf(T0, TK);
+    const bool ok = !act || ((hi < 823.0f || (lo >= 1398.0f && hi <= 1853.0f)) && fabsf(TK - T0) <= 50.0f);
+    const bool all = __ballot(!ok) == 0;
+    if ((threadIdx.x & (kWave - 1)) != 0) return;
+    atomicAdd(env.stats + kStatHotBlocks, 1ull);
+    if (all) atomicAdd(env.stats + kStatEligibleBlocks, 1ull);
+}
+
+// record whether every point of the wave is at rest after the launch
+__device__ __forceinline__ void record_rest(const EnvSet& env, int64_t wv, bool act, float a, float m) {
+    if (!env.below || wv >= env.n_waves) return;
+    const bool r = __ballot(act && !rest_bits(a, m)) == 0;
+    if ((threadIdx.x & (kWave - 1)) == 0) env.rest[wv] = r ? 1 : 0;
+}
+
+// grid of the persistent (slot) fused kernels in workgroups of bs threads:
+// one wave per kSlotsPerWave waves of the launch
+inline dim3 slots_grid(int64_t n_waves, int bs) {
+    const int64_t waves = (n_waves + kSlotsPerWave - 1) / kSlotsPerWave;
+    return dim3((unsigned)((waves + bs / kWave - 1) / (bs / kWave)));
+}
+
+// launch a slot kernel instantiated for workgroups of 128 and 256 threads
+#define LAUNCH_SLOTS(kernel, W, n_waves, st, ...)                                                          \
+    do {                                                                                                    \
+        if ((n_waves) >= kSlotsLargeGrid)                                                                   \
+            hipLaunchKernelGGL((kernel<W, 256>), slots_grid(n_waves, 256), dim3(256), 0, st, __VA_ARGS__); \
+        else                                                                                                \
+            hipLaunchKernelGGL((kernel<W, 128>), slots_grid(n_waves, 128), dim3(128), 0, st, __VA_ARGS__); \
+    } while (0)
+
+}  // namespace mstruct

@@ -43,9 +43,10 @@ inline void divide_magic(int64_t d, uint32_t& mag, int32_t& sh) {
     sh = l - 1;
 }
 
-// scan constants of one call
+// scan constants of one call, and the context's readings of the paper
 struct ScanArgs {
     float T0, Tclamp;
+    Readings rd;
 };
 
 // the envelope records of one launch (see EnvRec), and the per-wave flags of
@@ -62,10 +63,22 @@ struct EnvSet {
     uint8_t* rest;
     int64_t n_waves;
     int32_t read_rest;
-    // surrogate pass A only: tcached[w] != 0 when the previous block left
-    // wave w's block-end temperatures in the cache (a still group leaves none)
-    uint8_t* tcached;
+    // wave counts of fused PLAIN / IMPLICIT launches (nullptr: not counted),
+    // indexed by the kStat* constants
+    unsigned long long* stats;
 };
+
+// the counts of EnvSet::stats: points whose state a launch reads and writes,
+// and its waves by class (still by the certificates after reading the state,
+// cold, hot: the temperature evaluated at every step, still by the wave
+// flags without reading the state); then, for fused PLAIN launches, the hot
+// waves' whole sub-blocks of kStatBlock steps, and those of them in which
+// every point passes the surrogate's default error indicator (both
+// sub-block-end temperatures below 823 K or both within [1398, 1853] K, at
+// most 50 K apart): the share of hot-wave steps the network may replace
+enum { kStatLoaded = 0, kStatStored = 1, kStatStill = 2, kStatCold = 3, kStatHot = 4, kStatFlagged = 5,
+       kStatHotBlocks = 6, kStatEligibleBlocks = 7, kStatCount = 8 };
+constexpr int kStatBlock = 8;
 
 // points per wave of the fused kernels (one point per lane)
 constexpr int kWave = 64;
@@ -94,19 +107,24 @@ hipError_t launch_wave_boxes(const PointGeom& pg, int64_t n_waves, GridBox* boxe
 
 // xb: optional tracked X~beta side values (float64 per point), or nullptr
 hipError_t launch_step(const float* Tp, const float* Tn, float* beta, float* as, float* am, double* xb, int64_t n,
-                       float dt, hipStream_t st);
+                       float dt, Readings rd, hipStream_t st);
 hipError_t launch_fused_implicit(const PointGeom& pg, int W, const SrcRec* tab, EnvSet env, int K, float h, int n_sub,
                                  int max_iter, ScanArgs sa, float* beta, float* as, float* am, double* xb,
                                  unsigned long long* unconverged, hipStream_t st);
 // float64 explicit step (step_f64_lib.hip: device math library; step_f64_synth.hip:
 // exponent-bit exp2 / log2)
+// (the readings as plain flags: these translation units have their own model namespaces)
 hipError_t launch_step_f64_library(const double* Tp, const double* Tn, double* beta, double* as, double* am,
-                                   int64_t n, double dt, hipStream_t st);
+                                   int64_t n, double dt, bool corr_prev, bool mart_assign, hipStream_t st);
 hipError_t launch_step_f64_synth(const double* Tp, const double* Tn, double* beta, double* as, double* am,
-                                 int64_t n, double dt, hipStream_t st);
+                                 int64_t n, double dt, bool corr_prev, bool mart_assign, hipStream_t st);
+// step_f64_paper.hip: the paper's exp / ln (bit synthesis with its correction polynomials)
+hipError_t launch_step_f64_paper(const double* Tp, const double* Tn, double* beta, double* as, double* am,
+                                 int64_t n, double dt, bool corr_prev, bool mart_assign, hipStream_t st);
+// the implicit scheme corrects at T^{n+1}: only rd.mart_assign applies
 hipError_t launch_implicit_step(const float* Tp, const float* Tn, float* beta, float* as, float* am, double* xb,
                                 int64_t n, float h, int n_sub, int max_iter, unsigned long long* unconverged,
-                                hipStream_t st);
+                                Readings rd, hipStream_t st);
 hipError_t launch_temperature(const PointGeom& pg, int W, const SrcRec* rec, ScanArgs sa, float* T,
                               hipStream_t st);
 hipError_t launch_fused_plain(const PointGeom& pg, int W, const SrcRec* tab, EnvSet env, int K, float dt, ScanArgs sa,

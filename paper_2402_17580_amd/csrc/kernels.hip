@@ -2,33 +2,15 @@
 // arrays (HBM-bound streaming), the temperature field of a scan, and the fused
 // kernel that keeps each point's state in registers for K steps while
 // evaluating the temperature analytically (VALU-bound).
-#include "kernels.h"
+#include "fused.h"
 
 namespace mstruct {
 
 constexpr int kBlock = 256;
-// workgroup of the fused grid kernels (one wave per 64 points)
-constexpr int kFusedBlock = 256;
-// wave slots per wave of the persistent fused kernels (see fused_slots),
-// and the launch size (in waves) from which they run in workgroups of four
-// waves instead of two: on large, mostly still grids the occupancy of four
-// pays (island block, 1M waves: 2.2 s against 2.7 s), on smaller ones two
-// spread the waves that step over more CUs (block scan, 131k waves: 9 %
-// faster)
-constexpr int kSlotsPerWave = 4;
-constexpr int64_t kSlotsLargeGrid = (int64_t)1 << 18;
 #ifndef FUSED_PPT
 #define FUSED_PPT 1
 #endif
 typedef float vf4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ void decode_point(const PointGeom& pg, int64_t local, int& gi, int& gj, int& gk) {
-    const int lin = pg.index ? pg.index[local] : (int)local;
-    gk = divide_by(lin, pg.mag_nxy, pg.sh_nxy);
-    const int rem = lin - gk * pg.nxy;
-    gj = divide_by(rem, pg.mag_nx, pg.sh_nx);
-    gi = rem - gj * pg.nx;
-}
 
 // ---------------------------------------------------------------------------
 // plain step: Algorithm 1's loop over points with the local explicit step of
@@ -36,15 +18,15 @@ __device__ __forceinline__ void decode_point(const PointGeom& pg, int64_t local,
 // fractions (28 bytes per point).  VEC: four consecutive points per thread
 // with 16-byte accesses (all five arrays 16-byte aligned).
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ void step_point(float Tp, float Tn, float& b, float& a, float& m, float dt) {
+__device__ __forceinline__ void step_point(float Tp, float Tn, float& b, float& a, float& m, float dt, Readings rd) {
     float alo = 0.0f, mlo = 0.0f;
-    b = explicit_step<false>(a, m, alo, mlo, Tp, alpha_eq(Tp), Tn, alpha_eq(Tn), dt);
+    b = explicit_step<false>(a, m, alo, mlo, Tp, alpha_eq(Tp), Tn, alpha_eq(Tn), dt, rd);
 }
 
 template <bool VEC>
 __global__ __launch_bounds__(kBlock) void step_kernel(const float* __restrict__ Tp, const float* __restrict__ Tn,
                                                      float* __restrict__ beta, float* __restrict__ as,
-                                                     float* __restrict__ am, int64_t n, float dt) {
+                                                     float* __restrict__ am, int64_t n, float dt, Readings rd) {
     const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (VEC) {
         const int64_t i = 4 * g;
@@ -57,7 +39,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(const float* __restrict__ 
 #pragma unroll
             for (int c = 0; c < 4; ++c) {
                 float ac = a[c], mc = m[c], bc;
-                step_point(tp[c], tn[c], bc, ac, mc, dt);
+                step_point(tp[c], tn[c], bc, ac, mc, dt, rd);
                 a[c] = ac;
                 m[c] = mc;
                 b[c] = bc;
@@ -68,7 +50,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(const float* __restrict__ 
         } else {
             for (int64_t j = i; j < n; ++j) {
                 float a = as[j], m = am[j], b;
-                step_point(Tp[j], Tn[j], b, a, m, dt);
+                step_point(Tp[j], Tn[j], b, a, m, dt, rd);
                 as[j] = a;
                 am[j] = m;
                 beta[j] = b;
@@ -77,7 +59,7 @@ __global__ __launch_bounds__(kBlock) void step_kernel(const float* __restrict__ 
     } else {
         if (g < n) {
             float a = as[g], m = am[g], b;
-            step_point(Tp[g], Tn[g], b, a, m, dt);
+            step_point(Tp[g], Tn[g], b, a, m, dt, rd);
             as[g] = a;
             am[g] = m;
             beta[g] = b;
@@ -89,24 +71,25 @@ __global__ __launch_bounds__(kBlock) void step_kernel(const float* __restrict__ 
 __global__ __launch_bounds__(kBlock) void step_tracked_kernel(const float* __restrict__ Tp,
                                                              const float* __restrict__ Tn, float* __restrict__ beta,
                                                              float* __restrict__ as, float* __restrict__ am,
-                                                             double* __restrict__ xbv, int64_t n, float dt) {
+                                                             double* __restrict__ xbv, int64_t n, float dt,
+                                                             Readings rd) {
     const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (g >= n) return;
     float a = as[g], m = am[g], alo = 0.0f, mlo = 0.0f;
     double xb = track_check(xbv[g], a, m);
     const float tp = Tp[g], tn = Tn[g];
-    beta[g] = explicit_step_tracked<false>(a, m, alo, mlo, xb, tp, alpha_eq(tp), tn, alpha_eq(tn), dt);
+    beta[g] = explicit_step_tracked<false>(a, m, alo, mlo, xb, tp, alpha_eq(tp), tn, alpha_eq(tn), dt, rd);
     as[g] = a;
     am[g] = m;
     xbv[g] = xb;
 }
 
 hipError_t launch_step(const float* Tp, const float* Tn, float* beta, float* as, float* am, double* xb, int64_t n,
-                       float dt, hipStream_t st) {
+                       float dt, Readings rd, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     if (xb) {
         hipLaunchKernelGGL(step_tracked_kernel, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, Tp,
-                           Tn, beta, as, am, xb, n, dt);
+                           Tn, beta, as, am, xb, n, dt, rd);
         return hipGetLastError();
     }
     const uintptr_t align = (uintptr_t)Tp | (uintptr_t)Tn | (uintptr_t)beta | (uintptr_t)as | (uintptr_t)am;
@@ -114,11 +97,11 @@ hipError_t launch_step(const float* Tp, const float* Tn, float* beta, float* as,
         const int64_t threads = (n + 3) / 4;
         const int64_t blocks = (threads + kBlock - 1) / kBlock;
         hipLaunchKernelGGL(step_kernel<true>, dim3((unsigned)blocks), dim3(kBlock), 0, st, Tp, Tn, beta, as, am,
-                           n, dt);
+                           n, dt, rd);
     } else {
         const int64_t blocks = (n + kBlock - 1) / kBlock;
         hipLaunchKernelGGL(step_kernel<false>, dim3((unsigned)blocks), dim3(kBlock), 0, st, Tp, Tn, beta, as, am,
-                           n, dt);
+                           n, dt, rd);
     }
     return hipGetLastError();
 }
@@ -136,7 +119,8 @@ __global__ __launch_bounds__(kBlock) void implicit_step_kernel(const float* __re
                                                               float* __restrict__ beta, float* __restrict__ as,
                                                               float* __restrict__ am, double* __restrict__ xbv,
                                                               int64_t n, float h, int n_sub, int max_iter,
-                                                              unsigned long long* __restrict__ unconverged) {
+                                                              unsigned long long* __restrict__ unconverged,
+                                                              bool assign) {
     const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     int bad = 0;
     if (g < n) {
@@ -147,8 +131,8 @@ __global__ __launch_bounds__(kBlock) void implicit_step_kernel(const float* __re
         float Ta = T0;
         for (int s = 0; s < n_sub; ++s) {
             const float Tb = (s + 1 == n_sub) ? Tn[g] : fmaf(dT, (float)(s + 1) * inv, T0);
-            const int it = TRACK ? implicit_step_tracked<false>(a, m, alo, mlo, xb, b, Ta, Tb, h, max_iter)
-                                 : implicit_step<false>(a, m, alo, mlo, b, Ta, Tb, h, max_iter);
+            const int it = TRACK ? implicit_step_tracked<false>(a, m, alo, mlo, xb, b, Ta, Tb, h, max_iter, assign)
+                                 : implicit_step<false>(a, m, alo, mlo, b, Ta, Tb, h, max_iter, assign);
             if (it < 0) ++bad;
             Ta = Tb;
         }
@@ -167,15 +151,15 @@ __global__ __launch_bounds__(kBlock) void implicit_step_kernel(const float* __re
 
 hipError_t launch_implicit_step(const float* Tp, const float* Tn, float* beta, float* as, float* am, double* xb,
                                 int64_t n, float h, int n_sub, int max_iter, unsigned long long* unconverged,
-                                hipStream_t st) {
+                                Readings rd, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     const dim3 grid((unsigned)((n + kBlock - 1) / kBlock)), block(kBlock);
     if (xb)
         hipLaunchKernelGGL(implicit_step_kernel<true>, grid, block, 0, st, Tp, Tn, beta, as, am, xb, n, h, n_sub,
-                           max_iter, unconverged);
+                           max_iter, unconverged, rd.mart_assign);
     else
         hipLaunchKernelGGL(implicit_step_kernel<false>, grid, block, 0, st, Tp, Tn, beta, as, am, xb, n, h, n_sub,
-                           max_iter, unconverged);
+                           max_iter, unconverged, rd.mart_assign);
     return hipGetLastError();
 }
 
@@ -191,24 +175,6 @@ __global__ __launch_bounds__(kBlock) void temperature_kernel(PointGeom pg, const
     int gi, gj, gk;
     decode_point(pg, local, gi, gj, gk);
     T[local] = (gk < pg.k0) ? sa.T0 : scan_temperature<W>(rec, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
-}
-
-// squared distance [grid units^2] within which the envelope tests certify
-// nothing: one grid unit, and at least the clamp radius and the offset
-// radius of source_rise
-__host__ __device__ __forceinline__ float envelope_radius2(const PointGeom& pg) {
-    return fmaxf(1.0f, fmaxf(pg.roff * pg.roff, pg.r2min));
-}
-
-// limit of the still test: the alpha_s -> beta end temperature of at_rest,
-// with 0.5 K to spare for float32 rounding of the computed temperatures
-constexpr float kRestBelow = Const<float>::TasEnd - 0.5f;
-
-// whether the still test can succeed (wave-uniform): certificates enabled,
-// T0 below the limit and every point of the wave at rest at the start of
-// the launch
-__device__ __forceinline__ bool wave_may_rest(const EnvSet& env, bool act, float a, float m, float T0) {
-    return env.n >= 0 && T0 < kRestBelow && __ballot(act && !rest_bits(a, m)) == 0;
 }
 
 // the box of grid positions holding the points of wave w (points 64 w ..
@@ -291,66 +257,6 @@ hipError_t launch_wave_boxes(const PointGeom& pg, int64_t n_waves, GridBox* boxe
     return hipGetLastError();
 }
 
-// wave index of the calling lane in a fused launch (uniform across the wave)
-__device__ __forceinline__ int64_t fused_wave() {
-    return (int64_t)blockIdx.x * (kFusedBlock / kWave) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-}
-
-// A wave whose flags say still (wave_flag_still): its state is at rest and
-// stays as it is, so only beta (last launch of a call) is written, with the
-// value every step would give.
-// On an index list, points above the current surface are inactive and left
-// alone (on a box grid every point of a call is active).
-__device__ __forceinline__ void still_wave_beta(const PointGeom& pg, float T0c, float* beta, int64_t g) {
-    if (!beta || g >= pg.count) return;
-    const int64_t local = pg.first + g;
-    if (pg.index) {
-        int gi, gj, gk;
-        decode_point(pg, local, gi, gj, gk);
-        if (gk < pg.k0) return;
-    }
-    beta[local] = solid_fraction(T0c) - kXmax - 0.0f;
-}
-
-// The persistent form of a fused launch, used from the second launch of a
-// call when the wave flags are kept: a grid of about one wave per
-// kSlotsPerWave waves of the launch, in which wave p takes the wave slots p,
-// p + P, p + 2P, ... (P waves in the grid).  Each lane loads the flags of
-// one slot; the wave then runs body(w) for every slot w that is not still
-// (all 64 lanes, one point each) and writes beta for the still ones.  No
-// wave is launched only to find its flags set, and the interleaved slots
-// spread the few waves that step evenly over the grid.
-template <int BS, class Body>
-__device__ __forceinline__ void fused_slots(const PointGeom& pg, const EnvSet& env, float T0c, float* beta,
-                                            Body body) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t P = (int64_t)gridDim.x * (BS / kWave);
-    const int64_t p = (int64_t)blockIdx.x * (BS / kWave) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-    for (int64_t r = 0; p + r * kWave * P < env.n_waves; ++r) {
-        const int64_t w = p + (r * kWave + lane) * P;
-        const bool in = w < env.n_waves;
-        const bool still = in && env.below[w] && env.rest[w];
-        uint64_t todo = __ballot(in && !still), quiet = beta ? __ballot(still) : 0;
-        while (todo) {
-            const int i = __builtin_ctzll(todo);
-            todo &= todo - 1;
-            body(p + (r * kWave + i) * P);
-        }
-        while (quiet) {
-            const int i = __builtin_ctzll(quiet);
-            quiet &= quiet - 1;
-            still_wave_beta(pg, T0c, beta, (p + (r * kWave + i) * P) * kWave + lane);
-        }
-    }
-}
-
-// record whether every point of the wave is at rest after the launch
-__device__ __forceinline__ void record_rest(const EnvSet& env, int64_t wv, bool act, float a, float m) {
-    if (!env.below || wv >= env.n_waves) return;
-    const bool r = __ballot(act && !rest_bits(a, m)) == 0;
-    if ((threadIdx.x & (kWave - 1)) == 0) env.rest[wv] = r ? 1 : 0;
-}
-
 // ---------------------------------------------------------------------------
 // fused K steps with the analytic temperature: one point per lane, its state
 // held in registers (with compensated Euler accumulation); tab holds the
@@ -370,7 +276,7 @@ __device__ __forceinline__ void fused_plain_body(const PointGeom& pg, const SrcR
     int64_t local[PPT];
     int gi[PPT], gj[PPT], gk[PPT];
     bool act[PPT];
-    float a[PPT], m[PPT], alo[PPT], mlo[PPT], Tn[PPT], xeq_n[PPT];
+    float a[PPT], m[PPT], alo[PPT], mlo[PPT], Tn[PPT], xeq_n[PPT], Tc[PPT];
     double xb[PPT];
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
@@ -399,11 +305,14 @@ __device__ __forceinline__ void fused_plain_body(const PointGeom& pg, const SrcR
         // an all-at-rest wave that is not below the limit everywhere is not cold either
         cold[u] = still[u] || (!tried && wave_cold(env.rec, env.n, act[u], gi[u], gj[u], gk[u], rlim2));
         Tn[u] = cold[u] ? T0c : scan_temperature<W>(tab, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min, pg.roff);
+        Tc[u] = Tn[u];  // temperature of the last correction (beta's sum rule)
         xeq_n[u] = alpha_eq(Tn[u]);
         // a cold wave whose points are all at rest at T0 is still as well
         still[u] = still[u] || (cold[u] && T0c < Const<float>::TasEnd && __ballot(act[u] && !rest_bits(a[u], m[u])) == 0);
         if (TRACK && still[u]) xb[u] = track_none();
+        if (env.stats) count_wave(env, act[u], still[u], cold[u]);
     }
+    float Tblk[PPT];  // temperature at the start of the sub-block (wave counts only)
     for (int s = 0; s < K; ++s) {
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
@@ -411,11 +320,17 @@ __device__ __forceinline__ void fused_plain_body(const PointGeom& pg, const SrcR
             const float Tn1 = cold[u] ? T0c
                                       : scan_temperature<W>(tab + (s + 1) * W, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp,
                                                             pg.r2min, pg.roff);
+            if (env.stats && !cold[u]) {
+                if (s % kStatBlock == 0) Tblk[u] = Tn[u];
+                if (s % kStatBlock == kStatBlock - 1) count_block(env, act[u], Tblk[u], Tn1);
+            }
             const float xeq_n1 = alpha_eq(Tn1);
             if (TRACK)
-                explicit_step_tracked<true>(a[u], m[u], alo[u], mlo[u], xb[u], Tn[u], xeq_n[u], Tn1, xeq_n1, dt);
+                explicit_step_tracked<true>(a[u], m[u], alo[u], mlo[u], xb[u], Tn[u], xeq_n[u], Tn1, xeq_n1, dt,
+                                            sa.rd);
             else
-                explicit_step<true>(a[u], m[u], alo[u], mlo[u], Tn[u], xeq_n[u], Tn1, xeq_n1, dt);
+                explicit_step<true>(a[u], m[u], alo[u], mlo[u], Tn[u], xeq_n[u], Tn1, xeq_n1, dt, sa.rd);
+            Tc[u] = sa.rd.corr_prev ? Tn[u] : Tn1;
             Tn[u] = Tn1;
             xeq_n[u] = xeq_n1;
         }
@@ -430,7 +345,7 @@ __device__ __forceinline__ void fused_plain_body(const PointGeom& pg, const SrcR
             am[local[u]] = mf;
         }
         if (TRACK) xbv[local[u]] = xb[u];
-        if (beta) beta[local[u]] = solid_fraction(Tn[u]) - af - mf;
+        if (beta) beta[local[u]] = solid_fraction(Tc[u]) - af - mf;
     }
     if (PPT == 1 && !TRACK) record_rest(env, wv, act[0], a[0] + alo[0], m[0] + mlo[0]);
 }
@@ -444,6 +359,7 @@ __global__ __launch_bounds__(kFusedBlock) void fused_plain_kernel(PointGeom pg, 
     const int64_t wv = fused_wave();
     if (PPT == 1 && !TRACK && wave_flag_still(env, wv)) {
         still_wave_beta(pg, fminf(sa.T0, sa.Tclamp), beta, (int64_t)blockIdx.x * kFusedBlock + threadIdx.x);
+        if (env.stats && (threadIdx.x & (kWave - 1)) == 0) atomicAdd(env.stats + kStatFlagged, 1ull);
         return;
     }
     fused_plain_body<W, PPT, TRACK>(pg, tab, env, K, dt, sa, beta, as, am, xbv,
@@ -495,14 +411,16 @@ __device__ __forceinline__ void fused_implicit_body(const PointGeom& pg, const S
     const float inv = 1.0f / (float)n_sub;
     still = still || (cold && T0c < Const<float>::TasEnd && __ballot(act && !rest_bits(a, m)) == 0);
     if (TRACK && still) xb = track_none();
+    if (env.stats) count_wave(env, act, still, cold);
     for (int s = 0; s < K && !still; ++s) {
         const float Tn1 =
             cold ? T0c : scan_temperature<W>(tab + (s + 1) * W, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
         float Ta = Tn;
         for (int k = 0; k < n_sub; ++k) {
             const float Tb = (k + 1 == n_sub) ? Tn1 : fmaf(Tn1 - Tn, (float)(k + 1) * inv, Tn);
-            const int it = TRACK ? implicit_step_tracked<true>(a, m, alo, mlo, xb, b, Ta, Tb, h, max_iter)
-                                 : implicit_step<true>(a, m, alo, mlo, b, Ta, Tb, h, max_iter);
+            const int it = TRACK ? implicit_step_tracked<true>(a, m, alo, mlo, xb, b, Ta, Tb, h, max_iter,
+                                                               sa.rd.mart_assign)
+                                 : implicit_step<true>(a, m, alo, mlo, b, Ta, Tb, h, max_iter, sa.rd.mart_assign);
             if (it < 0) ++bad;
             Ta = Tb;
         }
@@ -536,6 +454,7 @@ __global__ __launch_bounds__(kFusedBlock) void fused_implicit_kernel(PointGeom p
     const int64_t g = (int64_t)blockIdx.x * kFusedBlock + threadIdx.x;
     if (!TRACK && wave_flag_still(env, wv)) {  // see fused_plain_kernel
         still_wave_beta(pg, fminf(sa.T0, sa.Tclamp), beta, g);
+        if (env.stats && (threadIdx.x & (kWave - 1)) == 0) atomicAdd(env.stats + kStatFlagged, 1ull);
         return;
     }
     fused_implicit_body<W, TRACK>(pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, xbv, unconverged, g, wv);
@@ -567,22 +486,6 @@ static hipError_t fused_implicit_w(const PointGeom& pg, int W, const SrcRec* tab
     }
     return hipGetLastError();
 }
-
-// grid of the persistent (slot) fused kernels in workgroups of bs threads:
-// one wave per kSlotsPerWave waves of the launch
-static dim3 slots_grid(int64_t n_waves, int bs) {
-    const int64_t waves = (n_waves + kSlotsPerWave - 1) / kSlotsPerWave;
-    return dim3((unsigned)((waves + bs / kWave - 1) / (bs / kWave)));
-}
-
-// launch a slot kernel instantiated for workgroups of 128 and 256 threads
-#define LAUNCH_SLOTS(kernel, W, n_waves, st, ...)                                                          \
-    do {                                                                                                    \
-        if ((n_waves) >= kSlotsLargeGrid)                                                                   \
-            hipLaunchKernelGGL((kernel<W, 256>), slots_grid(n_waves, 256), dim3(256), 0, st, __VA_ARGS__); \
-        else                                                                                                \
-            hipLaunchKernelGGL((kernel<W, 128>), slots_grid(n_waves, 128), dim3(128), 0, st, __VA_ARGS__); \
-    } while (0)
 
 hipError_t launch_fused_implicit(const PointGeom& pg, int W, const SrcRec* tab, EnvSet env, int K, float h, int n_sub,
                                  int max_iter, ScanArgs sa, float* beta, float* as, float* am, double* xb,

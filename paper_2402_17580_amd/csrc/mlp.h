@@ -53,20 +53,12 @@ struct MlpState {
     float* partial = nullptr;  // per-wave partial gradients [waves][kMlpParams + 1]
     int partial_waves = 0;
     int adam_t = 0;
-    // surrogate work queue: one entry (kQueueWords floats) per wave that needs
-    // the network, and two alternating entry counters
-    float* queue = nullptr;
-    int64_t queue_entries = 0;
+    // surrogate mode: records of the waves that stop for the network (see
+    // mlp.hip), and two record counters used by alternate launches
+    void* recs = nullptr;
+    int64_t rec_cap = 0;
     unsigned* counters = nullptr;
-    // block-end temperatures of the previous surrogate block of a call (the
-    // next block's start temperatures), indexed by local point number; two
-    // slots of tcache_n floats each, used alternately by consecutive blocks
-    float* tcache = nullptr;
-    int64_t tcache_n = 0;
-    int cu_count = 0;  // compute units of the context's device (pass A grid)
 };
-
-constexpr int kQueueWords = 7 * 64;  // index, T0, TK, alpha_s, alpha_m, pre_alpha_s, pre_alpha_m
 
 hipError_t mlp_alloc(MlpState& s);
 void mlp_free(MlpState& s);
@@ -75,12 +67,13 @@ hipError_t mlp_forward(const MlpState& s, const float* X, int64_t B, float* Y, h
 hipError_t mlp_grad(MlpState& s, const float* X, const float* Y, int64_t B, float* grad, float* loss,
                     hipStream_t st);
 hipError_t mlp_adam(MlpState& s, float lr, hipStream_t st);
-hipError_t surrogate_prepare(MlpState& s, int64_t points, hipStream_t st);
-// env: the wave flags of the launch (env.below == nullptr: not used; the
-// envelope records themselves are not used by the surrogate)
-hipError_t launch_surrogate(const MlpState& s, const PointGeom& pg, int W, const SrcRec* tab, EnvSet env, int K,
-                            float dt, ScanArgs sa, float* beta, float* as, float* am, int64_t block, bool first_block,
-                            bool last_block, hipStream_t st);
-hipError_t launch_correct(const float* T, float* beta, float* as, float* am, int64_t n, hipStream_t st);
+// before the launches of a surrogate call on `waves` waves of 64 points
+hipError_t surrogate_prepare(MlpState& s, int64_t waves, hipStream_t st);
+// one launch of Kl steps (launch li of the call) in blocks of Ks steps, with
+// the launch certificates and wave flags of env as in the plain fused launch
+hipError_t launch_surrogate(const MlpState& s, const PointGeom& pg, int W, const SrcRec* tab, EnvSet env, int Kl,
+                            int Ks, float dt, ScanArgs sa, float* beta, float* as, float* am, int64_t li,
+                            hipStream_t st);
+hipError_t launch_correct(const float* T, float* beta, float* as, float* am, int64_t n, bool assign, hipStream_t st);
 
 }  // namespace mstruct

@@ -14,15 +14,9 @@
 // features 16q + 4h + {0..3} and 16q + 8 + 4h + {0..3}; the product sums over
 // k, so the same permutation of k is applied to the weights and those eight
 // registers become the B operand as they are.
+#include "fused.h"
 #include "mlp.h"
 
-#ifndef SURROGATE_PPT
-#define SURROGATE_PPT 1
-#endif
-// pass A grid: blocks per compute unit (the grid strides over the chunks)
-#ifndef SURROGATE_BLOCKS_PER_CU
-#define SURROGATE_BLOCKS_PER_CU 32
-#endif
 
 namespace mstruct {
 
@@ -560,14 +554,19 @@ hipError_t mlp_adam(MlpState& s, float lr, hipStream_t st) {
 }
 
 // ---------------------------------------------------------------------------
-// surrogate K-block update in two passes.
-// Pass A (one point per lane, no matrix code, high occupancy): temperatures at
-// the block ends, the error indicator, the K plain steps for flagged points,
-// and for the others one explicit step of K dt, stored; a wave with any
-// point whose increment exceeds kNetMinIncrement appends its inputs to the
-// queue.
-// Pass B (persistent, weights staged in LDS): the network on queued waves,
-// whose output corrects the increment before the block-end correction.
+// Surrogate mode inside the fused launches.  A launch covers up to 64 steps
+// (a whole number of network blocks of Ks steps) with the launch
+// certificates, wave flags and slot kernels of the plain path.  A wave that
+// steps decides block by block: if every one of its active points passes
+// the error indicator, the block is one explicit step of Ks dt (rates at the
+// block-start temperature, the Appendix A start-up forms included), the
+// network's correction towards Ks plain steps where an increment exceeds
+// kNetMinIncrement, and the correction g at the block-end temperature;
+// otherwise the wave takes the Ks plain steps, evaluating the temperature
+// at each.  The network runs in a second kernel: a wave that needs it at
+// block j leaves its state at the start of block j in a record and stops,
+// and the resume kernel (weights staged in LDS) carries on from there.  So
+// the fused kernels keep the plain path's register budget.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ bool needs_plain(float T0, float TK, const MlpNorm& n) {
     const float lo = fminf(T0, TK), hi = fmaxf(T0, TK);
@@ -576,201 +575,249 @@ __device__ __forceinline__ bool needs_plain(float T0, float TK, const MlpNorm& n
     return !(cold || hot) || fabsf(TK - T0) > n.dT_max;
 }
 
-// tin and tout may be the same buffer (a point's block-start temperature is
-// read before its block-end temperature is written), so they are not restrict.
 // A point at its martensite formation front: within kFrontProbe of the lower
 // block-end temperature the formation law would raise alpha_m, so a dip of the
 // temperature inside the block would form martensite the block ends miss.
 constexpr float kFrontProbe = 5.0f;  // [K]
-// The network corrects one explicit step of K dt towards K plain steps.  The
-// two differ by the change of the rates over the block times K dt, at most
-// about the increment itself, so increments of at most 2^-20 (about 1e-6) in
-// both fractions are taken as they are.  Away from the laser these are the
-// slow low-temperature rates, e.g. the tempering of martensite.
+// The network corrects one explicit step of Ks dt towards Ks plain steps.
+// The two differ by the change of the rates over the block times Ks dt, at
+// most about the increment itself, so increments of at most 2^-20 (about
+// 1e-6) in both fractions are taken as they are.  Away from the laser these
+// are the slow low-temperature rates, e.g. the tempering of martensite.
 constexpr float kNetMinIncrement = 0x1p-20f;
-constexpr int kProbeEvery = 8;       // probe spacing inside longer blocks [steps]
+constexpr int kProbeEvery = 8;  // probe spacing inside longer blocks [steps]
 __device__ __forceinline__ bool formation_front(float T0, float TK, float a, float m) {
     const float Tlo = fminf(T0, TK) - kFrontProbe;
     return Tlo < kTamStart && am0_eq(Tlo) * (kXmax - a) * (1.0f / kXmax) > m;
 }
 
-template <int W, int PPT>
-__global__ __launch_bounds__(256) void surrogate_a_kernel(PointGeom pg, const SrcRec* __restrict__ tab, EnvSet env,
-                                                         int K, float dt, ScanArgs sa, float* __restrict__ beta,
-                                                         float* __restrict__ as, float* __restrict__ am,
-                                                         MlpNorm nrm, float* __restrict__ queue,
-                                                         unsigned* __restrict__ counter, const float* tin,
-                                                         float* tout, int64_t n_chunks) {
-    // A chunk is 256 * PPT consecutive points; the grid strides over the
-    // chunks (a few blocks per CU).  Each lane takes PPT points 256 apart
-    // (coalesced); their loads are issued together and their temperatures
-    // computed side by side.
-    const int lane = threadIdx.x & 63;
-    const int wib = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-    for (int64_t chunk = blockIdx.x; chunk < n_chunks; chunk += gridDim.x) {
-        const int64_t g0 = chunk * 256 * PPT + threadIdx.x;
-        int64_t local[PPT], wv[PPT];
-        int gi[PPT], gj[PPT], gk[PPT];
-        bool valid[PPT], still[PPT];
-        float a[PPT], m[PPT], T0[PPT], TK[PPT];
-        // 64 points of a wave whose flags say still (at rest, below 935 K
-        // through the block): every branch below would leave them as they
-        // are and write beta = 1 - 0.9 - 0, and none would be queued; only
-        // the block-end temperature is not computed (the wave's tcached byte
-        // makes the next block compute its start temperature, the same value)
-#pragma unroll
-        for (int u = 0; u < PPT; ++u) {
-            wv[u] = chunk * (256 * PPT / 64) + wib + u * (256 / 64);
-            still[u] = wave_flag_still(env, wv[u]);
-        }
-        // indices, then every load issued before any arithmetic that needs it
-#pragma unroll
-        for (int u = 0; u < PPT; ++u) {
-            const int64_t g = g0 + u * 256;
-            valid[u] = g < pg.count;
-            local[u] = pg.first + (valid[u] ? g : 0);
-            const int lin = pg.index ? pg.index[local[u]] : (int)local[u];
-            gk[u] = divide_by(lin, pg.mag_nxy, pg.sh_nxy);
-            const int rem = lin - gk[u] * pg.nxy;
-            gj[u] = divide_by(rem, pg.mag_nx, pg.sh_nx);
-            gi[u] = rem - gj[u] * pg.nx;
-            valid[u] = valid[u] && gk[u] >= pg.k0;
-        }
-#pragma unroll
-        for (int u = 0; u < PPT; ++u) {
-            if (still[u]) {
-                if (valid[u] && beta) beta[local[u]] = 1.0f - kXmax - 0.0f;
-                valid[u] = false;
-                continue;
-            }
-            a[u] = as[local[u]];
-            m[u] = am[local[u]];
-            T0[u] = tin ? tin[local[u]] : 0.0f;
-        }
-        // block-end temperature: independent of the loads above
-#pragma unroll
-        for (int u = 0; u < PPT; ++u)
-            if (!still[u])
-                TK[u] = scan_temperature<W>(tab + K * W, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min, pg.roff);
-        // block start: computed in the first block of a call, and where the
-        // previous block left no value
-#pragma unroll
-        for (int u = 0; u < PPT; ++u)
-            if (!still[u] && (!tin || (env.tcached && wv[u] < env.n_waves && !env.tcached[wv[u]])))
-                T0[u] = scan_temperature<W>(tab, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min, pg.roff);
-#pragma unroll
-        for (int u = 0; u < PPT; ++u) {
-            if (valid[u]) {
-                if (tout) tout[local[u]] = TK[u];
-            } else {
-                a[u] = m[u] = 0.0f;
-                T0[u] = TK[u] = sa.T0;
-            }
-            if (tout && env.tcached && wv[u] < env.n_waves && lane == 0) env.tcached[wv[u]] = still[u] ? 0 : 1;
-        }
-#pragma unroll
-        for (int u = 0; u < PPT; ++u) {
-            float pa = 0.0f, pm = 0.0f, fa = 0.0f, fm = 0.0f;
-            bool need = false;
-            if (valid[u]) {
-                float an = a[u], mn = m[u], bn;
-                const float xeq0 = alpha_eq(T0[u]);
-                bool plain = needs_plain(T0[u], TK[u], nrm);
-                if (!plain && formation_front(T0[u], TK[u], a[u], m[u])) {
-                    // martensite forms at the lowest temperature of the block:
-                    // a dip below both ends needs the plain steps.  Probed at
-                    // the block middle and every kProbeEvery steps.
-                    const float Tlo = fminf(T0[u], TK[u]);
-                    const float Tmid = scan_temperature<W>(tab + (K / 2) * W, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp,
-                                                           pg.r2min, pg.roff);
-                    plain = Tmid < Tlo;
-                    for (int s = kProbeEvery; s < K && !plain; s += kProbeEvery) {
-                        if (s == K / 2) continue;
-                        plain = scan_temperature<W>(tab + s * W, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min,
-                                                    pg.roff) < Tlo;
-                    }
-                }
-                if (plain) {
-                    float alo = 0.0f, mlo = 0.0f, Tn = T0[u], xeq_n = xeq0;
-                    for (int s = 0; s < K; ++s) {
-                        const float Tn1 = scan_temperature<W>(tab + (s + 1) * W, gi[u], gj[u], gk[u], sa.T0,
-                                                              sa.Tclamp, pg.r2min, pg.roff);
-                        const float xeq_n1 = alpha_eq(Tn1);
-                        explicit_step<true>(an, mn, alo, mlo, Tn, xeq_n, Tn1, xeq_n1, dt);
-                        Tn = Tn1;
-                        xeq_n = xeq_n1;
-                    }
-                    an += alo;
-                    mn += mlo;
-                    bn = solid_fraction(Tn) - an - mn;
-                } else if (at_rest(a[u], m[u], T0[u], TK[u])) {
-                    bn = 1.0f - an - mn;  // the step of K dt leaves the state as it is
-                } else {
-                    float da, dm;
-                    diffusive_increment(a[u], m[u], T0[u], xeq0, dt * (float)K, da, dm);
-                    pa = a[u] + da;
-                    pm = m[u] + dm;
-                    need = fmaxf(fabsf(da), fabsf(dm)) > kNetMinIncrement;
-                    an = pa;
-                    mn = pm;
-                    bn = correct(TK[u], alpha_eq(TK[u]), an, mn);
-                }
-                as[local[u]] = an;
-                am[local[u]] = mn;
-                if (beta) beta[local[u]] = bn;
-                fa = an;
-                fm = mn;
-            }
-            if (__ballot(need) != 0) {
-                unsigned slot = 0;
-                if (lane == 0) slot = atomicAdd(counter, 1u);
-                slot = __shfl(slot, 0);
-                float* e = queue + (int64_t)slot * kQueueWords;
-                e[lane] = __int_as_float(need ? (int)local[u] : -1);
-                e[64 + lane] = T0[u];
-                e[128 + lane] = TK[u];
-                e[192 + lane] = a[u];
-                e[256 + lane] = m[u];
-                e[320 + lane] = pa;
-                e[384 + lane] = pm;
-            }
-            // rest flag of the wave after this block (a queued point is
-            // corrected by pass B and does not count as at rest)
-            if (env.below && !still[u] && wv[u] < env.n_waves) {
-                const bool r = __ballot(valid[u] && !(rest_bits(fa, fm) && !need)) == 0;
-                if (lane == 0) env.rest[wv[u]] = r ? 1 : 0;
+// a wave's state at the start of a block, handed to the resume kernel
+struct SurrogateRecord {
+    int64_t wave;
+    int32_t block;
+    int32_t cold;
+    float a[kWave], m[kWave], alo[kWave], mlo[kWave], Tn[kWave];
+};
+
+// What a wave does with a block whose increments need the network.
+enum { kNetStop = 0, kNetRun = 1, kNetPlain = 2 };
+
+// Blocks j0 .. of a launch of Kl steps for the calling lane's point (state
+// in registers: (a, alo), (m, mlo) compensated pairs, Tn the temperature at
+// the start of block j0).  NET: kNetStop returns the block at which the
+// network is needed (state unchanged from that block's start); kNetRun
+// evaluates it (all 64 lanes; L: staged weights); kNetPlain takes the plain
+// steps instead.  Returns -1 when every block was taken.
+template <int W, int NET>
+__device__ __forceinline__ int surrogate_blocks(const PointGeom& pg, const SrcRec* __restrict__ tab, int Kl, int Ks,
+                                                float dt, const ScanArgs& sa, const MlpNorm& nrm,
+                                                const InferLds* L, bool act, bool cold, int gi, int gj, int gk, int j0,
+                                                float& a, float& m, float& alo, float& mlo, float& Tn) {
+    const float T0c = fminf(sa.T0, sa.Tclamp);
+    const int nb = (Kl + Ks - 1) / Ks;
+    float xeq_n = alpha_eq(Tn);
+    for (int j = j0; j < nb; ++j) {
+        const int s0 = j * Ks, Kb = min(Ks, Kl - s0);
+        const SrcRec* tb = tab + s0 * W;
+        const float TK = cold ? T0c : scan_temperature<W>(tb + Kb * W, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
+        // the indicator, point by point; a partial block (the end of a
+        // call) takes the plain steps
+        bool plain = Kb < Ks || needs_plain(Tn, TK, nrm);
+        if (act && !plain && !cold && formation_front(Tn, TK, a, m)) {
+            // martensite forms at the lowest temperature of the block: a dip
+            // below both ends needs the plain steps.  Probed at the block
+            // middle and every kProbeEvery steps.
+            const float Tlo = fminf(Tn, TK);
+            plain = scan_temperature<W>(tb + (Kb / 2) * W, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff) < Tlo;
+            for (int s = kProbeEvery; s < Kb && !plain; s += kProbeEvery) {
+                if (s == Kb / 2) continue;
+                plain = scan_temperature<W>(tb + s * W, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff) < Tlo;
             }
         }
+        const bool rest = !act || at_rest(a, m, Tn, TK);
+        float da = 0.0f, dm = 0.0f;
+        bool need = false;
+        if (!plain && !rest) {
+            diffusive_increment(a, m, Tn, xeq_n, dt * (float)Kb, da, dm);
+            need = fmaxf(fabsf(da), fabsf(dm)) > kNetMinIncrement;
+        }
+        const bool wave_plain = __ballot(act && plain) != 0;
+        const bool wave_net = !wave_plain && __ballot(need) != 0;
+        if (NET == kNetStop && wave_net) return j;
+        if (wave_plain || (NET == kNetPlain && wave_net)) {
+            // the Kb plain steps; the last temperature is TK
+            for (int s = 0; s < Kb; ++s) {
+                const float Tn1 = (s + 1 == Kb) ? TK
+                                  : cold        ? T0c
+                                                : scan_temperature<W>(tb + (s + 1) * W, gi, gj, gk, sa.T0, sa.Tclamp,
+                                                                      pg.r2min, pg.roff);
+                const float xeq_n1 = alpha_eq(Tn1);
+                explicit_step<true>(a, m, alo, mlo, Tn, xeq_n, Tn1, xeq_n1, dt);
+                Tn = Tn1;
+                xeq_n = xeq_n1;
+            }
+            continue;
+        }
+        float ra = 0.0f, rm = 0.0f;
+        if (NET == kNetRun && wave_net) {
+            // inputs (T_n, T_K, ln dt, beta, alpha_s, alpha_m) at the block start
+            const float raw[6] = {Tn, TK, logf(dt), solid_fraction(Tn) - a - m, a, m};
+            float x[8], y[3];
+            normalise(nrm, raw, x);
+            mlp_infer(*L, x, y, threadIdx.x & (kWave - 1));
+            if (need) {
+                ra = y[0] * nrm.out_scale[0];
+                rm = y[1] * nrm.out_scale[1];
+            }
+        }
+        const float xeq_K = alpha_eq(TK);
+        if (!rest) {
+            float at, mt;
+            two_sum(a, alo + (da + ra), at, alo);
+            two_sum(m, mlo + (dm + rm), mt, mlo);
+            const float a_before = at, m_before = mt;
+            correct(TK, xeq_K, at, mt);
+            if (at != a_before) alo = 0.0f;
+            if (mt != m_before) mlo = 0.0f;
+            a = at;
+            m = mt;
+        }
+        Tn = TK;
+        xeq_n = xeq_K;
     }
+    return -1;
 }
 
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void surrogate_b_kernel(
-    const float* __restrict__ queue, const unsigned* __restrict__ counter, unsigned* __restrict__ counter_next,
-    float ln_dt, float* __restrict__ beta, float* __restrict__ as, float* __restrict__ am,
-    const uint32_t* __restrict__ frag, MlpNorm nrm) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) *counter_next = 0u;  // for the next block's pass A
-    const unsigned count = *counter;
-    const unsigned n_waves = gridDim.x * (blockDim.x >> 6);
-    if (blockIdx.x * (blockDim.x >> 6) >= count) return;  // no queued wave for this block (uniform)
+// the end of a wave's launch: its state, beta in the last launch of a call,
+// its rest flag
+__device__ __forceinline__ void surrogate_store(const EnvSet& env, int64_t wv, bool act, int64_t local, float a,
+                                                float m, float alo, float mlo, float Tn, float* __restrict__ beta,
+                                                float* __restrict__ as, float* __restrict__ am) {
+    const float af = a + alo, mf = m + mlo;
+    if (act) {
+        as[local] = af;
+        am[local] = mf;
+        if (beta) beta[local] = solid_fraction(Tn) - af - mf;
+    }
+    record_rest(env, wv, act, af, mf);
+}
+
+// the body of a fused surrogate launch for wave wv (points g = 64 wv + lane)
+template <int W>
+__device__ __forceinline__ void surrogate_fused_body(const PointGeom& pg, const SrcRec* __restrict__ tab,
+                                                     const EnvSet& env, int Kl, int Ks, float dt, const ScanArgs& sa,
+                                                     const MlpNorm& nrm, float* __restrict__ beta,
+                                                     float* __restrict__ as, float* __restrict__ am,
+                                                     SurrogateRecord* __restrict__ recs, unsigned* __restrict__ n_recs,
+                                                     int64_t cap, int64_t g, int64_t wv) {
+    const float T0c = fminf(sa.T0, sa.Tclamp);
+    bool act = g < pg.count;
+    const int64_t local = pg.first + (act ? g : 0);
+    int gi, gj, gk;
+    decode_point(pg, local, gi, gj, gk);
+    act = act && gk >= pg.k0;
+    float a = act ? as[local] : 0.0f, m = act ? am[local] : 0.0f, alo = 0.0f, mlo = 0.0f;
+    // still and cold waves as in the plain fused kernel
+    const float rlim2 = envelope_radius2(pg);
+    const bool tried = wave_may_rest(env, act, a, m, T0c);
+    bool still = tried && wave_below(env.rec, env.n, act, gi, gj, gk, rlim2, T0c, kRestBelow);
+    const bool cold = still || (!tried && wave_cold(env.rec, env.n, act, gi, gj, gk, rlim2));
+    float Tn = cold ? T0c : scan_temperature<W>(tab, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
+    still = still || (cold && T0c < Const<float>::TasEnd && __ballot(act && !rest_bits(a, m)) == 0);
+    if (env.stats) count_wave(env, act, still, cold);
+    if (still) {  // its fractions are those in memory
+        if (act && beta) beta[local] = solid_fraction(Tn) - a - m;
+        record_rest(env, wv, act, a, m);
+        return;
+    }
+    const int j = surrogate_blocks<W, kNetStop>(pg, tab, Kl, Ks, dt, sa, nrm, nullptr, act, cold, gi, gj, gk, 0, a, m,
+                                                alo, mlo, Tn);
+    if (j >= 0) {
+        unsigned slot = 0;
+        if ((threadIdx.x & (kWave - 1)) == 0) slot = atomicAdd(n_recs, 1u);
+        slot = __shfl(slot, 0);
+        if ((int64_t)slot < cap) {
+            SurrogateRecord& r = recs[slot];
+            const int lane = threadIdx.x & (kWave - 1);
+            if (lane == 0) {
+                r.wave = wv;
+                r.block = j;
+                r.cold = cold ? 1 : 0;
+            }
+            r.a[lane] = a;
+            r.m[lane] = m;
+            r.alo[lane] = alo;
+            r.mlo[lane] = mlo;
+            r.Tn[lane] = Tn;
+            return;  // the resume kernel takes the wave from block j
+        }
+        // no room for the record: this wave takes plain steps where the network would act
+        surrogate_blocks<W, kNetPlain>(pg, tab, Kl, Ks, dt, sa, nrm, nullptr, act, cold, gi, gj, gk, j, a, m, alo, mlo,
+                                       Tn);
+    }
+    surrogate_store(env, wv, act, local, a, m, alo, mlo, Tn, beta, as, am);
+}
+
+template <int W>
+__global__ __launch_bounds__(kFusedBlock) void fused_surrogate_kernel(PointGeom pg, const SrcRec* __restrict__ tab,
+                                                                      EnvSet env, int Kl, int Ks, float dt,
+                                                                      ScanArgs sa, MlpNorm nrm,
+                                                                      float* __restrict__ beta, float* __restrict__ as,
+                                                                      float* __restrict__ am,
+                                                                      SurrogateRecord* __restrict__ recs,
+                                                                      unsigned* __restrict__ n_recs, int64_t cap) {
+    const int64_t wv = fused_wave();
+    const int64_t g = (int64_t)blockIdx.x * kFusedBlock + threadIdx.x;
+    if (wave_flag_still(env, wv)) {
+        still_wave_beta(pg, fminf(sa.T0, sa.Tclamp), beta, g);
+        if (env.stats && (threadIdx.x & (kWave - 1)) == 0) atomicAdd(env.stats + kStatFlagged, 1ull);
+        return;
+    }
+    surrogate_fused_body<W>(pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, n_recs, cap, g, wv);
+}
+
+template <int W, int BS>
+__global__ __launch_bounds__(BS) void fused_surrogate_slots_kernel(PointGeom pg, const SrcRec* __restrict__ tab,
+                                                                   EnvSet env, int Kl, int Ks, float dt, ScanArgs sa,
+                                                                   MlpNorm nrm, float* __restrict__ beta,
+                                                                   float* __restrict__ as, float* __restrict__ am,
+                                                                   SurrogateRecord* __restrict__ recs,
+                                                                   unsigned* __restrict__ n_recs, int64_t cap) {
+    const int lane = threadIdx.x & (kWave - 1);
+    fused_slots<BS>(pg, env, fminf(sa.T0, sa.Tclamp), beta, [&](int64_t w) {
+        surrogate_fused_body<W>(pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, n_recs, cap, w * kWave + lane,
+                                w);
+    });
+}
+
+// The waves that stopped for the network: a persistent grid, each wave one
+// record at a time, from the recorded block to the end of the launch with
+// the network evaluated where it is needed.  Zeroes the other record counter
+// for the next launch.
+template <int W>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void surrogate_resume_kernel(
+    PointGeom pg, const SrcRec* __restrict__ tab, EnvSet env, int Kl, int Ks, float dt, ScanArgs sa, MlpNorm nrm,
+    float* __restrict__ beta, float* __restrict__ as, float* __restrict__ am, const SurrogateRecord* __restrict__ recs,
+    const unsigned* __restrict__ n_recs, unsigned* __restrict__ n_recs_next, int64_t cap, const uint32_t* __restrict__ frag) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *n_recs_next = 0u;
+    const int64_t count = min((int64_t)*n_recs, cap);
+    const int64_t n_waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    if ((int64_t)blockIdx.x * (blockDim.x >> 6) >= count) return;  // no record for this block (uniform)
     __shared__ InferLds L;
     stage_infer_frag(L, frag);
-    const int lane = threadIdx.x & 63;
-    for (unsigned q = (blockIdx.x * blockDim.x + threadIdx.x) >> 6; q < count; q += n_waves) {
-        const float* e = queue + (int64_t)q * kQueueWords;
-        const int idx = __float_as_int(e[lane]);
-        const float T0 = e[64 + lane], TK = e[128 + lane], a = e[192 + lane], m = e[256 + lane];
-        const float pa = e[320 + lane], pm = e[384 + lane];
-        const float raw[6] = {T0, TK, ln_dt, solid_fraction(T0) - a - m, a, m};
-        float x[8], y[3];
-        normalise(nrm, raw, x);
-        mlp_infer(L, x, y, lane);
-        if (idx >= 0) {
-            float an = fmaf(y[0], nrm.out_scale[0], pa), mn = fmaf(y[1], nrm.out_scale[1], pm);
-            const float bn = correct(TK, alpha_eq(TK), an, mn);
-            as[idx] = an;
-            am[idx] = mn;
-            if (beta) beta[idx] = bn;
-        }
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; q < count; q += n_waves) {
+        const SurrogateRecord& r = recs[q];
+        const int64_t wv = r.wave, g = wv * kWave + lane;
+        bool act = g < pg.count;
+        const int64_t local = pg.first + (act ? g : 0);
+        int gi, gj, gk;
+        decode_point(pg, local, gi, gj, gk);
+        act = act && gk >= pg.k0;
+        float a = r.a[lane], m = r.m[lane], alo = r.alo[lane], mlo = r.mlo[lane], Tn = r.Tn[lane];
+        surrogate_blocks<W, kNetRun>(pg, tab, Kl, Ks, dt, sa, nrm, &L, act, r.cold != 0, gi, gj, gk, r.block, a, m, alo,
+                                     mlo, Tn);
+        surrogate_store(env, wv, act, local, a, m, alo, mlo, Tn, beta, as, am);
     }
 }
 
@@ -778,85 +825,86 @@ __global__ void reset_counters_kernel(unsigned* c) {
     if (threadIdx.x < 2) c[threadIdx.x] = 0u;
 }
 
-hipError_t surrogate_prepare(MlpState& s, int64_t points, hipStream_t st) {
-    if (points > s.tcache_n) {
+// records for at most this many waves per launch; more waves than that which
+// need the network take the plain steps of those blocks instead
+constexpr int64_t kMaxRecords = (int64_t)1 << 16;
+
+hipError_t surrogate_prepare(MlpState& s, int64_t waves, hipStream_t st) {
+    const int64_t need = waves < kMaxRecords ? (waves > 0 ? waves : 1) : kMaxRecords;
+    if (need > s.rec_cap) {
         hipError_t e = hipStreamSynchronize(st);
         if (e != hipSuccess) return e;
-        if (s.tcache) (void)hipFree(s.tcache);
-        s.tcache = nullptr;
-        s.tcache_n = 0;
-        // two slots: block b reads slot b & 1 and writes slot (b + 1) & 1, so the
-        // cached temperatures are never read and rewritten in the same buffer
-        if ((e = hipMalloc((void**)&s.tcache, 2 * (size_t)points * sizeof(float))) != hipSuccess) return e;
-        s.tcache_n = points;
-    }
-    // at most one queue entry per wave and point group of pass A
-    const int64_t need = (points + 63) / 64 + SURROGATE_PPT + 1;
-    if (need > s.queue_entries) {
-        hipError_t e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return e;
-        if (s.queue) (void)hipFree(s.queue);
-        s.queue = nullptr;
-        s.queue_entries = 0;
-        if ((e = hipMalloc((void**)&s.queue, (size_t)need * kQueueWords * sizeof(float))) != hipSuccess) return e;
-        s.queue_entries = need;
+        if (s.recs) (void)hipFree(s.recs);
+        s.recs = nullptr;
+        s.rec_cap = 0;
+        if ((e = hipMalloc(&s.recs, (size_t)need * sizeof(SurrogateRecord))) != hipSuccess) return e;
+        s.rec_cap = need;
     }
     if (!s.counters) {
         hipError_t e = hipMalloc((void**)&s.counters, 2 * sizeof(unsigned));
-        if (e != hipSuccess) return e;
-    }
-    if (s.cu_count <= 0) {
-        int dev = 0;
-        hipError_t e = hipGetDevice(&dev);
-        if (e == hipSuccess) e = hipDeviceGetAttribute(&s.cu_count, hipDeviceAttributeMultiprocessorCount, dev);
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, st, s.counters);
     return hipGetLastError();
 }
 
-hipError_t launch_surrogate(const MlpState& s, const PointGeom& pg, int W, const SrcRec* tab, EnvSet env, int K,
-                            float dt, ScanArgs sa, float* beta, float* as, float* am, int64_t block, bool first_block,
-                            bool last_block, hipStream_t st) {
-    const float* tin = first_block ? nullptr : s.tcache + (block & 1) * s.tcache_n;
-    float* tout = last_block ? nullptr : s.tcache + ((block + 1) & 1) * s.tcache_n;
-    if (!last_block) beta = nullptr;
+hipError_t launch_surrogate(const MlpState& s, const PointGeom& pg, int W, const SrcRec* tab, EnvSet env, int Kl,
+                            int Ks, float dt, ScanArgs sa, float* beta, float* as, float* am, int64_t li,
+                            hipStream_t st) {
     if (pg.count <= 0) return hipSuccess;
-    unsigned* cur = s.counters + (block & 1);
-    unsigned* nxt = s.counters + ((block + 1) & 1);
-    constexpr int P = SURROGATE_PPT;
-    const int64_t n_chunks = (pg.count + 256 * P - 1) / (256 * P);
-    const int64_t cap = (int64_t)s.cu_count * SURROGATE_BLOCKS_PER_CU;
-    const dim3 grid((unsigned)(cap > 0 && cap < n_chunks ? cap : n_chunks)), blk(256);
-    switch (W) {
-        case 1: hipLaunchKernelGGL((surrogate_a_kernel<1, P>), grid, blk, 0, st, pg, tab, env, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, tout, n_chunks); break;
-        case 2: hipLaunchKernelGGL((surrogate_a_kernel<2, P>), grid, blk, 0, st, pg, tab, env, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, tout, n_chunks); break;
-        case 3: hipLaunchKernelGGL((surrogate_a_kernel<3, P>), grid, blk, 0, st, pg, tab, env, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, tout, n_chunks); break;
-        case 4: hipLaunchKernelGGL((surrogate_a_kernel<4, P>), grid, blk, 0, st, pg, tab, env, K, dt, sa, beta, as, am, s.norm, s.queue, cur, tin, tout, n_chunks); break;
-        default: return hipErrorInvalidValue;
+    SurrogateRecord* recs = static_cast<SurrogateRecord*>(s.recs);
+    unsigned* cur = s.counters + (li & 1);
+    unsigned* nxt = s.counters + ((li + 1) & 1);
+    const int64_t cap = s.rec_cap;
+    const MlpNorm& nrm = s.norm;
+    if (env.below && env.read_rest) {
+        switch (W) {
+            case 1: LAUNCH_SLOTS(fused_surrogate_slots_kernel, 1, env.n_waves, st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
+            case 2: LAUNCH_SLOTS(fused_surrogate_slots_kernel, 2, env.n_waves, st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
+            case 3: LAUNCH_SLOTS(fused_surrogate_slots_kernel, 3, env.n_waves, st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
+            case 4: LAUNCH_SLOTS(fused_surrogate_slots_kernel, 4, env.n_waves, st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
+            default: return hipErrorInvalidValue;
+        }
+    } else {
+        const dim3 grid((unsigned)((pg.count + kFusedBlock - 1) / kFusedBlock)), block(kFusedBlock);
+        switch (W) {
+            case 1: hipLaunchKernelGGL(fused_surrogate_kernel<1>, grid, block, 0, st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
+            case 2: hipLaunchKernelGGL(fused_surrogate_kernel<2>, grid, block, 0, st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
+            case 3: hipLaunchKernelGGL(fused_surrogate_kernel<3>, grid, block, 0, st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
+            case 4: hipLaunchKernelGGL(fused_surrogate_kernel<4>, grid, block, 0, st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
+            default: return hipErrorInvalidValue;
+        }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(surrogate_b_kernel, dim3(256), dim3(256), 0, st, s.queue, cur, nxt, logf(dt), beta, as, am,
-                       s.frag, s.norm);
+    const dim3 rg(256), rb(256);
+    switch (W) {
+        case 1: hipLaunchKernelGGL(surrogate_resume_kernel<1>, rg, rb, 0, st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, nxt, cap, s.frag); break;
+        case 2: hipLaunchKernelGGL(surrogate_resume_kernel<2>, rg, rb, 0, st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, nxt, cap, s.frag); break;
+        case 3: hipLaunchKernelGGL(surrogate_resume_kernel<3>, rg, rb, 0, st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, nxt, cap, s.frag); break;
+        case 4: hipLaunchKernelGGL(surrogate_resume_kernel<4>, rg, rb, 0, st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, nxt, cap, s.frag); break;
+        default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 
 // the correction g at a given temperature, in place (training targets)
 __global__ __launch_bounds__(256) void correct_kernel(const float* __restrict__ T, float* __restrict__ beta,
-                                                     float* __restrict__ as, float* __restrict__ am, int64_t n) {
+                                                     float* __restrict__ as, float* __restrict__ am, int64_t n,
+                                                     bool assign) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= n) return;
     float a = as[i], m = am[i];
     const float Ti = T[i];
-    beta[i] = correct(Ti, alpha_eq(Ti), a, m);
+    beta[i] = correct(Ti, alpha_eq(Ti), a, m, assign);
     as[i] = a;
     am[i] = m;
 }
 
-hipError_t launch_correct(const float* T, float* beta, float* as, float* am, int64_t n, hipStream_t st) {
+hipError_t launch_correct(const float* T, float* beta, float* as, float* am, int64_t n, bool assign, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(correct_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, T, beta, as, am, n);
+    hipLaunchKernelGGL(correct_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, T, beta, as, am, n,
+                       assign);
     return hipGetLastError();
 }
 
@@ -878,7 +926,7 @@ hipError_t mlp_alloc(MlpState& s) {
 
 void mlp_free(MlpState& s) {
     for (void* p : {(void*)s.master, (void*)s.adam_m, (void*)s.adam_v, (void*)s.grad, (void*)s.loss, (void*)s.frag,
-                    (void*)s.partial, (void*)s.queue, (void*)s.counters, (void*)s.tcache})
+                    (void*)s.partial, (void*)s.recs, (void*)s.counters})
         if (p) (void)hipFree(p);
     s = MlpState{};
 }

@@ -53,6 +53,18 @@ struct Const {
     static constexpr R Log2e = R(1.4426950408889634);
 };
 
+// The two readings of the paper a context can switch (both false: the
+// documented defaults).  corr_prev: the explicit correction g at T^n, the
+// argument Algorithm 2 passes, instead of T^{n+1} as eq. explicit_correction
+// writes it (the implicit scheme corrects at T^{n+1} in both, eq.
+// implicit_correction).  mart_assign: eq. inst_martensite_formation's "="
+// taken literally, X_am <- X_am^eq below the martensite start, which lowers
+// alpha_m on reheating, instead of never lowering it.
+struct Readings {
+    bool corr_prev;
+    bool mart_assign;
+};
+
 // float constants used by the kernels
 constexpr float kTasStart = Const<float>::TasStart;
 constexpr float kTamStart = Const<float>::TamStart;
@@ -186,8 +198,9 @@ __device__ __forceinline__ void diffusive_increment(R a, R m, R Tn, R xeq, R dt,
 // The correction with its temperature functions given: xeq = X_alpha^eq(T),
 // am0 = X_alpha_m,0^eq(T) (used below the martensite start), xsol = 1 - g(T)
 // (for iterations at a fixed temperature).
+// assign: the literal reading of the formation law (see Readings).
 template <class R>
-__device__ __forceinline__ R correct_at(R T, R xeq, R am0, R xsol, R& a_io, R& m_io) {
+__device__ __forceinline__ R correct_at(R T, R xeq, R am0, R xsol, R& a_io, R& m_io, bool assign = false) {
     using C = Const<R>;
     R a = vmax(a_io, R(0)), m = vmax(m_io, R(0));
     R s = a + m;
@@ -201,7 +214,10 @@ __device__ __forceinline__ R correct_at(R T, R xeq, R am0, R xsol, R& a_io, R& m
         a = vmin(a, C::Xmax * f);
     }
     if (a + m > xeq) m = vmax(xeq - a, R(0));
-    if (T < C::TamStart) m = vmax(m, am0 * (C::Xmax - a) * (R(1) / C::Xmax));
+    if (T < C::TamStart) {
+        const R meq = am0 * (C::Xmax - a) * (R(1) / C::Xmax);
+        m = assign ? meq : vmax(m, meq);
+    }
     s = a + m;
     if (s > C::Xmax) {
         const R f = C::Xmax * frcp(s);
@@ -220,8 +236,8 @@ __device__ __forceinline__ R correct_at(R T, R xeq, R am0, R xsol, R& a_io, R& m
 }
 
 template <class R>
-__device__ __forceinline__ R correct(R T, R xeq, R& a_io, R& m_io) {
-    return correct_at(T, xeq, T < Const<R>::TamStart ? am0_eq(T) : R(0), solid_fraction(T), a_io, m_io);
+__device__ __forceinline__ R correct(R T, R xeq, R& a_io, R& m_io, bool assign = false) {
+    return correct_at(T, xeq, T < Const<R>::TamStart ? am0_eq(T) : R(0), solid_fraction(T), a_io, m_io, assign);
 }
 
 // A fully stable-alpha state (X_alpha_s = 0.9, no martensite) is a fixed point
@@ -230,8 +246,9 @@ __device__ __forceinline__ R correct(R T, R xeq, R& a_io, R& m_io) {
 // zero, and the correction leaves it alone (the formation law raises alpha_m
 // to at most X_alpha_m,0^eq (0.9 - X_alpha_s) / 0.9 = 0).  Steps of such a
 // state return it unchanged without evaluating the model; the result is the
-// same as that of the full evaluation, bit for bit.  Away from the laser
-// most of a part is in this state.
+// same as that of the full evaluation, bit for bit, in either reading of
+// Readings (g at T^n or T^{n+1}, both below 935 K; formation sets alpha_m to
+// 0 either way).  Away from the laser most of a part is in this state.
 template <class R>
 __device__ __forceinline__ bool at_rest(R a, R m, R Tn, R Tn1) {
     using C = Const<R>;
@@ -249,12 +266,13 @@ __device__ __forceinline__ void two_sum(R a, R b, R& s, R& e) {
 // One explicit step on a register state.  With COMPENSATED the Euler
 // increments are accumulated in (hi, lo) pairs so that increments below half
 // an ulp of the fraction are not lost; any correction that changes a
-// fraction resets its lo part.  Returns X_beta^{n+1}.  A state at rest is
-// returned as it is: with m == 0 its lo part is 0, and re-adding the (hi, lo)
-// pair of a previous two-sum reproduces it, so the full step would not change
-// it either.
+// fraction resets its lo part.  Returns X_beta^{n+1} (the sum rule at the
+// correction's temperature).  A state at rest is returned as it is: with
+// m == 0 its lo part is 0, and re-adding the (hi, lo) pair of a previous
+// two-sum reproduces it, so the full step would not change it either.
 template <bool COMPENSATED, class R>
-__device__ __forceinline__ R explicit_step(R& a, R& m, R& a_lo, R& m_lo, R Tn, R xeq_n, R Tn1, R xeq_n1, R dt) {
+__device__ __forceinline__ R explicit_step(R& a, R& m, R& a_lo, R& m_lo, R Tn, R xeq_n, R Tn1, R xeq_n1, R dt,
+                                           Readings rd = Readings{false, false}) {
     if (at_rest(a, m, Tn, Tn1)) return R(1) - a - m;  // X_sol = 1 below T_as,end
     R da, dm;
     diffusive_increment(a, m, Tn, xeq_n, dt, da, dm);
@@ -267,7 +285,8 @@ __device__ __forceinline__ R explicit_step(R& a, R& m, R& a_lo, R& m_lo, R Tn, R
         mt = m + dm;
     }
     const R a_before = at, m_before = mt;
-    const R beta = correct(Tn1, xeq_n1, at, mt);
+    const R beta = rd.corr_prev ? correct(Tn, xeq_n, at, mt, rd.mart_assign)
+                                : correct(Tn1, xeq_n1, at, mt, rd.mart_assign);
     if (COMPENSATED) {
         if (at != a_before) a_lo = R(0);
         if (mt != m_before) m_lo = R(0);
@@ -299,21 +318,25 @@ __device__ __forceinline__ void diffusive_rates(R a, R m, R xeq, R kas, R& fa, R
     }
 }
 
-// One step of the implicit scheme (eqs. implicit_integration,
-// implicit_correction): Crank-Nicolson on the diffusive term with g at
-// T^{n+1}, solved by the fixed-point iteration of eq. implicit_fp_iteration
-// from g(T^{n+1}, m^n).  The iteration stops when the WRMS norm of the
-// residual over (alpha_s, alpha_m), weights 1 / (eps_abs + |m_j| eps_rel) of
-// the newest iterate, falls below 1, or after max_iter iterations.  A state
-// in a start-up regime at T^n (zero rate of a starting transformation) takes
-// the explicit step with its Appendix A closed form instead.  With
-// COMPENSATED the increment m^{n+1} - m^n is added to (hi, lo) pairs as in
-// explicit_step.  Returns the iteration count (0 for a start-up step),
-// negated if the stop test failed.  A state at rest converges in the first
-// iteration with zero rates and is returned as it is (count 1).
+// One step of the implicit scheme: Crank-Nicolson on the diffusive term
+// (eq. implicit_integration) with the correction g at T^{n+1} (eq.
+// implicit_correction).  The step's result is the fixed point of eq.
+// implicit_fp_iteration,
+//   m_(i) = g(T^{n+1}, m^n + dt/2 [f(T^n, m^n) + f(T^{n+1}, m_(i-1))]),
+// taken from m_(0) = g(T^{n+1}, m^n) (reading R12); it is accepted at the
+// first i >= 1 where the WRMS norm of the equation's residual at m_(i),
+// dt/2 [f(T^{n+1}, m_(i)) - f(T^{n+1}, m_(i-1))] over (alpha_s, alpha_m)
+// with weights 1 / (eps_abs + |m_(i),j| eps_rel), falls below 1, or at
+// i = max_iter.  A state in a start-up regime at T^n (zero rate of a
+// starting transformation) takes the explicit step with its Appendix A
+// closed form instead.  With COMPENSATED the increment over m^n is added to
+// (hi, lo) pairs as in explicit_step.  Returns the number of iterations
+// (0 for a start-up step), negated if the stop test failed.  A state at rest
+// converges in the first iteration with zero rates and is returned as it is
+// (count 1).  assign: see Readings.
 template <bool COMPENSATED, class R>
 __device__ __forceinline__ int implicit_step(R& a, R& m, R& a_lo, R& m_lo, R& beta, R Tn, R Tn1, R dt,
-                                             int max_iter) {
+                                             int max_iter, bool assign = false) {
     using C = Const<R>;
     if (at_rest(a, m, Tn, Tn1)) {
         beta = R(1) - a - m;
@@ -325,59 +348,57 @@ __device__ __forceinline__ int implicit_step(R& a, R& m, R& a_lo, R& m_lo, R& be
     // alpha_s -> beta end temperature X_alpha > X_alpha^eq = 0.9 is rounding)
     if ((xa < xeq_n && !(a > R(0))) ||
         (xa > xeq_n && xeq_n < C::Xmax && vmax(C::Xmax - xa, R(0)) * dt <= C::StartupLimit)) {
-        beta = explicit_step<COMPENSATED>(a, m, a_lo, m_lo, Tn, xeq_n, Tn1, xeq_1, dt);
+        beta = explicit_step<COMPENSATED>(a, m, a_lo, m_lo, Tn, xeq_n, Tn1, xeq_1, dt, Readings{false, assign});
         return 0;
     }
+    // functions of T^{n+1}, fixed over the iteration, and f(T^n, m^n)
     const R k_1 = k_alpha_s(Tn1);
     const R am0_1 = Tn1 < C::TamStart ? am0_eq(Tn1) : R(0), xsol_1 = solid_fraction(Tn1);
     R fa_n, fm_n;
     diffusive_rates(a, m, xeq_n, k_alpha_s(Tn), fa_n, fm_n);
-    R ai = a, mi = m, ali = R(0), mli = R(0);
-    beta = correct_at(Tn1, xeq_1, am0_1, xsol_1, ai, mi);
-    R fa, fm;
-    diffusive_rates(ai, mi, xeq_1, k_1, fa, fm);
     const R h = R(0.5) * dt;
-    int it = 0;
-    bool converged = false;
-    while (it < max_iter) {
-        const R da = h * (fa + fa_n), dm = h * (fm + fm_n);
-        R a1, m1, al1 = R(0), ml1 = R(0);
+    R a_i = a, m_i = m, alo_i = a_lo, mlo_i = m_lo;  // m_(i)
+    R fa_p = R(0), fm_p = R(0);                       // f(T^{n+1}, m_(i-1))
+    for (int i = 0;; ++i) {
+        // m^n plus the Crank-Nicolson increment (none for m_(0)), then g
+        const R da = i > 0 ? h * (fa_p + fa_n) : R(0), dm = i > 0 ? h * (fm_p + fm_n) : R(0);
+        R a1, m1, alo1 = R(0), mlo1 = R(0);
         if (COMPENSATED) {
-            two_sum(a, a_lo + da, a1, al1);
-            two_sum(m, m_lo + dm, m1, ml1);
+            two_sum(a, a_lo + da, a1, alo1);
+            two_sum(m, m_lo + dm, m1, mlo1);
         } else {
             a1 = a + da;
             m1 = m + dm;
         }
         const R a_before = a1, m_before = m1;
-        beta = correct_at(Tn1, xeq_1, am0_1, xsol_1, a1, m1);
+        beta = correct_at(Tn1, xeq_1, am0_1, xsol_1, a1, m1, assign);
         if (COMPENSATED) {
-            if (a1 != a_before) al1 = R(0);
-            if (m1 != m_before) ml1 = R(0);
+            if (a1 != a_before) alo1 = R(0);
+            if (m1 != m_before) mlo1 = R(0);
         }
         R fa1, fm1;
         diffusive_rates(a1, m1, xeq_1, k_1, fa1, fm1);
-        const R wa = h * (fa1 - fa) * frcp(vfma(vabs(a1), C::CnEpsRel, C::CnEpsAbs));
-        const R wm = h * (fm1 - fm) * frcp(vfma(vabs(m1), C::CnEpsRel, C::CnEpsAbs));
-        ai = a1;
-        mi = m1;
-        ali = al1;
-        mli = ml1;
-        fa = fa1;
-        fm = fm1;
-        ++it;
-        if (R(0.5) * vfma(wa, wa, wm * wm) < R(1)) {
-            converged = true;
-            break;
+        a_i = a1;
+        m_i = m1;
+        alo_i = alo1;
+        mlo_i = mlo1;
+        if (i > 0) {
+            const R wa = h * (fa1 - fa_p) * frcp(vfma(vabs(a1), C::CnEpsRel, C::CnEpsAbs));
+            const R wm = h * (fm1 - fm_p) * frcp(vfma(vabs(m1), C::CnEpsRel, C::CnEpsAbs));
+            const bool converged = R(0.5) * vfma(wa, wa, wm * wm) < R(1);
+            if (converged || i >= max_iter) {
+                a = a_i;
+                m = m_i;
+                if (COMPENSATED) {
+                    a_lo = alo_i;
+                    m_lo = mlo_i;
+                }
+                return converged ? i : -i;
+            }
         }
+        fa_p = fa1;
+        fm_p = fm1;
     }
-    a = ai;
-    m = mi;
-    if (COMPENSATED) {
-        a_lo = ali;
-        m_lo = mli;
-    }
-    return converged ? it : -it;
 }
 
 // ---------------------------------------------------------------------------
@@ -435,17 +456,18 @@ __device__ __forceinline__ bool track_regime(float a, float m, double xb, double
     return m == 0.0f && bt < D && bt < kTrackMax;
 }
 
-// alpha_s = 0.9 - X~beta after a tracked step, then g at T^{n+1}; tracking
-// goes on if g left the state alone and X~beta stays below kTrackMax
+// alpha_s = 0.9 - X~beta after a tracked step, then g at Tc (T^{n+1}, or
+// T^n with Readings::corr_prev); tracking goes on if g left the state alone
+// and X~beta stays below kTrackMax
 template <bool COMPENSATED>
 __device__ __forceinline__ float track_finish(float& a, float& m, float& a_lo, float& m_lo, double& xb, double bn,
-                                              float Tn1, float xeq_n1) {
+                                              float Tc, float xeq_c, bool assign) {
     const double av = (double)Const<float>::Xmax - bn;
     float at = (float)av;
     const float lo = (float)(av - (double)at);
     float mt = 0.0f;
     const float a_before = at;
-    const float beta = correct(Tn1, xeq_n1, at, mt);
+    const float beta = correct(Tc, xeq_c, at, mt, assign);
     const bool kept = at == a_before && mt == 0.0f;
     xb = (kept && bn < kTrackMax) ? bn : track_none();
     a = at;
@@ -458,16 +480,18 @@ __device__ __forceinline__ float track_finish(float& a, float& m, float& a_lo, f
 // explicit_step with the tracked X~beta
 template <bool COMPENSATED>
 __device__ __forceinline__ float explicit_step_tracked(float& a, float& m, float& a_lo, float& m_lo, double& xb,
-                                                       float Tn, float xeq_n, float Tn1, float xeq_n1, float dt) {
+                                                       float Tn, float xeq_n, float Tn1, float xeq_n1, float dt,
+                                                       Readings rd = Readings{false, false}) {
     double bt;
     const double D = (double)Const<float>::Xmax - alpha_eq_f64(Tn);
     if (at_rest(a, m, Tn, Tn1) || !track_regime(a, m, xb, D, bt)) {
         xb = track_none();
-        return explicit_step<COMPENSATED>(a, m, a_lo, m_lo, Tn, xeq_n, Tn1, xeq_n1, dt);
+        return explicit_step<COMPENSATED>(a, m, a_lo, m_lo, Tn, xeq_n, Tn1, xeq_n1, dt, rd);
     }
     const double kb = k_beta_f64(Tn), h = dt;
     const double bn = bt * h <= 1e-15 ? beta_startup_f64(bt, D, kb, h) : bt + h * beta_rate_f64(bt, D, kb);
-    return track_finish<COMPENSATED>(a, m, a_lo, m_lo, xb, bn, Tn1, xeq_n1);
+    return rd.corr_prev ? track_finish<COMPENSATED>(a, m, a_lo, m_lo, xb, bn, Tn, xeq_n, rd.mart_assign)
+                        : track_finish<COMPENSATED>(a, m, a_lo, m_lo, xb, bn, Tn1, xeq_n1, rd.mart_assign);
 }
 
 // implicit_step with the tracked X~beta: the start-up takes the tracked
@@ -477,17 +501,19 @@ __device__ __forceinline__ float explicit_step_tracked(float& a, float& m, float
 // start), the value is handed over and the ordinary step is taken.
 template <bool COMPENSATED>
 __device__ __forceinline__ int implicit_step_tracked(float& a, float& m, float& a_lo, float& m_lo, double& xb,
-                                                     float& beta, float Tn, float Tn1, float dt, int max_iter) {
+                                                     float& beta, float Tn, float Tn1, float dt, int max_iter,
+                                                     bool assign = false) {
     using C = Const<float>;
     double bt;
     const double D = (double)C::Xmax - alpha_eq_f64(Tn);
     if (at_rest(a, m, Tn, Tn1) || !track_regime(a, m, xb, D, bt)) {
         xb = track_none();
-        return implicit_step<COMPENSATED>(a, m, a_lo, m_lo, beta, Tn, Tn1, dt, max_iter);
+        return implicit_step<COMPENSATED>(a, m, a_lo, m_lo, beta, Tn, Tn1, dt, max_iter, assign);
     }
     if (bt * (double)dt <= 1e-15) {
         xb = bt;
-        beta = explicit_step_tracked<COMPENSATED>(a, m, a_lo, m_lo, xb, Tn, alpha_eq(Tn), Tn1, alpha_eq(Tn1), dt);
+        beta = explicit_step_tracked<COMPENSATED>(a, m, a_lo, m_lo, xb, Tn, alpha_eq(Tn), Tn1, alpha_eq(Tn1), dt,
+                                                  Readings{false, assign});
         return 0;
     }
     if (!(Tn1 >= C::TamStart && Tn1 <= C::TasStart)) {
@@ -495,7 +521,7 @@ __device__ __forceinline__ int implicit_step_tracked(float& a, float& m, float& 
         a = (float)av;
         a_lo = COMPENSATED ? (float)(av - (double)a) : 0.0f;
         xb = track_none();
-        return implicit_step<COMPENSATED>(a, m, a_lo, m_lo, beta, Tn, Tn1, dt, max_iter);
+        return implicit_step<COMPENSATED>(a, m, a_lo, m_lo, beta, Tn, Tn1, dt, max_iter, assign);
     }
     const double D1 = (double)C::Xmax - alpha_eq_f64(Tn1), kb1 = k_beta_f64(Tn1);
     const double f_n = beta_rate_f64(bt, D, k_beta_f64(Tn));
@@ -515,7 +541,7 @@ __device__ __forceinline__ int implicit_step_tracked(float& a, float& m, float& 
             break;
         }
     }
-    beta = track_finish<COMPENSATED>(a, m, a_lo, m_lo, xb, x, Tn1, alpha_eq(Tn1));
+    beta = track_finish<COMPENSATED>(a, m, a_lo, m_lo, xb, x, Tn1, alpha_eq(Tn1), assign);
     return converged ? it : -it;
 }
 

@@ -14,7 +14,8 @@ __device__ __forceinline__ double one_minus_exp_neg(double x) { return -expm1(-x
 
 namespace mstruct {
 hipError_t launch_step_f64_library(const double* Tp, const double* Tn, double* beta, double* as, double* am,
-                                   int64_t n, double dt, hipStream_t st) {
-    return mstruct_f64lib::launch_step_f64_impl(Tp, Tn, beta, as, am, n, dt, st);
+                                   int64_t n, double dt, bool corr_prev, bool mart_assign, hipStream_t st) {
+    return mstruct_f64lib::launch_step_f64_impl(Tp, Tn, beta, as, am, n, dt,
+                                                mstruct_f64lib::Readings{corr_prev, mart_assign}, st);
 }
 }  // namespace mstruct

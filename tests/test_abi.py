@@ -51,12 +51,13 @@ def test_status_strings(L):
 
 def test_null_context_rejected_without_device(L):
     p = ctypes.c_void_p()
-    assert L.mstruct_init(0, None) == -1
+    assert L.mstruct_init(None, 0, None) == -1
     assert L.mstruct_destroy(None) == -1
     assert L.mstruct_step(None, None, None, 1e-6, None, None) == -1
     assert L.mstruct_step_implicit(None, None, None, 1e-3, 0.01, 50, None, None, None) == -1
     assert L.mstruct_implicit_unconverged(None, None, 0, None) == -1
     assert L.mstruct_set_option(None, 1, 0) == -1
+    assert L.mstruct_wave_counts(None, None, 0, None) == -1
     assert L.mstruct_step_f64(None, None, None, 1e-6, None, 0, None) == -1
     assert L.mstruct_temperature(None, None, None, 0.0, None, None) == -1
     assert L.mstruct_fused_scan_steps(None, None, None, 0.0, 1e-6, 1, 1, 0, None, None) == -1
@@ -90,7 +91,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no C compiler")
-    structs = {"mstruct_phases": ms.PhasesC, "mstruct_phases_f64": ms.PhasesF64C}
+    structs = {"mstruct_phases": ms.PhasesC, "mstruct_phases_f64": ms.PhasesF64C, "mstruct_params": ms.ParamsC}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "mstruct.h"', "int main(void) {"]
     for cname, py in structs.items():
         lines.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
@@ -107,3 +108,29 @@ def test_struct_layouts_match_the_header(tmp_path):
         assert int(got[f"{cname} size"]) == ctypes.sizeof(py)
         for f, _ in py._fields_:
             assert int(got[f"{cname} {f}"]) == getattr(py, f).offset, (cname, f)
+
+
+def test_default_params_are_the_paper_tables(L):
+    """mstruct_default_params (host only) returns Tables 1-3 and T_as,reg as
+    typed from the paper, and the default readings; mstruct_init rejects
+    other constants and unknown readings before touching a device."""
+    import json
+
+    import paper_2402_17580_amd as ms
+    want = json.load(open(os.path.join(ROOT, "tests", "golden", "paper_constants.json")))
+    p = ms.default_params()
+    pairs = {"T_solidus": "T_s", "T_liquidus": "T_l", "T_ambient": "T_inf", "T_alpha_s_start": "T_as_start",
+             "T_alpha_s_end": "T_as_end", "T_alpha_m_start": "T_am_start", "k_alpha_eq": "k_alpha_eq",
+             "k_alpha_m_eq": "k_am_eq", "c_alpha_s": "c_as", "c_beta": "c_beta", "k1": "k1", "k2": "k2", "k3": "k3",
+             "f": "f", "T_alpha_s_reg": "T_as_reg"}
+    for field, key in pairs.items():
+        assert getattr(p, field) == want[key], field
+    assert p.correction_T == 0 and p.martensite_mode == 0
+    h = ctypes.c_void_p()
+    q = ms.default_params()
+    q.k1 = 0.3
+    assert L.mstruct_init(ctypes.byref(q), 0, ctypes.byref(h)) == -4
+    q = ms.default_params()
+    q.martensite_mode = 2
+    assert L.mstruct_init(ctypes.byref(q), 0, ctypes.byref(h)) == -1
+    assert L.mstruct_default_params(None) == -1
