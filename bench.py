@@ -63,21 +63,26 @@ PAPER_CPU = {
 }
 
 # Per-kernel figures from rocprofv3 counter runs of this script (the profile
-# files named below): executed VALU instructions x 64 per point-update, the
-# VALU-busy fraction (VALUBusy) and the fraction of VALU quad-cycles with a
-# second instruction issued (SQ_ACTIVE_INST_VALU2 / SQ_ACTIVE_INST_VALU), and
-# HBM bytes per launch (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0: the factors a
-# plain 1 GiB device copy reads on the same counters).  Each holds for the
-# launch size K it was taken at; at another K the figures are reported null.
+# files named below): executed VALU instructions x 64 per point-update
+# (SQ_INSTS_VALU), the fraction of the dual-issue VALU capacity used
+# (SQ_ACTIVE_INST_VALU / (2 x SIMDs x quad-cycles)), the fraction of
+# quad-cycles with any VALU issue ((SQ_ACTIVE_INST_VALU - SQ_ACTIVE_INST_VALU2)
+# / (SIMDs x quad-cycles)), and HBM bytes per launch (FETCH_SIZE x 2.0 +
+# WRITE_SIZE x 1.0: the factors a plain 1 GiB device copy reads on the same
+# counters).  Each holds for the launch size K it was taken at; at another K
+# the figures are reported null.
 FUSED_PROFILE = {
     "file": "profiles/fused_plain_kernel_multilayer_block.txt", "K": 64,
-    "valu_lane_ops_per_update": 10.26, "valu_busy": None, "dual_issue": None,
-    "traffic_bytes_per_launch": (3364.18 * 2.0 + 3476.92) * 1024,
+    "valu_lane_ops_per_update": 10.532, "valu_issue": 0.328, "valu_busy": 0.478,
+    "traffic_bytes_per_launch": (3375.57 * 2.0 + 3476.92) * 1024,
 }
-FUSED_PROFILE_EVERY_T = {"K": 64, "valu_lane_ops_per_update": 128.07, "valu_busy": None}
+FUSED_PROFILE_EVERY_T = {"K": 64, "valu_lane_ops_per_update": 129.26, "valu_issue": 0.727, "valu_busy": 0.926}
+SURROGATE_PROFILE = {"file": "profiles/fused_surrogate_kernels_multilayer_block.txt", "K": 64,
+                     8: {"valu_lane_ops_per_update": 4.727, "valu_issue": 0.167, "valu_busy": 0.259},
+                     16: {"valu_lane_ops_per_update": 4.012, "valu_issue": 0.145, "valu_busy": 0.232}}
 C3_PROFILE = {"file": "profiles/fused_plain_kernel_cantilever_islands.txt", "K": K_C3,
-              "valu_lane_ops_per_update": None, "valu_busy": None, "dual_issue": None,
-              "traffic_bytes_per_launch": None}
+              "valu_lane_ops_per_update": 4.242, "valu_issue": 0.213, "valu_busy": 0.349,
+              "traffic_bytes_per_launch": (7039.82 * 2.0 + 2783.23) * 1024}
 
 
 def parse():
@@ -93,8 +98,9 @@ def parse():
     ap.add_argument("--no-cooldown", action="store_true")
     ap.add_argument("--no-c3", action="store_true")
     ap.add_argument("--no-c5", action="store_true")
-    ap.add_argument("--only", choices=("c2", "c3", "c5"),
-                    help="one workload only, without the oracle (profiling runs)")
+    ap.add_argument("--only", choices=("c2", "c3", "c5", "steps", "cooldown"),
+                    help="one part only, without the oracle (profiling runs): a workload, the unfused steps "
+                         "(plain, implicit, float64, divergence layouts) or the cool-down workload")
     ap.add_argument("--threads", type=int, default=0, help="oracle threads (default: OpenMP's, all host cores)")
     ap.add_argument("--calibrate", action="store_true",
                     help="instead: the VALU probes (FMA, exp, both) and a 1 GiB device copy, timed, for the "
@@ -102,10 +108,11 @@ def parse():
     args = ap.parse_args()
     if args.only:
         args.no_cpu_baseline = True
-        args.no_stepwise = args.no_cooldown = True
+        args.no_stepwise = args.only != "steps"
+        args.no_cooldown = args.only != "cooldown"
         args.no_c3 = args.only != "c3"
         args.no_c5 = args.only != "c5"
-        args.no_surrogate = args.only == "c3"
+        args.no_surrogate = args.only != "c2"
     return args
 
 
@@ -172,8 +179,8 @@ def fused_roofline(kernel, prof, K, rate, avg_launch_s, counts):
          "algorithmic_bytes_per_launch": alg,
          "traffic_over_algorithmic": traffic / alg if traffic and alg else None,
          "hbm_GBs": alg / avg_launch_s / 1e9 if alg else None,
-         "lane_ops_per_update": ops, "valu_busy_frac": prof.get("valu_busy") if ok else None,
-         "dual_issue_frac": prof.get("dual_issue") if ok else None,
+         "lane_ops_per_update": ops, "valu_issue_frac": prof.get("valu_issue") if ok else None,
+         "valu_busy_frac": prof.get("valu_busy") if ok else None,
          "peak_derivation": PEAK_DERIVATION, "avg_launch_us": avg_launch_s * 1e6,
          "point_updates_per_s_in_launch": rate, "profile": prof.get("file"), "profile_K": prof["K"]}
     return r
@@ -195,11 +202,15 @@ def main():
     ctx = ms.Context(0)
     result = {}
     states = {}
+    wl = workload.multilayer_block()
     if args.only in (None, "c2"):
         result, states = bench_c2(torch, ms, ctx, args)
     else:
         result = {"metric": f"profiling run: {args.only} only", "value": None}
-    wl = workload.multilayer_block()
+        if args.only == "steps":  # the state the plain run leaves, for the step kernels
+            g = [torch.from_numpy(x).cuda() for x in workload.initial_state(wl.grid.n, np.float32)]
+            ms.run_layers(ctx, wl, *g, K=K_FUSED)
+            states = {"plain": g}
     if not args.no_stepwise:
         result["plain_step"] = bench_stepwise(torch, ms, ctx, wl, torch.device("cuda:0"))
         result["implicit_step"] = bench_implicit(torch, ms, ctx, wl, states["plain"])
@@ -320,7 +331,9 @@ def bench_c2(torch, ms, ctx, args):
                      "achieved": rate_all * ops_all / 1e12 if ops_all else None, "peak": VALU_PEAK_TLANEOPS,
                      "unit": "Tlane-op/s",
                      "frac": rate_all * ops_all / 1e12 / VALU_PEAK_TLANEOPS if ops_all else None,
-                     "lane_ops_per_update": ops_all, "valu_busy_frac": FUSED_PROFILE_EVERY_T["valu_busy"] if ok else None,
+                     "lane_ops_per_update": ops_all,
+                     "valu_issue_frac": FUSED_PROFILE_EVERY_T["valu_issue"] if ok else None,
+                     "valu_busy_frac": FUSED_PROFILE_EVERY_T["valu_busy"] if ok else None,
                      "avg_launch_us": avg_all_s * 1e6},
     }
     states = {"plain": final}
@@ -331,13 +344,23 @@ def bench_c2(torch, ms, ctx, args):
             sur.load_into(ctx)
             ms_sur, _ = timed(ms.MODE_SURROGATE, sur.K)
             states[key] = [x.clone() for x in (b, a, m)]
+            sp = SURROGATE_PROFILE.get(sur.K) if SURROGATE_PROFILE["K"] == K_FUSED else None
+            sur_rate = updates * args.steps / (ms_sur * 1e-3)
             result[key] = {
-                "value": updates * args.steps / (ms_sur * 1e-3), "unit": "point-updates/s",
+                "value": sur_rate, "unit": "point-updates/s",
                 "ms_per_step": ms_sur / args.steps, "speedup_vs_plain": ms_total / ms_sur,
                 "target_speedup_vs_plain": 3.0, "target_met": ms_total / ms_sur >= 3.0, "K": sur.K,
-                "path": "mstruct_fused_scan_steps, SURROGATE: one explicit step of K dt + BF16-MFMA network "
-                        "correction where the indicator allows, K plain steps elsewhere",
+                "path": "mstruct_fused_scan_steps, SURROGATE: fused launches of 64 steps; per block of K steps a "
+                        "wave takes one explicit step of K dt + BF16-MFMA network correction where every point "
+                        "passes the indicator, K plain steps otherwise",
                 "indicator": list(sur.indicator),
+                "roofline": None if sp is None else {
+                    "kernel": "fused_surrogate_kernel<2> + fused_surrogate_slots_kernel<2> + surrogate_resume_kernel<2>",
+                    "bound": "alu", "lane_ops_per_update": sp["valu_lane_ops_per_update"],
+                    "achieved": sur_rate * sp["valu_lane_ops_per_update"] / 1e12, "peak": VALU_PEAK_TLANEOPS,
+                    "unit": "Tlane-op/s", "frac": sur_rate * sp["valu_lane_ops_per_update"] / 1e12 / VALU_PEAK_TLANEOPS,
+                    "valu_issue_frac": sp["valu_issue"], "valu_busy_frac": sp["valu_busy"],
+                    "profile": SURROGATE_PROFILE["file"]},
             }
         if "surrogate_share_of_hot_subblocks" in counts:
             result["surrogate_ceiling"] = surrogate_ceiling(counts, ms_total, launches * args.steps)

@@ -196,30 +196,39 @@ __device__ __forceinline__ GridBox wave_box(const PointGeom& pg, int64_t w) {
     return b;
 }
 
-// one lane per (launch, wave): whether T0 plus the box bounds of every track
-// of the launch stay below the still limit at every point of the wave
+// one lane per wave and group of `group` launches: whether T0 plus the box
+// bounds of every track of a launch stay below the still limit at every
+// point of the wave, for each launch of the group.  With an index list the
+// wave's box is loaded once per group (one lane per (launch, wave) re-read
+// every box once per launch: 12 MB per launch on a 32M-point cantilever);
+// on a box grid it follows from the wave index and group = 1.
 __global__ __launch_bounds__(kBlock) void still_flags_kernel(PointGeom pg, const EnvRec* __restrict__ env,
                                                             const int32_t* __restrict__ env_fc, int64_t nl,
-                                                            int64_t n_waves, float T0, float rlim2,
+                                                            int64_t n_waves, int group, float T0, float rlim2,
                                                             const GridBox* __restrict__ boxes,
                                                             uint8_t* __restrict__ flags) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (t >= nl * n_waves) return;
-    const int64_t l = t / n_waves, w = t - l * n_waves;
+    const int64_t n_groups = (nl + group - 1) / group;
+    if (t >= n_groups * n_waves) return;
+    const int64_t lg = t / n_waves, w = t - lg * n_waves;
     const GridBox b = boxes ? boxes[w] : wave_box(pg, w);
-    const EnvRec* e = env + env_fc[2 * l];
-    const int n = env_fc[2 * l + 1];
-    float T = T0;
-    for (int k = 0; k < n && T < kRestBelow; ++k) T += env_box_rise_bound(e[k], b, rlim2);
-    flags[t] = T < kRestBelow ? 1 : 0;
+    const int64_t l_end = min(nl, (lg + 1) * group);
+    for (int64_t l = lg * group; l < l_end; ++l) {
+        const EnvRec* e = env + env_fc[2 * l];
+        const int n = env_fc[2 * l + 1];
+        float T = T0;
+        for (int k = 0; k < n && T < kRestBelow; ++k) T += env_box_rise_bound(e[k], b, rlim2);
+        flags[l * n_waves + w] = T < kRestBelow ? 1 : 0;
+    }
 }
 
 hipError_t launch_still_flags(const PointGeom& pg, const EnvRec* env, const int32_t* env_fc, int64_t l0, int64_t nl,
                               int64_t n_waves, float T0, const GridBox* boxes, uint8_t* flags, hipStream_t st) {
-    const int64_t lanes = nl * n_waves;
+    const int group = boxes ? 16 : 1;
+    const int64_t lanes = (nl + group - 1) / group * n_waves;
     if (lanes <= 0) return hipSuccess;
     hipLaunchKernelGGL(still_flags_kernel, dim3((unsigned)((lanes + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, pg,
-                       env, env_fc + 2 * l0, nl, n_waves, T0, envelope_radius2(pg), boxes, flags);
+                       env, env_fc + 2 * l0, nl, n_waves, group, T0, envelope_radius2(pg), boxes, flags);
     return hipGetLastError();
 }
 

@@ -13,7 +13,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-namespace {
+namespace mstruct_probe {
 
 constexpr int kThreads = 256;
 
@@ -41,7 +41,9 @@ __global__ __launch_bounds__(kThreads) void valu_probe_kernel(int iters, float* 
     out[g] = s;
 }
 
-}  // namespace
+}  // namespace mstruct_probe
+
+using namespace mstruct_probe;
 
 extern "C" {
 
