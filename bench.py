@@ -73,16 +73,16 @@ PAPER_CPU = {
 # the figures are reported null.
 FUSED_PROFILE = {
     "file": "profiles/fused_plain_kernel_multilayer_block.txt", "K": 64,
-    "valu_lane_ops_per_update": 10.532, "valu_issue": 0.328, "valu_busy": 0.478,
-    "traffic_bytes_per_launch": (3375.57 * 2.0 + 3476.92) * 1024,
+    "valu_lane_ops_per_update": 10.532, "valu_issue": 0.329, "valu_busy": 0.479,
+    "traffic_bytes_per_launch": (3375.9 * 2.0 + 3476.9) * 1024,
 }
-FUSED_PROFILE_EVERY_T = {"K": 64, "valu_lane_ops_per_update": 129.26, "valu_issue": 0.727, "valu_busy": 0.926}
+FUSED_PROFILE_EVERY_T = {"K": 64, "valu_lane_ops_per_update": 129.26, "valu_issue": 0.727, "valu_busy": 0.927}
 SURROGATE_PROFILE = {"file": "profiles/fused_surrogate_kernels_multilayer_block.txt", "K": 64,
-                     8: {"valu_lane_ops_per_update": 4.727, "valu_issue": 0.167, "valu_busy": 0.259},
-                     16: {"valu_lane_ops_per_update": 4.012, "valu_issue": 0.145, "valu_busy": 0.232}}
+                     8: {"valu_lane_ops_per_update": 4.727, "valu_issue": 0.168, "valu_busy": 0.260},
+                     16: {"valu_lane_ops_per_update": 4.012, "valu_issue": 0.145, "valu_busy": 0.231}}
 C3_PROFILE = {"file": "profiles/fused_plain_kernel_cantilever_islands.txt", "K": K_C3,
-              "valu_lane_ops_per_update": 4.242, "valu_issue": 0.213, "valu_busy": 0.349,
-              "traffic_bytes_per_launch": (7039.82 * 2.0 + 2783.23) * 1024}
+              "valu_lane_ops_per_update": 4.270, "valu_issue": 0.214, "valu_busy": 0.349,
+              "traffic_bytes_per_launch": (7050.3 * 2.0 + 2793.0) * 1024}
 
 
 def parse():
@@ -175,6 +175,11 @@ def fused_roofline(kernel, prof, K, rate, avg_launch_s, counts):
     r = {"kernel": kernel, "bound": "alu",
          "achieved": rate * ops / 1e12 if ops else None, "peak": VALU_PEAK_TLANEOPS, "unit": "Tlane-op/s",
          "frac": rate * ops / 1e12 / VALU_PEAK_TLANEOPS if ops else None,
+         "frac_source": "live point-updates/s x the profile's VALU instructions per update (null: the profile "
+                        "was taken at another K)",
+         "measured_limit": "neither roofline is reached: the few hot waves per launch (3 % of the waves on a "
+                           "layer scan) run chains of K dependent steps, a handful per SIMD, and leave the VALU "
+                           "idle for much of the launch (valu_busy_frac); HBM traffic is under 1 % of 8 TB/s",
          "traffic": traffic, "traffic_unit": "bytes/launch",
          "algorithmic_bytes_per_launch": alg,
          "traffic_over_algorithmic": traffic / alg if traffic and alg else None,
@@ -536,7 +541,7 @@ def bench_stepwise(torch, ms, ctx, wl, dev):
 
 # Per-point VALU lane-ops of the implicit step kernel on the two regimes timed
 # below, from rocprofv3 counter runs of this script (SQ_INSTS_VALU x 64 / points)
-IMPLICIT_PROFILE = {"scan": 96.8, "cooldown": 385.8}
+IMPLICIT_PROFILE = {"scan": 94.37, "cooldown": 370.37}
 
 
 def bench_implicit(torch, ms, ctx, wl, state):
