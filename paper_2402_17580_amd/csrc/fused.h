@@ -44,6 +44,13 @@ __device__ __forceinline__ bool wave_may_rest(const EnvSet& env, bool act, float
     return env.n >= 0 && T0 < kRestBelow && __ballot(act && !rest_bits(a, m)) == 0;
 }
 
+// whether the box pre-pass (still_flags_kernel) bounded wave wv below the
+// still limit at every time point of this launch: then a wave whose points
+// are all at rest is still without the per-point bounds of wave_below
+__device__ __forceinline__ bool wave_box_below(const EnvSet& env, int64_t wv) {
+    return env.below && wv < env.n_waves && env.below[wv];
+}
+
 // wave index of the calling lane in a fused launch (uniform across the wave)
 __device__ __forceinline__ int64_t fused_wave() {
     return (int64_t)blockIdx.x * (kFusedBlock / kWave) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));

@@ -310,7 +310,8 @@ __device__ __forceinline__ void fused_plain_body(const PointGeom& pg, const SrcR
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
         const bool tried = wave_may_rest(env, act[u], a[u], m[u], T0c);
-        still[u] = tried && wave_below(env.rec, env.n, act[u], gi[u], gj[u], gk[u], rlim2, T0c, kRestBelow);
+        still[u] = tried && ((PPT == 1 && !TRACK && wave_box_below(env, wv)) ||
+                             wave_below(env.rec, env.n, act[u], gi[u], gj[u], gk[u], rlim2, T0c, kRestBelow));
         // an all-at-rest wave that is not below the limit everywhere is not cold either
         cold[u] = still[u] || (!tried && wave_cold(env.rec, env.n, act[u], gi[u], gj[u], gk[u], rlim2));
         Tn[u] = cold[u] ? T0c : scan_temperature<W>(tab, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min, pg.roff);
@@ -414,7 +415,8 @@ __device__ __forceinline__ void fused_implicit_body(const PointGeom& pg, const S
     // still and cold waves as in fused_plain_kernel
     const float rlim2 = envelope_radius2(pg);
     const bool tried = wave_may_rest(env, act, a, m, T0c);
-    bool still = tried && wave_below(env.rec, env.n, act, gi, gj, gk, rlim2, T0c, kRestBelow);
+    bool still = tried && ((!TRACK && wave_box_below(env, wv)) ||
+                           wave_below(env.rec, env.n, act, gi, gj, gk, rlim2, T0c, kRestBelow));
     const bool cold = still || (!tried && wave_cold(env.rec, env.n, act, gi, gj, gk, rlim2));
     float Tn = cold ? T0c : scan_temperature<W>(tab, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
     const float inv = 1.0f / (float)n_sub;

@@ -720,7 +720,8 @@ __device__ __forceinline__ void surrogate_fused_body(const PointGeom& pg, const 
     // still and cold waves as in the plain fused kernel
     const float rlim2 = envelope_radius2(pg);
     const bool tried = wave_may_rest(env, act, a, m, T0c);
-    bool still = tried && wave_below(env.rec, env.n, act, gi, gj, gk, rlim2, T0c, kRestBelow);
+    bool still = tried && (wave_box_below(env, wv) ||
+                           wave_below(env.rec, env.n, act, gi, gj, gk, rlim2, T0c, kRestBelow));
     const bool cold = still || (!tried && wave_cold(env.rec, env.n, act, gi, gj, gk, rlim2));
     float Tn = cold ? T0c : scan_temperature<W>(tab, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
     still = still || (cold && T0c < Const<float>::TasEnd && __ballot(act && !rest_bits(a, m)) == 0);
