@@ -74,7 +74,7 @@ __device__ __forceinline__ void still_wave_beta(const PointGeom& pg, float T0c, 
 
 // The persistent form of a fused launch, used from the second launch of a
 // call when the wave flags are kept: a grid of about one wave per
-// kSlotsPerWave waves of the launch, in which wave p takes the wave slots p,
+// slots_per_wave waves of the launch, in which wave p takes the wave slots p,
 // p + P, p + 2P, ... (P waves in the grid).  Each lane loads the flags of
 // one slot; the wave then runs body(w) for every slot w that is not still
 // (all 64 lanes, one point each) and writes beta for the still ones.  No
@@ -140,19 +140,34 @@ __device__ __forceinline__ void record_rest(const EnvSet& env, int64_t wv, bool 
 }
 
 // grid of the persistent (slot) fused kernels in workgroups of bs threads:
-// one wave per kSlotsPerWave waves of the launch
-inline dim3 slots_grid(int64_t n_waves, int bs) {
-    const int64_t waves = (n_waves + kSlotsPerWave - 1) / kSlotsPerWave;
+// one wave per spw waves of the launch
+inline dim3 slots_grid(int64_t n_waves, int bs, int spw) {
+    const int64_t waves = (n_waves + spw - 1) / spw;
     return dim3((unsigned)((waves + bs / kWave - 1) / (bs / kWave)));
 }
 
-// launch a slot kernel instantiated for workgroups of 128 and 256 threads
-#define LAUNCH_SLOTS(kernel, W, n_waves, st, ...)                                                          \
-    do {                                                                                                    \
-        if ((n_waves) >= kSlotsLargeGrid)                                                                   \
-            hipLaunchKernelGGL((kernel<W, 256>), slots_grid(n_waves, 256), dim3(256), 0, st, __VA_ARGS__); \
-        else                                                                                                \
-            hipLaunchKernelGGL((kernel<W, 128>), slots_grid(n_waves, 128), dim3(128), 0, st, __VA_ARGS__); \
+// launch a slot kernel instantiated for workgroups of 128 and 256 threads,
+// spw wave slots per wave
+#define LAUNCH_SLOTS(kernel, W, n_waves, spw, st, ...)                                                          \
+    do {                                                                                                         \
+        if ((n_waves) >= kSlotsLargeGrid)                                                                        \
+            hipLaunchKernelGGL((kernel<W, 256>), slots_grid(n_waves, 256, spw), dim3(256), 0, st, __VA_ARGS__); \
+        else                                                                                                     \
+            hipLaunchKernelGGL((kernel<W, 128>), slots_grid(n_waves, 128, spw), dim3(128), 0, st, __VA_ARGS__); \
     } while (0)
+
+// Wave slots per wave of a slot kernel.  Below kSlotsLargeGrid waves, four
+// (sixteen took the block scan from 62 to 101 ms).  On large grids, where
+// nearly every wave exits on its flags, fewer slot waves cut the cost of
+// launching them when the waves that step run short chains: 16 for plain
+// launches of at most 16 steps (masked cantilever, K = 16: 0.32 -> 0.19 s
+// per run), 8 for the surrogate, whose admitted blocks take one step (island
+// block: 0.643 -> 0.607 s); plain launches of more steps keep four (island
+// block at K = 64: 1.84 s, 2.01 s with 16).
+enum class SlotUse { PlainShort, PlainLong, Surrogate, Implicit };
+inline int slots_per_wave(int64_t n_waves, SlotUse use) {
+    if (n_waves < kSlotsLargeGrid) return kSlotsPerWave;
+    return use == SlotUse::PlainShort ? 16 : use == SlotUse::Surrogate ? 8 : kSlotsPerWave;
+}
 
 }  // namespace mstruct

@@ -504,10 +504,10 @@ hipError_t launch_fused_implicit(const PointGeom& pg, int W, const SrcRec* tab, 
     if (pg.count <= 0) return hipSuccess;
     if (!xb && env.below && env.read_rest) {
         switch (W) {
-            case 1: LAUNCH_SLOTS(fused_implicit_slots_kernel, 1, env.n_waves, st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
-            case 2: LAUNCH_SLOTS(fused_implicit_slots_kernel, 2, env.n_waves, st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
-            case 3: LAUNCH_SLOTS(fused_implicit_slots_kernel, 3, env.n_waves, st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
-            case 4: LAUNCH_SLOTS(fused_implicit_slots_kernel, 4, env.n_waves, st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
+            case 1: LAUNCH_SLOTS(fused_implicit_slots_kernel, 1, env.n_waves, slots_per_wave(env.n_waves, SlotUse::Implicit), st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
+            case 2: LAUNCH_SLOTS(fused_implicit_slots_kernel, 2, env.n_waves, slots_per_wave(env.n_waves, SlotUse::Implicit), st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
+            case 3: LAUNCH_SLOTS(fused_implicit_slots_kernel, 3, env.n_waves, slots_per_wave(env.n_waves, SlotUse::Implicit), st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
+            case 4: LAUNCH_SLOTS(fused_implicit_slots_kernel, 4, env.n_waves, slots_per_wave(env.n_waves, SlotUse::Implicit), st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
             default: return hipErrorInvalidValue;
         }
         return hipGetLastError();
@@ -550,11 +550,12 @@ hipError_t launch_fused_plain(const PointGeom& pg, int W, const SrcRec* tab, Env
                               float* beta, float* as, float* am, double* xb, hipStream_t st) {
     if (pg.count <= 0) return hipSuccess;
     if (kFusedPPT == 1 && !xb && env.below && env.read_rest) {
+        const int spw = slots_per_wave(env.n_waves, K <= 16 ? SlotUse::PlainShort : SlotUse::PlainLong);
         switch (W) {
-            case 1: LAUNCH_SLOTS(fused_plain_slots_kernel, 1, env.n_waves, st, pg, tab, env, K, dt, sa, beta, as, am); break;
-            case 2: LAUNCH_SLOTS(fused_plain_slots_kernel, 2, env.n_waves, st, pg, tab, env, K, dt, sa, beta, as, am); break;
-            case 3: LAUNCH_SLOTS(fused_plain_slots_kernel, 3, env.n_waves, st, pg, tab, env, K, dt, sa, beta, as, am); break;
-            case 4: LAUNCH_SLOTS(fused_plain_slots_kernel, 4, env.n_waves, st, pg, tab, env, K, dt, sa, beta, as, am); break;
+            case 1: LAUNCH_SLOTS(fused_plain_slots_kernel, 1, env.n_waves, spw, st, pg, tab, env, K, dt, sa, beta, as, am); break;
+            case 2: LAUNCH_SLOTS(fused_plain_slots_kernel, 2, env.n_waves, spw, st, pg, tab, env, K, dt, sa, beta, as, am); break;
+            case 3: LAUNCH_SLOTS(fused_plain_slots_kernel, 3, env.n_waves, spw, st, pg, tab, env, K, dt, sa, beta, as, am); break;
+            case 4: LAUNCH_SLOTS(fused_plain_slots_kernel, 4, env.n_waves, spw, st, pg, tab, env, K, dt, sa, beta, as, am); break;
             default: return hipErrorInvalidValue;
         }
         return hipGetLastError();

@@ -860,10 +860,10 @@ hipError_t launch_surrogate(const MlpState& s, const PointGeom& pg, int W, const
     const MlpNorm& nrm = s.norm;
     if (env.below && env.read_rest) {
         switch (W) {
-            case 1: LAUNCH_SLOTS(fused_surrogate_slots_kernel, 1, env.n_waves, st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
-            case 2: LAUNCH_SLOTS(fused_surrogate_slots_kernel, 2, env.n_waves, st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
-            case 3: LAUNCH_SLOTS(fused_surrogate_slots_kernel, 3, env.n_waves, st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
-            case 4: LAUNCH_SLOTS(fused_surrogate_slots_kernel, 4, env.n_waves, st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
+            case 1: LAUNCH_SLOTS(fused_surrogate_slots_kernel, 1, env.n_waves, slots_per_wave(env.n_waves, SlotUse::Surrogate), st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
+            case 2: LAUNCH_SLOTS(fused_surrogate_slots_kernel, 2, env.n_waves, slots_per_wave(env.n_waves, SlotUse::Surrogate), st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
+            case 3: LAUNCH_SLOTS(fused_surrogate_slots_kernel, 3, env.n_waves, slots_per_wave(env.n_waves, SlotUse::Surrogate), st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
+            case 4: LAUNCH_SLOTS(fused_surrogate_slots_kernel, 4, env.n_waves, slots_per_wave(env.n_waves, SlotUse::Surrogate), st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
             default: return hipErrorInvalidValue;
         }
     } else {
