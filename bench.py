@@ -73,16 +73,21 @@ PAPER_CPU = {
 # the figures are reported null.
 FUSED_PROFILE = {
     "file": "profiles/fused_plain_kernel_multilayer_block.txt", "K": 64,
-    "valu_lane_ops_per_update": 10.532, "valu_issue": 0.329, "valu_busy": 0.479,
-    "traffic_bytes_per_launch": (3375.9 * 2.0 + 3476.9) * 1024,
+    "valu_lane_ops_per_update": 10.485, "valu_issue": 0.326, "valu_busy": 0.476,
+    "traffic_bytes_per_launch": (3392.1 * 2.0 + 3477.1) * 1024,
 }
-FUSED_PROFILE_EVERY_T = {"K": 64, "valu_lane_ops_per_update": 129.26, "valu_issue": 0.727, "valu_busy": 0.927}
+FUSED_PROFILE_EVERY_T = {"K": 64, "valu_lane_ops_per_update": 129.27, "valu_issue": 0.730, "valu_busy": 0.930}
 SURROGATE_PROFILE = {"file": "profiles/fused_surrogate_kernels_multilayer_block.txt", "K": 64,
-                     8: {"valu_lane_ops_per_update": 4.727, "valu_issue": 0.168, "valu_busy": 0.260},
-                     16: {"valu_lane_ops_per_update": 4.012, "valu_issue": 0.145, "valu_busy": 0.231}}
+                     8: {"valu_lane_ops_per_update": 4.680, "valu_issue": 0.164, "valu_busy": 0.254},
+                     16: {"valu_lane_ops_per_update": 3.966, "valu_issue": 0.143, "valu_busy": 0.227}}
 C3_PROFILE = {"file": "profiles/fused_plain_kernel_cantilever_islands.txt", "K": K_C3,
-              "valu_lane_ops_per_update": 4.270, "valu_issue": 0.214, "valu_busy": 0.349,
-              "traffic_bytes_per_launch": (7050.3 * 2.0 + 2793.0) * 1024}
+              "valu_lane_ops_per_update": 2.875, "valu_issue": 0.240, "valu_busy": 0.379,
+              "traffic_bytes_per_launch": (7059.0 * 2.0 + 2793.1) * 1024}
+C5_PROFILE = {"file": "profiles/fused_kernels_island_block.txt",
+              "plain": {"K": K_FUSED, "valu_lane_ops_per_update": 4.084, "valu_issue": 0.253,
+                        "valu_busy": 0.382, "traffic_bytes_per_launch": (13583.7 * 2.0 + 12467.8) * 1024},
+              "surrogate": {"K": K_SURROGATE, "valu_lane_ops_per_update": 1.130, "valu_issue": 0.205,
+                            "valu_busy": 0.329, "traffic_bytes_per_launch": (13635.7 * 2.0 + 12466.1) * 1024}}
 
 
 def parse():
@@ -444,7 +449,18 @@ def bench_c5(torch, ms, ctx, args):
         e1.record()
         torch.cuda.synchronize()
         t = e0.elapsed_time(e1) * 1e-3
-        out[key] = {"seconds": t, "value": upd / t, "unit": "point-updates/s", "K": K}
+        prof = C5_PROFILE[key]
+        rate = upd / t
+        launches = call_launches(wl, 64)  # both modes launch 64 steps at a time
+        out[key] = {"seconds": t, "value": rate, "unit": "point-updates/s", "K": K,
+                    "roofline": {"bound": "alu", "peak": VALU_PEAK_TLANEOPS, "unit": "Tlane-op/s",
+                                 "achieved": rate * prof["valu_lane_ops_per_update"] / 1e12,
+                                 "frac": rate * prof["valu_lane_ops_per_update"] / 1e12 / VALU_PEAK_TLANEOPS,
+                                 "lane_ops_per_update": prof["valu_lane_ops_per_update"],
+                                 "valu_issue_frac": prof["valu_issue"], "valu_busy_frac": prof["valu_busy"],
+                                 "traffic": prof["traffic_bytes_per_launch"], "traffic_unit": "bytes/launch",
+                                 "hbm_GBs": prof["traffic_bytes_per_launch"] * launches / t / 1e9,
+                                 "profile": C5_PROFILE["file"]}}
         print(f"c5 {key}: {t:.2f} s", file=sys.stderr, flush=True)
         states[key] = g
     out["surrogate"]["speedup_vs_plain"] = out["plain"]["seconds"] / out["surrogate"]["seconds"]
