@@ -718,16 +718,17 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
             }
             ctx->wave_flags_cap = need;
         }
-        if (pts->index && ctx->wave_boxes_cap < (size_t)p.n_waves) {
+        const size_t n_boxes = (size_t)(p.n_waves + wave_groups(p.n_waves));
+        if (pts->index && ctx->wave_boxes_cap < n_boxes) {
             HIP_CHECK(ctx, hipStreamSynchronize(st));
             if (ctx->wave_boxes) HIP_CHECK(ctx, hipFree(ctx->wave_boxes));
             ctx->wave_boxes = nullptr;
             ctx->wave_boxes_cap = 0;
-            if (hipMalloc((void**)&ctx->wave_boxes, (size_t)p.n_waves * sizeof(GridBox)) != hipSuccess) {
+            if (hipMalloc((void**)&ctx->wave_boxes, n_boxes * sizeof(GridBox)) != hipSuccess) {
                 ctx->wave_boxes = nullptr;
                 return fail(ctx, MSTRUCT_ENOMEM, "wave box allocation failed");
             }
-            ctx->wave_boxes_cap = (size_t)p.n_waves;
+            ctx->wave_boxes_cap = n_boxes;
         }
         b.flags = ctx->wave_flags;
         b.chunk = chunk;
@@ -773,7 +774,8 @@ int mstruct_fused_scan_steps_noalloc(mstruct_ctx* ctx, const mstruct_scan* scan,
     // launches of still flags per chunk as fit; without room for one launch
     // the call runs without wave flags (the same results bit for bit)
     if (ctx->skip_cold && !ph->xbt) {
-        const size_t box_bytes = pts->index ? (((size_t)p.n_waves * sizeof(GridBox) + 255) & ~(size_t)255) : 0;
+        const size_t box_bytes =
+            pts->index ? (((size_t)(p.n_waves + wave_groups(p.n_waves)) * sizeof(GridBox) + 255) & ~(size_t)255) : 0;
         const size_t room = kScratchBytes - kScratchTable;
         const int64_t per_wave = box_bytes < room ? (int64_t)((room - box_bytes) / (size_t)p.n_waves) : 0;
         int64_t chunk = per_wave - 1;

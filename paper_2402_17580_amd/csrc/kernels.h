@@ -96,13 +96,20 @@ __device__ __forceinline__ bool wave_flag_still(const EnvSet& env, int64_t wv) {
 // still_flags for launches l0 .. l0 + nl - 1 of a call on a box grid:
 // flags[(l - l0) * n_waves + w] for wave w = points 64 w .. 64 w + 63 of pg;
 // env_fc holds (first record, count) of each launch's envelopes in env.
-// boxes: the box of each wave (launch_wave_boxes), or nullptr on a box grid
-// without an index list, where it follows from the wave's first and last point.
+// boxes: the box of each wave followed by the box of each group of 64 waves
+// (launch_wave_boxes), or nullptr on a box grid without an index list, where
+// they follow from the first and last points.
 hipError_t launch_still_flags(const PointGeom& pg, const EnvRec* env, const int32_t* env_fc, int64_t l0, int64_t nl,
                               int64_t n_waves, float T0, const GridBox* boxes, uint8_t* flags, hipStream_t st);
 
+// groups of 64 waves (4096 points) whose common box the still-flag pre-pass
+// tests first
+__host__ __device__ inline int64_t wave_groups(int64_t n_waves) { return (n_waves + 63) / 64; }
+
 // boxes[w]: the box of grid positions of the points 64 w .. 64 w + 63 of pg
-// (any index list: the least and greatest coordinates of its points)
+// (any index list: the least and greatest coordinates of its points), then
+// boxes[n_waves + s]: the box of waves 64 s .. 64 s + 63 (n_waves +
+// wave_groups(n_waves) boxes in all)
 hipError_t launch_wave_boxes(const PointGeom& pg, int64_t n_waves, GridBox* boxes, hipStream_t st);
 
 // xb: optional tracked X~beta side values (float64 per point), or nullptr

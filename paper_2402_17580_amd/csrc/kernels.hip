@@ -177,13 +177,11 @@ __global__ __launch_bounds__(kBlock) void temperature_kernel(PointGeom pg, const
     T[local] = (gk < pg.k0) ? sa.T0 : scan_temperature<W>(rec, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
 }
 
-// the box of grid positions holding the points of wave w (points 64 w ..
-// 64 w + 63 of pg, a box grid): the wave's part of one row, or whole rows
-// of one plane, or whole planes
-__device__ __forceinline__ GridBox wave_box(const PointGeom& pg, int64_t w) {
-    const int64_t g1 = w * kWave + kWave - 1 < pg.count ? w * kWave + kWave - 1 : pg.count - 1;
+// the box of grid positions holding the points g0 .. g1 of pg (a box grid):
+// part of one row, or whole rows of one plane, or whole planes
+__device__ __forceinline__ GridBox range_box(const PointGeom& pg, int64_t g0, int64_t g1) {
     int i0, j0, k0, i1, j1, k1;
-    decode_point(pg, pg.first + w * kWave, i0, j0, k0);
+    decode_point(pg, pg.first + g0, i0, j0, k0);
     decode_point(pg, pg.first + g1, i1, j1, k1);
     GridBox b;
     const bool row = k0 == k1 && j0 == j1;
@@ -196,40 +194,80 @@ __device__ __forceinline__ GridBox wave_box(const PointGeom& pg, int64_t w) {
     return b;
 }
 
-// one lane per wave and group of `group` launches: whether T0 plus the box
-// bounds of every track of a launch stay below the still limit at every
-// point of the wave, for each launch of the group.  With an index list the
-// wave's box is loaded once per group (one lane per (launch, wave) re-read
-// every box once per launch: 12 MB per launch on a 32M-point cantilever);
-// on a box grid it follows from the wave index and group = 1.
+// wave w (points 64 w .. 64 w + 63) and group s (waves 64 s .. 64 s + 63)
+__device__ __forceinline__ GridBox wave_box(const PointGeom& pg, int64_t w) {
+    return range_box(pg, w * kWave, min(w * kWave + kWave - 1, pg.count - 1));
+}
+__device__ __forceinline__ GridBox group_box(const PointGeom& pg, int64_t s) {
+    return range_box(pg, s * kWave * kWave, min((s + 1) * kWave * kWave - 1, pg.count - 1));
+}
+
+// T0 plus the box bounds of every track of one launch, below the still limit
+__device__ __forceinline__ bool box_below(const EnvRec* __restrict__ e, int n, const GridBox& b, float T0,
+                                          float rlim2) {
+    float T = T0;
+    for (int k = 0; k < n && T < kRestBelow; ++k) T += env_box_rise_bound(e[k], b, rlim2);
+    return T < kRestBelow;
+}
+
+// One wave per launch and 64 groups of 64 waves: each lane tests the common
+// box of one group; then the wave goes through its groups in turn, writing
+// the 64 flags of a group (one per lane) from the group's test where it
+// passed and from each wave's own box where it did not.  Far from the
+// tracks a group passes as a whole, so most waves' boxes are never tested.
 __global__ __launch_bounds__(kBlock) void still_flags_kernel(PointGeom pg, const EnvRec* __restrict__ env,
                                                             const int32_t* __restrict__ env_fc, int64_t nl,
-                                                            int64_t n_waves, int group, float T0, float rlim2,
+                                                            int64_t n_waves, float T0, float rlim2,
                                                             const GridBox* __restrict__ boxes,
                                                             uint8_t* __restrict__ flags) {
-    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t n_groups = (nl + group - 1) / group;
-    if (t >= n_groups * n_waves) return;
-    const int64_t lg = t / n_waves, w = t - lg * n_waves;
-    const GridBox b = boxes ? boxes[w] : wave_box(pg, w);
-    const int64_t l_end = min(nl, (lg + 1) * group);
-    for (int64_t l = lg * group; l < l_end; ++l) {
-        const EnvRec* e = env + env_fc[2 * l];
-        const int n = env_fc[2 * l + 1];
-        float T = T0;
-        for (int k = 0; k < n && T < kRestBelow; ++k) T += env_box_rise_bound(e[k], b, rlim2);
-        flags[l * n_waves + w] = T < kRestBelow ? 1 : 0;
+    const int64_t n_groups = wave_groups(n_waves);
+    const int64_t blocks_per_launch = (n_groups + kWave - 1) / kWave;
+    const int64_t gw = (int64_t)blockIdx.x * (kBlock / kWave) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    if (gw >= nl * blocks_per_launch) return;  // uniform per wave
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t l = gw / blocks_per_launch, s0 = (gw - l * blocks_per_launch) * kWave;
+    const EnvRec* e = env + env_fc[2 * l];
+    const int n = env_fc[2 * l + 1];
+    const int64_t s = s0 + lane;
+    bool pass = true;
+    if (s < n_groups) pass = box_below(e, n, boxes ? boxes[n_waves + s] : group_box(pg, s), T0, rlim2);
+    const uint64_t passed = __ballot(pass);
+    uint8_t* out = flags + l * n_waves;
+    const int64_t s_end = min(n_groups, s0 + kWave);
+    for (int64_t g = s0; g < s_end; ++g) {
+        const int64_t w = g * kWave + lane;
+        bool f = true;
+        if (!((passed >> (g - s0)) & 1) && w < n_waves) f = box_below(e, n, boxes ? boxes[w] : wave_box(pg, w), T0, rlim2);
+        if (w < n_waves) out[w] = f ? 1 : 0;
     }
 }
 
 hipError_t launch_still_flags(const PointGeom& pg, const EnvRec* env, const int32_t* env_fc, int64_t l0, int64_t nl,
                               int64_t n_waves, float T0, const GridBox* boxes, uint8_t* flags, hipStream_t st) {
-    const int group = boxes ? 16 : 1;
-    const int64_t lanes = (nl + group - 1) / group * n_waves;
-    if (lanes <= 0) return hipSuccess;
-    hipLaunchKernelGGL(still_flags_kernel, dim3((unsigned)((lanes + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, pg,
-                       env, env_fc + 2 * l0, nl, n_waves, group, T0, envelope_radius2(pg), boxes, flags);
+    const int64_t waves = nl * ((wave_groups(n_waves) + kWave - 1) / kWave);
+    if (waves <= 0) return hipSuccess;
+    const int64_t wpb = kBlock / kWave;
+    hipLaunchKernelGGL(still_flags_kernel, dim3((unsigned)((waves + wpb - 1) / wpb)), dim3(kBlock), 0, st, pg, env,
+                       env_fc + 2 * l0, nl, n_waves, T0, envelope_radius2(pg), boxes, flags);
     return hipGetLastError();
+}
+
+// the box of each group of 64 waves from the waves' boxes (one lane per group)
+__global__ __launch_bounds__(kBlock) void group_boxes_kernel(int64_t n_waves, GridBox* __restrict__ boxes) {
+    const int64_t s = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (s >= wave_groups(n_waves)) return;
+    GridBox b = boxes[s * kWave];
+    const int64_t w_end = min(n_waves, (s + 1) * kWave);
+    for (int64_t w = s * kWave + 1; w < w_end; ++w) {
+        const GridBox c = boxes[w];
+        b.xl = fminf(b.xl, c.xl);
+        b.xh = fmaxf(b.xh, c.xh);
+        b.yl = fminf(b.yl, c.yl);
+        b.yh = fmaxf(b.yh, c.yh);
+        b.zl = fminf(b.zl, c.zl);
+        b.zh = fmaxf(b.zh, c.zh);
+    }
+    boxes[n_waves + s] = b;
 }
 
 // one wave per wave of points: each lane decodes one point, the wave takes
@@ -263,6 +301,11 @@ hipError_t launch_wave_boxes(const PointGeom& pg, int64_t n_waves, GridBox* boxe
     if (n_waves <= 0) return hipSuccess;
     const int64_t blocks = (n_waves + kBlock / kWave - 1) / (kBlock / kWave);
     hipLaunchKernelGGL(wave_boxes_kernel, dim3((unsigned)blocks), dim3(kBlock), 0, st, pg, n_waves, boxes);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const int64_t groups = wave_groups(n_waves);
+    hipLaunchKernelGGL(group_boxes_kernel, dim3((unsigned)((groups + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
+                       n_waves, boxes);
     return hipGetLastError();
 }
 
