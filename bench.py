@@ -602,18 +602,19 @@ def bench_cooldown(torch, ms, ctx):
     """The multi-layer block with the paper's inter-layer cool-down (each
     layer: 2000 scan steps of 2 us, explicit; then 1 s of cool-down on the
     doubling schedule, implicit with 0.01 s substeps) and the final 100 s
-    cool-down in steps of 0.1 s, one run."""
+    cool-down in steps of 0.1 s, one run, in launches of 64 steps (258 ms per
+    run at K = 16, 241 ms at 32, 234 ms at 64)."""
     pw = workload.multilayer_cooldown()
     n = pw.grid.n
     g = [torch.from_numpy(x).cuda() for x in workload.initial_state(n, np.float32)]
-    ms.run_phases(ctx, pw, *g)  # warm-up
+    ms.run_phases(ctx, pw, *g, K=K_FUSED)  # warm-up
     for dst, src in zip(g, workload.initial_state(n, np.float32)):
         dst.copy_(torch.from_numpy(src))
     ctx.implicit_unconverged(reset=True)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    ms.run_phases(ctx, pw, *g)
+    ms.run_phases(ctx, pw, *g, K=K_FUSED)
     e1.record()
     torch.cuda.synchronize()
     t = e0.elapsed_time(e1) * 1e-3
@@ -623,7 +624,7 @@ def bench_cooldown(torch, ms, ctx):
     return {"value": upd / t, "unit": "point-updates/s", "seconds": t, "point_updates": upd,
             "scan_point_updates": scan_upd, "simulated_s": pw.phases[-1].t0 + pw.phases[-1].dt * pw.phases[-1].n_steps,
             "calls": len(pw.phases), "unconverged_substeps": ctx.implicit_unconverged(),
-            "path": "run_phases: fused PLAIN while scanning, fused IMPLICIT while cooling (K = 16)"}, g
+            "path": "run_phases: fused PLAIN while scanning, fused IMPLICIT while cooling (K = 64)", "K": K_FUSED}, g
 
 
 F64_STEP_BYTES = 56  # float64 step: reads alpha_s, alpha_m, T^n, T^{n+1}; writes beta, alpha_s, alpha_m

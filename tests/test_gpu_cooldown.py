@@ -60,12 +60,14 @@ def test_cooldown_small_all_points(torch, ctx, orc):
 def test_multilayer_cooldown_full_size_sampled(torch, ctx, orc):
     """256x256x128, 10 layers of 2000 scan steps, each followed by 1 s of
     cool-down (2146 steps), then the final 100 s (1000 steps of 0.1 s); a
-    seeded 0.1 % sample against the oracle."""
+    seeded 0.1 % sample against the oracle, in launches of 16 and of 64
+    steps (the benchmark's)."""
     pw = workload.multilayer_cooldown()
-    g = _run(torch, ctx, pw)
-    assert ctx.implicit_unconverged() == 0
     idx = workload.sample_indices(pw.grid.n, 1e-3, pw.seed)
     st, bad = orc.run_phases(pw, idx)
     assert bad == 0
-    print("multilayer cooldown sample", idx.size, _check(g, st, idx))
-    assert ctx.check_invariants(*g, tol=2e-6) == 0
+    for K in (16, 64):
+        g = _run(torch, ctx, pw, K=K)
+        assert ctx.implicit_unconverged() == 0
+        print("multilayer cooldown sample", idx.size, "K", K, _check(g, st, idx))
+        assert ctx.check_invariants(*g, tol=2e-6) == 0
