@@ -210,30 +210,31 @@ __device__ __forceinline__ bool box_below(const EnvRec* __restrict__ e, int n, c
     return T < kRestBelow;
 }
 
-// One wave per launch and 64 groups of 64 waves: each lane tests the common
-// box of one group; then the wave goes through its groups in turn, writing
-// the 64 flags of a group (one per lane) from the group's test where it
-// passed and from each wave's own box where it did not.  Far from the
+// One wave per launch and gpw groups of 64 waves: lane i < gpw tests the
+// common box of one group; then the wave goes through its groups in turn,
+// writing the 64 flags of a group (one per lane) from the group's test where
+// it passed and from each wave's own box where it did not.  Far from the
 // tracks a group passes as a whole, so most waves' boxes are never tested.
+// gpw (1 .. 64) keeps enough waves in flight on small grids.
 __global__ __launch_bounds__(kBlock) void still_flags_kernel(PointGeom pg, const EnvRec* __restrict__ env,
                                                             const int32_t* __restrict__ env_fc, int64_t nl,
-                                                            int64_t n_waves, float T0, float rlim2,
+                                                            int64_t n_waves, int gpw, float T0, float rlim2,
                                                             const GridBox* __restrict__ boxes,
                                                             uint8_t* __restrict__ flags) {
     const int64_t n_groups = wave_groups(n_waves);
-    const int64_t blocks_per_launch = (n_groups + kWave - 1) / kWave;
+    const int64_t blocks_per_launch = (n_groups + gpw - 1) / gpw;
     const int64_t gw = (int64_t)blockIdx.x * (kBlock / kWave) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
     if (gw >= nl * blocks_per_launch) return;  // uniform per wave
     const int lane = threadIdx.x & (kWave - 1);
-    const int64_t l = gw / blocks_per_launch, s0 = (gw - l * blocks_per_launch) * kWave;
+    const int64_t l = gw / blocks_per_launch, s0 = (gw - l * blocks_per_launch) * gpw;
     const EnvRec* e = env + env_fc[2 * l];
     const int n = env_fc[2 * l + 1];
     const int64_t s = s0 + lane;
     bool pass = true;
-    if (s < n_groups) pass = box_below(e, n, boxes ? boxes[n_waves + s] : group_box(pg, s), T0, rlim2);
+    if (lane < gpw && s < n_groups) pass = box_below(e, n, boxes ? boxes[n_waves + s] : group_box(pg, s), T0, rlim2);
     const uint64_t passed = __ballot(pass);
     uint8_t* out = flags + l * n_waves;
-    const int64_t s_end = min(n_groups, s0 + kWave);
+    const int64_t s_end = min(n_groups, s0 + gpw);
     for (int64_t g = s0; g < s_end; ++g) {
         const int64_t w = g * kWave + lane;
         bool f = true;
@@ -244,11 +245,15 @@ __global__ __launch_bounds__(kBlock) void still_flags_kernel(PointGeom pg, const
 
 hipError_t launch_still_flags(const PointGeom& pg, const EnvRec* env, const int32_t* env_fc, int64_t l0, int64_t nl,
                               int64_t n_waves, float T0, const GridBox* boxes, uint8_t* flags, hipStream_t st) {
-    const int64_t waves = nl * ((wave_groups(n_waves) + kWave - 1) / kWave);
+    // groups per wave: 64, or fewer to keep about 8192 waves in flight
+    const int64_t groups = wave_groups(n_waves) * nl;
+    int gpw = 64;
+    while (gpw > 1 && groups / gpw < 8192) gpw >>= 1;
+    const int64_t waves = nl * ((wave_groups(n_waves) + gpw - 1) / gpw);
     if (waves <= 0) return hipSuccess;
     const int64_t wpb = kBlock / kWave;
     hipLaunchKernelGGL(still_flags_kernel, dim3((unsigned)((waves + wpb - 1) / wpb)), dim3(kBlock), 0, st, pg, env,
-                       env_fc + 2 * l0, nl, n_waves, T0, envelope_radius2(pg), boxes, flags);
+                       env_fc + 2 * l0, nl, n_waves, gpw, T0, envelope_radius2(pg), boxes, flags);
     return hipGetLastError();
 }
 
