@@ -73,20 +73,20 @@ PAPER_CPU = {
 # the figures are reported null.
 FUSED_PROFILE = {
     "file": "profiles/fused_plain_kernel_multilayer_block.txt", "K": 64,
-    "valu_lane_ops_per_update": 10.485, "valu_issue": 0.326, "valu_busy": 0.476,
-    "traffic_bytes_per_launch": (3392.1 * 2.0 + 3477.1) * 1024,
+    "valu_lane_ops_per_update": 10.485, "valu_issue": 0.324, "valu_busy": 0.472,
+    "traffic_bytes_per_launch": (3391.4 * 2.0 + 3477.1) * 1024,
 }
 FUSED_PROFILE_EVERY_T = {"K": 64, "valu_lane_ops_per_update": 129.27, "valu_issue": 0.730, "valu_busy": 0.930}
 SURROGATE_PROFILE = {"file": "profiles/fused_surrogate_kernels_multilayer_block.txt", "K": 64,
-                     8: {"valu_lane_ops_per_update": 4.680, "valu_issue": 0.164, "valu_busy": 0.254},
-                     16: {"valu_lane_ops_per_update": 3.966, "valu_issue": 0.143, "valu_busy": 0.227}}
+                     8: {"valu_lane_ops_per_update": 4.680, "valu_issue": 0.164, "valu_busy": 0.255},
+                     16: {"valu_lane_ops_per_update": 3.966, "valu_issue": 0.143, "valu_busy": 0.228}}
 C3_PROFILE = {"file": "profiles/fused_plain_kernel_cantilever_islands.txt", "K": K_C3,
-              "valu_lane_ops_per_update": 2.875, "valu_issue": 0.240, "valu_busy": 0.379,
-              "traffic_bytes_per_launch": (7059.0 * 2.0 + 2793.1) * 1024}
+              "valu_lane_ops_per_update": 2.875, "valu_issue": 0.239, "valu_busy": 0.378,
+              "traffic_bytes_per_launch": (7057.9 * 2.0 + 2793.1) * 1024}
 C5_PROFILE = {"file": "profiles/fused_kernels_island_block.txt",
               "plain": {"K": K_FUSED, "valu_lane_ops_per_update": 4.084, "valu_issue": 0.253,
-                        "valu_busy": 0.382, "traffic_bytes_per_launch": (13583.7 * 2.0 + 12467.8) * 1024},
-              "surrogate": {"K": K_SURROGATE, "valu_lane_ops_per_update": 1.130, "valu_issue": 0.205,
+                        "valu_busy": 0.382, "traffic_bytes_per_launch": (13582.8 * 2.0 + 12467.7) * 1024},
+              "surrogate": {"K": K_SURROGATE, "valu_lane_ops_per_update": 1.130, "valu_issue": 0.204,
                             "valu_busy": 0.329, "traffic_bytes_per_launch": (13635.7 * 2.0 + 12466.1) * 1024}}
 
 
