@@ -7,6 +7,10 @@
 namespace mstruct {
 
 constexpr int kBlock = 256;
+// points per lane of the fused grid kernel, a build-time choice: 1 (the
+// wave flags, slot kernels and still shortcuts assume it); 2 or 4 advance
+// independent points together for instruction-level parallelism, without
+// those shortcuts
 #ifndef FUSED_PPT
 #define FUSED_PPT 1
 #endif
