@@ -257,8 +257,8 @@ int mstruct_fused_scan_steps(mstruct_ctx *ctx, const mstruct_scan *scan, const m
  * and 8 bytes per launch, must fit in 4 MiB (65,536 records), else
  * MSTRUCT_EINVAL and nothing is enqueued; wave flags are used when at least
  * one launch of them fits in the remaining 28 MiB (2 bytes per 64 points,
- * plus 24 bytes per 64 points with an index list), otherwise the call runs
- * without them (same results).  Every call on a GPU uses that GPU's one
+ * plus 24 bytes per 64 points and per 4096 points with an index list),
+ * otherwise the call runs without them (same results).  Every call on a GPU uses that GPU's one
  * array: calls on different streams, or from different host threads, that
  * overlap in time race on it; calls on one stream are ordered.  The host
  * part of these calls is serialised by a lock, and each waits until the
@@ -283,8 +283,8 @@ int mstruct_fused_scan_steps_noalloc(mstruct_ctx *ctx, const mstruct_scan *scan,
  * every launch's tracks in a pre-pass, and the context remembers which such
  * waves were at rest: from the second launch of a call such a wave reads
  * neither its state nor a track.  For this the context keeps 2 n/64 bytes
- * (and 24 n/64 bytes of boxes with an index list) plus at most 64 MiB of
- * still flags per call on the device, until mstruct_destroy.  The results are the same bit for bit as with 0, which
+ * (and 24 (n/64 + n/4096) bytes of boxes with an index list) plus at most
+ * 64 MiB of still flags per call on the device, until mstruct_destroy.  The results are the same bit for bit as with 0, which
  * evaluates every temperature and takes every step (for comparison). */
 enum { MSTRUCT_OPTION_SKIP_COLD_WAVES = 1, MSTRUCT_OPTION_COUNT_WAVES = 2 };
 /* MSTRUCT_OPTION_COUNT_WAVES (default 0): fused PLAIN and IMPLICIT launches
