@@ -550,6 +550,9 @@ FusedPlan fused_plan(const mstruct_scan* scan, const PointGeom& pg, int64_t n_st
 // device copy (cap records each), and the wave flags (n_waves bytes of rest
 // flags, then still flags for chunks of `chunk` launches; flags == nullptr:
 // none) with the waves' boxes on an index list.
+//
+// With wave flags, calls also list the waves each slot launch steps (4 bytes
+// per wave, and two counts: list_bytes in all).
 struct FusedBufs {
     SrcRec* host = nullptr;
     SrcRec* dev = nullptr;
@@ -557,7 +560,23 @@ struct FusedBufs {
     uint8_t* flags = nullptr;
     int64_t chunk = 0;
     GridBox* boxes = nullptr;
+    uint32_t* cand = nullptr;
+    unsigned* cand_counts = nullptr;
 };
+
+size_t round256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// bytes of a launch's wave list and its two counts (0: the waves cannot be
+// numbered in 32 bits, and the slot kernels read the flags themselves)
+size_t list_bytes(int64_t n_waves) {
+    return n_waves <= (int64_t)UINT32_MAX ? round256((size_t)n_waves * sizeof(uint32_t)) + 256 : 0;
+}
+
+void place_list(FusedBufs& b, uint8_t* at, int64_t n_waves) {
+    if (!list_bytes(n_waves)) return;
+    b.cand = reinterpret_cast<uint32_t*>(at);
+    b.cand_counts = reinterpret_cast<unsigned*>(at + round256((size_t)n_waves * sizeof(uint32_t)));
+}
 
 // Argument checks shared by the fused entry points; fills pg.  Returns
 // MSTRUCT_OK, an error status, or 1 when there is nothing to do.
@@ -613,6 +632,14 @@ int fused_run(mstruct_ctx* ctx, const mstruct_scan* scan, const mstruct_points* 
         hipError_t e = surrogate_prepare(ctx->mlp, n_waves, st);
         if (e != hipSuccess) return hip_fail(ctx, e, "surrogate records");
     }
+#ifndef CAND_LIST
+#define CAND_LIST 1
+#endif
+    const bool list = CAND_LIST && wave_flags && b.cand;
+    if (list) {
+        hipError_t e = launch_clear_counts(b.cand_counts, st);
+        if (e != hipSuccess) return hip_fail(ctx, e, "wave list counts");
+    }
     for (int64_t s0 = 0; s0 < n_steps; s0 += K) {
         const int Kb = (int)((n_steps - s0) < K ? (n_steps - s0) : K);
         const bool last = s0 + Kb >= n_steps;
@@ -634,8 +661,15 @@ int fused_run(mstruct_ctx* ctx, const mstruct_scan* scan, const mstruct_points* 
                 if (fe != hipSuccess) return hip_fail(ctx, fe, "still flags launch");
             }
         }
+        const bool use_list = list && li > 0;
         const EnvSet es{env_dev + fc_host[2 * li], ctx->skip_cold ? fc_host[2 * li + 1] : -1, below,
-                        wave_flags ? b.flags : nullptr, n_waves, li > 0, ctx->count_waves ? ctx->stats : nullptr};
+                        wave_flags ? b.flags : nullptr, n_waves, li > 0, ctx->count_waves ? ctx->stats : nullptr,
+                        use_list ? b.cand : nullptr, use_list ? b.cand_counts + (li & 1) : nullptr,
+                        use_list ? b.cand_counts + ((li + 1) & 1) : nullptr};
+        if (use_list) {
+            hipError_t le = launch_candidates(pg, es, fminf(sa.T0, sa.Tclamp), beta, st);
+            if (le != hipSuccess) return hip_fail(ctx, le, "wave list launch");
+        }
         if (mode == MSTRUCT_MODE_PLAIN) {
             e = launch_fused_plain(pg, W, b.dev + s0 * W, es, Kb, (float)dt, sa, beta, ph->alpha_s, ph->alpha_m,
                                    ph->xbt, st);
@@ -706,7 +740,8 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
     if (ctx->skip_cold && !ph->xbt) {
         int64_t chunk = kWaveFlagBudget / p.n_waves;
         chunk = chunk < 1 ? 1 : (chunk > p.n_launches ? p.n_launches : chunk);
-        const size_t need = (size_t)p.n_waves * (size_t)(1 + chunk);
+        const size_t flag_bytes = round256((size_t)p.n_waves * (size_t)(1 + chunk));
+        const size_t need = flag_bytes + list_bytes(p.n_waves);
         if (ctx->wave_flags_cap < need) {
             HIP_CHECK(ctx, hipStreamSynchronize(st));
             if (ctx->wave_flags) HIP_CHECK(ctx, hipFree(ctx->wave_flags));
@@ -733,6 +768,7 @@ int mstruct_fused_scan_steps(mstruct_ctx* ctx, const mstruct_scan* scan, const m
         b.flags = ctx->wave_flags;
         b.chunk = chunk;
         b.boxes = ctx->wave_boxes;
+        place_list(b, ctx->wave_flags + flag_bytes, p.n_waves);
     }
     TableSlot* s;
     if ((rc = acquire_slot(ctx, p.table(), s))) return rc;
@@ -775,13 +811,16 @@ int mstruct_fused_scan_steps_noalloc(mstruct_ctx* ctx, const mstruct_scan* scan,
     // the call runs without wave flags (the same results bit for bit)
     if (ctx->skip_cold && !ph->xbt) {
         const size_t box_bytes =
-            pts->index ? (((size_t)(p.n_waves + wave_groups(p.n_waves)) * sizeof(GridBox) + 255) & ~(size_t)255) : 0;
+            pts->index ? round256((size_t)(p.n_waves + wave_groups(p.n_waves)) * sizeof(GridBox)) : 0;
+        const size_t lb = list_bytes(p.n_waves);
         const size_t room = kScratchBytes - kScratchTable;
-        const int64_t per_wave = box_bytes < room ? (int64_t)((room - box_bytes) / (size_t)p.n_waves) : 0;
+        const size_t used = box_bytes + lb + 256;
+        const int64_t per_wave = used < room ? (int64_t)((room - used) / (size_t)p.n_waves) : 0;
         int64_t chunk = per_wave - 1;
         if (chunk >= 1) {
             b.boxes = pts->index ? reinterpret_cast<GridBox*>(base + kScratchTable) : nullptr;
-            b.flags = base + kScratchTable + box_bytes;
+            place_list(b, base + kScratchTable + box_bytes, p.n_waves);
+            b.flags = base + kScratchTable + box_bytes + lb;
             b.chunk = chunk > p.n_launches ? p.n_launches : chunk;
         }
     }

@@ -72,6 +72,21 @@ __device__ __forceinline__ void still_wave_beta(const PointGeom& pg, float T0c, 
     beta[local] = solid_fraction(T0c) - kXmax - 0.0f;
 }
 
+// The list form of a slot launch: the waves of the launch that are not
+// still by their flags, listed by candidates_kernel (which also wrote beta
+// for the still ones); wave p of the grid takes the entries p, p + P, ...
+// (P waves in the grid).  Consecutive entries, which are neighbouring waves
+// of points, go to consecutive waves of the grid and so to different CUs,
+// and every wave that steps is launched at the start of the kernel.
+template <int BS, class Body>
+__device__ __forceinline__ void fused_list(const EnvSet& env, Body body) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) *env.cand_next = 0u;
+    const int64_t n = *env.cand_n;
+    const int64_t P = (int64_t)gridDim.x * (BS / kWave);
+    const int64_t p = (int64_t)blockIdx.x * (BS / kWave) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    for (int64_t e = p; e < n; e += P) body((int64_t)__builtin_amdgcn_readfirstlane((int)env.cand[e]));
+}
+
 // The persistent form of a fused launch, used from the second launch of a
 // call when the wave flags are kept: a grid of about one wave per
 // slots_per_wave waves of the launch, in which wave p takes the wave slots p,
@@ -79,10 +94,15 @@ __device__ __forceinline__ void still_wave_beta(const PointGeom& pg, float T0c, 
 // one slot; the wave then runs body(w) for every slot w that is not still
 // (all 64 lanes, one point each) and writes beta for the still ones.  No
 // wave is launched only to find its flags set, and the interleaved slots
-// spread the few waves that step evenly over the grid.
+// spread the few waves that step evenly over the grid.  With a list of the
+// waves that step (EnvSet::cand), the launch takes its list form instead.
 template <int BS, class Body>
 __device__ __forceinline__ void fused_slots(const PointGeom& pg, const EnvSet& env, float T0c, float* beta,
                                             Body body) {
+    if (env.cand) {  // the launch's list of the waves that step
+        fused_list<BS>(env, body);
+        return;
+    }
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t P = (int64_t)gridDim.x * (BS / kWave);
     const int64_t p = (int64_t)blockIdx.x * (BS / kWave) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));

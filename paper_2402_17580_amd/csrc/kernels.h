@@ -66,6 +66,13 @@ struct EnvSet {
     // wave counts of fused PLAIN / IMPLICIT launches (nullptr: not counted),
     // indexed by the kStat* constants
     unsigned long long* stats;
+    // the waves of a slot launch that are not still by their flags, listed
+    // by candidates_kernel (cand[0 .. *cand_n)); nullptr: the slot kernel
+    // reads the flags itself.  The slot launch clears *cand_next, the next
+    // launch's count.
+    uint32_t* cand;
+    unsigned* cand_n;
+    unsigned* cand_next;
 };
 
 // the counts of EnvSet::stats: points whose state a launch reads and writes,
@@ -111,6 +118,12 @@ __host__ __device__ inline int64_t wave_groups(int64_t n_waves) { return (n_wave
 // boxes[n_waves + s]: the box of waves 64 s .. 64 s + 63 (n_waves +
 // wave_groups(n_waves) boxes in all)
 hipError_t launch_wave_boxes(const PointGeom& pg, int64_t n_waves, GridBox* boxes, hipStream_t st);
+
+// list the waves of a slot launch that are not still by their flags into
+// env.cand (count in *env.cand_n), and write beta (if not nullptr) for the
+// still ones; clear_counts zeroes the two counts of a call
+hipError_t launch_candidates(const PointGeom& pg, const EnvSet& env, float T0c, float* beta, hipStream_t st);
+hipError_t launch_clear_counts(unsigned* counts, hipStream_t st);
 
 // xb: optional tracked X~beta side values (float64 per point), or nullptr
 hipError_t launch_step(const float* Tp, const float* Tn, float* beta, float* as, float* am, double* xb, int64_t n,

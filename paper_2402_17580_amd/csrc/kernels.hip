@@ -440,6 +440,51 @@ __global__ __launch_bounds__(BS) void fused_plain_slots_kernel(PointGeom pg, con
     });
 }
 
+// One wave per 64 waves of a slot launch: the waves that are not still by
+// their flags go to the launch's list (one atomic per wave of this kernel),
+// the still ones write beta in the last launch of a call.
+__global__ __launch_bounds__(kBlock) void candidates_kernel(PointGeom pg, EnvSet env, float T0c,
+                                                           float* __restrict__ beta) {
+    const int64_t gw = (int64_t)blockIdx.x * (kBlock / kWave) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    if (gw * kWave >= env.n_waves) return;  // uniform per wave
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t w = gw * kWave + lane;
+    const bool in = w < env.n_waves;
+    const bool still = in && env.below[w] && env.rest[w];
+    const uint64_t todo = __ballot(in && !still);
+    uint64_t quiet = beta ? __ballot(still) : 0;
+    if (env.stats) {
+        const int nq = __popcll(__ballot(still));
+        if (nq && lane == 0) atomicAdd(env.stats + kStatFlagged, (unsigned long long)nq);
+    }
+    unsigned base = 0;
+    if (lane == 0 && todo) base = atomicAdd(env.cand_n, (unsigned)__popcll(todo));
+    base = __shfl(base, 0);
+    if (in && !still) env.cand[base + __popcll(todo & ((1ull << lane) - 1))] = (uint32_t)w;
+    while (quiet) {
+        const int i = __builtin_ctzll(quiet);
+        quiet &= quiet - 1;
+        still_wave_beta(pg, T0c, beta, (gw * kWave + i) * kWave + lane);
+    }
+}
+
+hipError_t launch_candidates(const PointGeom& pg, const EnvSet& env, float T0c, float* beta, hipStream_t st) {
+    const int64_t waves = (env.n_waves + kWave - 1) / kWave, wpb = kBlock / kWave;
+    if (waves <= 0) return hipSuccess;
+    hipLaunchKernelGGL(candidates_kernel, dim3((unsigned)((waves + wpb - 1) / wpb)), dim3(kBlock), 0, st, pg, env, T0c,
+                       beta);
+    return hipGetLastError();
+}
+
+__global__ void clear_counts_kernel(unsigned* c) {
+    if (threadIdx.x < 2) c[threadIdx.x] = 0u;
+}
+
+hipError_t launch_clear_counts(unsigned* counts, hipStream_t st) {
+    hipLaunchKernelGGL(clear_counts_kernel, dim3(1), dim3(64), 0, st, counts);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------------------
 // fused K steps with the implicit scheme: as the plain fused kernel, with the
 // Crank-Nicolson fixed-point step at every step (n_sub equal substeps of
