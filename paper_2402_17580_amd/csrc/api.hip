@@ -661,13 +661,15 @@ int fused_run(mstruct_ctx* ctx, const mstruct_scan* scan, const mstruct_points* 
                 if (fe != hipSuccess) return hip_fail(ctx, fe, "still flags launch");
             }
         }
-        const bool use_list = list && li > 0;
+        const bool use_list = list;
         const EnvSet es{env_dev + fc_host[2 * li], ctx->skip_cold ? fc_host[2 * li + 1] : -1, below,
                         wave_flags ? b.flags : nullptr, n_waves, li > 0, ctx->count_waves ? ctx->stats : nullptr,
                         use_list ? b.cand : nullptr, use_list ? b.cand_counts + (li & 1) : nullptr,
                         use_list ? b.cand_counts + ((li + 1) & 1) : nullptr};
         if (use_list) {
-            hipError_t le = launch_candidates(pg, es, fminf(sa.T0, sa.Tclamp), beta, st);
+            hipError_t le = li == 0 ? launch_first_candidates(pg, es, fminf(sa.T0, sa.Tclamp), beta, ph->alpha_s,
+                                                              ph->alpha_m, st)
+                                    : launch_candidates(pg, es, fminf(sa.T0, sa.Tclamp), beta, st);
             if (le != hipSuccess) return hip_fail(ctx, le, "wave list launch");
         }
         if (mode == MSTRUCT_MODE_PLAIN) {

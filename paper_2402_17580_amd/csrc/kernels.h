@@ -123,6 +123,10 @@ hipError_t launch_wave_boxes(const PointGeom& pg, int64_t n_waves, GridBox* boxe
 // env.cand (count in *env.cand_n), and write beta (if not nullptr) for the
 // still ones; clear_counts zeroes the two counts of a call
 hipError_t launch_candidates(const PointGeom& pg, const EnvSet& env, float T0c, float* beta, hipStream_t st);
+// the same for the first launch of a call, from the state (as, am) and the
+// box pre-pass's flags; sets the rest flags of the still waves
+hipError_t launch_first_candidates(const PointGeom& pg, const EnvSet& env, float T0c, float* beta, const float* as,
+                                   const float* am, hipStream_t st);
 hipError_t launch_clear_counts(unsigned* counts, hipStream_t st);
 
 // xb: optional tracked X~beta side values (float64 per point), or nullptr

@@ -441,12 +441,17 @@ __global__ __launch_bounds__(BS) void fused_plain_slots_kernel(PointGeom pg, con
 }
 
 // One wave per 64 waves of a slot launch: the waves that are not still by
-// their flags go to the launch's list (one atomic per wave of this kernel),
-// the still ones write beta in the last launch of a call.
-__global__ __launch_bounds__(kBlock) void candidates_kernel(PointGeom pg, EnvSet env, float T0c,
-                                                           float* __restrict__ beta) {
-    const int64_t gw = (int64_t)blockIdx.x * (kBlock / kWave) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-    if (gw * kWave >= env.n_waves) return;  // uniform per wave
+// their flags go to the launch's list, the still ones write beta in the
+// last launch of a call.  A workgroup of 16 waves takes its places in the
+// list with one atomic (all workgroups add to the same count, so atomics per
+// wave would queue up: 16.8 us per launch on a 1M-wave grid).
+constexpr int kListBlock = 1024;
+
+__global__ __launch_bounds__(kListBlock) void candidates_kernel(PointGeom pg, EnvSet env, float T0c,
+                                                               float* __restrict__ beta) {
+    __shared__ unsigned wave_n[kListBlock / kWave + 1];
+    const int wib = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const int64_t gw = (int64_t)blockIdx.x * (kListBlock / kWave) + wib;
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t w = gw * kWave + lane;
     const bool in = w < env.n_waves;
@@ -457,9 +462,19 @@ __global__ __launch_bounds__(kBlock) void candidates_kernel(PointGeom pg, EnvSet
         const int nq = __popcll(__ballot(still));
         if (nq && lane == 0) atomicAdd(env.stats + kStatFlagged, (unsigned long long)nq);
     }
-    unsigned base = 0;
-    if (lane == 0 && todo) base = atomicAdd(env.cand_n, (unsigned)__popcll(todo));
-    base = __shfl(base, 0);
+    if (lane == 0) wave_n[wib] = (unsigned)__popcll(todo);
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned total = 0;
+        for (int i = 0; i < kListBlock / kWave; ++i) {
+            const unsigned c = wave_n[i];
+            wave_n[i] = total;
+            total += c;
+        }
+        wave_n[kListBlock / kWave] = total ? atomicAdd(env.cand_n, total) : 0u;
+    }
+    __syncthreads();
+    const unsigned base = wave_n[kListBlock / kWave] + wave_n[wib];
     if (in && !still) env.cand[base + __popcll(todo & ((1ull << lane) - 1))] = (uint32_t)w;
     while (quiet) {
         const int i = __builtin_ctzll(quiet);
@@ -468,11 +483,65 @@ __global__ __launch_bounds__(kBlock) void candidates_kernel(PointGeom pg, EnvSet
     }
 }
 
+// The first launch of a call, which has no rest flags yet: one wave per
+// wave of points reads its state; a wave at rest that the box pre-pass
+// bounds below the still limit is still (its rest flag is set and, in a
+// one-launch call, beta written), the others go to the list (one atomic per
+// workgroup of 16 waves).
+__global__ __launch_bounds__(kListBlock) void first_candidates_kernel(PointGeom pg, EnvSet env, float T0c,
+                                                                     float* __restrict__ beta,
+                                                                     const float* __restrict__ as,
+                                                                     const float* __restrict__ am) {
+    __shared__ unsigned wave_n[kListBlock / kWave + 1];
+    const int wib = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const int64_t w = (int64_t)blockIdx.x * (kListBlock / kWave) + wib;
+    const int lane = threadIdx.x & (kWave - 1);
+    const bool in = w < env.n_waves;  // uniform per wave
+    bool still = false;
+    if (in) {
+        const int64_t g = w * kWave + lane;
+        bool act = g < pg.count;
+        const int64_t local = pg.first + (act ? g : 0);
+        int gi, gj, gk;
+        decode_point(pg, local, gi, gj, gk);
+        act = act && gk >= pg.k0;
+        const float a = act ? as[local] : 0.0f, m = act ? am[local] : 0.0f;
+        still = env.below[w] && wave_may_rest(env, act, a, m, T0c);
+        if (still) {
+            if (act && beta) beta[local] = solid_fraction(T0c) - a - m;
+            if (env.stats) count_wave(env, act, true, true);
+            if (lane == 0) env.rest[w] = 1;
+        }
+    }
+    if (lane == 0) wave_n[wib] = (in && !still) ? 1u : 0u;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned total = 0;
+        for (int i = 0; i < kListBlock / kWave; ++i) {
+            const unsigned c = wave_n[i];
+            wave_n[i] = total;
+            total += c;
+        }
+        wave_n[kListBlock / kWave] = total ? atomicAdd(env.cand_n, total) : 0u;
+    }
+    __syncthreads();
+    if (in && !still && lane == 0) env.cand[wave_n[kListBlock / kWave] + wave_n[wib]] = (uint32_t)w;
+}
+
+hipError_t launch_first_candidates(const PointGeom& pg, const EnvSet& env, float T0c, float* beta, const float* as,
+                                   const float* am, hipStream_t st) {
+    const int64_t wpb = kListBlock / kWave;
+    if (env.n_waves <= 0) return hipSuccess;
+    hipLaunchKernelGGL(first_candidates_kernel, dim3((unsigned)((env.n_waves + wpb - 1) / wpb)), dim3(kListBlock), 0,
+                       st, pg, env, T0c, beta, as, am);
+    return hipGetLastError();
+}
+
 hipError_t launch_candidates(const PointGeom& pg, const EnvSet& env, float T0c, float* beta, hipStream_t st) {
-    const int64_t waves = (env.n_waves + kWave - 1) / kWave, wpb = kBlock / kWave;
+    const int64_t waves = (env.n_waves + kWave - 1) / kWave, wpb = kListBlock / kWave;
     if (waves <= 0) return hipSuccess;
-    hipLaunchKernelGGL(candidates_kernel, dim3((unsigned)((waves + wpb - 1) / wpb)), dim3(kBlock), 0, st, pg, env, T0c,
-                       beta);
+    hipLaunchKernelGGL(candidates_kernel, dim3((unsigned)((waves + wpb - 1) / wpb)), dim3(kListBlock), 0, st, pg,
+                       env, T0c, beta);
     return hipGetLastError();
 }
 
@@ -599,7 +668,7 @@ hipError_t launch_fused_implicit(const PointGeom& pg, int W, const SrcRec* tab, 
                                  int max_iter, ScanArgs sa, float* beta, float* as, float* am, double* xb,
                                  unsigned long long* unconverged, hipStream_t st) {
     if (pg.count <= 0) return hipSuccess;
-    if (!xb && env.below && env.read_rest) {
+    if (!xb && env.below && (env.read_rest || env.cand)) {
         switch (W) {
             case 1: LAUNCH_SLOTS(fused_implicit_slots_kernel, 1, env.n_waves, slots_per_wave(env.n_waves, SlotUse::Implicit), st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
             case 2: LAUNCH_SLOTS(fused_implicit_slots_kernel, 2, env.n_waves, slots_per_wave(env.n_waves, SlotUse::Implicit), st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
@@ -646,7 +715,7 @@ static hipError_t fused_plain_w(const PointGeom& pg, int W, const SrcRec* tab, E
 hipError_t launch_fused_plain(const PointGeom& pg, int W, const SrcRec* tab, EnvSet env, int K, float dt, ScanArgs sa,
                               float* beta, float* as, float* am, double* xb, hipStream_t st) {
     if (pg.count <= 0) return hipSuccess;
-    if (kFusedPPT == 1 && !xb && env.below && env.read_rest) {
+    if (kFusedPPT == 1 && !xb && env.below && (env.read_rest || env.cand)) {
         const int spw = slots_per_wave(env.n_waves, K <= 16 ? SlotUse::PlainShort : SlotUse::PlainLong);
         switch (W) {
             case 1: LAUNCH_SLOTS(fused_plain_slots_kernel, 1, env.n_waves, spw, st, pg, tab, env, K, dt, sa, beta, as, am); break;

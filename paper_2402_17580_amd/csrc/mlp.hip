@@ -858,7 +858,7 @@ hipError_t launch_surrogate(const MlpState& s, const PointGeom& pg, int W, const
     unsigned* nxt = s.counters + ((li + 1) & 1);
     const int64_t cap = s.rec_cap;
     const MlpNorm& nrm = s.norm;
-    if (env.below && env.read_rest) {
+    if (env.below && (env.read_rest || env.cand)) {
         switch (W) {
             case 1: LAUNCH_SLOTS(fused_surrogate_slots_kernel, 1, env.n_waves, slots_per_wave(env.n_waves, SlotUse::Surrogate), st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
             case 2: LAUNCH_SLOTS(fused_surrogate_slots_kernel, 2, env.n_waves, slots_per_wave(env.n_waves, SlotUse::Surrogate), st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
