@@ -73,21 +73,22 @@ PAPER_CPU = {
 # the figures are reported null.
 FUSED_PROFILE = {
     "file": "profiles/fused_plain_kernel_multilayer_block.txt", "K": 64,
-    "valu_lane_ops_per_update": 10.485, "valu_issue": 0.324, "valu_busy": 0.472,
-    "traffic_bytes_per_launch": (3391.4 * 2.0 + 3477.1) * 1024,
+    "valu_lane_ops_per_update": 10.140, "valu_issue": 0.366, "valu_busy": 0.530,
+    # the slot kernel and the list passes, per launch
+    "traffic_bytes_per_launch": 9272310,
 }
-FUSED_PROFILE_EVERY_T = {"K": 64, "valu_lane_ops_per_update": 129.27, "valu_issue": 0.730, "valu_busy": 0.930}
+FUSED_PROFILE_EVERY_T = {"K": 64, "valu_lane_ops_per_update": 129.27, "valu_issue": 0.727, "valu_busy": 0.926}
 SURROGATE_PROFILE = {"file": "profiles/fused_surrogate_kernels_multilayer_block.txt", "K": 64,
-                     8: {"valu_lane_ops_per_update": 4.680, "valu_issue": 0.164, "valu_busy": 0.255},
-                     16: {"valu_lane_ops_per_update": 3.966, "valu_issue": 0.143, "valu_busy": 0.228}}
+                     8: {"valu_lane_ops_per_update": 4.274, "valu_issue": 0.192, "valu_busy": 0.309},
+                     16: {"valu_lane_ops_per_update": 3.561, "valu_issue": 0.168, "valu_busy": 0.280}}
 C3_PROFILE = {"file": "profiles/fused_plain_kernel_cantilever_islands.txt", "K": K_C3,
-              "valu_lane_ops_per_update": 2.875, "valu_issue": 0.239, "valu_busy": 0.378,
-              "traffic_bytes_per_launch": (7057.9 * 2.0 + 2793.1) * 1024}
+              "valu_lane_ops_per_update": 2.591, "valu_issue": 0.290, "valu_busy": 0.427,
+              "traffic_bytes_per_launch": 10711633}
 C5_PROFILE = {"file": "profiles/fused_kernels_island_block.txt",
-              "plain": {"K": K_FUSED, "valu_lane_ops_per_update": 4.084, "valu_issue": 0.253,
-                        "valu_busy": 0.382, "traffic_bytes_per_launch": (13582.8 * 2.0 + 12467.7) * 1024},
-              "surrogate": {"K": K_SURROGATE, "valu_lane_ops_per_update": 1.130, "valu_issue": 0.204,
-                            "valu_busy": 0.329, "traffic_bytes_per_launch": (13635.7 * 2.0 + 12466.1) * 1024}}
+              "plain": {"K": K_FUSED, "valu_lane_ops_per_update": 3.732, "valu_issue": 0.563,
+                        "valu_busy": 0.774, "traffic_bytes_per_launch": (3986.7 * 2.0 + 7292.2) * 1024},
+              "surrogate": {"K": K_SURROGATE, "valu_lane_ops_per_update": 0.904, "valu_issue": 0.313,
+                            "valu_busy": 0.462, "traffic_bytes_per_launch": (4047.2 * 2.0 + 7292.4) * 1024}}
 
 
 def parse():
@@ -293,9 +294,9 @@ def bench_c2(torch, ms, ctx, args):
     ms_total, wall = timed(ms.MODE_PLAIN, args.K)
     ms_per_step = ms_total / args.steps
     value = updates * args.steps / (ms_total * 1e-3)
-    # average duration of one fused launch over the timed region (the fused
-    # kernels are the only kernels in it besides the still-flag pre-pass, one
-    # per call, and three state resets per step)
+    # average duration of one fused launch over the timed region (with its
+    # list pass; besides them only the still-flag pre-pass, one per call, and
+    # three state resets per step)
     avg_launch_s = ms_total * 1e-3 / (args.steps * launches)
     rate = updates / launches / avg_launch_s  # point-updates/s inside one launch
     result = {
@@ -319,8 +320,8 @@ def bench_c2(torch, ms, ctx, args):
     final = [x.clone() for x in (b, a, m)]
     counts = counted_run(torch, ms, ctx, wl, args.K)
     result["roofline"] = fused_roofline(
-        f"fused_plain_kernel<{wl.scan.window}> (first launch of each call) + "
-        f"fused_plain_slots_kernel<{wl.scan.window}> (the others)", FUSED_PROFILE, args.K, rate, avg_launch_s, counts)
+        f"fused_plain_slots_kernel<{wl.scan.window},128> (list form) + candidates_kernel / first_candidates_kernel",
+        FUSED_PROFILE, args.K, rate, avg_launch_s, counts)
     result["roofline"]["launches_timed"] = args.steps * launches
     result["wave_counts"] = counts
 
@@ -365,7 +366,7 @@ def bench_c2(torch, ms, ctx, args):
                         "passes the indicator, K plain steps otherwise",
                 "indicator": list(sur.indicator),
                 "roofline": None if sp is None else {
-                    "kernel": "fused_surrogate_kernel<2> + fused_surrogate_slots_kernel<2> + surrogate_resume_kernel<2>",
+                    "kernel": "fused_surrogate_slots_kernel<2,128> (list form) + surrogate_resume_kernel<2>",
                     "bound": "alu", "lane_ops_per_update": sp["valu_lane_ops_per_update"],
                     "achieved": sur_rate * sp["valu_lane_ops_per_update"] / 1e12, "peak": VALU_PEAK_TLANEOPS,
                     "unit": "Tlane-op/s", "frac": sur_rate * sp["valu_lane_ops_per_update"] / 1e12 / VALU_PEAK_TLANEOPS,
@@ -419,7 +420,7 @@ def bench_c3(torch, ms, ctx, args):
     out = {"workload": "cantilever_islands", "points": n, "box": [wl.grid.nx, wl.grid.ny, wl.grid.nz],
            "layers": len(wl.layers), "time_steps": wl.n_steps, "active_point_updates": upd, "K": K,
            "seconds": t, "value": upd / t, "unit": "point-updates/s",
-           "roofline": fused_roofline("fused_plain_kernel<2> + fused_plain_slots_kernel<2> (index list)",
+           "roofline": fused_roofline("fused_plain_slots_kernel<2,256> (list form, index list) + list passes",
                                       C3_PROFILE, K, upd / launches / avg, avg, counts),
            "wave_counts": counts}
     print(f"c3: {t:.2f} s", file=sys.stderr, flush=True)
