@@ -267,7 +267,7 @@ int mstruct_fused_scan_steps_noalloc(mstruct_ctx *ctx, const mstruct_scan *scan,
                                      double t0, double dt, int64_t n_steps, int K, int mode,
                                      const mstruct_phases *ph, void *stream);
 
-/* Context options (value 0 or 1).
+/* Context options (value 0 or 1 unless stated).
  * MSTRUCT_OPTION_SKIP_COLD_WAVES (default 1): before each launch of fused
  * PLAIN or IMPLICIT mode the host lists every track that occupies a window
  * slot at any of the launch's time points, with its positions at the first
@@ -279,14 +279,36 @@ int mstruct_fused_scan_steps_noalloc(mstruct_ctx *ctx, const mstruct_scan *scan,
  * term of every track by the drop test of the temperature model (a term
  * provably below 1e-4 K is dropped) has T = T0 throughout and skips the
  * evaluation of the sources.  Without xbt, each call also bounds the box
- * of every 64 consecutive points (of the box, or of the index list) against
+ * of every wave of 64 points (of the box, see MSTRUCT_OPTION_TILE_WAVES, or
+ * 64 consecutive points of the index list) against
  * every launch's tracks in a pre-pass, and the context remembers which such
  * waves were at rest: from the second launch of a call such a wave reads
  * neither its state nor a track.  For this the context keeps 2 n/64 bytes
  * (and 24 (n/64 + n/4096) bytes of boxes with an index list) plus at most
  * 64 MiB of still flags per call on the device, until mstruct_destroy.  The results are the same bit for bit as with 0, which
  * evaluates every temperature and takes every step (for comparison). */
-enum { MSTRUCT_OPTION_SKIP_COLD_WAVES = 1, MSTRUCT_OPTION_COUNT_WAVES = 2 };
+enum {
+    MSTRUCT_OPTION_SKIP_COLD_WAVES = 1,
+    MSTRUCT_OPTION_COUNT_WAVES = 2,
+    MSTRUCT_OPTION_TILE_WAVES = 3,
+    MSTRUCT_OPTION_WAVE_TILE_WIDTH = 4
+};
+/* MSTRUCT_OPTION_TILE_WAVES (default 1): on a box grid (no index list) the
+ * fused kernels may group the points of each plane into waves of a x b = 64
+ * points (a along x, a power of two) instead of 64 consecutive points of a
+ * row (the "waves" of the option above and of mstruct_wave_counts).  Each
+ * call keeps the row order when the tracks on during the call, weighted by
+ * their time on, run along x (sum of |uy| at most a tenth of the sum of
+ * |ux|) or no track is on, and otherwise takes 8 x 8 tiles (or the nearest
+ * of 16 x 4, 4 x 16, 32 x 2, 2 x 32 that divides nx and ny): near the
+ * tracks the waves that step then cover fewer points that need not step.
+ * With 0, always the row order.  The arrays keep the box order.  PLAIN and IMPLICIT results are
+ * the same bit for bit for every shape; in SURROGATE mode, where a wave
+ * takes the network only if all its points pass the error indicator, the
+ * shape decides where the network acts (both within the surrogate's error).
+ * MSTRUCT_OPTION_WAVE_TILE_WIDTH (default 0: chosen per call as above): a
+ * power of two a in 1..64 forces tiles of a x (64 / a) points where they
+ * divide nx and ny (else the row order); other values MSTRUCT_EINVAL. */
 /* MSTRUCT_OPTION_COUNT_WAVES (default 0): fused PLAIN and IMPLICIT launches
  * count, per wave of 64 points, what they read and write, into counters of
  * the context read by mstruct_wave_counts (one atomic per wave and class;

@@ -24,6 +24,8 @@ MODE_SURROGATE = 1
 MODE_IMPLICIT = 2
 OPTION_SKIP_COLD_WAVES = 1
 OPTION_COUNT_WAVES = 2
+OPTION_TILE_WAVES = 3
+OPTION_WAVE_TILE_WIDTH = 4
 WAVE_COUNT_NAMES = ("points_loaded", "points_stored", "still_waves", "cold_waves", "hot_waves", "flagged_waves",
                     "hot_subblocks", "indicator_subblocks")
 F64_LIBRARY = 0

@@ -26,6 +26,30 @@ __device__ __forceinline__ void decode_point(const PointGeom& pg, int64_t local,
     gi = rem - gj * pg.nx;
 }
 
+// The point at position g (0 <= g < count) of a call's wave order (wave w:
+// positions 64 w .. 64 w + 63): its array index, and its grid coordinates.
+// On an index list, and on a box grid without tiles, the order is that of
+// the arrays.  On a tiled box grid (tiles of a = 2^tw_log by b = 64 / a
+// points), position q = first + g lies on plane q / (nx ny), and the
+// positions of a plane run through its tiles row by row, 64 per tile, lane
+// l of a tile at (a tx + l % a, b ty + l / a): the waves along a track then
+// cover fewer points that need not step than parts of rows would when the
+// track does not run along x.
+__device__ __forceinline__ int64_t point_at(const PointGeom& pg, int64_t g, int& gi, int& gj, int& gk) {
+    const int64_t q = pg.first + g;
+    if (!pg.tiled) {
+        decode_point(pg, q, gi, gj, gk);
+        return q;
+    }
+    const int lin = (int)q;
+    gk = divide_by(lin, pg.mag_nxy, pg.sh_nxy);
+    const int r = lin - gk * pg.nxy, t = r >> 6, l = r & 63;
+    const int ty = divide_by(t, pg.mag_tr, pg.sh_tr);
+    gi = ((t - ty * pg.tr) << pg.tw_log) + (l & ((1 << pg.tw_log) - 1));
+    gj = (ty << (6 - pg.tw_log)) + (l >> pg.tw_log);
+    return (int64_t)gk * pg.nxy + (int64_t)gj * pg.nx + gi;
+}
+
 // squared distance [grid units^2] within which the envelope tests certify
 // nothing: one grid unit, and at least the clamp radius and the offset
 // radius of source_rise
@@ -63,12 +87,9 @@ __device__ __forceinline__ int64_t fused_wave() {
 // alone (on a box grid every point of a call is active).
 __device__ __forceinline__ void still_wave_beta(const PointGeom& pg, float T0c, float* beta, int64_t g) {
     if (!beta || g >= pg.count) return;
-    const int64_t local = pg.first + g;
-    if (pg.index) {
-        int gi, gj, gk;
-        decode_point(pg, local, gi, gj, gk);
-        if (gk < pg.k0) return;
-    }
+    int gi, gj, gk;
+    const int64_t local = point_at(pg, g, gi, gj, gk);
+    if (pg.index && gk < pg.k0) return;
     beta[local] = solid_fraction(T0c) - kXmax - 0.0f;
 }
 

@@ -18,6 +18,12 @@ struct PointGeom {
     uint32_t mag_nx, mag_nxy;
     int32_t sh_nx, sh_nxy;
     int32_t k0;            // points on planes k < k0 are inactive
+    // tiled != 0 (box grid only): the waves of the fused kernels take tiles of
+    // 2^tw_log x 2^(6 - tw_log) points of a plane (see point_at); tr tiles
+    // per row, divided by with (mag_tr, sh_tr)
+    int32_t tiled, tw_log, tr;
+    uint32_t mag_tr;
+    int32_t sh_tr;
     float r2min;           // squared clamp radius around a switched-on source [grid units^2]
     float roff;            // radius around a switched-off track's virtual position [grid units]
 };

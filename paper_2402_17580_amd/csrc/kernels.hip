@@ -181,14 +181,17 @@ __global__ __launch_bounds__(kBlock) void temperature_kernel(PointGeom pg, const
     T[local] = (gk < pg.k0) ? sa.T0 : scan_temperature<W>(rec, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
 }
 
-// the box of grid positions holding the points g0 .. g1 of pg (a box grid):
-// part of one row, or whole rows of one plane, or whole planes
+// the box of grid positions holding the points g0 .. g1 of pg's wave order
+// (a box grid): part of one row, or whole rows of one plane, or whole
+// planes; on a tiled grid (g0 and g1 + 1 multiples of 64) part of one row of
+// tiles, from the first tile's first point to the last tile's last, or whole
+// rows of tiles of one plane, or whole planes
 __device__ __forceinline__ GridBox range_box(const PointGeom& pg, int64_t g0, int64_t g1) {
     int i0, j0, k0, i1, j1, k1;
-    decode_point(pg, pg.first + g0, i0, j0, k0);
-    decode_point(pg, pg.first + g1, i1, j1, k1);
+    point_at(pg, g0, i0, j0, k0);
+    point_at(pg, g1, i1, j1, k1);
     GridBox b;
-    const bool row = k0 == k1 && j0 == j1;
+    const bool row = k0 == k1 && (pg.tiled ? (j0 >> (6 - pg.tw_log)) == (j1 >> (6 - pg.tw_log)) : j0 == j1);
     b.xl = row ? (float)i0 : 0.0f;
     b.xh = row ? (float)i1 : (float)(pg.nx - 1);
     b.yl = k0 == k1 ? (float)j0 : 0.0f;
@@ -289,7 +292,7 @@ __global__ __launch_bounds__(kBlock) void wave_boxes_kernel(PointGeom pg, int64_
     int i0 = INT32_MAX, i1 = INT32_MIN, j0 = INT32_MAX, j1 = INT32_MIN, k0 = INT32_MAX, k1 = INT32_MIN;
     if (g < pg.count) {
         int gi, gj, gk;
-        decode_point(pg, pg.first + g, gi, gj, gk);
+        point_at(pg, g, gi, gj, gk);
         i0 = i1 = gi;
         j0 = j1 = gj;
         k0 = k1 = gk;
@@ -343,8 +346,7 @@ __device__ __forceinline__ void fused_plain_body(const PointGeom& pg, const SrcR
     for (int u = 0; u < PPT; ++u) {
         const int64_t g = g0 + u * kFusedBlock;
         act[u] = g < pg.count;
-        local[u] = pg.first + (act[u] ? g : 0);
-        decode_point(pg, local[u], gi[u], gj[u], gk[u]);
+        local[u] = point_at(pg, act[u] ? g : 0, gi[u], gj[u], gk[u]);
         act[u] = act[u] && gk[u] >= pg.k0;
         a[u] = act[u] ? as[local[u]] : 0.0f;
         m[u] = act[u] ? am[local[u]] : 0.0f;
@@ -501,9 +503,8 @@ __global__ __launch_bounds__(kListBlock) void first_candidates_kernel(PointGeom 
     if (in) {
         const int64_t g = w * kWave + lane;
         bool act = g < pg.count;
-        const int64_t local = pg.first + (act ? g : 0);
         int gi, gj, gk;
-        decode_point(pg, local, gi, gj, gk);
+        const int64_t local = point_at(pg, act ? g : 0, gi, gj, gk);
         act = act && gk >= pg.k0;
         const float a = act ? as[local] : 0.0f, m = act ? am[local] : 0.0f;
         still = env.below[w] && wave_may_rest(env, act, a, m, T0c);
@@ -571,9 +572,8 @@ __device__ __forceinline__ void fused_implicit_body(const PointGeom& pg, const S
                                                     int64_t wv) {
     const float T0c = fminf(sa.T0, sa.Tclamp);
     bool act = g < pg.count;
-    const int64_t local = pg.first + (act ? g : 0);
     int gi, gj, gk;
-    decode_point(pg, local, gi, gj, gk);
+    const int64_t local = point_at(pg, act ? g : 0, gi, gj, gk);
     act = act && gk >= pg.k0;
     float a = act ? as[local] : 0.0f, m = act ? am[local] : 0.0f, b = 0.0f, alo = 0.0f, mlo = 0.0f;
     double xb = (TRACK && act) ? track_check(xbv[local], a, m) : track_none();

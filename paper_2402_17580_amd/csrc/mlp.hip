@@ -712,9 +712,8 @@ __device__ __forceinline__ void surrogate_fused_body(const PointGeom& pg, const 
                                                      int64_t cap, int64_t g, int64_t wv) {
     const float T0c = fminf(sa.T0, sa.Tclamp);
     bool act = g < pg.count;
-    const int64_t local = pg.first + (act ? g : 0);
     int gi, gj, gk;
-    decode_point(pg, local, gi, gj, gk);
+    const int64_t local = point_at(pg, act ? g : 0, gi, gj, gk);
     act = act && gk >= pg.k0;
     float a = act ? as[local] : 0.0f, m = act ? am[local] : 0.0f, alo = 0.0f, mlo = 0.0f;
     // still and cold waves as in the plain fused kernel
@@ -811,9 +810,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void s
         const SurrogateRecord& r = recs[q];
         const int64_t wv = r.wave, g = wv * kWave + lane;
         bool act = g < pg.count;
-        const int64_t local = pg.first + (act ? g : 0);
         int gi, gj, gk;
-        decode_point(pg, local, gi, gj, gk);
+        const int64_t local = point_at(pg, act ? g : 0, gi, gj, gk);
         act = act && gk >= pg.k0;
         float a = r.a[lane], m = r.m[lane], alo = r.alo[lane], mlo = r.mlo[lane], Tn = r.Tn[lane];
         surrogate_blocks<W, kNetRun>(pg, tab, Kl, Ks, dt, sa, nrm, &L, act, r.cold != 0, gi, gj, gk, r.block, a, m, alo,

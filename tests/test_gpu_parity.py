@@ -390,6 +390,72 @@ def test_cold_waves_skip_is_bit_exact(torch, ctx, mode):
         ctx.set_option(ms.OPTION_SKIP_COLD_WAVES, 1)
 
 
+@pytest.mark.parametrize("mode", ["plain", "implicit", "surrogate"])
+def test_tiled_waves_are_bit_exact(torch, ctx, orc, mode):
+    """MSTRUCT_OPTION_TILE_WAVES only regroups the points of a box grid into
+    waves (a x b patches of a plane instead of 64 consecutive points), which
+    changes which waves the launch certificates and the wave flags skip but
+    not what any point computes.  Fused PLAIN and IMPLICIT runs give the same
+    bits as the row order for every forced tile width that divides the
+    planes (rows of 64, 48 and 96 points: a group of 64 waves spans one,
+    several or part of a row of tiles, or two planes) and for the shape
+    chosen per call (on the island scan, rotated per layer, it tiles).  In
+    SURROGATE mode a wave takes the network only if all its points pass the
+    indicator, so the grouping decides where the network acts: the groupings
+    stay within the surrogate's 1e-3 bar of the oracle (sampled on the first
+    case) and of each other."""
+    import paper_2402_17580_amd as ms
+    m = {"plain": ms.MODE_PLAIN, "implicit": ms.MODE_IMPLICIT, "surrogate": ms.MODE_SURROGATE}[mode]
+    K = 16
+    if mode == "surrogate":
+        from paper_2402_17580_amd import surrogate as S
+        sur = S.Surrogate.load(S.DEFAULT_WEIGHTS)
+        sur.load_into(ctx)
+        K = sur.K
+    cases = [(name, wl) for name, wl in _cold_cases() if wl.grid.nx % 8 == 0 and wl.grid.ny % 8 == 0]
+    assert len(cases) >= 5
+    widths = {"plain": (0, 1, 2, 4, 8, 16, 32), "implicit": (0, 1, 8), "surrogate": (0, 8)}[mode]
+    try:
+        for name, wl in cases:
+            if mode == "plain" and name not in ("block_w4", "islands", "warm_934"):
+                continue
+            ctx.set_option(ms.OPTION_TILE_WAVES, 0)
+            g = [torch.from_numpy(x).cuda() for x in workload.initial_state(wl.grid.n, np.float32)]
+            ms.run_layers(ctx, wl, *g, K=K, mode=m)
+            ref = [x.cpu().numpy() for x in g]
+            assert np.any(ref[1] != np.float32(0.9)), name
+            ctx.set_option(ms.OPTION_TILE_WAVES, 1)
+            outs = [ref]
+            for width in widths:
+                ctx.set_option(ms.OPTION_WAVE_TILE_WIDTH, width)
+                g = [torch.from_numpy(x).cuda() for x in workload.initial_state(wl.grid.n, np.float32)]
+                ms.run_layers(ctx, wl, *g, K=K, mode=m)
+                out = [x.cpu().numpy() for x in g]
+                outs.append(out)
+                for x, y in zip(out, ref):
+                    if mode == "surrogate":
+                        assert float(np.abs(x.astype(np.float64) - y).max()) <= 1e-3, (name, width)
+                    else:
+                        assert np.array_equal(x.view(np.uint32), y.view(np.uint32)), (name, mode, width)
+            if mode == "surrogate" and name == cases[0][0]:
+                idx = np.random.default_rng(11).choice(wl.grid.n, 3000, replace=False)
+                st = orc.run_workload(wl, idx)
+                for out in outs:
+                    for x, o in zip(out, (st.beta, st.alpha_s, st.alpha_m)):
+                        assert float(np.abs(x[idx].astype(np.float64) - o).max()) <= 1e-3, name
+    finally:
+        ctx.set_option(ms.OPTION_TILE_WAVES, 1)
+        ctx.set_option(ms.OPTION_WAVE_TILE_WIDTH, 0)
+
+
+def test_wave_tile_width_option_is_checked(ctx):
+    import paper_2402_17580_amd as ms
+    for bad in (-1, 3, 65, 128):
+        with pytest.raises(RuntimeError):
+            ctx.set_option(ms.OPTION_WAVE_TILE_WIDTH, bad)
+    ctx.set_option(ms.OPTION_WAVE_TILE_WIDTH, 0)
+
+
 def test_tracks_switching_within_a_step(torch, ctx, orc):
     """A window of 4 tracks, each switched on for 0.1 us, ten per step of
     1 us (3 kW, so that the 0.4 us the window spans melts points next to the
