@@ -87,8 +87,13 @@ typedef struct {
 
 /* Material points on a regular box grid: point (i, j, k) sits at
  * (ox + i h, oy + j h, oz - k h) with box linear index i + nx (j + ny k).
- * `index` (device int32, n sorted box linear indices, each in [0, nx*ny*nz);
- * not checked on the device) selects a masked subset;
+ * `index` (device int32, n distinct box linear indices, each in
+ * [0, nx*ny*nz), in any order; not checked on the device) selects a masked
+ * subset.  The fused kernels take 64 consecutive entries per wave, so an
+ * order that keeps each 64 close together in a plane lets more waves skip
+ * launches (see MSTRUCT_OPTION_SKIP_COLD_WAVES): e.g. each plane's points
+ * through its 8 x 8 tiles, row by row (a sorted list gives parts of rows,
+ * which only suit tracks along x);
  * NULL means all nx*ny*nz box points in linear order (then n must equal
  * nx*ny*nz).  Points with z > z_top + 1e-3 h are inactive: the fused call
  * leaves them untouched (material not yet deposited). */

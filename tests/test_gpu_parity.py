@@ -448,6 +448,36 @@ def test_tiled_waves_are_bit_exact(torch, ctx, orc, mode):
         ctx.set_option(ms.OPTION_WAVE_TILE_WIDTH, 0)
 
 
+@pytest.mark.parametrize("mode", ["plain", "implicit"])
+def test_index_list_order_is_free(torch, ctx, mode):
+    """An index list may come in any order: the fused kernels group 64
+    consecutive entries into a wave, which decides only which waves the
+    launch certificates skip.  The masked island case with its sorted list,
+    the same points in 8 x 8 tile order and in a seeded random order (waves
+    of scattered points, whose boxes span the body) gives every point the
+    same bits."""
+    import paper_2402_17580_amd as ms
+    m = {"plain": ms.MODE_PLAIN, "implicit": ms.MODE_IMPLICIT}[mode]
+    wl0 = workload.island_scan(96, 64, 24, n_layers=3, layer_thick=20e-6, steps_per_layer=300, dt=2e-6,
+                               seed=77, island=0.5e-3)
+    idx = workload.cantilever_mask(96, 64, 24, seed=77, top=6, base=6, leg_frac=0.1)
+    orders = {"sorted": idx, "tiles": workload.tile_order(idx, 96, 64),
+              "random": idx[np.random.default_rng(5).permutation(idx.size)]}
+    assert not np.array_equal(orders["tiles"], idx)
+    outs = {}
+    for name, order in orders.items():
+        wl = workload.Workload("masked", workload.Grid(96, 64, 24, 10e-6, index=order), wl0.scan, wl0.layers,
+                               wl0.dt, wl0.seed)
+        g = [torch.from_numpy(x).cuda() for x in workload.initial_state(wl.grid.n, np.float32)]
+        ms.run_layers(ctx, wl, *g, K=16, mode=m, index=torch.from_numpy(order).cuda())
+        back = np.argsort(order, kind="stable")  # sorted position -> position in this order
+        outs[name] = [x.cpu().numpy()[back] for x in g]
+    for name in ("tiles", "random"):
+        for x, y in zip(outs[name], outs["sorted"]):
+            assert np.array_equal(x.view(np.uint32), y.view(np.uint32)), (name, mode)
+    assert np.any(outs["sorted"][1] != np.float32(0.9))
+
+
 def test_wave_tile_width_option_is_checked(ctx):
     import paper_2402_17580_amd as ms
     for bad in (-1, 3, 65, 128):

@@ -73,7 +73,7 @@ class Grid:
     ox: float = 0.0
     oy: float = 0.0
     oz: float = 0.0
-    index: Optional[np.ndarray] = None  # int32 box linear indices (sorted), or None = full box
+    index: Optional[np.ndarray] = None  # int32 distinct box linear indices, or None = full box
 
     @property
     def n_box(self) -> int:
@@ -151,13 +151,6 @@ class Workload:
             return (g.nz - k0) * g.nx * g.ny
         return int(np.count_nonzero(g.index >= k0 * g.nx * g.ny))
 
-    def active_offset(self, z_top: float) -> int:
-        """First local point number that is active (active points are a suffix)."""
-        g = self.grid
-        k0 = g.first_active_k(z_top)
-        if g.index is None:
-            return k0 * g.nx * g.ny
-        return int(np.searchsorted(g.index, k0 * g.nx * g.ny))
 
 
 def initial_state(n: int, dtype=np.float64):
@@ -404,10 +397,27 @@ def cantilever_mask(nx, ny, nz, seed, top=32, base=24, leg_frac=0.08):
     return idx.astype(np.int32)
 
 
+def tile_order(index: np.ndarray, nx: int, ny: int, a: int = 8) -> np.ndarray:
+    """The same box indices, each plane's points through its a x a tiles row
+    by row (within a tile row by row): 64 consecutive entries of a full
+    plane are then one 8 x 8 patch instead of part of a row."""
+    lin = index.astype(np.int64)
+    plane = nx * ny
+    k, r = lin // plane, lin % plane
+    j, i = r // nx, r % nx
+    tx, ty = (nx + a - 1) // a, (ny + a - 1) // a
+    key = ((k * ty + j // a) * tx + i // a) * (a * a) + (j % a) * a + i % a
+    return index[np.argsort(key, kind="stable")]
+
+
 def cantilever_islands(nx=1024, ny=512, nz=128, n_layers=10, steps_per_layer=5000,
-                       dt=2e-6, seed=1003) -> Workload:
-    """Masked cantilever-like body (about 32M points) with 5x5 mm island scan."""
+                       dt=2e-6, seed=1003, order="tiles") -> Workload:
+    """Masked cantilever-like body (about 32M points) with 5x5 mm island scan;
+    the point list in 8 x 8 tile order per plane (order="tiles") or sorted
+    ("sorted")."""
     idx = cantilever_mask(nx, ny, nz, seed)
+    if order == "tiles":
+        idx = tile_order(idx, nx, ny)
     return island_scan(nx, ny, nz, n_layers, 30e-6, steps_per_layer, dt, seed,
                        index=idx, name="cantilever_islands")
 
