@@ -75,6 +75,24 @@ __device__ __forceinline__ bool wave_box_below(const EnvSet& env, int64_t wv) {
     return env.below && wv < env.n_waves && env.below[wv];
 }
 
+// A cold wave (T = T0 at every step) whose first explicit step of a launch
+// left a point's fractions x0 (alpha_s, alpha_m) with the same bits, with lo
+// the compensated low part after that step (its increment, or 0 where the
+// correction reset it).  Every later step then starts from the same high
+// parts at the same temperature, takes the same increments and gives the
+// correction the same input: a low part that stays below a quarter of the
+// float spacing around x0 keeps x0 + lo rounding to x0 at every step and at
+// the end.  K |lo| <= 2^(e - 27) for x0 = f 2^e, f in [0.5, 1), is half of
+// that (covering the rounding of the K additions); x0 = 0 needs lo = 0 and
+// x0 = +0.0, so that the final x0 + lo has the bits of x0.  Then the K steps
+// leave the stored fractions as they are, bit for bit (frozen): at the
+// 300 K of material far from the tracks the rates are of order 1e-9 / s.
+__device__ __forceinline__ bool frozen_part(float x0, float x1, float lo, int K) {
+    if (__float_as_uint(x1) != __float_as_uint(x0)) return false;
+    if (x0 == 0.0f) return lo == 0.0f && __float_as_uint(x0) == 0u;
+    return lo == 0.0f || (float)K * fabsf(lo) <= ldexpf(1.0f, __builtin_amdgcn_frexp_expf(x0) - 27);
+}
+
 // wave index of the calling lane in a fused launch (uniform across the wave)
 __device__ __forceinline__ int64_t fused_wave() {
     return (int64_t)blockIdx.x * (kFusedBlock / kWave) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));

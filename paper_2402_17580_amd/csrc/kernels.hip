@@ -376,8 +376,14 @@ __device__ __forceinline__ void fused_plain_body(const PointGeom& pg, const SrcR
         if (TRACK && still[u]) xb[u] = track_none();
         if (env.stats) count_wave(env, act[u], still[u], cold[u]);
     }
+    // the waves that evaluate the temperature run the longest chains: they
+    // issue first, and the other waves of their SIMD fill the gaps
+    if (PPT == 1 && !still[0] && !cold[0]) __builtin_amdgcn_s_setprio(3);
     float Tblk[PPT];  // temperature at the start of the sub-block (wave counts only)
-    for (int s = 0; s < K; ++s) {
+    // a cold wave whose first step changed nothing it stores stops there (see frozen_part)
+    const float a0 = a[0], m0 = m[0];
+    bool frozen = false;
+    for (int s = 0; s < K && !frozen; ++s) {
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
             if (still[u]) continue;
@@ -398,13 +404,15 @@ __device__ __forceinline__ void fused_plain_body(const PointGeom& pg, const SrcR
             Tn[u] = Tn1;
             xeq_n[u] = xeq_n1;
         }
+        if (PPT == 1 && !TRACK && s == 0 && cold[0] && !still[0])
+            frozen = __ballot(act[0] && !(frozen_part(a0, a[0], alo[0], K) && frozen_part(m0, m[0], mlo[0], K))) == 0;
     }
 #pragma unroll
     for (int u = 0; u < PPT; ++u) {
         if (!act[u]) continue;
-        const float af = a[u] + alo[u], mf = m[u] + mlo[u];
-        // a still wave's fractions are those in memory
-        if (!still[u]) {
+        const float af = frozen ? a0 : a[u] + alo[u], mf = frozen ? m0 : m[u] + mlo[u];
+        // a still or frozen wave's fractions are those in memory
+        if (!still[u] && !frozen) {
             as[local[u]] = af;
             am[local[u]] = mf;
         }
@@ -412,6 +420,7 @@ __device__ __forceinline__ void fused_plain_body(const PointGeom& pg, const SrcR
         if (beta) beta[local[u]] = solid_fraction(Tc[u]) - af - mf;
     }
     if (PPT == 1 && !TRACK) record_rest(env, wv, act[0], a[0] + alo[0], m[0] + mlo[0]);
+    if (PPT == 1) __builtin_amdgcn_s_setprio(0);  // for the next wave of a slot kernel's grid wave
 }
 
 // PPT points per lane, kFusedBlock apart (coalesced), advanced together for ILP
@@ -589,24 +598,37 @@ __device__ __forceinline__ void fused_implicit_body(const PointGeom& pg, const S
     still = still || (cold && T0c < Const<float>::TasEnd && __ballot(act && !rest_bits(a, m)) == 0);
     if (TRACK && still) xb = track_none();
     if (env.stats) count_wave(env, act, still, cold);
-    for (int s = 0; s < K && !still; ++s) {
+    if (!still && !cold) __builtin_amdgcn_s_setprio(3);  // as in fused_plain_body
+    // a cold wave whose first step changed nothing it stores stops there (see
+    // frozen_part): with the high parts unchanged after every substep, each
+    // substep's iteration starts from the same state, converges at its first
+    // iterate with a zero residual and adds the same increments to the low
+    // parts; a first step with an unconverged substep does not stop, so that
+    // the count stays exact
+    const float a0 = a, m0 = m;
+    bool frozen = false;
+    for (int s = 0; s < K && !still && !frozen; ++s) {
         const float Tn1 =
             cold ? T0c : scan_temperature<W>(tab + (s + 1) * W, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
         float Ta = Tn;
+        bool same = true;
         for (int k = 0; k < n_sub; ++k) {
             const float Tb = (k + 1 == n_sub) ? Tn1 : fmaf(Tn1 - Tn, (float)(k + 1) * inv, Tn);
             const int it = TRACK ? implicit_step_tracked<true>(a, m, alo, mlo, xb, b, Ta, Tb, h, max_iter,
                                                                sa.rd.mart_assign)
                                  : implicit_step<true>(a, m, alo, mlo, b, Ta, Tb, h, max_iter, sa.rd.mart_assign);
             if (it < 0) ++bad;
+            same = same && __float_as_uint(a) == __float_as_uint(a0) && __float_as_uint(m) == __float_as_uint(m0);
             Ta = Tb;
         }
         Tn = Tn1;
+        if (!TRACK && s == 0 && cold)
+            frozen = __ballot(act && !(same && bad == 0 && frozen_part(a0, a, alo, K) && frozen_part(m0, m, mlo, K))) == 0;
     }
     if (act) {
-        a += alo;
-        m += mlo;
-        if (!still) {  // a still wave's fractions are those in memory
+        a = frozen ? a0 : a + alo;
+        m = frozen ? m0 : m + mlo;
+        if (!still && !frozen) {  // a still or frozen wave's fractions are those in memory
             as[local] = a;
             am[local] = m;
         }
@@ -618,6 +640,7 @@ __device__ __forceinline__ void fused_implicit_body(const PointGeom& pg, const S
     int total = bad;
     for (int o = 32; o > 0; o >>= 1) total += __shfl_xor(total, o);
     if ((threadIdx.x & 63) == 0 && total) atomicAdd(unconverged, (unsigned long long)total);
+    __builtin_amdgcn_s_setprio(0);
 }
 
 template <int W, bool TRACK>

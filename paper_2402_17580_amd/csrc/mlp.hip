@@ -730,8 +730,10 @@ __device__ __forceinline__ void surrogate_fused_body(const PointGeom& pg, const 
         record_rest(env, wv, act, a, m);
         return;
     }
+    if (!cold) __builtin_amdgcn_s_setprio(3);  // as in fused_plain_body
     const int j = surrogate_blocks<W, kNetStop>(pg, tab, Kl, Ks, dt, sa, nrm, nullptr, act, cold, gi, gj, gk, 0, a, m,
                                                 alo, mlo, Tn);
+    __builtin_amdgcn_s_setprio(0);
     if (j >= 0) {
         unsigned slot = 0;
         if ((threadIdx.x & (kWave - 1)) == 0) slot = atomicAdd(n_recs, 1u);
