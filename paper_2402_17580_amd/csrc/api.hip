@@ -621,14 +621,11 @@ struct FusedBufs {
 
 size_t round256(size_t n) { return (n + 255) & ~(size_t)255; }
 
-// bytes of a launch's wave list and its two counts (0: the waves cannot be
-// numbered in 32 bits, and the slot kernels read the flags themselves)
-size_t list_bytes(int64_t n_waves) {
-    return n_waves <= (int64_t)UINT32_MAX ? round256((size_t)n_waves * sizeof(uint32_t)) + 256 : 0;
-}
+// bytes of a launch's wave list and its two counts (a call has fewer than
+// 2^31 points, so its waves are numbered in 32 bits)
+size_t list_bytes(int64_t n_waves) { return round256((size_t)n_waves * sizeof(uint32_t)) + 256; }
 
 void place_list(FusedBufs& b, uint8_t* at, int64_t n_waves) {
-    if (!list_bytes(n_waves)) return;
     b.cand = reinterpret_cast<uint32_t*>(at);
     b.cand_counts = reinterpret_cast<unsigned*>(at + round256((size_t)n_waves * sizeof(uint32_t)));
 }
@@ -688,10 +685,26 @@ int fused_run(mstruct_ctx* ctx, const mstruct_scan* scan, const mstruct_points* 
         hipError_t e = surrogate_prepare(ctx->mlp, n_waves, st);
         if (e != hipSuccess) return hip_fail(ctx, e, "surrogate records");
     }
-#ifndef CAND_LIST
-#define CAND_LIST 1
-#endif
-    const bool list = CAND_LIST && wave_flags && b.cand;
+    if (mode == MSTRUCT_MODE_PLAIN && wave_flags && b.cand) {
+        // each chunk of launches in one persistent kernel (fused_plain_call_kernel)
+        for (int64_t l0 = 0; l0 < n_launches; l0 += chunk) {
+            const int64_t nl = (n_launches - l0) < chunk ? (n_launches - l0) : chunk;
+            const GridBox* boxes = pts->index ? b.boxes : nullptr;
+            hipError_t e = hipSuccess;
+            if (l0 == 0 && boxes) e = launch_wave_boxes(pg, n_waves, b.boxes, st);
+            if (e == hipSuccess)
+                e = launch_still_flags(pg, env_dev, fc_dev, l0, nl, n_waves, fminf(sa.T0, sa.Tclamp), boxes,
+                                       b.flags + n_waves, st);
+            if (e == hipSuccess)
+                e = launch_fused_plain_call(pg, W, b.dev, env_dev, fc_dev, b.flags + n_waves, b.flags, n_waves, l0,
+                                            nl, K, n_steps, (float)dt, sa, l0 + nl == n_launches ? ph->beta : nullptr,
+                                            ph->alpha_s, ph->alpha_m, b.cand, b.cand_counts,
+                                            ctx->count_waves ? ctx->stats : nullptr, st);
+            if (e != hipSuccess) return hip_fail(ctx, e, "fused call launch");
+        }
+        return MSTRUCT_OK;
+    }
+    const bool list = wave_flags && b.cand;
     if (list) {
         hipError_t e = launch_clear_counts(b.cand_counts, st);
         if (e != hipSuccess) return hip_fail(ctx, e, "wave list counts");

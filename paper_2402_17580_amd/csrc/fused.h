@@ -8,12 +8,9 @@ namespace mstruct {
 
 // workgroup of the fused grid kernels (one wave per 64 points)
 constexpr int kFusedBlock = 256;
-// wave slots per wave of the persistent fused kernels (see fused_slots),
-// and the launch size (in waves) from which they run in workgroups of four
-// waves instead of two: on large, mostly still grids the occupancy of four
-// pays (island block, 1M waves: 2.2 s against 2.7 s), on smaller ones two
-// spread the waves that step over more CUs (block scan, 131k waves: 9 %
-// faster)
+// waves of points per grid wave of the slot kernels (see fused_slots and
+// slots_per_wave), and the launch size (in waves of points) from which their
+// workgroups hold four waves instead of two
 constexpr int kSlotsPerWave = 4;
 constexpr int64_t kSlotsLargeGrid = (int64_t)1 << 18;
 
@@ -111,14 +108,17 @@ __device__ __forceinline__ void still_wave_beta(const PointGeom& pg, float T0c, 
     beta[local] = solid_fraction(T0c) - kXmax - 0.0f;
 }
 
-// The list form of a slot launch: the waves of the launch that are not
-// still by their flags, listed by candidates_kernel (which also wrote beta
-// for the still ones); wave p of the grid takes the entries p, p + P, ...
-// (P waves in the grid).  Consecutive entries, which are neighbouring waves
-// of points, go to consecutive waves of the grid and so to different CUs,
-// and every wave that steps is launched at the start of the kernel.
+// A slot launch: the waves of the launch that are not still by their flags,
+// listed by candidates_kernel or first_candidates_kernel (which also wrote
+// beta for the still ones) in env.cand[0 .. *env.cand_n), taken by a grid of
+// about one wave per slots_per_wave waves of points: wave p of the grid takes
+// the entries p, p + P, ... (P waves in the grid) and runs body(w) for each
+// (all 64 lanes, one point each).  Consecutive entries, which are
+// neighbouring waves of points, go to consecutive waves of the grid and so to
+// different CUs, and every wave that steps starts with the kernel.  The
+// launch clears *env.cand_next, the next launch's count.
 template <int BS, class Body>
-__device__ __forceinline__ void fused_list(const EnvSet& env, Body body) {
+__device__ __forceinline__ void fused_slots(const EnvSet& env, Body body) {
     if (blockIdx.x == 0 && threadIdx.x == 0) *env.cand_next = 0u;
     const int64_t n = *env.cand_n;
     const int64_t P = (int64_t)gridDim.x * (BS / kWave);
@@ -126,58 +126,22 @@ __device__ __forceinline__ void fused_list(const EnvSet& env, Body body) {
     for (int64_t e = p; e < n; e += P) body((int64_t)__builtin_amdgcn_readfirstlane((int)env.cand[e]));
 }
 
-// The persistent form of a fused launch, used from the second launch of a
-// call when the wave flags are kept: a grid of about one wave per
-// slots_per_wave waves of the launch, in which wave p takes the wave slots p,
-// p + P, p + 2P, ... (P waves in the grid).  Each lane loads the flags of
-// one slot; the wave then runs body(w) for every slot w that is not still
-// (all 64 lanes, one point each) and writes beta for the still ones.  No
-// wave is launched only to find its flags set, and the interleaved slots
-// spread the few waves that step evenly over the grid.  With a list of the
-// waves that step (EnvSet::cand), the launch takes its list form instead.
-template <int BS, class Body>
-__device__ __forceinline__ void fused_slots(const PointGeom& pg, const EnvSet& env, float T0c, float* beta,
-                                            Body body) {
-    if (env.cand) {  // the launch's list of the waves that step
-        fused_list<BS>(env, body);
-        return;
-    }
-    const int lane = threadIdx.x & (kWave - 1);
-    const int64_t P = (int64_t)gridDim.x * (BS / kWave);
-    const int64_t p = (int64_t)blockIdx.x * (BS / kWave) + __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-    for (int64_t r = 0; p + r * kWave * P < env.n_waves; ++r) {
-        const int64_t w = p + (r * kWave + lane) * P;
-        const bool in = w < env.n_waves;
-        const bool still = in && env.below[w] && env.rest[w];
-        uint64_t todo = __ballot(in && !still), quiet = beta ? __ballot(still) : 0;
-        if (env.stats) {
-            const int nq = __popcll(__ballot(still));  // (all lanes take part in the ballot)
-            if (nq && lane == 0) atomicAdd(env.stats + kStatFlagged, (unsigned long long)nq);
-        }
-        while (todo) {
-            const int i = __builtin_ctzll(todo);
-            todo &= todo - 1;
-            body(p + (r * kWave + i) * P);
-        }
-        while (quiet) {
-            const int i = __builtin_ctzll(quiet);
-            quiet &= quiet - 1;
-            still_wave_beta(pg, T0c, beta, (p + (r * kWave + i) * P) * kWave + lane);
-        }
-    }
-}
+// The counts below are added by every lane, lane 0 with the value and the
+// others with 0, so that no branch on the lane sits inside the kernels'
+// loops (see fused_plain_call_kernel).
 
 // count a wave that read its state: its active points, and its class
 __device__ __forceinline__ void count_wave(const EnvSet& env, bool act, bool still, bool cold) {
     const unsigned long long n = __popcll(__ballot(act));
-    if ((threadIdx.x & (kWave - 1)) != 0 || n == 0) return;
-    atomicAdd(env.stats + kStatLoaded, n);
+    if (n == 0) return;  // (uniform)
+    const unsigned long long one = (threadIdx.x & (kWave - 1)) == 0 ? 1ull : 0ull;
+    atomicAdd(env.stats + kStatLoaded, n * one);
     if (still) {
-        atomicAdd(env.stats + kStatStill, 1ull);
+        atomicAdd(env.stats + kStatStill, one);
         return;
     }
-    atomicAdd(env.stats + kStatStored, n);
-    atomicAdd(env.stats + (cold ? kStatCold : kStatHot), 1ull);
+    atomicAdd(env.stats + kStatStored, n * one);
+    atomicAdd(env.stats + (cold ? kStatCold : kStatHot), one);
 }
 
 // count a hot wave's sub-block from T0 to TK, and whether every point passes
@@ -186,9 +150,9 @@ __device__ __forceinline__ void count_block(const EnvSet& env, bool act, float T
     const float lo = fminf(T0, TK), hi = fmaxf(T0, TK);
     const bool ok = !act || ((hi < 823.0f || (lo >= 1398.0f && hi <= 1853.0f)) && fabsf(TK - T0) <= 50.0f);
     const bool all = __ballot(!ok) == 0;
-    if ((threadIdx.x & (kWave - 1)) != 0) return;
-    atomicAdd(env.stats + kStatHotBlocks, 1ull);
-    if (all) atomicAdd(env.stats + kStatEligibleBlocks, 1ull);
+    const unsigned long long one = (threadIdx.x & (kWave - 1)) == 0 ? 1ull : 0ull;
+    atomicAdd(env.stats + kStatHotBlocks, one);
+    if (all) atomicAdd(env.stats + kStatEligibleBlocks, one);
 }
 
 // record whether every point of the wave is at rest after the launch
@@ -215,18 +179,16 @@ inline dim3 slots_grid(int64_t n_waves, int bs, int spw) {
             hipLaunchKernelGGL((kernel<W, 128>), slots_grid(n_waves, 128, spw), dim3(128), 0, st, __VA_ARGS__); \
     } while (0)
 
-// Wave slots per wave of a slot kernel.  Below kSlotsLargeGrid waves, four
-// (sixteen took the block scan from 62 to 101 ms).  On large grids, where
-// nearly every wave exits on its flags, fewer slot waves cut the cost of
-// launching them when the waves that step run short chains: 16 for plain
-// launches of at most 16 steps (masked cantilever, K = 16: 0.32 -> 0.19 s
-// per run), 8 for the surrogate, whose admitted blocks take one step (island
-// block: 0.643 -> 0.607 s); plain launches of more steps keep four (island
-// block at K = 64: 1.84 s, 2.01 s with 16).
-enum class SlotUse { PlainShort, PlainLong, Surrogate, Implicit };
+// Waves of points per grid wave of a slot kernel (IMPLICIT and SURROGATE
+// launches): the grid only has to hold the listed waves, a few per cent of a
+// launch.  Four below kSlotsLargeGrid waves; on large grids 8 for the
+// surrogate, 4 otherwise (sizes chosen when the grid waves scanned the flags
+// themselves; with the lists anything from 4 to 32 is within 1 %, and 2 is
+// 6-9 % slower on the large grids).
+enum class SlotUse { Surrogate, Implicit };
 inline int slots_per_wave(int64_t n_waves, SlotUse use) {
     if (n_waves < kSlotsLargeGrid) return kSlotsPerWave;
-    return use == SlotUse::PlainShort ? 16 : use == SlotUse::Surrogate ? 8 : kSlotsPerWave;
+    return use == SlotUse::Surrogate ? 8 : kSlotsPerWave;
 }
 
 }  // namespace mstruct

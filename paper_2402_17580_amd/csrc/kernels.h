@@ -73,9 +73,10 @@ struct EnvSet {
     // indexed by the kStat* constants
     unsigned long long* stats;
     // the waves of a slot launch that are not still by their flags, listed
-    // by candidates_kernel (cand[0 .. *cand_n)); nullptr: the slot kernel
-    // reads the flags itself.  The slot launch clears *cand_next, the next
-    // launch's count.
+    // by candidates_kernel (cand[0 .. *cand_n)); the slot kernels run only
+    // with a list (nullptr: the grid kernels, which read the flags
+    // themselves).  The slot launch clears *cand_next, the next launch's
+    // count.
     uint32_t* cand;
     unsigned* cand_n;
     unsigned* cand_next;
@@ -159,6 +160,17 @@ hipError_t launch_temperature(const PointGeom& pg, int W, const SrcRec* rec, Sca
                               hipStream_t st);
 hipError_t launch_fused_plain(const PointGeom& pg, int W, const SrcRec* tab, EnvSet env, int K, float dt, ScanArgs sa,
                               float* beta, float* as, float* am, double* xb, hipStream_t st);
+// fused PLAIN launches l0 .. l0 + nl - 1 of a call with wave flags: a list
+// pass (chunk_list_kernel) and one persistent kernel (fused_plain_call_kernel)
+// for the listed waves.  tab and env_fc as for the whole call, below the
+// chunk's still flags, rest one byte per wave, cand room for n_waves
+// entries, counts two counters (cleared here); beta (nullptr: not written)
+// when the chunk ends the call
+hipError_t launch_fused_plain_call(const PointGeom& pg, int W, const SrcRec* tab, const EnvRec* env,
+                                   const int32_t* env_fc, const uint8_t* below, uint8_t* rest, int64_t n_waves,
+                                   int64_t l0, int64_t nl, int K, int64_t n_steps, float dt, ScanArgs sa, float* beta,
+                                   float* as, float* am, uint32_t* cand, unsigned* counts,
+                                   unsigned long long* stats, hipStream_t st);
 hipError_t launch_gather(const float* src, const int64_t* idx, int64_t m, float* dst, hipStream_t st);
 hipError_t launch_invariants(const float* beta, const float* as, const float* am, const float* T, int64_t n,
                              float tol, unsigned long long* counter, hipStream_t st);

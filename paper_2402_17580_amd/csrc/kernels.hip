@@ -326,101 +326,166 @@ hipError_t launch_wave_boxes(const PointGeom& pg, int64_t n_waves, GridBox* boxe
 // held in registers (with compensated Euler accumulation); tab holds the
 // K + 1 time points x W window slots of this launch.
 // ---------------------------------------------------------------------------
+// One launch of a wave on its register state (one point per lane, no
+// tracked X~beta).  A wave whose points are all at rest and provably stay
+// below the alpha_s -> beta end temperature at every time point of the
+// launch is left as it is by every step (still).  Otherwise, a wave that no
+// source of this launch reaches (every term of every track dropped at every
+// time point) has T = T0 throughout (cold), and a cold wave whose first step
+// changed nothing it stores stops there (frozen, see frozen_part).  The
+// others take K explicit steps with the increments accumulated in (hi, lo)
+// pairs.  a, m: the fractions as loaded in, and on return the fractions in
+// memory after the launch (the loaded ones for a still or frozen wave, hi +
+// lo otherwise); Tc: the temperature of the last correction (beta's sum
+// rule).  Returns 0 (still), 1 (frozen) or 2 (stepped).  The fractions a
+// still wave's beta and rest flag see are a + 0, m + 0.
+template <int W>
+__device__ __forceinline__ int plain_launch(const PointGeom& pg, const SrcRec* __restrict__ tab, const EnvSet& env,
+                                            int64_t wv, int K, float dt, const ScanArgs& sa, bool act, int gi, int gj,
+                                            int gk, float& a, float& m, float& Tc) {
+    const float T0c = fminf(sa.T0, sa.Tclamp);
+    const float rlim2 = envelope_radius2(pg);
+    const bool tried = wave_may_rest(env, act, a, m, T0c);
+    bool still = tried && (wave_box_below(env, wv) || wave_below(env.rec, env.n, act, gi, gj, gk, rlim2, T0c, kRestBelow));
+    // an all-at-rest wave that is not below the limit everywhere is not cold either
+    const bool cold = still || (!tried && wave_cold(env.rec, env.n, act, gi, gj, gk, rlim2));
+    float Tn = cold ? T0c : scan_temperature<W>(tab, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
+    Tc = Tn;
+    float xeq_n = alpha_eq(Tn);
+    // a cold wave whose points are all at rest at T0 is still as well
+    still = still || (cold && T0c < Const<float>::TasEnd && __ballot(act && !rest_bits(a, m)) == 0);
+    if (env.stats) count_wave(env, act, still, cold);
+    if (still) return 0;
+    // the waves that evaluate the temperature run the longest chains: they
+    // issue first, and the other waves of their SIMD fill the gaps
+    if (!cold) __builtin_amdgcn_s_setprio(3);
+    const float a0 = a, m0 = m;
+    float alo = 0.0f, mlo = 0.0f, Tblk = Tn;  // Tblk: sub-block start (wave counts only)
+    bool frozen = false;
+    for (int s = 0; s < K && !frozen; ++s) {
+        const float Tn1 =
+            cold ? T0c : scan_temperature<W>(tab + (s + 1) * W, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
+        if (env.stats && !cold) {
+            if (s % kStatBlock == 0) Tblk = Tn;
+            if (s % kStatBlock == kStatBlock - 1) count_block(env, act, Tblk, Tn1);
+        }
+        const float xeq_n1 = alpha_eq(Tn1);
+        explicit_step<true>(a, m, alo, mlo, Tn, xeq_n, Tn1, xeq_n1, dt, sa.rd);
+        Tc = sa.rd.corr_prev ? Tn : Tn1;
+        Tn = Tn1;
+        xeq_n = xeq_n1;
+        if (s == 0 && cold)
+            frozen = __ballot(act && !(frozen_part(a0, a, alo, K) && frozen_part(m0, m, mlo, K))) == 0;
+    }
+    __builtin_amdgcn_s_setprio(0);
+    if (frozen) {
+        a = a0;
+        m = m0;
+        return 1;
+    }
+    a += alo;
+    m += mlo;
+    return 2;
+}
+
 // The points g0 + u kFusedBlock (u < PPT) of the calling lane; wv is the
 // wave of the points for PPT = 1.  beta == nullptr: not written (inside a
 // call only the last launch writes it; no kernel reads beta, it follows from
-// the sum rule).
+// the sum rule).  One point per lane without a tracked X~beta goes through
+// plain_launch; the general form (PPT > 1, or TRACK) takes every launch
+// certificate but the wave flags and the frozen stop.
 template <int W, int PPT, bool TRACK>
 __device__ __forceinline__ void fused_plain_body(const PointGeom& pg, const SrcRec* __restrict__ tab,
                                                  const EnvSet& env, int K, float dt, const ScanArgs& sa,
                                                  float* __restrict__ beta, float* __restrict__ as,
                                                  float* __restrict__ am, double* __restrict__ xbv, int64_t g0,
                                                  int64_t wv) {
-    const float T0c = fminf(sa.T0, sa.Tclamp);
-    int64_t local[PPT];
-    int gi[PPT], gj[PPT], gk[PPT];
-    bool act[PPT];
-    float a[PPT], m[PPT], alo[PPT], mlo[PPT], Tn[PPT], xeq_n[PPT], Tc[PPT];
-    double xb[PPT];
-#pragma unroll
-    for (int u = 0; u < PPT; ++u) {
-        const int64_t g = g0 + u * kFusedBlock;
-        act[u] = g < pg.count;
-        local[u] = point_at(pg, act[u] ? g : 0, gi[u], gj[u], gk[u]);
-        act[u] = act[u] && gk[u] >= pg.k0;
-        a[u] = act[u] ? as[local[u]] : 0.0f;
-        m[u] = act[u] ? am[local[u]] : 0.0f;
-        xb[u] = (TRACK && act[u]) ? track_check(xbv[local[u]], a[u], m[u]) : track_none();
-        alo[u] = 0.0f;
-        mlo[u] = 0.0f;
-    }
-    // A wave whose points are all at rest and provably stay below the
-    // alpha_s -> beta end temperature at every time point of the launch is
-    // left as it is by every step (still).  Otherwise, a wave that no source
-    // of this launch reaches (every term of every track dropped at every time
-    // point) has T = T0 throughout (cold).
-    bool cold[PPT], still[PPT];
-    const float rlim2 = envelope_radius2(pg);
-#pragma unroll
-    for (int u = 0; u < PPT; ++u) {
-        const bool tried = wave_may_rest(env, act[u], a[u], m[u], T0c);
-        still[u] = tried && ((PPT == 1 && !TRACK && wave_box_below(env, wv)) ||
-                             wave_below(env.rec, env.n, act[u], gi[u], gj[u], gk[u], rlim2, T0c, kRestBelow));
-        // an all-at-rest wave that is not below the limit everywhere is not cold either
-        cold[u] = still[u] || (!tried && wave_cold(env.rec, env.n, act[u], gi[u], gj[u], gk[u], rlim2));
-        Tn[u] = cold[u] ? T0c : scan_temperature<W>(tab, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min, pg.roff);
-        Tc[u] = Tn[u];  // temperature of the last correction (beta's sum rule)
-        xeq_n[u] = alpha_eq(Tn[u]);
-        // a cold wave whose points are all at rest at T0 is still as well
-        still[u] = still[u] || (cold[u] && T0c < Const<float>::TasEnd && __ballot(act[u] && !rest_bits(a[u], m[u])) == 0);
-        if (TRACK && still[u]) xb[u] = track_none();
-        if (env.stats) count_wave(env, act[u], still[u], cold[u]);
-    }
-    // the waves that evaluate the temperature run the longest chains: they
-    // issue first, and the other waves of their SIMD fill the gaps
-    if (PPT == 1 && !still[0] && !cold[0]) __builtin_amdgcn_s_setprio(3);
-    float Tblk[PPT];  // temperature at the start of the sub-block (wave counts only)
-    // a cold wave whose first step changed nothing it stores stops there (see frozen_part)
-    const float a0 = a[0], m0 = m[0];
-    bool frozen = false;
-    for (int s = 0; s < K && !frozen; ++s) {
+    if constexpr (PPT == 1 && !TRACK) {
+        bool act = g0 < pg.count;
+        int gi, gj, gk;
+        const int64_t local = point_at(pg, act ? g0 : 0, gi, gj, gk);
+        act = act && gk >= pg.k0;
+        float a = act ? as[local] : 0.0f, m = act ? am[local] : 0.0f, Tc;
+        const int r = plain_launch<W>(pg, tab, env, wv, K, dt, sa, act, gi, gj, gk, a, m, Tc);
+        const float af = r == 0 ? a + 0.0f : a, mf = r == 0 ? m + 0.0f : m;
+        if (act) {
+            if (r == 2) {  // a still or frozen wave's fractions are those in memory
+                as[local] = af;
+                am[local] = mf;
+            }
+            if (beta) beta[local] = solid_fraction(Tc) - af - mf;
+        }
+        record_rest(env, wv, act, af, mf);
+        return;
+    } else {
+        const float T0c = fminf(sa.T0, sa.Tclamp);
+        int64_t local[PPT];
+        int gi[PPT], gj[PPT], gk[PPT];
+        bool act[PPT];
+        float a[PPT], m[PPT], alo[PPT], mlo[PPT], Tn[PPT], xeq_n[PPT], Tc[PPT];
+        double xb[PPT];
 #pragma unroll
         for (int u = 0; u < PPT; ++u) {
-            if (still[u]) continue;
-            const float Tn1 = cold[u] ? T0c
-                                      : scan_temperature<W>(tab + (s + 1) * W, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp,
-                                                            pg.r2min, pg.roff);
-            if (env.stats && !cold[u]) {
-                if (s % kStatBlock == 0) Tblk[u] = Tn[u];
-                if (s % kStatBlock == kStatBlock - 1) count_block(env, act[u], Tblk[u], Tn1);
-            }
-            const float xeq_n1 = alpha_eq(Tn1);
-            if (TRACK)
-                explicit_step_tracked<true>(a[u], m[u], alo[u], mlo[u], xb[u], Tn[u], xeq_n[u], Tn1, xeq_n1, dt,
-                                            sa.rd);
-            else
-                explicit_step<true>(a[u], m[u], alo[u], mlo[u], Tn[u], xeq_n[u], Tn1, xeq_n1, dt, sa.rd);
-            Tc[u] = sa.rd.corr_prev ? Tn[u] : Tn1;
-            Tn[u] = Tn1;
-            xeq_n[u] = xeq_n1;
+            const int64_t g = g0 + u * kFusedBlock;
+            act[u] = g < pg.count;
+            local[u] = point_at(pg, act[u] ? g : 0, gi[u], gj[u], gk[u]);
+            act[u] = act[u] && gk[u] >= pg.k0;
+            a[u] = act[u] ? as[local[u]] : 0.0f;
+            m[u] = act[u] ? am[local[u]] : 0.0f;
+            xb[u] = (TRACK && act[u]) ? track_check(xbv[local[u]], a[u], m[u]) : track_none();
+            alo[u] = 0.0f;
+            mlo[u] = 0.0f;
         }
-        if (PPT == 1 && !TRACK && s == 0 && cold[0] && !still[0])
-            frozen = __ballot(act[0] && !(frozen_part(a0, a[0], alo[0], K) && frozen_part(m0, m[0], mlo[0], K))) == 0;
-    }
+        // still and cold waves as in plain_launch
+        bool cold[PPT], still[PPT];
+        const float rlim2 = envelope_radius2(pg);
 #pragma unroll
-    for (int u = 0; u < PPT; ++u) {
-        if (!act[u]) continue;
-        const float af = frozen ? a0 : a[u] + alo[u], mf = frozen ? m0 : m[u] + mlo[u];
-        // a still or frozen wave's fractions are those in memory
-        if (!still[u] && !frozen) {
-            as[local[u]] = af;
-            am[local[u]] = mf;
+        for (int u = 0; u < PPT; ++u) {
+            const bool tried = wave_may_rest(env, act[u], a[u], m[u], T0c);
+            still[u] = tried && wave_below(env.rec, env.n, act[u], gi[u], gj[u], gk[u], rlim2, T0c, kRestBelow);
+            cold[u] = still[u] || (!tried && wave_cold(env.rec, env.n, act[u], gi[u], gj[u], gk[u], rlim2));
+            Tn[u] = cold[u] ? T0c : scan_temperature<W>(tab, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp, pg.r2min, pg.roff);
+            Tc[u] = Tn[u];
+            xeq_n[u] = alpha_eq(Tn[u]);
+            still[u] = still[u] || (cold[u] && T0c < Const<float>::TasEnd && __ballot(act[u] && !rest_bits(a[u], m[u])) == 0);
+            if (TRACK && still[u]) xb[u] = track_none();
+            if (env.stats) count_wave(env, act[u], still[u], cold[u]);
         }
-        if (TRACK) xbv[local[u]] = xb[u];
-        if (beta) beta[local[u]] = solid_fraction(Tc[u]) - af - mf;
+        float Tblk[PPT];
+        for (int s = 0; s < K; ++s) {
+#pragma unroll
+            for (int u = 0; u < PPT; ++u) {
+                if (still[u]) continue;
+                const float Tn1 = cold[u] ? T0c
+                                          : scan_temperature<W>(tab + (s + 1) * W, gi[u], gj[u], gk[u], sa.T0, sa.Tclamp,
+                                                                pg.r2min, pg.roff);
+                if (env.stats && !cold[u]) {
+                    if (s % kStatBlock == 0) Tblk[u] = Tn[u];
+                    if (s % kStatBlock == kStatBlock - 1) count_block(env, act[u], Tblk[u], Tn1);
+                }
+                const float xeq_n1 = alpha_eq(Tn1);
+                if (TRACK)
+                    explicit_step_tracked<true>(a[u], m[u], alo[u], mlo[u], xb[u], Tn[u], xeq_n[u], Tn1, xeq_n1, dt,
+                                                sa.rd);
+                else
+                    explicit_step<true>(a[u], m[u], alo[u], mlo[u], Tn[u], xeq_n[u], Tn1, xeq_n1, dt, sa.rd);
+                Tc[u] = sa.rd.corr_prev ? Tn[u] : Tn1;
+                Tn[u] = Tn1;
+                xeq_n[u] = xeq_n1;
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < PPT; ++u) {
+            if (!act[u]) continue;
+            const float af = a[u] + alo[u], mf = m[u] + mlo[u];
+            if (!still[u]) {  // a still wave's fractions are those in memory
+                as[local[u]] = af;
+                am[local[u]] = mf;
+            }
+            if (TRACK) xbv[local[u]] = xb[u];
+            if (beta) beta[local[u]] = solid_fraction(Tc[u]) - af - mf;
+        }
     }
-    if (PPT == 1 && !TRACK) record_rest(env, wv, act[0], a[0] + alo[0], m[0] + mlo[0]);
-    if (PPT == 1) __builtin_amdgcn_s_setprio(0);  // for the next wave of a slot kernel's grid wave
 }
 
 // PPT points per lane, kFusedBlock apart (coalesced), advanced together for ILP
@@ -439,16 +504,175 @@ __global__ __launch_bounds__(kFusedBlock) void fused_plain_kernel(PointGeom pg, 
                                     (int64_t)blockIdx.x * kFusedBlock * PPT + threadIdx.x, wv);
 }
 
-template <int W, int BS>
-__global__ __launch_bounds__(BS) void fused_plain_slots_kernel(PointGeom pg, const SrcRec* __restrict__ tab,
-                                                                        EnvSet env, int K, float dt, ScanArgs sa,
-                                                                        float* __restrict__ beta,
-                                                                        float* __restrict__ as,
-                                                                        float* __restrict__ am) {
+// workgroup of the list passes (sixteen waves; see candidates_kernel)
+constexpr int kListBlock = 1024;
+
+// The waves of a chunk of launches l0 .. l0 + nl - 1 that the call kernel
+// takes: one wave per wave of points finds whether it is at rest (from its
+// state in the first chunk of a call, from its rest flag after) and loads its
+// still flags for the chunk (lane i: launch l0 + i, 64 at a time).  A wave
+// at rest that the box pre-pass bounds below the still limit in every launch
+// of the chunk is still throughout it: its rest flag is set and, if the
+// chunk ends the call, beta written.  The others are listed (one atomic per
+// workgroup of 16 waves) in cand[0 .. counts[0]).
+__global__ __launch_bounds__(kListBlock) void chunk_list_kernel(
+    PointGeom pg, const uint8_t* __restrict__ below, uint8_t* __restrict__ rest, int64_t n_waves, int64_t l0,
+    int64_t nl, float T0c, float* __restrict__ beta, const float* __restrict__ as, const float* __restrict__ am,
+    uint32_t* __restrict__ cand, unsigned* __restrict__ counts, unsigned long long* __restrict__ stats) {
+    __shared__ unsigned wave_n[kListBlock / kWave + 1];
+    const int wib = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const int64_t w = (int64_t)blockIdx.x * (kListBlock / kWave) + wib;
     const int lane = threadIdx.x & (kWave - 1);
-    fused_slots<BS>(pg, env, fminf(sa.T0, sa.Tclamp), beta, [&](int64_t w) {
-        fused_plain_body<W, 1, false>(pg, tab, env, K, dt, sa, beta, as, am, nullptr, w * kWave + lane, w);
-    });
+    const bool in = w < n_waves;  // uniform per wave
+    bool still = false;
+    if (in) {
+        const int64_t g = w * kWave + lane;
+        bool act = g < pg.count;
+        int gi, gj, gk;
+        const int64_t local = point_at(pg, act ? g : 0, gi, gj, gk);
+        act = act && gk >= pg.k0;
+        bool at_rest;
+        if (l0 == 0) {  // (below implies T0 under the still limit)
+            const float a = act ? as[local] : 0.0f, m = act ? am[local] : 0.0f;
+            at_rest = __ballot(act && !rest_bits(a, m)) == 0;
+        } else {
+            at_rest = rest[w] != 0;
+        }
+        still = at_rest;
+        for (int64_t i0 = 0; i0 < nl && still; i0 += kWave)
+            still = __ballot(i0 + lane < nl && below[(i0 + lane) * n_waves + w] == 0) == 0;
+        if (still) {
+            if (act && beta) beta[local] = solid_fraction(T0c) - kXmax - 0.0f;
+            if (stats) atomicAdd(stats + kStatFlagged, lane == 0 ? (unsigned long long)nl : 0ull);
+            rest[w] = 1;  // (the same byte from every lane)
+        }
+    }
+    if (lane == 0) wave_n[wib] = (in && !still) ? 1u : 0u;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned total = 0;
+        for (int i = 0; i < kListBlock / kWave; ++i) {
+            const unsigned c = wave_n[i];
+            wave_n[i] = total;
+            total += c;
+        }
+        wave_n[kListBlock / kWave] = total ? atomicAdd(counts, total) : 0u;
+    }
+    __syncthreads();
+    if (in && !still && lane == 0) cand[wave_n[kListBlock / kWave] + wave_n[wib]] = (uint32_t)w;
+}
+
+// ---------------------------------------------------------------------------
+// A fused PLAIN call, or a chunk of its launches, in one persistent kernel:
+// each wave of the grid takes waves of points from a shared counter, loads
+// one once, runs every launch of the chunk on its registers (plain_launch;
+// a launch that the wave flags say is still costs one byte) and stores it
+// once.  The waves of points do not depend on each other, so no launch waits
+// for the whole grid to finish the one before: the few waves near the
+// tracks, which run chains of K dependent steps launch after launch, share
+// the GPU with the rest of the call instead of ending every launch alone.
+// What each point computes is what the launch-by-launch form computes, bit
+// for bit: a launch starts from the fractions the previous one left in
+// memory (hi + lo), and a still or frozen launch leaves them as they were.
+// Wave flags: below (the chunk's still flags, [l - l0][w]), rest (per wave,
+// at rest after the last launch that took its steps: read from the second
+// chunk, written at the end of each).
+// ---------------------------------------------------------------------------
+constexpr int kCallBlock = 256;
+// grid waves of the persistent call kernel: eight per SIMD
+constexpr int kCallWaves = 256 * 4 * 8;
+
+template <int W>
+__global__ __launch_bounds__(kCallBlock) void fused_plain_call_kernel(
+    PointGeom pg, const SrcRec* __restrict__ tab, const EnvRec* __restrict__ env, const int32_t* __restrict__ env_fc,
+    const uint8_t* __restrict__ below, uint8_t* __restrict__ rest, int64_t n_waves, int64_t l0, int64_t nl, int K,
+    int64_t n_steps, float dt, ScanArgs sa, float* __restrict__ beta, float* __restrict__ as, float* __restrict__ am,
+    const uint32_t* __restrict__ cand, const unsigned* __restrict__ cand_n, unsigned* __restrict__ next,
+    unsigned long long* __restrict__ stats) {
+    const float T0c = fminf(sa.T0, sa.Tclamp);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t n_list = *cand_n;
+    // No branch on the lane inside this loop: every lane takes part in the
+    // atomic (lane 0 adds 1, the others 0) and lane 0's old value is the
+    // wave's, and the per-wave stores are made by all lanes.  (A lane-0
+    // branch at the top and another at the bottom of the body let the
+    // compiler send lane 0 round the loop alone, so that the other lanes
+    // read the wave number from an inactive lane and never left.)
+    for (;;) {
+        const unsigned ei = atomicAdd(next, lane == 0 ? 1u : 0u);
+        const int64_t e = (int64_t)(unsigned)__builtin_amdgcn_readfirstlane((int)ei);
+        if (e >= n_list) return;  // uniform per wave: every wave ends once the counter passes the list
+        const int64_t w = (int64_t)(unsigned)__builtin_amdgcn_readfirstlane((int)cand[e]);
+        const int64_t g = w * kWave + lane;
+        bool act = g < pg.count;
+        int gi, gj, gk;
+        const int64_t local = point_at(pg, act ? g : 0, gi, gj, gk);
+        act = act && gk >= pg.k0;
+        float a = act ? as[local] : 0.0f, m = act ? am[local] : 0.0f;
+        float af = a, mf = m, Tc = T0c;
+        // at rest: from the state for the first launch of a call (below implies T0 under the limit)
+        bool rest_w = l0 == 0 ? __ballot(act && !rest_bits(a, m)) == 0 : rest[w] != 0;
+        bool changed = false, flagged = false;
+        uint64_t bm = 0;  // the wave's still flags for launches lb .. lb + 63, one bit each
+        int64_t lb = l0 - kWave;
+        for (int64_t l = l0; l < l0 + nl; ++l) {
+            const uint8_t* bl = below + (l - l0) * n_waves;
+            if (l - lb >= kWave) {  // (uniform) lane i loads launch l + i's flag
+                lb = l;
+                bm = __ballot(l + lane < l0 + nl && below[(l - l0 + lane) * n_waves + w] != 0);
+            }
+            flagged = rest_w && ((bm >> (l - lb)) & 1);
+            if (flagged) {  // still by its flags: nothing read, nothing changes
+                if (stats) atomicAdd(stats + kStatFlagged, lane == 0 ? 1ull : 0ull);
+                continue;
+            }
+            const int64_t s0 = l * K;
+            const int Kl = (int)min((int64_t)K, n_steps - s0);
+            const EnvSet es{env + env_fc[2 * l], env_fc[2 * l + 1], bl, nullptr, n_waves, 0, stats,
+                            nullptr, nullptr, nullptr};
+            const int r = plain_launch<W>(pg, tab + s0 * W, es, w, Kl, dt, sa, act, gi, gj, gk, a, m, Tc);
+            af = r == 0 ? a + 0.0f : a;
+            mf = r == 0 ? m + 0.0f : m;
+            changed = changed || r == 2;
+            rest_w = __ballot(act && !rest_bits(af, mf)) == 0;
+        }
+        if (act) {
+            if (changed) {
+                as[local] = a;
+                am[local] = m;
+            }
+            if (beta) beta[local] = flagged ? solid_fraction(T0c) - kXmax - 0.0f : solid_fraction(Tc) - af - mf;
+        }
+        rest[w] = rest_w ? 1 : 0;  // (the same byte from every lane)
+    }
+}
+
+hipError_t launch_fused_plain_call(const PointGeom& pg, int W, const SrcRec* tab, const EnvRec* env,
+                                   const int32_t* env_fc, const uint8_t* below, uint8_t* rest, int64_t n_waves,
+                                   int64_t l0, int64_t nl, int K, int64_t n_steps, float dt, ScanArgs sa, float* beta,
+                                   float* as, float* am, uint32_t* cand, unsigned* counts,
+                                   unsigned long long* stats, hipStream_t st) {
+    if (n_waves <= 0 || nl <= 0) return hipSuccess;
+    hipError_t e = launch_clear_counts(counts, st);
+    if (e != hipSuccess) return e;
+    const int64_t lpb = kListBlock / kWave;
+    hipLaunchKernelGGL(chunk_list_kernel, dim3((unsigned)((n_waves + lpb - 1) / lpb)), dim3(kListBlock), 0, st, pg,
+                       below, rest, n_waves, l0, nl, fminf(sa.T0, sa.Tclamp), beta, (const float*)as,
+                       (const float*)am, cand, counts, stats);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const int64_t wpb = kCallBlock / kWave;
+    const int64_t waves = n_waves < kCallWaves ? n_waves : kCallWaves;
+    const dim3 grid((unsigned)((waves + wpb - 1) / wpb)), block(kCallBlock);
+    const unsigned* n_list = counts;
+    unsigned* next = counts + 1;
+    switch (W) {
+        case 1: hipLaunchKernelGGL(fused_plain_call_kernel<1>, grid, block, 0, st, pg, tab, env, env_fc, below, rest, n_waves, l0, nl, K, n_steps, dt, sa, beta, as, am, cand, n_list, next, stats); break;
+        case 2: hipLaunchKernelGGL(fused_plain_call_kernel<2>, grid, block, 0, st, pg, tab, env, env_fc, below, rest, n_waves, l0, nl, K, n_steps, dt, sa, beta, as, am, cand, n_list, next, stats); break;
+        case 3: hipLaunchKernelGGL(fused_plain_call_kernel<3>, grid, block, 0, st, pg, tab, env, env_fc, below, rest, n_waves, l0, nl, K, n_steps, dt, sa, beta, as, am, cand, n_list, next, stats); break;
+        case 4: hipLaunchKernelGGL(fused_plain_call_kernel<4>, grid, block, 0, st, pg, tab, env, env_fc, below, rest, n_waves, l0, nl, K, n_steps, dt, sa, beta, as, am, cand, n_list, next, stats); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 // One wave per 64 waves of a slot launch: the waves that are not still by
@@ -456,7 +680,6 @@ __global__ __launch_bounds__(BS) void fused_plain_slots_kernel(PointGeom pg, con
 // last launch of a call.  A workgroup of 16 waves takes its places in the
 // list with one atomic (all workgroups add to the same count, so atomics per
 // wave would queue up: 16.8 us per launch on a 1M-wave grid).
-constexpr int kListBlock = 1024;
 
 __global__ __launch_bounds__(kListBlock) void candidates_kernel(PointGeom pg, EnvSet env, float T0c,
                                                                float* __restrict__ beta) {
@@ -666,7 +889,7 @@ __global__ __launch_bounds__(BS) void fused_implicit_slots_kernel(
     float* __restrict__ beta, float* __restrict__ as, float* __restrict__ am,
     unsigned long long* __restrict__ unconverged) {
     const int lane = threadIdx.x & (kWave - 1);
-    fused_slots<BS>(pg, env, fminf(sa.T0, sa.Tclamp), beta, [&](int64_t w) {
+    fused_slots<BS>(env, [&](int64_t w) {
         fused_implicit_body<W, false>(pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, nullptr, unconverged,
                                       w * kWave + lane, w);
     });
@@ -691,7 +914,7 @@ hipError_t launch_fused_implicit(const PointGeom& pg, int W, const SrcRec* tab, 
                                  int max_iter, ScanArgs sa, float* beta, float* as, float* am, double* xb,
                                  unsigned long long* unconverged, hipStream_t st) {
     if (pg.count <= 0) return hipSuccess;
-    if (!xb && env.below && (env.read_rest || env.cand)) {
+    if (!xb && env.below && env.cand) {
         switch (W) {
             case 1: LAUNCH_SLOTS(fused_implicit_slots_kernel, 1, env.n_waves, slots_per_wave(env.n_waves, SlotUse::Implicit), st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
             case 2: LAUNCH_SLOTS(fused_implicit_slots_kernel, 2, env.n_waves, slots_per_wave(env.n_waves, SlotUse::Implicit), st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
@@ -738,17 +961,6 @@ static hipError_t fused_plain_w(const PointGeom& pg, int W, const SrcRec* tab, E
 hipError_t launch_fused_plain(const PointGeom& pg, int W, const SrcRec* tab, EnvSet env, int K, float dt, ScanArgs sa,
                               float* beta, float* as, float* am, double* xb, hipStream_t st) {
     if (pg.count <= 0) return hipSuccess;
-    if (kFusedPPT == 1 && !xb && env.below && (env.read_rest || env.cand)) {
-        const int spw = slots_per_wave(env.n_waves, K <= 16 ? SlotUse::PlainShort : SlotUse::PlainLong);
-        switch (W) {
-            case 1: LAUNCH_SLOTS(fused_plain_slots_kernel, 1, env.n_waves, spw, st, pg, tab, env, K, dt, sa, beta, as, am); break;
-            case 2: LAUNCH_SLOTS(fused_plain_slots_kernel, 2, env.n_waves, spw, st, pg, tab, env, K, dt, sa, beta, as, am); break;
-            case 3: LAUNCH_SLOTS(fused_plain_slots_kernel, 3, env.n_waves, spw, st, pg, tab, env, K, dt, sa, beta, as, am); break;
-            case 4: LAUNCH_SLOTS(fused_plain_slots_kernel, 4, env.n_waves, spw, st, pg, tab, env, K, dt, sa, beta, as, am); break;
-            default: return hipErrorInvalidValue;
-        }
-        return hipGetLastError();
-    }
     return xb ? fused_plain_w<true>(pg, W, tab, env, K, dt, sa, beta, as, am, xb, st)
               : fused_plain_w<false>(pg, W, tab, env, K, dt, sa, beta, as, am, xb, st);
 }

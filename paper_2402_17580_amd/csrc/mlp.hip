@@ -786,7 +786,7 @@ __global__ __launch_bounds__(BS) void fused_surrogate_slots_kernel(PointGeom pg,
                                                                    SurrogateRecord* __restrict__ recs,
                                                                    unsigned* __restrict__ n_recs, int64_t cap) {
     const int lane = threadIdx.x & (kWave - 1);
-    fused_slots<BS>(pg, env, fminf(sa.T0, sa.Tclamp), beta, [&](int64_t w) {
+    fused_slots<BS>(env, [&](int64_t w) {
         surrogate_fused_body<W>(pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, n_recs, cap, w * kWave + lane,
                                 w);
     });
@@ -858,7 +858,7 @@ hipError_t launch_surrogate(const MlpState& s, const PointGeom& pg, int W, const
     unsigned* nxt = s.counters + ((li + 1) & 1);
     const int64_t cap = s.rec_cap;
     const MlpNorm& nrm = s.norm;
-    if (env.below && (env.read_rest || env.cand)) {
+    if (env.below && env.cand) {
         switch (W) {
             case 1: LAUNCH_SLOTS(fused_surrogate_slots_kernel, 1, env.n_waves, slots_per_wave(env.n_waves, SlotUse::Surrogate), st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
             case 2: LAUNCH_SLOTS(fused_surrogate_slots_kernel, 2, env.n_waves, slots_per_wave(env.n_waves, SlotUse::Surrogate), st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
