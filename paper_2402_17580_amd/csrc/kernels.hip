@@ -504,6 +504,71 @@ __global__ __launch_bounds__(kFusedBlock) void fused_plain_kernel(PointGeom pg, 
                                     (int64_t)blockIdx.x * kFusedBlock * PPT + threadIdx.x, wv);
 }
 
+// One implicit launch of a wave on its register state (one point per lane,
+// no tracked X~beta), as plain_launch: still and cold waves as there, and a
+// cold wave whose first step changed nothing it stores stops there (see
+// frozen_part): with the high parts unchanged after every substep, each
+// substep's iteration starts from the same state, converges at its first
+// iterate with a zero residual and adds the same increments to the low
+// parts; a first step with an unconverged substep does not stop, so that
+// the count stays exact.  Adds the lane's unconverged substeps to bad.
+template <int W>
+__device__ __forceinline__ int implicit_launch(const PointGeom& pg, const SrcRec* __restrict__ tab, const EnvSet& env,
+                                               int64_t wv, int K, float h, int n_sub, int max_iter, const ScanArgs& sa,
+                                               bool act, int gi, int gj, int gk, float& a, float& m, float& Tc,
+                                               int& bad) {
+    const float T0c = fminf(sa.T0, sa.Tclamp);
+    const float rlim2 = envelope_radius2(pg);
+    const bool tried = wave_may_rest(env, act, a, m, T0c);
+    bool still = tried && (wave_box_below(env, wv) || wave_below(env.rec, env.n, act, gi, gj, gk, rlim2, T0c, kRestBelow));
+    const bool cold = still || (!tried && wave_cold(env.rec, env.n, act, gi, gj, gk, rlim2));
+    float Tn = cold ? T0c : scan_temperature<W>(tab, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
+    Tc = Tn;
+    still = still || (cold && T0c < Const<float>::TasEnd && __ballot(act && !rest_bits(a, m)) == 0);
+    if (env.stats) count_wave(env, act, still, cold);
+    if (still) return 0;
+    if (!cold) __builtin_amdgcn_s_setprio(3);  // as in plain_launch
+    const float inv = 1.0f / (float)n_sub;
+    const float a0 = a, m0 = m;
+    float alo = 0.0f, mlo = 0.0f, b = 0.0f;
+    int lbad = 0;
+    bool frozen = false;
+    for (int s = 0; s < K && !frozen; ++s) {
+        const float Tn1 =
+            cold ? T0c : scan_temperature<W>(tab + (s + 1) * W, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
+        float Ta = Tn;
+        bool same = true;
+        for (int k = 0; k < n_sub; ++k) {
+            const float Tb = (k + 1 == n_sub) ? Tn1 : fmaf(Tn1 - Tn, (float)(k + 1) * inv, Tn);
+            if (implicit_step<true>(a, m, alo, mlo, b, Ta, Tb, h, max_iter, sa.rd.mart_assign) < 0) ++lbad;
+            same = same && __float_as_uint(a) == __float_as_uint(a0) && __float_as_uint(m) == __float_as_uint(m0);
+            Ta = Tb;
+        }
+        Tn = Tn1;
+        if (s == 0 && cold)
+            frozen = __ballot(act && !(same && lbad == 0 && frozen_part(a0, a, alo, K) && frozen_part(m0, m, mlo, K))) == 0;
+    }
+    __builtin_amdgcn_s_setprio(0);
+    Tc = Tn;
+    if (act) bad += lbad;
+    if (frozen) {
+        a = a0;
+        m = m0;
+        return 1;
+    }
+    a += alo;
+    m += mlo;
+    return 2;
+}
+
+// the lanes' counts of unconverged substeps, summed over the wave and added
+// to the context's count (by every lane, lane 0 with the sum)
+__device__ __forceinline__ void add_unconverged(unsigned long long* unconverged, int bad) {
+    int total = bad;
+    for (int o = 32; o > 0; o >>= 1) total += __shfl_xor(total, o);
+    if (total) atomicAdd(unconverged, (threadIdx.x & (kWave - 1)) == 0 ? (unsigned long long)total : 0ull);
+}
+
 // workgroup of the list passes (sixteen waves; see candidates_kernel)
 constexpr int kListBlock = 1024;
 
@@ -582,14 +647,17 @@ constexpr int kCallBlock = 256;
 // grid waves of the persistent call kernel: eight per SIMD
 constexpr int kCallWaves = 256 * 4 * 8;
 
-template <int W>
-__global__ __launch_bounds__(kCallBlock) void fused_plain_call_kernel(
-    PointGeom pg, const SrcRec* __restrict__ tab, const EnvRec* __restrict__ env, const int32_t* __restrict__ env_fc,
-    const uint8_t* __restrict__ below, uint8_t* __restrict__ rest, int64_t n_waves, int64_t l0, int64_t nl, int K,
-    int64_t n_steps, float dt, ScanArgs sa, float* __restrict__ beta, float* __restrict__ as, float* __restrict__ am,
-    const uint32_t* __restrict__ cand, const unsigned* __restrict__ cand_n, unsigned* __restrict__ next,
-    unsigned long long* __restrict__ stats) {
-    const float T0c = fminf(sa.T0, sa.Tclamp);
+// The loop of a call kernel: launch(es, w, tab_l, Kl, act, gi, gj, gk, a, m,
+// Tc) runs one launch on a wave's register state as plain_launch does.
+template <class Launch>
+__device__ __forceinline__ void fused_call(const PointGeom& pg, const SrcRec* __restrict__ tab,
+                                           const EnvRec* __restrict__ env, const int32_t* __restrict__ env_fc,
+                                           const uint8_t* __restrict__ below, uint8_t* __restrict__ rest,
+                                           int64_t n_waves, int64_t l0, int64_t nl, int K, int64_t n_steps, int W,
+                                           float T0c, float* __restrict__ beta, float* __restrict__ as,
+                                           float* __restrict__ am, const uint32_t* __restrict__ cand,
+                                           const unsigned* __restrict__ cand_n, unsigned* __restrict__ next,
+                                           unsigned long long* __restrict__ stats, Launch launch) {
     const int lane = threadIdx.x & (kWave - 1);
     const int64_t n_list = *cand_n;
     // No branch on the lane inside this loop: every lane takes part in the
@@ -630,7 +698,7 @@ __global__ __launch_bounds__(kCallBlock) void fused_plain_call_kernel(
             const int Kl = (int)min((int64_t)K, n_steps - s0);
             const EnvSet es{env + env_fc[2 * l], env_fc[2 * l + 1], bl, nullptr, n_waves, 0, stats,
                             nullptr, nullptr, nullptr};
-            const int r = plain_launch<W>(pg, tab + s0 * W, es, w, Kl, dt, sa, act, gi, gj, gk, a, m, Tc);
+            const int r = launch(es, w, tab + s0 * W, Kl, act, gi, gj, gk, a, m, Tc);
             af = r == 0 ? a + 0.0f : a;
             mf = r == 0 ? m + 0.0f : m;
             changed = changed || r == 2;
@@ -647,29 +715,54 @@ __global__ __launch_bounds__(kCallBlock) void fused_plain_call_kernel(
     }
 }
 
+template <int W>
+__global__ __launch_bounds__(kCallBlock) void fused_plain_call_kernel(
+    PointGeom pg, const SrcRec* __restrict__ tab, const EnvRec* __restrict__ env, const int32_t* __restrict__ env_fc,
+    const uint8_t* __restrict__ below, uint8_t* __restrict__ rest, int64_t n_waves, int64_t l0, int64_t nl, int K,
+    int64_t n_steps, float dt, ScanArgs sa, float* __restrict__ beta, float* __restrict__ as, float* __restrict__ am,
+    const uint32_t* __restrict__ cand, const unsigned* __restrict__ cand_n, unsigned* __restrict__ next,
+    unsigned long long* __restrict__ stats) {
+    fused_call(pg, tab, env, env_fc, below, rest, n_waves, l0, nl, K, n_steps, W, fminf(sa.T0, sa.Tclamp), beta, as,
+               am, cand, cand_n, next, stats,
+               [&](const EnvSet& es, int64_t w, const SrcRec* t, int Kl, bool act, int gi, int gj, int gk, float& a,
+                   float& m, float& Tc) {
+                   return plain_launch<W>(pg, t, es, w, Kl, dt, sa, act, gi, gj, gk, a, m, Tc);
+               });
+}
+
+// the list pass of a chunk (counts cleared first); then the call kernel
+static hipError_t chunk_list(const PointGeom& pg, const uint8_t* below, uint8_t* rest, int64_t n_waves, int64_t l0,
+                             int64_t nl, float T0c, float* beta, const float* as, const float* am, uint32_t* cand,
+                             unsigned* counts, unsigned long long* stats, hipStream_t st) {
+    hipError_t e = launch_clear_counts(counts, st);
+    if (e != hipSuccess) return e;
+    const int64_t lpb = kListBlock / kWave;
+    hipLaunchKernelGGL(chunk_list_kernel, dim3((unsigned)((n_waves + lpb - 1) / lpb)), dim3(kListBlock), 0, st, pg,
+                       below, rest, n_waves, l0, nl, T0c, beta, as, am, cand, counts, stats);
+    return hipGetLastError();
+}
+
+static dim3 call_grid(int64_t n_waves) {
+    const int64_t wpb = kCallBlock / kWave;
+    const int64_t waves = n_waves < kCallWaves ? n_waves : kCallWaves;
+    return dim3((unsigned)((waves + wpb - 1) / wpb));
+}
+
 hipError_t launch_fused_plain_call(const PointGeom& pg, int W, const SrcRec* tab, const EnvRec* env,
                                    const int32_t* env_fc, const uint8_t* below, uint8_t* rest, int64_t n_waves,
                                    int64_t l0, int64_t nl, int K, int64_t n_steps, float dt, ScanArgs sa, float* beta,
                                    float* as, float* am, uint32_t* cand, unsigned* counts,
                                    unsigned long long* stats, hipStream_t st) {
     if (n_waves <= 0 || nl <= 0) return hipSuccess;
-    hipError_t e = launch_clear_counts(counts, st);
+    hipError_t e = chunk_list(pg, below, rest, n_waves, l0, nl, fminf(sa.T0, sa.Tclamp), beta, as, am, cand, counts,
+                              stats, st);
     if (e != hipSuccess) return e;
-    const int64_t lpb = kListBlock / kWave;
-    hipLaunchKernelGGL(chunk_list_kernel, dim3((unsigned)((n_waves + lpb - 1) / lpb)), dim3(kListBlock), 0, st, pg,
-                       below, rest, n_waves, l0, nl, fminf(sa.T0, sa.Tclamp), beta, (const float*)as,
-                       (const float*)am, cand, counts, stats);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    const int64_t wpb = kCallBlock / kWave;
-    const int64_t waves = n_waves < kCallWaves ? n_waves : kCallWaves;
-    const dim3 grid((unsigned)((waves + wpb - 1) / wpb)), block(kCallBlock);
-    const unsigned* n_list = counts;
-    unsigned* next = counts + 1;
+    const dim3 grid = call_grid(n_waves), block(kCallBlock);
     switch (W) {
-        case 1: hipLaunchKernelGGL(fused_plain_call_kernel<1>, grid, block, 0, st, pg, tab, env, env_fc, below, rest, n_waves, l0, nl, K, n_steps, dt, sa, beta, as, am, cand, n_list, next, stats); break;
-        case 2: hipLaunchKernelGGL(fused_plain_call_kernel<2>, grid, block, 0, st, pg, tab, env, env_fc, below, rest, n_waves, l0, nl, K, n_steps, dt, sa, beta, as, am, cand, n_list, next, stats); break;
-        case 3: hipLaunchKernelGGL(fused_plain_call_kernel<3>, grid, block, 0, st, pg, tab, env, env_fc, below, rest, n_waves, l0, nl, K, n_steps, dt, sa, beta, as, am, cand, n_list, next, stats); break;
-        case 4: hipLaunchKernelGGL(fused_plain_call_kernel<4>, grid, block, 0, st, pg, tab, env, env_fc, below, rest, n_waves, l0, nl, K, n_steps, dt, sa, beta, as, am, cand, n_list, next, stats); break;
+        case 1: hipLaunchKernelGGL(fused_plain_call_kernel<1>, grid, block, 0, st, pg, tab, env, env_fc, below, rest, n_waves, l0, nl, K, n_steps, dt, sa, beta, as, am, cand, counts, counts + 1, stats); break;
+        case 2: hipLaunchKernelGGL(fused_plain_call_kernel<2>, grid, block, 0, st, pg, tab, env, env_fc, below, rest, n_waves, l0, nl, K, n_steps, dt, sa, beta, as, am, cand, counts, counts + 1, stats); break;
+        case 3: hipLaunchKernelGGL(fused_plain_call_kernel<3>, grid, block, 0, st, pg, tab, env, env_fc, below, rest, n_waves, l0, nl, K, n_steps, dt, sa, beta, as, am, cand, counts, counts + 1, stats); break;
+        case 4: hipLaunchKernelGGL(fused_plain_call_kernel<4>, grid, block, 0, st, pg, tab, env, env_fc, below, rest, n_waves, l0, nl, K, n_steps, dt, sa, beta, as, am, cand, counts, counts + 1, stats); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -807,63 +900,58 @@ __device__ __forceinline__ void fused_implicit_body(const PointGeom& pg, const S
     int gi, gj, gk;
     const int64_t local = point_at(pg, act ? g : 0, gi, gj, gk);
     act = act && gk >= pg.k0;
-    float a = act ? as[local] : 0.0f, m = act ? am[local] : 0.0f, b = 0.0f, alo = 0.0f, mlo = 0.0f;
-    double xb = (TRACK && act) ? track_check(xbv[local], a, m) : track_none();
+    float a = act ? as[local] : 0.0f, m = act ? am[local] : 0.0f;
     int bad = 0;
-    // still and cold waves as in fused_plain_kernel
-    const float rlim2 = envelope_radius2(pg);
-    const bool tried = wave_may_rest(env, act, a, m, T0c);
-    bool still = tried && ((!TRACK && wave_box_below(env, wv)) ||
-                           wave_below(env.rec, env.n, act, gi, gj, gk, rlim2, T0c, kRestBelow));
-    const bool cold = still || (!tried && wave_cold(env.rec, env.n, act, gi, gj, gk, rlim2));
-    float Tn = cold ? T0c : scan_temperature<W>(tab, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
-    const float inv = 1.0f / (float)n_sub;
-    still = still || (cold && T0c < Const<float>::TasEnd && __ballot(act && !rest_bits(a, m)) == 0);
-    if (TRACK && still) xb = track_none();
-    if (env.stats) count_wave(env, act, still, cold);
-    if (!still && !cold) __builtin_amdgcn_s_setprio(3);  // as in fused_plain_body
-    // a cold wave whose first step changed nothing it stores stops there (see
-    // frozen_part): with the high parts unchanged after every substep, each
-    // substep's iteration starts from the same state, converges at its first
-    // iterate with a zero residual and adds the same increments to the low
-    // parts; a first step with an unconverged substep does not stop, so that
-    // the count stays exact
-    const float a0 = a, m0 = m;
-    bool frozen = false;
-    for (int s = 0; s < K && !still && !frozen; ++s) {
-        const float Tn1 =
-            cold ? T0c : scan_temperature<W>(tab + (s + 1) * W, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
-        float Ta = Tn;
-        bool same = true;
-        for (int k = 0; k < n_sub; ++k) {
-            const float Tb = (k + 1 == n_sub) ? Tn1 : fmaf(Tn1 - Tn, (float)(k + 1) * inv, Tn);
-            const int it = TRACK ? implicit_step_tracked<true>(a, m, alo, mlo, xb, b, Ta, Tb, h, max_iter,
-                                                               sa.rd.mart_assign)
-                                 : implicit_step<true>(a, m, alo, mlo, b, Ta, Tb, h, max_iter, sa.rd.mart_assign);
-            if (it < 0) ++bad;
-            same = same && __float_as_uint(a) == __float_as_uint(a0) && __float_as_uint(m) == __float_as_uint(m0);
-            Ta = Tb;
+    if constexpr (!TRACK) {
+        float Tc;
+        const int r = implicit_launch<W>(pg, tab, env, wv, K, h, n_sub, max_iter, sa, act, gi, gj, gk, a, m, Tc, bad);
+        const float af = r == 0 ? a + 0.0f : a, mf = r == 0 ? m + 0.0f : m;
+        if (act) {
+            if (r == 2) {  // a still or frozen wave's fractions are those in memory
+                as[local] = af;
+                am[local] = mf;
+            }
+            if (beta) beta[local] = solid_fraction(Tc) - af - mf;
         }
-        Tn = Tn1;
-        if (!TRACK && s == 0 && cold)
-            frozen = __ballot(act && !(same && bad == 0 && frozen_part(a0, a, alo, K) && frozen_part(m0, m, mlo, K))) == 0;
-    }
-    if (act) {
-        a = frozen ? a0 : a + alo;
-        m = frozen ? m0 : m + mlo;
-        if (!still && !frozen) {  // a still or frozen wave's fractions are those in memory
-            as[local] = a;
-            am[local] = m;
+        record_rest(env, wv, act, af, mf);
+    } else {
+        float b = 0.0f, alo = 0.0f, mlo = 0.0f;
+        double xb = act ? track_check(xbv[local], a, m) : track_none();
+        // still and cold waves as in plain_launch (without the wave flags)
+        const float rlim2 = envelope_radius2(pg);
+        const bool tried = wave_may_rest(env, act, a, m, T0c);
+        bool still = tried && wave_below(env.rec, env.n, act, gi, gj, gk, rlim2, T0c, kRestBelow);
+        const bool cold = still || (!tried && wave_cold(env.rec, env.n, act, gi, gj, gk, rlim2));
+        float Tn = cold ? T0c : scan_temperature<W>(tab, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
+        const float inv = 1.0f / (float)n_sub;
+        still = still || (cold && T0c < Const<float>::TasEnd && __ballot(act && !rest_bits(a, m)) == 0);
+        if (still) xb = track_none();
+        if (env.stats) count_wave(env, act, still, cold);
+        for (int s = 0; s < K && !still; ++s) {
+            const float Tn1 =
+                cold ? T0c : scan_temperature<W>(tab + (s + 1) * W, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
+            float Ta = Tn;
+            for (int k = 0; k < n_sub; ++k) {
+                const float Tb = (k + 1 == n_sub) ? Tn1 : fmaf(Tn1 - Tn, (float)(k + 1) * inv, Tn);
+                if (implicit_step_tracked<true>(a, m, alo, mlo, xb, b, Ta, Tb, h, max_iter, sa.rd.mart_assign) < 0)
+                    ++bad;
+                Ta = Tb;
+            }
+            Tn = Tn1;
         }
-        if (beta) beta[local] = solid_fraction(Tn) - a - m;
-        if (TRACK) xbv[local] = xb;
+        if (act) {
+            a += alo;
+            m += mlo;
+            if (!still) {  // a still wave's fractions are those in memory
+                as[local] = a;
+                am[local] = m;
+            }
+            if (beta) beta[local] = solid_fraction(Tn) - a - m;
+            xbv[local] = xb;
+        }
+        if (!act) bad = 0;
     }
-    if (!TRACK) record_rest(env, wv, act, a, m);
-    if (!act) bad = 0;
-    int total = bad;
-    for (int o = 32; o > 0; o >>= 1) total += __shfl_xor(total, o);
-    if ((threadIdx.x & 63) == 0 && total) atomicAdd(unconverged, (unsigned long long)total);
-    __builtin_amdgcn_s_setprio(0);
+    add_unconverged(unconverged, bad);
 }
 
 template <int W, bool TRACK>
@@ -883,18 +971,6 @@ __global__ __launch_bounds__(kFusedBlock) void fused_implicit_kernel(PointGeom p
     fused_implicit_body<W, TRACK>(pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, xbv, unconverged, g, wv);
 }
 
-template <int W, int BS>
-__global__ __launch_bounds__(BS) void fused_implicit_slots_kernel(
-    PointGeom pg, const SrcRec* __restrict__ tab, EnvSet env, int K, float h, int n_sub, int max_iter, ScanArgs sa,
-    float* __restrict__ beta, float* __restrict__ as, float* __restrict__ am,
-    unsigned long long* __restrict__ unconverged) {
-    const int lane = threadIdx.x & (kWave - 1);
-    fused_slots<BS>(env, [&](int64_t w) {
-        fused_implicit_body<W, false>(pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, nullptr, unconverged,
-                                      w * kWave + lane, w);
-    });
-}
-
 template <bool TRACK>
 static hipError_t fused_implicit_w(const PointGeom& pg, int W, const SrcRec* tab, EnvSet env, int K, float h,
                                    int n_sub, int max_iter, ScanArgs sa, float* beta, float* as, float* am, double* xb,
@@ -908,6 +984,18 @@ static hipError_t fused_implicit_w(const PointGeom& pg, int W, const SrcRec* tab
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int W, int BS>
+__global__ __launch_bounds__(BS) void fused_implicit_slots_kernel(
+    PointGeom pg, const SrcRec* __restrict__ tab, EnvSet env, int K, float h, int n_sub, int max_iter, ScanArgs sa,
+    float* __restrict__ beta, float* __restrict__ as, float* __restrict__ am,
+    unsigned long long* __restrict__ unconverged) {
+    const int lane = threadIdx.x & (kWave - 1);
+    fused_slots<BS>(env, [&](int64_t w) {
+        fused_implicit_body<W, false>(pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, nullptr, unconverged,
+                                      w * kWave + lane, w);
+    });
 }
 
 hipError_t launch_fused_implicit(const PointGeom& pg, int W, const SrcRec* tab, EnvSet env, int K, float h, int n_sub,
