@@ -67,28 +67,34 @@ PAPER_CPU = {
 # (SQ_INSTS_VALU), the fraction of the dual-issue VALU capacity used
 # (SQ_ACTIVE_INST_VALU / (2 x SIMDs x quad-cycles)), the fraction of
 # quad-cycles with any VALU issue ((SQ_ACTIVE_INST_VALU - SQ_ACTIVE_INST_VALU2)
-# / (SIMDs x quad-cycles)), and HBM bytes per launch (FETCH_SIZE x 2.0 +
+# / (SIMDs x quad-cycles)), and HBM bytes per dispatch (FETCH_SIZE x 2.0 +
 # WRITE_SIZE x 1.0: the factors a plain 1 GiB device copy reads on the same
-# counters).  Each holds for the launch size K it was taken at; at another K
-# the figures are reported null.
+# counters; the PLAIN path's persistent kernel runs once per chunk of
+# launches of a call, the surrogate's slot kernel once per launch).  Each
+# holds for the launch size K it was taken at; at another K the figures are
+# reported null.
 FUSED_PROFILE = {
     "file": "profiles/fused_plain_kernel_multilayer_block.txt", "K": 64,
-    "valu_lane_ops_per_update": 10.140, "valu_issue": 0.366, "valu_busy": 0.530,
-    # the slot kernel and the list passes, per launch
-    "traffic_bytes_per_launch": 9272310,
+    "valu_lane_ops_per_update": 8.765, "valu_issue": 0.372, "valu_busy": 0.532,
+    # the persistent kernel with its list and still-flag passes, per dispatch (one per call)
+    "traffic_bytes_per_dispatch": 139318071,
 }
-FUSED_PROFILE_EVERY_T = {"K": 64, "valu_lane_ops_per_update": 129.27, "valu_issue": 0.727, "valu_busy": 0.926}
+FUSED_PROFILE_EVERY_T = {"K": 64, "valu_lane_ops_per_update": 130.31, "valu_issue": 0.730,
+                         "valu_busy": 0.926}
 SURROGATE_PROFILE = {"file": "profiles/fused_surrogate_kernels_multilayer_block.txt", "K": 64,
-                     8: {"valu_lane_ops_per_update": 4.274, "valu_issue": 0.192, "valu_busy": 0.309},
-                     16: {"valu_lane_ops_per_update": 3.561, "valu_issue": 0.168, "valu_busy": 0.280}}
+                     8: {"valu_lane_ops_per_update": 4.175, "valu_issue": 0.185, "valu_busy": 0.302},
+                     16: {"valu_lane_ops_per_update": 3.468, "valu_issue": 0.161, "valu_busy": 0.273}}
 C3_PROFILE = {"file": "profiles/fused_plain_kernel_cantilever_islands.txt", "K": K_C3,
-              "valu_lane_ops_per_update": 2.591, "valu_issue": 0.290, "valu_busy": 0.427,
-              "traffic_bytes_per_launch": 10711633}
+              "valu_lane_ops_per_update": 1.390, "valu_issue": 0.271, "valu_busy": 0.408,
+              "traffic_bytes_per_dispatch": 760057854}
 C5_PROFILE = {"file": "profiles/fused_kernels_island_block.txt",
-              "plain": {"K": K_FUSED, "valu_lane_ops_per_update": 3.732, "valu_issue": 0.563,
-                        "valu_busy": 0.774, "traffic_bytes_per_launch": (3986.7 * 2.0 + 7292.2) * 1024},
-              "surrogate": {"K": K_SURROGATE, "valu_lane_ops_per_update": 0.904, "valu_issue": 0.313,
-                            "valu_busy": 0.462, "traffic_bytes_per_launch": (4047.2 * 2.0 + 7292.4) * 1024}}
+              "plain": {"K": K_FUSED, "kernel": "fused_plain_call_kernel<2> + chunk_list_kernel + still_flags_kernel",
+                        "valu_lane_ops_per_update": 1.945, "valu_issue": 0.507, "valu_busy": 0.701,
+                        "traffic_bytes": 721086573, "traffic_unit": "bytes/dispatch"},
+              "surrogate": {"K": K_SURROGATE,
+                            "kernel": "fused_surrogate_slots_kernel<2,256> + surrogate_resume_kernel<2> + list passes",
+                            "valu_lane_ops_per_update": 0.613, "valu_issue": 0.249, "valu_busy": 0.375,
+                            "traffic_bytes": 23694107, "traffic_unit": "bytes/launch"}}
 
 
 def parse():
@@ -131,6 +137,39 @@ def call_launches(wl, K):
     return sum(math.ceil((L.step_end - L.step_begin) / K) for L in wl.layers)
 
 
+FLAG_BUDGET = 64 << 20  # bytes of still flags per chunk of launches of a fused call
+
+
+def call_chunks(wl, K):
+    """Per call of a layered workload: (active points, waves, launches, chunks
+    of launches).  A fused PLAIN call with wave flags runs one list pass and
+    one persistent kernel per chunk of launches whose still flags fit in 64 MiB
+    (1 byte per wave and launch)."""
+    out = []
+    for L in wl.layers:
+        pts = wl.active_count(L.z_top) if wl.grid.index is None else wl.grid.n
+        waves = (pts + 63) // 64
+        nl = math.ceil((L.step_end - L.step_begin) / K)
+        chunk = max(1, min(nl, FLAG_BUDGET // waves))
+        out.append((wl.active_count(L.z_top), waves, nl, math.ceil(nl / chunk)))
+    return out
+
+
+def call_dispatches(wl, K):
+    """Dispatches of the persistent PLAIN kernel in one run."""
+    return sum(c[3] for c in call_chunks(wl, K))
+
+
+def call_algorithmic_bytes(wl, K):
+    """Bytes a fused PLAIN run must move at least: per call the state read
+    once (8 B), beta written once (4 B) and the state written once (8 B, an
+    upper bound: still and frozen waves write nothing) per active point, 4 B
+    of index per point of an index list, and one byte of still flag per wave
+    and launch."""
+    idx = 4 if wl.grid.index is not None else 0
+    return sum((20 + idx) * pts + waves * nl for pts, waves, nl, _ in call_chunks(wl, K))
+
+
 def point_launches(wl, K):
     """Active points summed over the launches of one run."""
     return sum(wl.active_count(L.z_top) * math.ceil((L.step_end - L.step_begin) / K) for L in wl.layers)
@@ -151,49 +190,51 @@ def counted_run(torch, ms, ctx, wl, K, index=None):
     finally:
         ctx.set_option(ms.OPTION_COUNT_WAVES, 0)
     total = point_launches(wl, K)
-    beta_pts = sum(wl.active_count(L.z_top) for L in wl.layers)
-    launches = call_launches(wl, K)
-    idx_bytes = 4 if wl.grid.index is not None else 0  # index entry of each point a wave decodes
-    alg = 8.0 * c["points_loaded"] + 8.0 * c["points_stored"] + 4.0 * beta_pts + idx_bytes * c["points_loaded"]
     waves = c["still_waves"] + c["cold_waves"] + c["hot_waves"] + c["flagged_waves"]
     out = {"counts": c, "point_launches": total, "read_fraction": c["points_loaded"] / total,
            "written_fraction": c["points_stored"] / total,
            "wave_classes": {k: c[k] / waves for k in ("flagged_waves", "still_waves", "cold_waves", "hot_waves")},
-           "algorithmic_bytes_per_launch": alg / launches,
-           "bytes_rule": f"8 B read per point of the waves that read their state, 8 B written per point of the "
-                         f"waves that are not still, 4 B of beta per active point once per call"
-                         + (", 4 B of index per point read" if idx_bytes else "")}
+           "algorithmic_bytes_per_dispatch": call_algorithmic_bytes(wl, K) / call_dispatches(wl, K),
+           "bytes_rule": "per call: 8 B of state read, 8 B of state written (an upper bound) and 4 B of beta per "
+                         "active point, 1 B of still flag per wave and launch"
+                         + (", 4 B of index per point" if wl.grid.index is not None else "")
+                         + "; per dispatch of the persistent kernel (one per chunk of launches)",
+           "counts_note": "classes per wave and launch: a wave that is not still by its flags reads its state "
+                          "from registers inside a call, from memory once per call"}
     if c["hot_subblocks"]:
         s = c["indicator_subblocks"] / c["hot_subblocks"]
         out["surrogate_share_of_hot_subblocks"] = s
     return out
 
 
-def fused_roofline(kernel, prof, K, rate, avg_launch_s, counts):
-    """The fused kernels' roofline entry: VALU-bound.  achieved = point-updates
-    per second inside a launch (live HIP-event time) x the profile's executed
-    VALU lane-ops per update; traffic from the profile's counters; the
-    algorithmic bytes from this run's device-side counts."""
+def fused_roofline(kernel, prof, K, rate, avg_dispatch_s, counts):
+    """The fused PLAIN path's roofline entry: VALU-bound.  achieved =
+    point-updates per second over the timed region (live HIP-event time, the
+    persistent kernel with its list and still-flag passes) x the profile's
+    executed VALU lane-ops per update; traffic per dispatch of the persistent
+    kernel (with its passes) from the profile's counters; algorithmic bytes
+    per dispatch from the call sizes."""
     ok = prof["K"] == K
     ops = prof["valu_lane_ops_per_update"] if ok else None
-    traffic = prof["traffic_bytes_per_launch"] if ok else None
-    alg = counts["algorithmic_bytes_per_launch"] if counts else None
+    traffic = prof["traffic_bytes_per_dispatch"] if ok else None
+    alg = counts["algorithmic_bytes_per_dispatch"] if counts else None
     r = {"kernel": kernel, "bound": "alu",
          "achieved": rate * ops / 1e12 if ops else None, "peak": VALU_PEAK_TLANEOPS, "unit": "Tlane-op/s",
          "frac": rate * ops / 1e12 / VALU_PEAK_TLANEOPS if ops else None,
          "frac_source": "live point-updates/s x the profile's VALU instructions per update (null: the profile "
                         "was taken at another K)",
-         "measured_limit": "neither roofline is reached: the few hot waves per launch (3 % of the waves on a "
-                           "layer scan) run chains of K dependent steps, a handful per SIMD, and leave the VALU "
-                           "idle for much of the launch (valu_busy_frac); HBM traffic is under 1 % of 8 TB/s",
-         "traffic": traffic, "traffic_unit": "bytes/launch",
-         "algorithmic_bytes_per_launch": alg,
+         "measured_limit": "neither roofline is reached: the waves near the tracks (3 % of the wave-launches "
+                           "on a layer scan) run chains of K dependent steps launch after launch, a few per "
+                           "SIMD, and leave the VALU idle for part of the time (valu_busy_frac); HBM traffic is "
+                           "under 1 % of 8 TB/s",
+         "traffic": traffic, "traffic_unit": "bytes/dispatch",
+         "algorithmic_bytes_per_dispatch": alg,
          "traffic_over_algorithmic": traffic / alg if traffic and alg else None,
-         "hbm_GBs": alg / avg_launch_s / 1e9 if alg else None,
+         "hbm_GBs": alg / avg_dispatch_s / 1e9 if alg else None,
          "lane_ops_per_update": ops, "valu_issue_frac": prof.get("valu_issue") if ok else None,
          "valu_busy_frac": prof.get("valu_busy") if ok else None,
-         "peak_derivation": PEAK_DERIVATION, "avg_launch_us": avg_launch_s * 1e6,
-         "point_updates_per_s_in_launch": rate, "profile": prof.get("file"), "profile_K": prof["K"]}
+         "peak_derivation": PEAK_DERIVATION, "avg_dispatch_us": avg_dispatch_s * 1e6,
+         "point_updates_per_s": rate, "profile": prof.get("file"), "profile_K": prof["K"]}
     return r
 
 
@@ -294,11 +335,12 @@ def bench_c2(torch, ms, ctx, args):
     ms_total, wall = timed(ms.MODE_PLAIN, args.K)
     ms_per_step = ms_total / args.steps
     value = updates * args.steps / (ms_total * 1e-3)
-    # average duration of one fused launch over the timed region (with its
-    # list pass; besides them only the still-flag pre-pass, one per call, and
+    # average duration of one dispatch of the persistent kernel over the timed
+    # region (with its list and still-flag passes, one each per dispatch, and
     # three state resets per step)
-    avg_launch_s = ms_total * 1e-3 / (args.steps * launches)
-    rate = updates / launches / avg_launch_s  # point-updates/s inside one launch
+    dispatches = call_dispatches(wl, args.K)
+    avg_dispatch_s = ms_total * 1e-3 / (args.steps * dispatches)
+    rate = updates * args.steps / (ms_total * 1e-3)
     result = {
         "metric": "microstructure point-updates/s @8.4M pts (256x256x128 block, 10 layers, 20k steps): FP32 plain",
         "value": value,
@@ -320,9 +362,10 @@ def bench_c2(torch, ms, ctx, args):
     final = [x.clone() for x in (b, a, m)]
     counts = counted_run(torch, ms, ctx, wl, args.K)
     result["roofline"] = fused_roofline(
-        f"fused_plain_slots_kernel<{wl.scan.window},128> (list form) + candidates_kernel / first_candidates_kernel",
-        FUSED_PROFILE, args.K, rate, avg_launch_s, counts)
-    result["roofline"]["launches_timed"] = args.steps * launches
+        f"fused_plain_call_kernel<{wl.scan.window}> (one per call) + chunk_list_kernel + still_flags_kernel",
+        FUSED_PROFILE, args.K, rate, avg_dispatch_s, counts)
+    result["roofline"]["dispatches_timed"] = args.steps * dispatches
+    result["roofline"]["launches_of_K_steps_timed"] = args.steps * launches
     result["wave_counts"] = counts
 
     # the same run with every temperature evaluated (launch certificates
@@ -414,15 +457,16 @@ def bench_c3(torch, ms, ctx, args):
     e1.record()
     torch.cuda.synchronize()
     t = e0.elapsed_time(e1) * 1e-3
-    launches = call_launches(wl, K)
-    avg = t / launches
+    dispatches = call_dispatches(wl, K)
     counts = counted_run(torch, ms, ctx, wl, K, index=idx)
     out = {"workload": "cantilever_islands", "points": n, "box": [wl.grid.nx, wl.grid.ny, wl.grid.nz],
            "layers": len(wl.layers), "time_steps": wl.n_steps, "active_point_updates": upd, "K": K,
+           "point_order": "8 x 8 tiles of each plane (workload.tile_order)",
            "seconds": t, "value": upd / t, "unit": "point-updates/s",
-           "roofline": fused_roofline("fused_plain_slots_kernel<2,256> (list form, index list) + list passes",
-                                      C3_PROFILE, K, upd / launches / avg, avg, counts),
+           "roofline": fused_roofline("fused_plain_call_kernel<2> (index list) + chunk_list_kernel + still_flags_kernel",
+                                      C3_PROFILE, K, upd / t, t / dispatches, counts),
            "wave_counts": counts}
+    out["roofline"]["dispatches_timed"] = dispatches
     print(f"c3: {t:.2f} s", file=sys.stderr, flush=True)
     return out, g
 
@@ -452,15 +496,18 @@ def bench_c5(torch, ms, ctx, args):
         t = e0.elapsed_time(e1) * 1e-3
         prof = C5_PROFILE[key]
         rate = upd / t
-        launches = call_launches(wl, 64)  # both modes launch 64 steps at a time
+        # the plain path: one persistent kernel per chunk of launches; the
+        # surrogate: one slot kernel per launch of 64 steps
+        units = call_dispatches(wl, K) if key == "plain" else call_launches(wl, 64)
         out[key] = {"seconds": t, "value": rate, "unit": "point-updates/s", "K": K,
-                    "roofline": {"bound": "alu", "peak": VALU_PEAK_TLANEOPS, "unit": "Tlane-op/s",
+                    "roofline": {"kernel": prof["kernel"], "bound": "alu", "peak": VALU_PEAK_TLANEOPS,
+                                 "unit": "Tlane-op/s",
                                  "achieved": rate * prof["valu_lane_ops_per_update"] / 1e12,
                                  "frac": rate * prof["valu_lane_ops_per_update"] / 1e12 / VALU_PEAK_TLANEOPS,
                                  "lane_ops_per_update": prof["valu_lane_ops_per_update"],
                                  "valu_issue_frac": prof["valu_issue"], "valu_busy_frac": prof["valu_busy"],
-                                 "traffic": prof["traffic_bytes_per_launch"], "traffic_unit": "bytes/launch",
-                                 "hbm_GBs": prof["traffic_bytes_per_launch"] * launches / t / 1e9,
+                                 "traffic": prof["traffic_bytes"], "traffic_unit": prof["traffic_unit"],
+                                 "hbm_GBs": prof["traffic_bytes"] * units / t / 1e9 if prof["traffic_bytes"] else None,
                                  "profile": C5_PROFILE["file"]}}
         print(f"c5 {key}: {t:.2f} s", file=sys.stderr, flush=True)
         states[key] = g
