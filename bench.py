@@ -85,8 +85,8 @@ SURROGATE_PROFILE = {"file": "profiles/fused_surrogate_kernels_multilayer_block.
                      8: {"valu_lane_ops_per_update": 4.175, "valu_issue": 0.185, "valu_busy": 0.302},
                      16: {"valu_lane_ops_per_update": 3.468, "valu_issue": 0.161, "valu_busy": 0.273}}
 C3_PROFILE = {"file": "profiles/fused_plain_kernel_cantilever_islands.txt", "K": K_C3,
-              "valu_lane_ops_per_update": 1.390, "valu_issue": 0.271, "valu_busy": 0.408,
-              "traffic_bytes_per_dispatch": 760057854}
+              "valu_lane_ops_per_update": 1.392, "valu_issue": 0.283, "valu_busy": 0.423,
+              "traffic_bytes_per_dispatch": 2045373600}
 C5_PROFILE = {"file": "profiles/fused_kernels_island_block.txt",
               "plain": {"K": K_FUSED, "kernel": "fused_plain_call_kernel<2> + chunk_list_kernel + still_flags_kernel",
                         "valu_lane_ops_per_update": 1.945, "valu_issue": 0.507, "valu_busy": 0.701,
@@ -137,13 +137,13 @@ def call_launches(wl, K):
     return sum(math.ceil((L.step_end - L.step_begin) / K) for L in wl.layers)
 
 
-FLAG_BUDGET = 64 << 20  # bytes of still flags per chunk of launches of a fused call
+FLAG_BUDGET = 256 << 20  # bytes of still flags per chunk of launches of a fused call
 
 
 def call_chunks(wl, K):
     """Per call of a layered workload: (active points, waves, launches, chunks
     of launches).  A fused PLAIN call with wave flags runs one list pass and
-    one persistent kernel per chunk of launches whose still flags fit in 64 MiB
+    one persistent kernel per chunk of launches whose still flags fit in 256 MiB
     (1 byte per wave and launch)."""
     out = []
     for L in wl.layers:

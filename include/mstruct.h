@@ -290,7 +290,7 @@ int mstruct_fused_scan_steps_noalloc(mstruct_ctx *ctx, const mstruct_scan *scan,
  * waves were at rest: from the second launch of a call such a wave reads
  * neither its state nor a track.  For this the context keeps 2 n/64 bytes
  * (and 24 (n/64 + n/4096) bytes of boxes with an index list) plus at most
- * 64 MiB of still flags per call on the device, until mstruct_destroy.  The results are the same bit for bit as with 0, which
+ * 256 MiB of still flags per call on the device, until mstruct_destroy.  The results are the same bit for bit as with 0, which
  * evaluates every temperature and takes every step (for comparison). */
 enum {
     MSTRUCT_OPTION_SKIP_COLD_WAVES = 1,

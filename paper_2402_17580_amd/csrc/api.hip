@@ -230,7 +230,7 @@ constexpr double kImplicitDtSub = 0.01;
 constexpr int kImplicitMaxIter = 50;
 
 // bytes of still flags per chunk of launches of a fused call
-constexpr int64_t kWaveFlagBudget = (int64_t)64 << 20;
+constexpr int64_t kWaveFlagBudget = (int64_t)256 << 20;
 
 void split(double g, int32_t& i, float& f) {
     const double fl = floor(g);
