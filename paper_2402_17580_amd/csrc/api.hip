@@ -685,10 +685,11 @@ int fused_run(mstruct_ctx* ctx, const mstruct_scan* scan, const mstruct_points* 
         hipError_t e = surrogate_prepare(ctx->mlp, n_waves, st);
         if (e != hipSuccess) return hip_fail(ctx, e, "surrogate records");
     }
-    if (mode == MSTRUCT_MODE_PLAIN && wave_flags && b.cand) {
-        // each chunk of launches in one persistent kernel (fused_plain_call_kernel); IMPLICIT calls, whose
-        // cool-downs step most waves in every launch, keep one kernel per launch: in one kernel per chunk
-        // the last waves run whole chunks alone (cool-down workload 194 -> 216 ms)
+    if (mode != MSTRUCT_MODE_IMPLICIT && wave_flags && b.cand) {
+        // each chunk of launches in one persistent kernel (fused_plain_call_kernel; SURROGATE:
+        // fused_surrogate_call_kernel and surrogate_resume_call_kernel); IMPLICIT calls, whose cool-downs
+        // step most waves in every launch, keep one kernel per launch: in one kernel per chunk the last
+        // waves run whole chunks alone (cool-down workload 194 -> 216 ms)
         for (int64_t l0 = 0; l0 < n_launches; l0 += chunk) {
             const int64_t nl = (n_launches - l0) < chunk ? (n_launches - l0) : chunk;
             const GridBox* boxes = pts->index ? b.boxes : nullptr;
@@ -699,10 +700,14 @@ int fused_run(mstruct_ctx* ctx, const mstruct_scan* scan, const mstruct_points* 
                                        b.flags + n_waves, st);
             float* beta = l0 + nl == n_launches ? ph->beta : nullptr;
             unsigned long long* stats = ctx->count_waves ? ctx->stats : nullptr;
-            if (e == hipSuccess)
+            if (e == hipSuccess && mode == MSTRUCT_MODE_PLAIN)
                 e = launch_fused_plain_call(pg, W, b.dev, env_dev, fc_dev, b.flags + n_waves, b.flags, n_waves, l0,
                                             nl, K, n_steps, (float)dt, sa, beta, ph->alpha_s, ph->alpha_m, b.cand,
                                             b.cand_counts, stats, st);
+            else if (e == hipSuccess)
+                e = launch_surrogate_call(ctx->mlp, pg, W, b.dev, env_dev, fc_dev, b.flags + n_waves, b.flags, n_waves,
+                                          l0, nl, K, Ks, n_steps, (float)dt, sa, beta, ph->alpha_s, ph->alpha_m, b.cand,
+                                          b.cand_counts, stats, st);
             if (e != hipSuccess) return hip_fail(ctx, e, "fused call launch");
         }
         return MSTRUCT_OK;

@@ -179,16 +179,9 @@ inline dim3 slots_grid(int64_t n_waves, int bs, int spw) {
             hipLaunchKernelGGL((kernel<W, 128>), slots_grid(n_waves, 128, spw), dim3(128), 0, st, __VA_ARGS__); \
     } while (0)
 
-// Waves of points per grid wave of a slot kernel (IMPLICIT and SURROGATE
-// launches): the grid only has to hold the listed waves, a few per cent of a
-// launch.  Four below kSlotsLargeGrid waves; on large grids 8 for the
-// surrogate, 4 otherwise (sizes chosen when the grid waves scanned the flags
-// themselves; with the lists anything from 4 to 32 is within 1 %, and 2 is
-// 6-9 % slower on the large grids).
-enum class SlotUse { Surrogate, Implicit };
-inline int slots_per_wave(int64_t n_waves, SlotUse use) {
-    if (n_waves < kSlotsLargeGrid) return kSlotsPerWave;
-    return use == SlotUse::Surrogate ? 8 : kSlotsPerWave;
-}
+// Waves of points per grid wave of a slot kernel (IMPLICIT launches): the
+// grid only has to hold the listed waves, a few per cent of a launch (from
+// 4 to 32 within 1 %; 2 was 6-9 % slower on the large grids).
+inline int slots_per_wave(int64_t) { return kSlotsPerWave; }
 
 }  // namespace mstruct

@@ -171,6 +171,16 @@ hipError_t launch_fused_plain_call(const PointGeom& pg, int W, const SrcRec* tab
                                    int64_t l0, int64_t nl, int K, int64_t n_steps, float dt, ScanArgs sa, float* beta,
                                    float* as, float* am, uint32_t* cand, unsigned* counts,
                                    unsigned long long* stats, hipStream_t st);
+// the list pass of a chunk of launches l0 .. l0 + nl - 1 (chunk_list_kernel):
+// the waves that are not still throughout the chunk in cand[0 .. counts[0]);
+// counts[0] and counts[1] cleared first
+hipError_t launch_chunk_list(const PointGeom& pg, const uint8_t* below, uint8_t* rest, int64_t n_waves, int64_t l0,
+                             int64_t nl, float T0c, float* beta, const float* as, const float* am, uint32_t* cand,
+                             unsigned* counts, unsigned long long* stats, hipStream_t st);
+// workgroup and grid of the persistent call kernels (kCallBlock threads, at
+// most eight waves per SIMD)
+constexpr int kCallBlock = 256;
+dim3 call_grid(int64_t n_waves);
 hipError_t launch_gather(const float* src, const int64_t* idx, int64_t m, float* dst, hipStream_t st);
 hipError_t launch_invariants(const float* beta, const float* as, const float* am, const float* T, int64_t n,
                              float tol, unsigned long long* counter, hipStream_t st);

@@ -643,7 +643,6 @@ __global__ __launch_bounds__(kListBlock) void chunk_list_kernel(
 // at rest after the last launch that took its steps: read from the second
 // chunk, written at the end of each).
 // ---------------------------------------------------------------------------
-constexpr int kCallBlock = 256;
 // grid waves of the persistent call kernel: eight per SIMD
 constexpr int kCallWaves = 256 * 4 * 8;
 
@@ -730,8 +729,8 @@ __global__ __launch_bounds__(kCallBlock) void fused_plain_call_kernel(
                });
 }
 
-// the list pass of a chunk (counts cleared first); then the call kernel
-static hipError_t chunk_list(const PointGeom& pg, const uint8_t* below, uint8_t* rest, int64_t n_waves, int64_t l0,
+// the list pass of a chunk (counts cleared first)
+hipError_t launch_chunk_list(const PointGeom& pg, const uint8_t* below, uint8_t* rest, int64_t n_waves, int64_t l0,
                              int64_t nl, float T0c, float* beta, const float* as, const float* am, uint32_t* cand,
                              unsigned* counts, unsigned long long* stats, hipStream_t st) {
     hipError_t e = launch_clear_counts(counts, st);
@@ -742,7 +741,7 @@ static hipError_t chunk_list(const PointGeom& pg, const uint8_t* below, uint8_t*
     return hipGetLastError();
 }
 
-static dim3 call_grid(int64_t n_waves) {
+dim3 call_grid(int64_t n_waves) {
     const int64_t wpb = kCallBlock / kWave;
     const int64_t waves = n_waves < kCallWaves ? n_waves : kCallWaves;
     return dim3((unsigned)((waves + wpb - 1) / wpb));
@@ -754,8 +753,8 @@ hipError_t launch_fused_plain_call(const PointGeom& pg, int W, const SrcRec* tab
                                    float* as, float* am, uint32_t* cand, unsigned* counts,
                                    unsigned long long* stats, hipStream_t st) {
     if (n_waves <= 0 || nl <= 0) return hipSuccess;
-    hipError_t e = chunk_list(pg, below, rest, n_waves, l0, nl, fminf(sa.T0, sa.Tclamp), beta, as, am, cand, counts,
-                              stats, st);
+    hipError_t e = launch_chunk_list(pg, below, rest, n_waves, l0, nl, fminf(sa.T0, sa.Tclamp), beta, as, am, cand,
+                                     counts, stats, st);
     if (e != hipSuccess) return e;
     const dim3 grid = call_grid(n_waves), block(kCallBlock);
     switch (W) {
@@ -1004,10 +1003,10 @@ hipError_t launch_fused_implicit(const PointGeom& pg, int W, const SrcRec* tab, 
     if (pg.count <= 0) return hipSuccess;
     if (!xb && env.below && env.cand) {
         switch (W) {
-            case 1: LAUNCH_SLOTS(fused_implicit_slots_kernel, 1, env.n_waves, slots_per_wave(env.n_waves, SlotUse::Implicit), st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
-            case 2: LAUNCH_SLOTS(fused_implicit_slots_kernel, 2, env.n_waves, slots_per_wave(env.n_waves, SlotUse::Implicit), st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
-            case 3: LAUNCH_SLOTS(fused_implicit_slots_kernel, 3, env.n_waves, slots_per_wave(env.n_waves, SlotUse::Implicit), st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
-            case 4: LAUNCH_SLOTS(fused_implicit_slots_kernel, 4, env.n_waves, slots_per_wave(env.n_waves, SlotUse::Implicit), st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
+            case 1: LAUNCH_SLOTS(fused_implicit_slots_kernel, 1, env.n_waves, slots_per_wave(env.n_waves), st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
+            case 2: LAUNCH_SLOTS(fused_implicit_slots_kernel, 2, env.n_waves, slots_per_wave(env.n_waves), st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
+            case 3: LAUNCH_SLOTS(fused_implicit_slots_kernel, 3, env.n_waves, slots_per_wave(env.n_waves), st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
+            case 4: LAUNCH_SLOTS(fused_implicit_slots_kernel, 4, env.n_waves, slots_per_wave(env.n_waves), st, pg, tab, env, K, h, n_sub, max_iter, sa, beta, as, am, unconverged); break;
             default: return hipErrorInvalidValue;
         }
         return hipGetLastError();

@@ -71,6 +71,16 @@ hipError_t mlp_adam(MlpState& s, float lr, hipStream_t st);
 hipError_t surrogate_prepare(MlpState& s, int64_t waves, hipStream_t st);
 // one launch of Kl steps (launch li of the call) in blocks of Ks steps, with
 // the launch certificates and wave flags of env as in the plain fused launch
+// SURROGATE launches l0 .. l0 + nl - 1 of a call with wave flags: the list
+// pass, fused_surrogate_call_kernel (no network; waves that need it are
+// recorded) and surrogate_resume_call_kernel (the recorded waves to the end of
+// the chunk, with the network); arguments as for launch_fused_plain_call, Kl
+// steps per launch, networks of Ks steps
+hipError_t launch_surrogate_call(const MlpState& s, const PointGeom& pg, int W, const SrcRec* tab, const EnvRec* env,
+                                 const int32_t* env_fc, const uint8_t* below, uint8_t* rest, int64_t n_waves,
+                                 int64_t l0, int64_t nl, int Kl, int Ks, int64_t n_steps, float dt, ScanArgs sa,
+                                 float* beta, float* as, float* am, uint32_t* cand, unsigned* counts,
+                                 unsigned long long* stats, hipStream_t st);
 hipError_t launch_surrogate(const MlpState& s, const PointGeom& pg, int W, const SrcRec* tab, EnvSet env, int Kl,
                             int Ks, float dt, ScanArgs sa, float* beta, float* as, float* am, int64_t li,
                             hipStream_t st);

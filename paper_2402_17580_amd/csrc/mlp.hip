@@ -596,6 +596,8 @@ struct SurrogateRecord {
     int64_t wave;
     int32_t block;
     int32_t cold;
+    int32_t launch;  // the launch of the call (persistent form; the launch form does not read it)
+    int32_t pad;
     float a[kWave], m[kWave], alo[kWave], mlo[kWave], Tn[kWave];
 };
 
@@ -702,6 +704,54 @@ __device__ __forceinline__ void surrogate_store(const EnvSet& env, int64_t wv, b
     record_rest(env, wv, act, af, mf);
 }
 
+// One surrogate launch of a wave on its register state: still and cold
+// waves as in the plain fused kernel, then the network blocks.  a, m: the
+// fractions as loaded; returns 0 (still: a, m unchanged, Tn = T0), 2 (done:
+// hi parts a, m and lo parts alo, mlo at the end of the launch, Tn its last
+// temperature) or, with NET == kNetStop, 3: block j needs the network, and
+// a, m, alo, mlo, Tn hold the state at that block's start (cold: whether the
+// wave is cold in this launch).
+template <int W, int NET>
+__device__ __forceinline__ int surrogate_launch(const PointGeom& pg, const SrcRec* __restrict__ tab, const EnvSet& env,
+                                                int64_t wv, int Kl, int Ks, float dt, const ScanArgs& sa,
+                                                const MlpNorm& nrm, const InferLds* L, bool act, int gi, int gj,
+                                                int gk, float& a, float& m, float& alo, float& mlo, float& Tn,
+                                                bool& cold_out, int& j) {
+    const float T0c = fminf(sa.T0, sa.Tclamp);
+    alo = 0.0f;
+    mlo = 0.0f;
+    const float rlim2 = envelope_radius2(pg);
+    const bool tried = wave_may_rest(env, act, a, m, T0c);
+    bool still = tried && (wave_box_below(env, wv) ||
+                           wave_below(env.rec, env.n, act, gi, gj, gk, rlim2, T0c, kRestBelow));
+    const bool cold = still || (!tried && wave_cold(env.rec, env.n, act, gi, gj, gk, rlim2));
+    Tn = cold ? T0c : scan_temperature<W>(tab, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
+    still = still || (cold && T0c < Const<float>::TasEnd && __ballot(act && !rest_bits(a, m)) == 0);
+    if (env.stats) count_wave(env, act, still, cold);
+    cold_out = cold;
+    if (still) return 0;  // its fractions are those in memory
+    if (!cold) __builtin_amdgcn_s_setprio(3);  // as in plain_launch
+    j = surrogate_blocks<W, NET>(pg, tab, Kl, Ks, dt, sa, nrm, L, act, cold, gi, gj, gk, 0, a, m, alo, mlo, Tn);
+    __builtin_amdgcn_s_setprio(0);
+    return j >= 0 ? 3 : 2;
+}
+
+// a wave's state at the start of block j of launch l, for the resume kernels
+// (written by every lane: no branch on the lane)
+__device__ __forceinline__ void write_record(SurrogateRecord& r, int64_t wv, int j, bool cold, int64_t l, float a,
+                                             float m, float alo, float mlo, float Tn) {
+    const int lane = threadIdx.x & (kWave - 1);
+    r.wave = wv;
+    r.block = j;
+    r.cold = cold ? 1 : 0;
+    r.launch = (int32_t)l;
+    r.a[lane] = a;
+    r.m[lane] = m;
+    r.alo[lane] = alo;
+    r.mlo[lane] = mlo;
+    r.Tn[lane] = Tn;
+}
+
 // the body of a fused surrogate launch for wave wv (points g = 64 wv + lane)
 template <int W>
 __device__ __forceinline__ void surrogate_fused_body(const PointGeom& pg, const SrcRec* __restrict__ tab,
@@ -710,47 +760,25 @@ __device__ __forceinline__ void surrogate_fused_body(const PointGeom& pg, const 
                                                      float* __restrict__ as, float* __restrict__ am,
                                                      SurrogateRecord* __restrict__ recs, unsigned* __restrict__ n_recs,
                                                      int64_t cap, int64_t g, int64_t wv) {
-    const float T0c = fminf(sa.T0, sa.Tclamp);
     bool act = g < pg.count;
     int gi, gj, gk;
     const int64_t local = point_at(pg, act ? g : 0, gi, gj, gk);
     act = act && gk >= pg.k0;
-    float a = act ? as[local] : 0.0f, m = act ? am[local] : 0.0f, alo = 0.0f, mlo = 0.0f;
-    // still and cold waves as in the plain fused kernel
-    const float rlim2 = envelope_radius2(pg);
-    const bool tried = wave_may_rest(env, act, a, m, T0c);
-    bool still = tried && (wave_box_below(env, wv) ||
-                           wave_below(env.rec, env.n, act, gi, gj, gk, rlim2, T0c, kRestBelow));
-    const bool cold = still || (!tried && wave_cold(env.rec, env.n, act, gi, gj, gk, rlim2));
-    float Tn = cold ? T0c : scan_temperature<W>(tab, gi, gj, gk, sa.T0, sa.Tclamp, pg.r2min, pg.roff);
-    still = still || (cold && T0c < Const<float>::TasEnd && __ballot(act && !rest_bits(a, m)) == 0);
-    if (env.stats) count_wave(env, act, still, cold);
-    if (still) {  // its fractions are those in memory
+    float a = act ? as[local] : 0.0f, m = act ? am[local] : 0.0f, alo, mlo, Tn;
+    bool cold;
+    int j = -1;
+    const int r = surrogate_launch<W, kNetStop>(pg, tab, env, wv, Kl, Ks, dt, sa, nrm, nullptr, act, gi, gj, gk, a, m,
+                                                alo, mlo, Tn, cold, j);
+    if (r == 0) {  // still: its fractions are those in memory
         if (act && beta) beta[local] = solid_fraction(Tn) - a - m;
         record_rest(env, wv, act, a, m);
         return;
     }
-    if (!cold) __builtin_amdgcn_s_setprio(3);  // as in fused_plain_body
-    const int j = surrogate_blocks<W, kNetStop>(pg, tab, Kl, Ks, dt, sa, nrm, nullptr, act, cold, gi, gj, gk, 0, a, m,
-                                                alo, mlo, Tn);
-    __builtin_amdgcn_s_setprio(0);
-    if (j >= 0) {
-        unsigned slot = 0;
-        if ((threadIdx.x & (kWave - 1)) == 0) slot = atomicAdd(n_recs, 1u);
-        slot = __shfl(slot, 0);
+    if (r == 3) {
+        const unsigned slot =
+            __builtin_amdgcn_readfirstlane(atomicAdd(n_recs, (threadIdx.x & (kWave - 1)) == 0 ? 1u : 0u));
         if ((int64_t)slot < cap) {
-            SurrogateRecord& r = recs[slot];
-            const int lane = threadIdx.x & (kWave - 1);
-            if (lane == 0) {
-                r.wave = wv;
-                r.block = j;
-                r.cold = cold ? 1 : 0;
-            }
-            r.a[lane] = a;
-            r.m[lane] = m;
-            r.alo[lane] = alo;
-            r.mlo[lane] = mlo;
-            r.Tn[lane] = Tn;
+            write_record(recs[slot], wv, j, cold, 0, a, m, alo, mlo, Tn);
             return;  // the resume kernel takes the wave from block j
         }
         // no room for the record: this wave takes plain steps where the network would act
@@ -776,20 +804,6 @@ __global__ __launch_bounds__(kFusedBlock) void fused_surrogate_kernel(PointGeom 
         return;
     }
     surrogate_fused_body<W>(pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, n_recs, cap, g, wv);
-}
-
-template <int W, int BS>
-__global__ __launch_bounds__(BS) void fused_surrogate_slots_kernel(PointGeom pg, const SrcRec* __restrict__ tab,
-                                                                   EnvSet env, int Kl, int Ks, float dt, ScanArgs sa,
-                                                                   MlpNorm nrm, float* __restrict__ beta,
-                                                                   float* __restrict__ as, float* __restrict__ am,
-                                                                   SurrogateRecord* __restrict__ recs,
-                                                                   unsigned* __restrict__ n_recs, int64_t cap) {
-    const int lane = threadIdx.x & (kWave - 1);
-    fused_slots<BS>(env, [&](int64_t w) {
-        surrogate_fused_body<W>(pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, n_recs, cap, w * kWave + lane,
-                                w);
-    });
 }
 
 // The waves that stopped for the network: a persistent grid, each wave one
@@ -819,6 +833,170 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void s
         surrogate_blocks<W, kNetRun>(pg, tab, Kl, Ks, dt, sa, nrm, &L, act, r.cold != 0, gi, gj, gk, r.block, a, m, alo,
                                      mlo, Tn);
         surrogate_store(env, wv, act, local, a, m, alo, mlo, Tn, beta, as, am);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// SURROGATE calls in the persistent form of the plain path (see
+// fused_plain_call_kernel): per chunk of launches the list pass,
+// fused_surrogate_call_kernel and surrogate_resume_call_kernel.  The call
+// kernel runs each listed wave through the chunk's launches on registers
+// without the network; a wave with a block that needs the network records
+// its state at that block's start and the launch, and leaves the rest of the
+// chunk to the resume kernel, which evaluates the network there and runs the
+// wave's remaining launches of the chunk, the network wherever it is needed.
+// What each wave computes is what the launch-by-launch form computes.  No
+// branch on the lane inside the kernels' loops (see fused_call).
+// ---------------------------------------------------------------------------
+template <int W>
+__global__ __launch_bounds__(kCallBlock) void fused_surrogate_call_kernel(
+    PointGeom pg, const SrcRec* __restrict__ tab, const EnvRec* __restrict__ env, const int32_t* __restrict__ env_fc,
+    const uint8_t* __restrict__ below, uint8_t* __restrict__ rest, int64_t n_waves, int64_t l0, int64_t nl, int Kl,
+    int Ks, int64_t n_steps, float dt, ScanArgs sa, MlpNorm nrm, float* __restrict__ beta, float* __restrict__ as,
+    float* __restrict__ am, const uint32_t* __restrict__ cand, const unsigned* __restrict__ counts,
+    unsigned* __restrict__ next, unsigned long long* __restrict__ stats, SurrogateRecord* __restrict__ recs,
+    unsigned* __restrict__ n_recs, int64_t cap) {
+    const float T0c = fminf(sa.T0, sa.Tclamp);
+    const int lane = threadIdx.x & (kWave - 1);
+    const int64_t n_list = counts[0];
+    for (;;) {
+        const unsigned ei = atomicAdd(next, lane == 0 ? 1u : 0u);
+        const int64_t e = (int64_t)(unsigned)__builtin_amdgcn_readfirstlane((int)ei);
+        if (e >= n_list) return;  // uniform per wave: every wave ends once the counter passes the list
+        const int64_t w = (int64_t)(unsigned)__builtin_amdgcn_readfirstlane((int)cand[e]);
+        const int64_t g = w * kWave + lane;
+        bool act = g < pg.count;
+        int gi, gj, gk;
+        const int64_t local = point_at(pg, act ? g : 0, gi, gj, gk);
+        act = act && gk >= pg.k0;
+        float a = act ? as[local] : 0.0f, m = act ? am[local] : 0.0f;
+        float af = a, mf = m, Tc = T0c;
+        bool rest_w = l0 == 0 ? __ballot(act && !rest_bits(a, m)) == 0 : rest[w] != 0;
+        bool changed = false, flagged = false, parked = false;
+        uint64_t bm = 0;
+        int64_t lb = l0 - kWave;
+        for (int64_t l = l0; l < l0 + nl; ++l) {
+            const uint8_t* bl = below + (l - l0) * n_waves;
+            if (l - lb >= kWave) {  // (uniform) lane i loads launch l + i's flag
+                lb = l;
+                bm = __ballot(l + lane < l0 + nl && below[(l - l0 + lane) * n_waves + w] != 0);
+            }
+            flagged = rest_w && ((bm >> (l - lb)) & 1);
+            if (flagged) {
+                if (stats) atomicAdd(stats + kStatFlagged, lane == 0 ? 1ull : 0ull);
+                continue;
+            }
+            const int64_t s0 = l * Kl;
+            const int Kb = (int)min((int64_t)Kl, n_steps - s0);
+            const EnvSet es{env + env_fc[2 * l], env_fc[2 * l + 1], bl, nullptr, n_waves, 0, stats,
+                            nullptr, nullptr, nullptr};
+            float alo, mlo, Tn;
+            bool cold;
+            int j = -1;
+            int r = surrogate_launch<W, kNetStop>(pg, tab + s0 * W, es, w, Kb, Ks, dt, sa, nrm, nullptr, act, gi, gj,
+                                                  gk, a, m, alo, mlo, Tn, cold, j);
+            if (r == 3) {
+                const unsigned slot = __builtin_amdgcn_readfirstlane(atomicAdd(n_recs, lane == 0 ? 1u : 0u));
+                if ((int64_t)slot < cap) {
+                    write_record(recs[slot], w, j, cold, l, a, m, alo, mlo, Tn);
+                    parked = true;  // the resume kernel takes the wave from block j of launch l
+                    break;
+                }
+                // no room for the record: plain steps where the network would act
+                surrogate_blocks<W, kNetPlain>(pg, tab + s0 * W, Kb, Ks, dt, sa, nrm, nullptr, act, cold, gi, gj, gk,
+                                               j, a, m, alo, mlo, Tn);
+                r = 2;
+            }
+            if (r == 2) {  // a still wave's fractions are those in memory
+                a += alo;
+                m += mlo;
+                changed = true;
+            }
+            af = a;
+            mf = m;
+            Tc = Tn;
+            rest_w = __ballot(act && !rest_bits(af, mf)) == 0;
+        }
+        if (!parked) {
+            if (act) {
+                if (changed) {
+                    as[local] = a;
+                    am[local] = m;
+                }
+                if (beta) beta[local] = flagged ? solid_fraction(T0c) - kXmax - 0.0f : solid_fraction(Tc) - af - mf;
+            }
+            rest[w] = rest_w ? 1 : 0;  // (the same byte from every lane)
+        }
+    }
+}
+
+template <int W>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void surrogate_resume_call_kernel(
+    PointGeom pg, const SrcRec* __restrict__ tab, const EnvRec* __restrict__ env, const int32_t* __restrict__ env_fc,
+    const uint8_t* __restrict__ below, uint8_t* __restrict__ rest, int64_t n_waves, int64_t l0, int64_t nl, int Kl,
+    int Ks, int64_t n_steps, float dt, ScanArgs sa, MlpNorm nrm, float* __restrict__ beta, float* __restrict__ as,
+    float* __restrict__ am, const SurrogateRecord* __restrict__ recs, const unsigned* __restrict__ n_recs, int64_t cap,
+    const uint32_t* __restrict__ frag, unsigned long long* __restrict__ stats) {
+    const int64_t count = min((int64_t)*n_recs, cap);
+    const int64_t n_grid = (int64_t)gridDim.x * (blockDim.x >> 6);
+    if ((int64_t)blockIdx.x * (blockDim.x >> 6) >= count) return;  // no record for this block (uniform)
+    __shared__ InferLds L;
+    stage_infer_frag(L, frag);
+    const float T0c = fminf(sa.T0, sa.Tclamp);
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6; q < count; q += n_grid) {
+        const SurrogateRecord& r = recs[q];
+        const int64_t w = r.wave, lp = r.launch, g = w * kWave + lane;
+        bool act = g < pg.count;
+        int gi, gj, gk;
+        const int64_t local = point_at(pg, act ? g : 0, gi, gj, gk);
+        act = act && gk >= pg.k0;
+        float a = r.a[lane], m = r.m[lane], alo = r.alo[lane], mlo = r.mlo[lane], Tn = r.Tn[lane];
+        // the recorded launch from its block, with the network
+        int64_t s0 = lp * Kl;
+        int Kb = (int)min((int64_t)Kl, n_steps - s0);
+        surrogate_blocks<W, kNetRun>(pg, tab + s0 * W, Kb, Ks, dt, sa, nrm, &L, act, r.cold != 0, gi, gj, gk, r.block, a,
+                                     m, alo, mlo, Tn);
+        a += alo;
+        m += mlo;
+        float af = a, mf = m, Tc = Tn;
+        bool rest_w = __ballot(act && !rest_bits(af, mf)) == 0, flagged = false;
+        // the chunk's remaining launches
+        uint64_t bm = 0;
+        int64_t lb = lp + 1 - kWave;
+        for (int64_t l = lp + 1; l < l0 + nl; ++l) {
+            const uint8_t* bl = below + (l - l0) * n_waves;
+            if (l - lb >= kWave) {
+                lb = l;
+                bm = __ballot(l + lane < l0 + nl && below[(l - l0 + lane) * n_waves + w] != 0);
+            }
+            flagged = rest_w && ((bm >> (l - lb)) & 1);
+            if (flagged) {
+                if (stats) atomicAdd(stats + kStatFlagged, lane == 0 ? 1ull : 0ull);
+                continue;
+            }
+            s0 = l * Kl;
+            Kb = (int)min((int64_t)Kl, n_steps - s0);
+            const EnvSet es{env + env_fc[2 * l], env_fc[2 * l + 1], bl, nullptr, n_waves, 0, stats,
+                            nullptr, nullptr, nullptr};
+            bool cold;
+            int j = -1;
+            if (surrogate_launch<W, kNetRun>(pg, tab + s0 * W, es, w, Kb, Ks, dt, sa, nrm, &L, act, gi, gj, gk, a, m,
+                                             alo, mlo, Tn, cold, j) == 2) {
+                a += alo;
+                m += mlo;
+            }
+            af = a;
+            mf = m;
+            Tc = Tn;
+            rest_w = __ballot(act && !rest_bits(af, mf)) == 0;
+        }
+        if (act) {
+            as[local] = a;
+            am[local] = m;
+            if (beta) beta[local] = flagged ? solid_fraction(T0c) - kXmax - 0.0f : solid_fraction(Tc) - af - mf;
+        }
+        rest[w] = rest_w ? 1 : 0;
     }
 }
 
@@ -858,23 +1036,13 @@ hipError_t launch_surrogate(const MlpState& s, const PointGeom& pg, int W, const
     unsigned* nxt = s.counters + ((li + 1) & 1);
     const int64_t cap = s.rec_cap;
     const MlpNorm& nrm = s.norm;
-    if (env.below && env.cand) {
-        switch (W) {
-            case 1: LAUNCH_SLOTS(fused_surrogate_slots_kernel, 1, env.n_waves, slots_per_wave(env.n_waves, SlotUse::Surrogate), st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
-            case 2: LAUNCH_SLOTS(fused_surrogate_slots_kernel, 2, env.n_waves, slots_per_wave(env.n_waves, SlotUse::Surrogate), st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
-            case 3: LAUNCH_SLOTS(fused_surrogate_slots_kernel, 3, env.n_waves, slots_per_wave(env.n_waves, SlotUse::Surrogate), st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
-            case 4: LAUNCH_SLOTS(fused_surrogate_slots_kernel, 4, env.n_waves, slots_per_wave(env.n_waves, SlotUse::Surrogate), st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
-            default: return hipErrorInvalidValue;
-        }
-    } else {
-        const dim3 grid((unsigned)((pg.count + kFusedBlock - 1) / kFusedBlock)), block(kFusedBlock);
-        switch (W) {
-            case 1: hipLaunchKernelGGL(fused_surrogate_kernel<1>, grid, block, 0, st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
-            case 2: hipLaunchKernelGGL(fused_surrogate_kernel<2>, grid, block, 0, st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
-            case 3: hipLaunchKernelGGL(fused_surrogate_kernel<3>, grid, block, 0, st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
-            case 4: hipLaunchKernelGGL(fused_surrogate_kernel<4>, grid, block, 0, st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
-            default: return hipErrorInvalidValue;
-        }
+    const dim3 grid((unsigned)((pg.count + kFusedBlock - 1) / kFusedBlock)), block(kFusedBlock);
+    switch (W) {
+        case 1: hipLaunchKernelGGL(fused_surrogate_kernel<1>, grid, block, 0, st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
+        case 2: hipLaunchKernelGGL(fused_surrogate_kernel<2>, grid, block, 0, st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
+        case 3: hipLaunchKernelGGL(fused_surrogate_kernel<3>, grid, block, 0, st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
+        case 4: hipLaunchKernelGGL(fused_surrogate_kernel<4>, grid, block, 0, st, pg, tab, env, Kl, Ks, dt, sa, nrm, beta, as, am, recs, cur, cap); break;
+        default: return hipErrorInvalidValue;
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
@@ -930,6 +1098,43 @@ void mlp_free(MlpState& s) {
                     (void*)s.partial, (void*)s.recs, (void*)s.counters})
         if (p) (void)hipFree(p);
     s = MlpState{};
+}
+
+
+hipError_t launch_surrogate_call(const MlpState& s, const PointGeom& pg, int W, const SrcRec* tab, const EnvRec* env,
+                                 const int32_t* env_fc, const uint8_t* below, uint8_t* rest, int64_t n_waves,
+                                 int64_t l0, int64_t nl, int Kl, int Ks, int64_t n_steps, float dt, ScanArgs sa,
+                                 float* beta, float* as, float* am, uint32_t* cand, unsigned* counts,
+                                 unsigned long long* stats, hipStream_t st) {
+    if (n_waves <= 0 || nl <= 0) return hipSuccess;
+    hipError_t e = launch_chunk_list(pg, below, rest, n_waves, l0, nl, fminf(sa.T0, sa.Tclamp), beta, as, am, cand,
+                                     counts, stats, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reset_counters_kernel, dim3(1), dim3(64), 0, st, s.counters);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    SurrogateRecord* recs = static_cast<SurrogateRecord*>(s.recs);
+    const int64_t cap = s.rec_cap;
+    const MlpNorm& nrm = s.norm;
+    const dim3 grid = call_grid(n_waves), block(kCallBlock), rg(256), rb(256);
+    switch (W) {
+#define MSTRUCT_SURROGATE_CALL(WW)                                                                                   \
+    case WW:                                                                                                         \
+        hipLaunchKernelGGL(fused_surrogate_call_kernel<WW>, grid, block, 0, st, pg, tab, env, env_fc, below, rest,    \
+                           n_waves, l0, nl, Kl, Ks, n_steps, dt, sa, nrm, beta, as, am, cand, counts, counts + 1,     \
+                           stats, recs, s.counters, cap);                                                            \
+        if ((e = hipGetLastError()) != hipSuccess) return e;                                                         \
+        hipLaunchKernelGGL(surrogate_resume_call_kernel<WW>, rg, rb, 0, st, pg, tab, env, env_fc, below, rest,        \
+                           n_waves, l0, nl, Kl, Ks, n_steps, dt, sa, nrm, beta, as, am, recs, s.counters, cap,        \
+                           s.frag, stats);                                                                           \
+        break;
+        MSTRUCT_SURROGATE_CALL(1)
+        MSTRUCT_SURROGATE_CALL(2)
+        MSTRUCT_SURROGATE_CALL(3)
+        MSTRUCT_SURROGATE_CALL(4)
+#undef MSTRUCT_SURROGATE_CALL
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 }  // namespace mstruct
