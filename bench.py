@@ -75,26 +75,26 @@ PAPER_CPU = {
 # reported null.
 FUSED_PROFILE = {
     "file": "profiles/fused_plain_kernel_multilayer_block.txt", "K": 64,
-    "valu_lane_ops_per_update": 8.765, "valu_issue": 0.372, "valu_busy": 0.532,
+    "valu_lane_ops_per_update": 8.765, "valu_issue": 0.373, "valu_busy": 0.534,
     # the persistent kernel with its list and still-flag passes, per dispatch (one per call)
-    "traffic_bytes_per_dispatch": 139318071,
+    "traffic_bytes_per_dispatch": 139390305,
 }
 FUSED_PROFILE_EVERY_T = {"K": 64, "valu_lane_ops_per_update": 130.31, "valu_issue": 0.730,
-                         "valu_busy": 0.926}
+                         "valu_busy": 0.927}
 SURROGATE_PROFILE = {"file": "profiles/fused_surrogate_kernels_multilayer_block.txt", "K": 64,
-                     8: {"valu_lane_ops_per_update": 4.175, "valu_issue": 0.185, "valu_busy": 0.302},
-                     16: {"valu_lane_ops_per_update": 3.468, "valu_issue": 0.161, "valu_busy": 0.273}}
+                     8: {"valu_lane_ops_per_update": 4.068, "valu_issue": 0.264, "valu_busy": 0.403},
+                     16: {"valu_lane_ops_per_update": 3.360, "valu_issue": 0.229, "valu_busy": 0.366}}
 C3_PROFILE = {"file": "profiles/fused_plain_kernel_cantilever_islands.txt", "K": K_C3,
               "valu_lane_ops_per_update": 1.392, "valu_issue": 0.283, "valu_busy": 0.423,
               "traffic_bytes_per_dispatch": 2045373600}
 C5_PROFILE = {"file": "profiles/fused_kernels_island_block.txt",
               "plain": {"K": K_FUSED, "kernel": "fused_plain_call_kernel<2> + chunk_list_kernel + still_flags_kernel",
-                        "valu_lane_ops_per_update": 1.945, "valu_issue": 0.507, "valu_busy": 0.701,
-                        "traffic_bytes": 721086573, "traffic_unit": "bytes/dispatch"},
+                        "valu_lane_ops_per_update": 1.945, "valu_issue": 0.506, "valu_busy": 0.700,
+                        "traffic_bytes": 721446748, "traffic_unit": "bytes/dispatch"},
               "surrogate": {"K": K_SURROGATE,
-                            "kernel": "fused_surrogate_slots_kernel<2,256> + surrogate_resume_kernel<2> + list passes",
-                            "valu_lane_ops_per_update": 0.613, "valu_issue": 0.249, "valu_busy": 0.375,
-                            "traffic_bytes": 23694107, "traffic_unit": "bytes/launch"}}
+                            "kernel": "fused_surrogate_call_kernel<2> + surrogate_resume_call_kernel<2> + list passes",
+                            "valu_lane_ops_per_update": 0.561, "valu_issue": 0.345, "valu_busy": 0.500,
+                            "traffic_bytes": 721421198, "traffic_unit": "bytes/dispatch"}}
 
 
 def parse():
@@ -404,12 +404,13 @@ def bench_c2(torch, ms, ctx, args):
                 "value": sur_rate, "unit": "point-updates/s",
                 "ms_per_step": ms_sur / args.steps, "speedup_vs_plain": ms_total / ms_sur,
                 "target_speedup_vs_plain": 3.0, "target_met": ms_total / ms_sur >= 3.0, "K": sur.K,
-                "path": "mstruct_fused_scan_steps, SURROGATE: fused launches of 64 steps; per block of K steps a "
-                        "wave takes one explicit step of K dt + BF16-MFMA network correction where every point "
-                        "passes the indicator, K plain steps otherwise",
+                "path": "mstruct_fused_scan_steps, SURROGATE: launches of 64 steps, a call's launches in one "
+                        "persistent kernel; per block of K steps a wave takes one explicit step of K dt + BF16-MFMA "
+                        "network correction where every point passes the indicator, K plain steps otherwise",
                 "indicator": list(sur.indicator),
                 "roofline": None if sp is None else {
-                    "kernel": "fused_surrogate_slots_kernel<2,128> (list form) + surrogate_resume_kernel<2>",
+                    "kernel": "fused_surrogate_call_kernel<2> + surrogate_resume_call_kernel<2> (one each per call) "
+                              "+ chunk_list_kernel + still_flags_kernel",
                     "bound": "alu", "lane_ops_per_update": sp["valu_lane_ops_per_update"],
                     "achieved": sur_rate * sp["valu_lane_ops_per_update"] / 1e12, "peak": VALU_PEAK_TLANEOPS,
                     "unit": "Tlane-op/s", "frac": sur_rate * sp["valu_lane_ops_per_update"] / 1e12 / VALU_PEAK_TLANEOPS,
@@ -496,9 +497,9 @@ def bench_c5(torch, ms, ctx, args):
         t = e0.elapsed_time(e1) * 1e-3
         prof = C5_PROFILE[key]
         rate = upd / t
-        # the plain path: one persistent kernel per chunk of launches; the
-        # surrogate: one slot kernel per launch of 64 steps
-        units = call_dispatches(wl, K) if key == "plain" else call_launches(wl, 64)
+        # both paths: one persistent kernel per chunk of launches (the
+        # surrogate's launches are 64 steps too)
+        units = call_dispatches(wl, 64)
         out[key] = {"seconds": t, "value": rate, "unit": "point-updates/s", "K": K,
                     "roofline": {"kernel": prof["kernel"], "bound": "alu", "peak": VALU_PEAK_TLANEOPS,
                                  "unit": "Tlane-op/s",
