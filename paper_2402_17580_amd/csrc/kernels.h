@@ -177,8 +177,8 @@ hipError_t launch_fused_plain_call(const PointGeom& pg, int W, const SrcRec* tab
 hipError_t launch_chunk_list(const PointGeom& pg, const uint8_t* below, uint8_t* rest, int64_t n_waves, int64_t l0,
                              int64_t nl, float T0c, float* beta, const float* as, const float* am, uint32_t* cand,
                              unsigned* counts, unsigned long long* stats, hipStream_t st);
-// workgroup and grid of the persistent call kernels (kCallBlock threads, at
-// most eight waves per SIMD)
+// workgroup and grid of the persistent call kernels (kCallBlock threads,
+// kCallWaves grid waves at most: eight per SIMD)
 constexpr int kCallBlock = 256;
 dim3 call_grid(int64_t n_waves);
 hipError_t launch_gather(const float* src, const int64_t* idx, int64_t m, float* dst, hipStream_t st);

@@ -643,7 +643,9 @@ __global__ __launch_bounds__(kListBlock) void chunk_list_kernel(
 // at rest after the last launch that took its steps: read from the second
 // chunk, written at the end of each).
 // ---------------------------------------------------------------------------
-// grid waves of the persistent call kernel: eight per SIMD
+// grid waves of the persistent call kernels: eight per SIMD (their registers
+// let seven stay resident; the rest start as the first workgroups end and
+// take what is left of the list)
 constexpr int kCallWaves = 256 * 4 * 8;
 
 // The loop of a call kernel: launch(es, w, tab_l, Kl, act, gi, gj, gk, a, m,
