@@ -609,13 +609,19 @@ enum { kNetStop = 0, kNetRun = 1, kNetPlain = 2 };
 // the start of block j0).  NET: kNetStop returns the block at which the
 // network is needed (state unchanged from that block's start); kNetRun
 // evaluates it (all 64 lanes; L: staged weights); kNetPlain takes the plain
-// steps instead.  Returns -1 when every block was taken.
+// steps instead.  Returns -1 when every block was taken.  frozen_nb > 1 (a
+// cold wave from block 0, whose blocks all take the block update): if block
+// 0 left the fractions' stored values as they were over frozen_nb blocks
+// (frozen_part), every later block repeats it, and the blocks stop there
+// with a, m as on entry and alo = mlo = 0 (returns -2).
 template <int W, int NET>
 __device__ __forceinline__ int surrogate_blocks(const PointGeom& pg, const SrcRec* __restrict__ tab, int Kl, int Ks,
                                                 float dt, const ScanArgs& sa, const MlpNorm& nrm,
                                                 const InferLds* L, bool act, bool cold, int gi, int gj, int gk, int j0,
-                                                float& a, float& m, float& alo, float& mlo, float& Tn) {
+                                                float& a, float& m, float& alo, float& mlo, float& Tn,
+                                                int frozen_nb = 0) {
     const float T0c = fminf(sa.T0, sa.Tclamp);
+    const float a0 = a, m0 = m;
     const int nb = (Kl + Ks - 1) / Ks;
     float xeq_n = alpha_eq(Tn);
     for (int j = j0; j < nb; ++j) {
@@ -686,6 +692,14 @@ __device__ __forceinline__ int surrogate_blocks(const PointGeom& pg, const SrcRe
         }
         Tn = TK;
         xeq_n = xeq_K;
+        if (frozen_nb > 1 && j == 0 &&
+            __ballot(act && !(frozen_part(a0, a, alo, frozen_nb) && frozen_part(m0, m, mlo, frozen_nb))) == 0) {
+            a = a0;
+            m = m0;
+            alo = 0.0f;
+            mlo = 0.0f;
+            return -2;
+        }
     }
     return -1;
 }
@@ -705,12 +719,17 @@ __device__ __forceinline__ void surrogate_store(const EnvSet& env, int64_t wv, b
 }
 
 // One surrogate launch of a wave on its register state: still and cold
-// waves as in the plain fused kernel, then the network blocks.  a, m: the
-// fractions as loaded; returns 0 (still: a, m unchanged, Tn = T0), 2 (done:
-// hi parts a, m and lo parts alo, mlo at the end of the launch, Tn its last
-// temperature) or, with NET == kNetStop, 3: block j needs the network, and
-// a, m, alo, mlo, Tn hold the state at that block's start (cold: whether the
-// wave is cold in this launch).
+// waves as in the plain fused kernel, then the network blocks.  A cold wave
+// whose blocks all take the block update (whole blocks, and the indicator
+// passes at T0) stops after its first block if that block left the stored
+// fractions as they were (frozen: every block starts from the same high
+// parts at T0 and repeats the first, so the launch would store the loaded
+// values).  a, m: the fractions as loaded; returns 0 (still: a, m unchanged,
+// Tn = T0), 1 (frozen: the same, with alo = mlo = 0), 2 (done: hi parts a, m
+// and lo parts alo, mlo at the end of the launch, Tn its last temperature)
+// or, with NET == kNetStop, 3: block j needs the network, and a, m, alo,
+// mlo, Tn hold the state at that block's start (cold: whether the wave is
+// cold in this launch).
 template <int W, int NET>
 __device__ __forceinline__ int surrogate_launch(const PointGeom& pg, const SrcRec* __restrict__ tab, const EnvSet& env,
                                                 int64_t wv, int Kl, int Ks, float dt, const ScanArgs& sa,
@@ -731,9 +750,12 @@ __device__ __forceinline__ int surrogate_launch(const PointGeom& pg, const SrcRe
     cold_out = cold;
     if (still) return 0;  // its fractions are those in memory
     if (!cold) __builtin_amdgcn_s_setprio(3);  // as in plain_launch
-    j = surrogate_blocks<W, NET>(pg, tab, Kl, Ks, dt, sa, nrm, L, act, cold, gi, gj, gk, 0, a, m, alo, mlo, Tn);
+    const int nb = Kl / Ks;
+    const int frozen_nb = (cold && nb > 1 && nb * Ks == Kl && !needs_plain(T0c, T0c, nrm)) ? nb : 0;
+    j = surrogate_blocks<W, NET>(pg, tab, Kl, Ks, dt, sa, nrm, L, act, cold, gi, gj, gk, 0, a, m, alo, mlo, Tn,
+                                 frozen_nb);
     __builtin_amdgcn_s_setprio(0);
-    return j >= 0 ? 3 : 2;
+    return j >= 0 ? 3 : j == -2 ? 1 : 2;
 }
 
 // a wave's state at the start of block j of launch l, for the resume kernels
@@ -769,7 +791,7 @@ __device__ __forceinline__ void surrogate_fused_body(const PointGeom& pg, const 
     int j = -1;
     const int r = surrogate_launch<W, kNetStop>(pg, tab, env, wv, Kl, Ks, dt, sa, nrm, nullptr, act, gi, gj, gk, a, m,
                                                 alo, mlo, Tn, cold, j);
-    if (r == 0) {  // still: its fractions are those in memory
+    if (r == 0 || r == 1) {  // still or frozen: its fractions are those in memory
         if (act && beta) beta[local] = solid_fraction(Tn) - a - m;
         record_rest(env, wv, act, a, m);
         return;
@@ -907,7 +929,7 @@ __global__ __launch_bounds__(kCallBlock) void fused_surrogate_call_kernel(
                                                j, a, m, alo, mlo, Tn);
                 r = 2;
             }
-            if (r == 2) {  // a still wave's fractions are those in memory
+            if (r == 2) {  // a still or frozen wave's fractions are those in memory
                 a += alo;
                 m += mlo;
                 changed = true;
