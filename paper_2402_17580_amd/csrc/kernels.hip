@@ -596,15 +596,20 @@ __global__ __launch_bounds__(kListBlock) void chunk_list_kernel(
         int gi, gj, gk;
         const int64_t local = point_at(pg, act ? g : 0, gi, gj, gk);
         act = act && gk >= pg.k0;
-        bool at_rest;
+        // the first 64 launches' flags are loaded with the state, not after it
+        // (lanes past nl load launch nl - 1's flag and ignore it; nl >= 1)
+        const uint8_t f0 = below[min((int64_t)lane, nl - 1) * n_waves + w];
+        float a = 0.0f, m = 0.0f;
+        uint8_t r = 0;
         if (l0 == 0) {  // (below implies T0 under the still limit)
-            const float a = act ? as[local] : 0.0f, m = act ? am[local] : 0.0f;
-            at_rest = __ballot(act && !rest_bits(a, m)) == 0;
+            a = act ? as[local] : 0.0f;
+            m = act ? am[local] : 0.0f;
         } else {
-            at_rest = rest[w] != 0;
+            r = rest[w];
         }
-        still = at_rest;
-        for (int64_t i0 = 0; i0 < nl && still; i0 += kWave)
+        const bool at_rest = l0 == 0 ? __ballot(act && !rest_bits(a, m)) == 0 : r != 0;
+        still = at_rest && __ballot(lane < nl && f0 == 0) == 0;
+        for (int64_t i0 = kWave; i0 < nl && still; i0 += kWave)
             still = __ballot(i0 + lane < nl && below[(i0 + lane) * n_waves + w] == 0) == 0;
         if (still) {
             if (act && beta) beta[local] = solid_fraction(T0c) - kXmax - 0.0f;
@@ -736,7 +741,7 @@ hipError_t launch_chunk_list(const PointGeom& pg, const uint8_t* below, uint8_t*
                              int64_t nl, float T0c, float* beta, const float* as, const float* am, uint32_t* cand,
                              unsigned* counts, unsigned long long* stats, hipStream_t st) {
     hipError_t e = launch_clear_counts(counts, st);
-    if (e != hipSuccess) return e;
+    if (e != hipSuccess || n_waves <= 0 || nl <= 0) return e;
     const int64_t lpb = kListBlock / kWave;
     hipLaunchKernelGGL(chunk_list_kernel, dim3((unsigned)((n_waves + lpb - 1) / lpb)), dim3(kListBlock), 0, st, pg,
                        below, rest, n_waves, l0, nl, T0c, beta, as, am, cand, counts, stats);
