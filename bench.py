@@ -75,26 +75,26 @@ PAPER_CPU = {
 # reported null.
 FUSED_PROFILE = {
     "file": "profiles/fused_plain_kernel_multilayer_block.txt", "K": 64,
-    "valu_lane_ops_per_update": 8.765, "valu_issue": 0.373, "valu_busy": 0.534,
+    "valu_lane_ops_per_update": 8.765, "valu_issue": 0.370, "valu_busy": 0.530,
     # the persistent kernel with its list and still-flag passes, per dispatch (one per call)
-    "traffic_bytes_per_dispatch": 139392830,
+    "traffic_bytes_per_dispatch": 139802356,
 }
-FUSED_PROFILE_EVERY_T = {"K": 64, "valu_lane_ops_per_update": 130.31, "valu_issue": 0.734,
-                         "valu_busy": 0.931}
+FUSED_PROFILE_EVERY_T = {"K": 64, "valu_lane_ops_per_update": 130.31, "valu_issue": 0.730,
+                         "valu_busy": 0.927}
 SURROGATE_PROFILE = {"file": "profiles/fused_surrogate_kernels_multilayer_block.txt", "K": 64,
-                     8: {"valu_lane_ops_per_update": 3.809, "valu_issue": 0.251, "valu_busy": 0.389},
-                     16: {"valu_lane_ops_per_update": 3.241, "valu_issue": 0.225, "valu_busy": 0.362}}
+                     8: {"valu_lane_ops_per_update": 3.809, "valu_issue": 0.253, "valu_busy": 0.392},
+                     16: {"valu_lane_ops_per_update": 3.241, "valu_issue": 0.228, "valu_busy": 0.368}}
 C3_PROFILE = {"file": "profiles/fused_plain_kernel_cantilever_islands.txt", "K": K_C3,
-              "valu_lane_ops_per_update": 1.392, "valu_issue": 0.283, "valu_busy": 0.423,
-              "traffic_bytes_per_dispatch": 2045373600}
+              "valu_lane_ops_per_update": 1.392, "valu_issue": 0.284, "valu_busy": 0.425,
+              "traffic_bytes_per_dispatch": 2046456748}
 C5_PROFILE = {"file": "profiles/fused_kernels_island_block.txt",
               "plain": {"K": K_FUSED, "kernel": "fused_plain_call_kernel<2> + chunk_list_kernel + still_flags_kernel",
-                        "valu_lane_ops_per_update": 1.945, "valu_issue": 0.508, "valu_busy": 0.703,
-                        "traffic_bytes": 721468671, "traffic_unit": "bytes/dispatch"},
+                        "valu_lane_ops_per_update": 1.945, "valu_issue": 0.507, "valu_busy": 0.702,
+                        "traffic_bytes": 721815966, "traffic_unit": "bytes/dispatch"},
               "surrogate": {"K": K_SURROGATE,
                             "kernel": "fused_surrogate_call_kernel<2> + surrogate_resume_call_kernel<2> + list passes",
                             "valu_lane_ops_per_update": 0.443, "valu_issue": 0.284, "valu_busy": 0.430,
-                            "traffic_bytes": 720768688, "traffic_unit": "bytes/dispatch"}}
+                            "traffic_bytes": 721103344, "traffic_unit": "bytes/dispatch"}}
 
 
 def parse():
